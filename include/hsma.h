@@ -1,0 +1,157 @@
+/*
+ * hsma.h -- C ABI of the MI355X (gfx950) implementation of the harmonic surface
+ * mapping algorithm (HSMA) for the reaction potential of N ions in a dielectric
+ * sphere embedded in a linearised Poisson-Boltzmann continuum.
+ *
+ * Method: J. Fu and Z. Gan, arXiv:1907.01724.  The interface problem is Sec. 2.1
+ * (eqs. "phiinsideeq", "phioutsideeq", "boundarycondition"); the quantity computed
+ * is the reaction potential Phi_RF of eq. "phiin" at the ions, in the
+ * image-plus-surface form of eq. "phirffinall" (Sec. 2.4, Algorithm 1):
+ *
+ *   Phi_RF(x_i) = sum_{j} q_K,j / (4 pi eps1 |x_i - r_K,j|)           (modified Kelvin images)
+ *               + sum_{s<P} [Q_s + D_s (x_i - y_s).y^_s / |x_i - y_s|^2] / (4 pi |x_i - y_s|)
+ *
+ * with r_K,j = (a/r_j)^2 x_j and q_K,j = (q_j/a)[gamma r_K,j + dbar (R_tau - r_K,j)/2]
+ * (Sec. 2.4), surface nodes y_s of the Fibonacci rule on the auxiliary sphere of
+ * radius R_tau = (1 + tau) a, and monopole/dipole strengths Q_s, D_s obtained from a
+ * fixed least-squares fit of the ions' potential at M check points (Algorithm 1,
+ * steps 1-3) mapped through Green's second identity (eq. "GreenSecond").
+ * The ion's own image (j = i) is included: it is the ion's self polarisation.
+ *
+ * Units: a charge q in medium eps1 has potential q / (4 pi eps1 r) (eq. "phicoul").
+ * Multiply by the caller's Coulomb constant if another unit system is wanted.
+ *
+ * Conventions shared by every entry point:
+ *  - Every double is IEEE binary64.  Arrays marked [device] are device pointers on
+ *    the plan's device; [host] marks host pointers.  Coordinates and charges are
+ *    structure-of-arrays: x[i], y[i], z[i], q[i], i < N, with the sphere centred at
+ *    the origin.
+ *  - Ownership: the caller owns every input/output array and the workspace and must
+ *    keep them alive until the stream has executed the call.  Plans and systems own
+ *    their internal device buffers and free them in the matching destroy call.
+ *  - Streams: compute entry points only enqueue work on the given stream (0 = the
+ *    null stream); they never synchronise, allocate or free, so they may be captured
+ *    into a HIP graph.  hsma_plan*, hsma_system_create/destroy and hsma_stream_check
+ *    synchronise and may allocate.
+ *  - Validation: scalar arguments are checked on the host before anything is
+ *    enqueued (HSMA_EINVAL).  An ion with |x_i| >= a or a non-finite input value is
+ *    detected on the device: it raises the plan's domain flag, which
+ *    hsma_stream_check reports as HSMA_EDOMAIN; the outputs of that call are
+ *    undefined.
+ *  - Determinism: every reduction runs in a fixed order, so a result is bitwise
+ *    reproducible for the same inputs, plan and device.
+ *  - Thread safety: a plan is immutable after creation and may be used from several
+ *    threads and streams at once (they share its domain flag); a system must not be
+ *    used concurrently.
+ */
+#ifndef HSMA_H
+#define HSMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HSMA_OK = 0,
+  HSMA_EINVAL = 1,  /* invalid scalar argument or null pointer */
+  HSMA_EDOMAIN = 2, /* an ion outside the cavity or a non-finite input (device flag) */
+  HSMA_ENOMEM = 3,  /* device or host allocation failed */
+  HSMA_EBUSY = 4,   /* reserved for admission control */
+  HSMA_EDEVICE = 5, /* a HIP runtime call failed */
+  HSMA_ESTATE = 6   /* object in the wrong state (e.g. plan built for another device) */
+} hsma_status;
+
+/* Arithmetic of the pair sums (the two Coulomb sums of Algorithm 1, steps 2 and 5). */
+typedef enum {
+  HSMA_PAIR_FP32 = 0,      /* FP32 pairs, FP32 running sum per target (precision sweep only) */
+  HSMA_PAIR_FP32_COMP = 1, /* FP32 pairs, FP32 sums over 32-source tiles folded into FP64 (default) */
+  HSMA_PAIR_FP64 = 2       /* FP64 coordinates and pairs, FP32-seeded FP64 Newton reciprocal root */
+} hsma_pair_precision;
+
+typedef struct hsma_plan_s *hsma_plan_t;
+typedef struct hsma_system_s *hsma_system_t;
+
+/* Discretisation options.  Fields left at the values of hsma_plan_opts_default()
+ * give: p = floor(sqrt(P)/2), tau = 0.1, rc_over_a = 1 + tau, F1 = the integer
+ * nearest F2/golden-ratio that is coprime to F2, FP32 compensated pair sums. */
+typedef struct {
+  int p;            /* spherical-harmonic truncation order (eq. "phim"); < 0: default */
+  double tau;       /* auxiliary sphere R_tau = (1 + tau) a, tau > 0 (Sec. 2.4) */
+  double rc_over_a; /* radius of the check points / a, > 1; <= 0: 1 + tau */
+  int F1;           /* Fibonacci-rule F1 (Sec. 2.4), 0 < F1 < F2; 0: default */
+  int pair_prec;    /* hsma_pair_precision */
+} hsma_plan_opts;
+
+/* Read-only description of a plan (for callers and tests). */
+typedef struct {
+  double a, eps1, eps2, kappa;
+  double tau, R_tau, rc;           /* auxiliary radius and check-point radius */
+  double gamma, sigma, dbar;       /* constants of eq. "Anuapp" */
+  int p, K, P, M, F1, F2;          /* K = (p+1)^2 fitted coefficients; P = 2 (F2 + 1) */
+  int pair_prec;
+  int device;
+} hsma_plan_info;
+
+hsma_plan_opts hsma_plan_opts_default(void);
+
+/* Build a plan for one cavity: a > 0 (radius), eps1, eps2 > 0 (dielectric constants
+ * inside/outside), kappa >= 0 (inverse Debye length outside), P surface nodes (even,
+ * >= 8; P = 2 (F2 + 1) nodes of the Fibonacci rule of Sec. 2.4) and M check points
+ * (M >= ceil(1.5 (p+1)^2)).  Runs the FP64 plan kernels on the current device
+ * (Kirkwood factors M_n of eq. "Anuapp1", node sets, real SH bases, the normal
+ * equations' Cholesky factor and the fixed fit/surface operators) and synchronises.
+ * Plans with equal (p, P, M, F1, tau, rc/a) share their dimensionless operators.
+ * Errors: HSMA_EINVAL (bad scalar), HSMA_ENOMEM, HSMA_EDEVICE. */
+hsma_status hsma_plan(double a, double eps1, double eps2, double kappa, int P, int M, hsma_plan_t *out);
+hsma_status hsma_plan_ex(double a, double eps1, double eps2, double kappa, int P, int M,
+                         const hsma_plan_opts *opts /* [host], NULL = defaults */, hsma_plan_t *out);
+hsma_status hsma_plan_destroy(hsma_plan_t plan);
+hsma_status hsma_plan_get_info(hsma_plan_t plan, hsma_plan_info *info /* [host] */);
+
+/* Bytes of device workspace hsma_potential / hsma_energy need for N ions
+ * (256-byte aligned pointer required). */
+size_t hsma_workspace_bytes(hsma_plan_t plan, int64_t N);
+
+/* Reaction potential Phi_RF at every ion (eq. "phirffinall"), N >= 0.
+ * x, y, z, q: [device] N doubles each; phi: [device] N doubles (output);
+ * ws: [device] hsma_workspace_bytes(plan, N) bytes.  Errors: HSMA_EINVAL, HSMA_EDEVICE. */
+hsma_status hsma_potential(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
+                           const double *q, double *phi, void *ws, hipStream_t stream);
+
+/* Reaction energy E = (1/2) sum_i q_i Phi_RF(x_i) (the self energy of Sec. 4.1
+ * generalised to N ions), reduced in FP64 in a fixed order.  E: [device] one double.
+ * phi: [device] N doubles receiving the potentials, or NULL to keep them in ws. */
+hsma_status hsma_energy(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
+                        const double *q, double *phi, double *E, void *ws, hipStream_t stream);
+
+/* Intermediate results of the last hsma_potential/hsma_energy call that used ws,
+ * copied to host arrays (for tests and diagnostics; synchronises the stream).
+ * Any output pointer may be NULL.  u, v: M check fields; Q, D: P surface strengths
+ * (Q_s and D_s of the header comment, divided by 4 pi and 4 pi R_tau). */
+hsma_status hsma_debug_intermediates(hsma_plan_t plan, int64_t N, const void *ws, hipStream_t stream,
+                                     double *u, double *v, double *Q, double *D);
+
+/* Stage timing: when enabled, every compute call records HIP events on its stream
+ * around its kernel groups (0 Kelvin images/packing, 1 check sums, 2 fit apply,
+ * 3 evaluation pair sums, 4 final reductions).  hsma_profile_read waits for the
+ * recorded events, returns the summed milliseconds and launch counts per stage
+ * (arrays of 5, [host]) and clears the records.  For measurement only; enabling
+ * it makes the compute calls create events (not graph-capturable). */
+hsma_status hsma_profile_enable(hsma_plan_t plan, int on);
+hsma_status hsma_profile_read(hsma_plan_t plan, double *ms /* [host] 5 */, int64_t *count /* [host] 5 */);
+
+/* Synchronise the stream and report a device-side domain error raised since the
+ * last check (then clear it). */
+hsma_status hsma_stream_check(hsma_plan_t plan, hipStream_t stream);
+
+const char *hsma_status_string(hsma_status s);
+int hsma_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSMA_H */

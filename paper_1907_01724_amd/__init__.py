@@ -1,0 +1,226 @@
+"""MI355X (gfx950) HSMA reaction potential: thin Python binding over libhsma.so.
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+``libhsma.so`` (C ABI declared in ``include/hsma.h``).  PyTorch supplies device memory
+and streams.  Importing works without a GPU; every compute call requires the built
+library and a GPU and raises otherwise (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsma.so")
+
+HSMA_PAIR_FP32 = 0
+HSMA_PAIR_FP32_COMP = 1
+HSMA_PAIR_FP64 = 2
+PAIR_PREC = {"fp32": HSMA_PAIR_FP32, "fp32c": HSMA_PAIR_FP32_COMP, "fp64": HSMA_PAIR_FP64}
+
+STATUS = {0: "HSMA_OK", 1: "HSMA_EINVAL", 2: "HSMA_EDOMAIN", 3: "HSMA_ENOMEM", 4: "HSMA_EBUSY",
+          5: "HSMA_EDEVICE", 6: "HSMA_ESTATE"}
+
+
+class HsmaError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)}")
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("p", C.c_int), ("tau", C.c_double), ("rc_over_a", C.c_double), ("F1", C.c_int),
+                ("pair_prec", C.c_int)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("a", C.c_double), ("eps1", C.c_double), ("eps2", C.c_double), ("kappa", C.c_double),
+                ("tau", C.c_double), ("R_tau", C.c_double), ("rc", C.c_double), ("gamma", C.c_double),
+                ("sigma", C.c_double), ("dbar", C.c_double), ("p", C.c_int), ("K", C.c_int), ("P", C.c_int),
+                ("M", C.c_int), ("F1", C.c_int), ("F2", C.c_int), ("pair_prec", C.c_int), ("device", C.c_int)]
+
+
+_lib = None
+_VP = C.c_void_p
+_DP = C.POINTER(C.c_double)
+
+
+def load_library(path: str | None = None):
+    """Load libhsma.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libhsma.so not built at {path}: run paper_1907_01724_amd/build.py "
+                           f"(or __graft_entry__.build())")
+    L = C.CDLL(path)
+    L.hsma_plan_opts_default.restype = PlanOpts
+    L.hsma_plan.argtypes = [C.c_double] * 4 + [C.c_int, C.c_int, C.POINTER(_VP)]
+    L.hsma_plan_ex.argtypes = [C.c_double] * 4 + [C.c_int, C.c_int, C.POINTER(PlanOpts), C.POINTER(_VP)]
+    L.hsma_plan_destroy.argtypes = [_VP]
+    L.hsma_plan_get_info.argtypes = [_VP, C.POINTER(PlanInfo)]
+    L.hsma_workspace_bytes.argtypes = [_VP, C.c_int64]
+    L.hsma_workspace_bytes.restype = C.c_size_t
+    L.hsma_potential.argtypes = [_VP, C.c_int64] + [_VP] * 5 + [_VP, _VP]
+    L.hsma_energy.argtypes = [_VP, C.c_int64] + [_VP] * 6 + [_VP, _VP]
+    L.hsma_debug_intermediates.argtypes = [_VP, C.c_int64, _VP, _VP, _DP, _DP, _DP, _DP]
+    L.hsma_stream_check.argtypes = [_VP, _VP]
+    L.hsma_status_string.argtypes = [C.c_int]
+    L.hsma_status_string.restype = C.c_char_p
+    L.hsma_version.restype = C.c_int
+    L.hsma_profile_enable.argtypes = [_VP, C.c_int]
+    L.hsma_profile_read.argtypes = [_VP, _DP, C.POINTER(C.c_int64)]
+    for name in ("hsma_plan", "hsma_plan_ex", "hsma_plan_destroy", "hsma_plan_get_info", "hsma_potential",
+                 "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
+                 "hsma_profile_read"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise HsmaError(code, where)
+
+
+def _torch():
+    import torch  # imported lazily: the binding itself only needs ctypes
+    return torch
+
+
+def _dev_ptr(t, name: str, n: int | None = None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def workspace(nbytes: int, device=None):
+    """A 256-byte aligned device buffer of at least nbytes (a uint8 tensor and its pointer)."""
+    torch = _torch()
+    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device or "cuda")
+    ptr = buf.data_ptr()
+    off = (-ptr) % 256
+    return buf, ptr + off
+
+
+class Plan:
+    """One cavity (a, eps1, eps2, kappa) discretised with P surface nodes and M check points."""
+
+    def __init__(self, a: float, eps1: float, eps2: float, kappa: float, P: int, M: int, p: int | None = None,
+                 tau: float = 0.1, rc_over_a: float | None = None, F1: int | None = None,
+                 pair_prec: str | int = "fp32c"):
+        L = load_library()
+        o = L.hsma_plan_opts_default()
+        if p is not None:
+            o.p = int(p)
+        o.tau = float(tau)
+        if rc_over_a is not None:
+            o.rc_over_a = float(rc_over_a)
+        if F1 is not None:
+            o.F1 = int(F1)
+        o.pair_prec = PAIR_PREC[pair_prec] if isinstance(pair_prec, str) else int(pair_prec)
+        h = _VP()
+        _check(L.hsma_plan_ex(float(a), float(eps1), float(eps2), float(kappa), int(P), int(M), C.byref(o),
+                              C.byref(h)), "hsma_plan_ex")
+        self._h = h
+        self._ws = {}
+        inf = PlanInfo()
+        _check(L.hsma_plan_get_info(h, C.byref(inf)), "hsma_plan_get_info")
+        self.info = {k: getattr(inf, k) for k, _ in PlanInfo._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().hsma_plan_destroy(self._h)
+            self._h = None
+            self._ws = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, N: int) -> int:
+        return int(load_library().hsma_workspace_bytes(self._h, int(N)))
+
+    def _workspace(self, N: int, device):
+        key = (int(N), str(device))
+        if key not in self._ws:
+            self._ws[key] = workspace(self.workspace_bytes(N), device)
+        return self._ws[key]
+
+    def potential(self, x, y, z, q, phi=None, stream=None, ws=None):
+        torch = _torch()
+        N = x.numel()
+        if phi is None:
+            phi = torch.empty(N, dtype=torch.float64, device=x.device)
+        ws_ptr = ws if ws is not None else self._workspace(N, x.device)[1]
+        _check(load_library().hsma_potential(self._h, N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N),
+                                             _dev_ptr(z, "z", N), _dev_ptr(q, "q", N), _dev_ptr(phi, "phi", N),
+                                             ws_ptr, _stream_ptr(stream)), "hsma_potential")
+        return phi
+
+    def energy(self, x, y, z, q, phi=None, E=None, stream=None, ws=None):
+        torch = _torch()
+        N = x.numel()
+        if E is None:
+            E = torch.empty(1, dtype=torch.float64, device=x.device)
+        ws_ptr = ws if ws is not None else self._workspace(N, x.device)[1]
+        _check(load_library().hsma_energy(self._h, N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N),
+                                          _dev_ptr(z, "z", N), _dev_ptr(q, "q", N),
+                                          _dev_ptr(phi, "phi", N) if phi is not None else None,
+                                          _dev_ptr(E, "E", 1), ws_ptr, _stream_ptr(stream)), "hsma_energy")
+        return E
+
+    def intermediates(self, N: int, device, stream=None):
+        """Check fields u, v and surface strengths Q', D' of the last call with this workspace."""
+        import numpy as np
+        inf = self.info
+        u = np.zeros(inf["M"])
+        v = np.zeros(inf["M"])
+        Q = np.zeros(inf["P"])
+        D = np.zeros(inf["P"])
+        ws_ptr = self._workspace(N, device)[1]
+        p = lambda a: a.ctypes.data_as(_DP)  # noqa: E731
+        _check(load_library().hsma_debug_intermediates(self._h, int(N), ws_ptr, _stream_ptr(stream), p(u), p(v),
+                                                       p(Q), p(D)), "hsma_debug_intermediates")
+        return u, v, Q, D
+
+    STAGES = ("pack", "check", "fit", "eval", "finish")
+
+    def profile(self, on: bool = True):
+        _check(load_library().hsma_profile_enable(self._h, 1 if on else 0), "hsma_profile_enable")
+
+    def profile_read(self) -> dict:
+        ms = (C.c_double * 5)()
+        cnt = (C.c_int64 * 5)()
+        _check(load_library().hsma_profile_read(self._h, ms, cnt), "hsma_profile_read")
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(self.STAGES)}
+
+    def stream_check(self, stream=None) -> int:
+        """Synchronise; return 0 or the status code (2 = an ion outside the cavity)."""
+        return int(load_library().hsma_stream_check(self._h, _stream_ptr(stream)))
+
+
+def status_string(code: int) -> str:
+    return load_library().hsma_status_string(int(code)).decode()
