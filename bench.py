@@ -28,14 +28,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Derived ALU ceiling of the evaluation kernel (pairs/s): 256 CUs x 4 SIMDs x 16 lanes
-# issue 256*64 lane-instructions per cycle at 2.4 GHz.  A Kelvin pair needs 7 full-rate
-# FP32 VALU instructions (3 sub, 1 mul, 2 fma for |d|^2, 1 fma to accumulate) and one
-# v_rsq_f32, a transcendental issued at a quarter of the full rate (4 slots).
+# Derived ALU ceiling of the evaluation kernel: 256 CUs x 4 SIMDs x 16 lanes issue
+# 256 * 64 FP32 lane-instructions per cycle at 2.4 GHz (78.6 TFLOP/s of FMA; packed FP32
+# is not used).  A Kelvin-image pair needs 8 VALU issue slots: 3 sub, 1 mul + 2 fma for
+# |d|^2, 1 v_rsq_f32 and 1 fma to accumulate; v_rsq_f32 runs at half rate back to back but
+# takes one issue slot when interleaved with other VALU work (measured).  A surface-node
+# pair needs 14: 3 sub, 3 for |d|^2, v_rsq_f32, 3 for d.y_s, 4 for the monopole+dipole.
 CU, LANES, CLOCK = 256, 64, 2.4e9
 ISSUE_RATE = CU * LANES * CLOCK              # lane-instructions / s
-SLOTS_PER_PAIR = 7 + 4                        # full-rate + transcendental
-PEAK_PAIRS = ISSUE_RATE / SLOTS_PER_PAIR      # 3.57e12 pairs / s
+SLOTS_KELVIN, SLOTS_SURFACE = 8, 14
 
 
 def log(msg: str):
@@ -68,12 +69,18 @@ def main() -> int:
     systems = wl.systems
     s0 = systems[0]
     N = s0.n
-    x, y, z, q = (torch.tensor(v, dtype=torch.float64, device=dev) for v in (s0.x, s0.y, s0.z, s0.q))
+    nsys = len(systems)
     plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=args.prec)
              for s in systems]
-    phis = [torch.empty(N, dtype=torch.float64, device=dev) for _ in plans]
-    Es = [torch.empty(1, dtype=torch.float64, device=dev) for _ in plans]
-    wss = [hs.workspace(p.workspace_bytes(N), dev) for p in plans]
+    group = hs.Group(plans)
+    # the four parameter sets share the ion configuration: one batch of four systems
+    cat = [np.concatenate([getattr(s, k) for s in systems]) for k in "xyzq"]
+    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
+    off = torch.tensor(np.arange(nsys + 1) * N, dtype=torch.int64, device=dev)
+    plan_of = torch.arange(nsys, dtype=torch.int32, device=dev)
+    phi = torch.empty(nsys * N, dtype=torch.float64, device=dev)
+    E = torch.empty(nsys, dtype=torch.float64, device=dev)
+    ws = hs.workspace(group.workspace_bytes(nsys, nsys * N, N), dev)
     stream = torch.cuda.current_stream()
     inf = plans[0].info
     M, P = inf["M"], inf["P"]
@@ -81,22 +88,20 @@ def main() -> int:
     pairs_kelvin = N * (N - 1)
     pairs_surface = N * P
     pairs_sys = pairs_check + pairs_kelvin + pairs_surface
-    pairs_step = pairs_sys * len(plans)
+    pairs_step = pairs_sys * nsys
 
     def step():
-        for p, ph, e, w in zip(plans, phis, Es, wss):
-            p.energy(x, y, z, q, phi=ph, E=e, stream=stream, ws=w[1])
+        group.energy(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of, phi=phi, E=E,
+                     stream=stream, ws=ws)
 
-    log(f"bench: workload {wl.name}, N={N}, P={P}, M={M}, p={inf['p']}, prec={args.prec}")
+    log(f"bench: workload {wl.name}, N={N}, P={P}, M={M}, p={inf['p']}, prec={args.prec}, {nsys} systems/step")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    for p in plans:
-        assert p.stream_check() == 0
+    assert group.stream_check() == 0
     if not args.no_profile:
-        for p in plans:
-            p.profile(True)
-            p.profile_read()
+        group.profile(True)
+        group.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -106,13 +111,28 @@ def main() -> int:
     ms = (t1 - t0) * 1e3 / args.steps
     stages = {}
     if not args.no_profile:
-        for p in plans:
-            for k, (t, c) in p.profile_read().items():
-                a = stages.setdefault(k, [0.0, 0])
-                a[0] += t
-                a[1] += c
-            p.profile(False)
+        stages = {k: list(v) for k, v in group.profile_read().items()}
+        group.profile(False)
     log(f"bench: {ms:.4f} ms/step over {args.steps} steps")
+
+    # the plain per-system path on the same work, for comparison (not the reported value)
+    x, y, z, q = xb[:N], yb[:N], zb[:N], qb[:N]
+    single_ws = [hs.workspace(p.workspace_bytes(N), dev) for p in plans]
+    single_phi = [torch.empty(N, dtype=torch.float64, device=dev) for _ in plans]
+    single_E = [torch.empty(1, dtype=torch.float64, device=dev) for _ in plans]
+
+    def step_single():
+        for p, w, ph, e in zip(plans, single_ws, single_phi, single_E):
+            p.energy(x, y, z, q, phi=ph, E=e, stream=stream, ws=w)
+
+    for _ in range(args.warmup):
+        step_single()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step_single()
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t2) * 1e3 / args.steps
 
     out = {
         "metric": "GPairs/s (HSMA reaction potential + energy, pairs = check + Kelvin + surface)",
@@ -131,29 +151,35 @@ def main() -> int:
                                "P=1600, M=2400, p=20, 4 (eps1,eps2,kappa) sets",
                    "N": N, "P": P, "M": M, "p": inf["p"], "systems_per_step": len(plans),
                    "pair_precision": args.prec},
-        "systems_per_s": len(plans) / (ms * 1e-3),
+        "systems_per_s": nsys / (ms * 1e-3),
+        "per_system_path_ms_per_step": ms_single,
     }
     if stages:
         ev_ms, ev_n = stages["eval"]
-        avg = ev_ms / max(ev_n, 1) * 1e-3
-        eval_pairs = pairs_kelvin + pairs_surface
+        avg = ev_ms / max(ev_n, 1) * 1e-3               # one launch covers the whole batch
+        eval_pairs = (pairs_kelvin + pairs_surface) * nsys
+        t_min = (pairs_kelvin * SLOTS_KELVIN + pairs_surface * SLOTS_SURFACE) * nsys / ISSUE_RATE
+        peak = eval_pairs / t_min
         achieved = eval_pairs / avg
         out["roofline"] = {
             "bound": "alu",
-            "kernel": "k_eval (evaluation pair sums)",
+            "kernel": "k_eval (evaluation pair sums, all systems of the step in one launch)",
             "achieved": achieved / 1e9,
-            "peak": PEAK_PAIRS / 1e9,
+            "peak": peak / 1e9,
             "unit": "Gpair/s",
-            "frac": achieved / PEAK_PAIRS,
+            "frac": achieved / peak,
             "traffic": None,
             "avg_launch_ms": avg * 1e3,
-            "peak_model": "256 CU x 64 lanes x 2.4 GHz / (7 VALU + 4-slot v_rsq_f32) per pair",
+            "pairs_per_launch": eval_pairs,
+            "peak_model": "256 CU x 64 lanes x 2.4 GHz VALU issue; 8 slots per Kelvin pair, 14 per surface pair",
         }
         out["stage_ms_per_step"] = {k: v[0] / args.steps for k, v in stages.items()}
 
     if not args.no_oracle:
         import oracle
         worst_phi, worst_e = 0.0, 0.0
+        phis = [phi[b * N:(b + 1) * N] for b in range(nsys)]
+        Es = [E[b:b + 1] for b in range(nsys)]
         for p, ph, e, s in zip(plans, phis, Es, systems):
             i = p.info
             prm = oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],

@@ -73,6 +73,7 @@ typedef enum {
 } hsma_pair_precision;
 
 typedef struct hsma_plan_s *hsma_plan_t;
+typedef struct hsma_group_s *hsma_group_t;
 typedef struct hsma_system_s *hsma_system_t;
 
 /* Discretisation options.  Fields left at the values of hsma_plan_opts_default()
@@ -118,15 +119,17 @@ size_t hsma_workspace_bytes(hsma_plan_t plan, int64_t N);
 
 /* Reaction potential Phi_RF at every ion (eq. "phirffinall"), N >= 0.
  * x, y, z, q: [device] N doubles each; phi: [device] N doubles (output);
- * ws: [device] hsma_workspace_bytes(plan, N) bytes.  Errors: HSMA_EINVAL, HSMA_EDEVICE. */
+ * ws: [device] workspace of ws_bytes >= hsma_workspace_bytes(plan, N) bytes (a smaller one,
+ * e.g. one sized before a change of hsma_group_tune, is refused with HSMA_EINVAL).
+ * Errors: HSMA_EINVAL, HSMA_ESTATE (current device is not the plan's), HSMA_EDEVICE. */
 hsma_status hsma_potential(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
-                           const double *q, double *phi, void *ws, hipStream_t stream);
+                           const double *q, double *phi, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Reaction energy E = (1/2) sum_i q_i Phi_RF(x_i) (the self energy of Sec. 4.1
  * generalised to N ions), reduced in FP64 in a fixed order.  E: [device] one double.
  * phi: [device] N doubles receiving the potentials, or NULL to keep them in ws. */
 hsma_status hsma_energy(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
-                        const double *q, double *phi, double *E, void *ws, hipStream_t stream);
+                        const double *q, double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Intermediate results of the last hsma_potential/hsma_energy call that used ws,
  * copied to host arrays (for tests and diagnostics; synchronises the stream).
@@ -135,18 +138,60 @@ hsma_status hsma_energy(hsma_plan_t plan, int64_t N, const double *x, const doub
 hsma_status hsma_debug_intermediates(hsma_plan_t plan, int64_t N, const void *ws, hipStream_t stream,
                                      double *u, double *v, double *Q, double *D);
 
-/* Stage timing: when enabled, every compute call records HIP events on its stream
- * around its kernel groups (0 Kelvin images/packing, 1 check sums, 2 fit apply,
- * 3 evaluation pair sums, 4 final reductions).  hsma_profile_read waits for the
- * recorded events, returns the summed milliseconds and launch counts per stage
- * (arrays of 5, [host]) and clears the records.  For measurement only; enabling
- * it makes the compute calls create events (not graph-capturable). */
-hsma_status hsma_profile_enable(hsma_plan_t plan, int on);
-hsma_status hsma_profile_read(hsma_plan_t plan, double *ms /* [host] 5 */, int64_t *count /* [host] 5 */);
+/* Groups: nplans plans built with the same discretisation (p, P, M, F1, tau, rc/a) and
+ * pair precision, evaluated together.  Each plan keeps its own cavity (a, eps1, eps2,
+ * kappa); a group stores the plans' constants on the device.  The plans must outlive
+ * the group.  Errors: HSMA_EINVAL, HSMA_ESTATE (plans of different discretisations,
+ * precisions or devices), HSMA_EDEVICE.  hsma_plan_group returns the one-plan group a
+ * plan owns (freed with the plan; not to be passed to hsma_group_destroy). */
+hsma_status hsma_group_create(int nplans, const hsma_plan_t *plans /* [host] */, hsma_group_t *out);
+hsma_status hsma_group_destroy(hsma_group_t group);
+hsma_group_t hsma_plan_group(hsma_plan_t plan);
 
-/* Synchronise the stream and report a device-side domain error raised since the
- * last check (then clear it). */
+/* Batched reaction potentials and energies of nsys independent ion configurations in
+ * one set of launches (the persistent pair kernels take (system, 64 ions, source chunk)
+ * items from a device work counter; the fit is applied to all systems at once, as FP32
+ * MFMA GEMMs when nsys >= 8 in the FP32 pair modes).
+ *   offsets: [device] nsys + 1 int64, offsets[0] = 0, non-decreasing; system b owns ions
+ *            [offsets[b], offsets[b+1]) of x, y, z, q, phi;
+ *   plan_of: [device] nsys int32 plan indices into the group, or NULL (all use plan 0);
+ *   total_n = offsets[nsys] and max_n >= every system's size: [host] scalars that size
+ *            the work and the workspace (hsma_batched_workspace_bytes);
+ *   phi: [device] total_n doubles or NULL; E: [device] nsys energies or NULL;
+ *   ws: [device] ws_bytes >= hsma_batched_workspace_bytes(group, nsys, total_n, max_n).
+ * A system of 0 ions has energy 0.  The device checks offsets and plan_of against
+ * total_n, max_n and the group size before any work: on a mismatch the call does nothing
+ * and hsma_group_stream_check reports HSMA_EINVAL.  Errors: HSMA_EINVAL, HSMA_ESTATE,
+ * HSMA_EDEVICE. */
+size_t hsma_batched_workspace_bytes(hsma_group_t group, int nsys, int64_t total_n, int64_t max_n);
+hsma_status hsma_energy_batched(hsma_group_t group, int nsys, const int64_t *offsets, const int32_t *plan_of,
+                                int64_t total_n, int64_t max_n, const double *x, const double *y, const double *z,
+                                const double *q, double *phi, double *E, void *ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/* Launch shape of the group's pair kernels (check and evaluation sums).  persistent = 1:
+ * one grid of 8 blocks per compute unit whose blocks take (system, 64 targets, source
+ * chunk) items from a device counter; 0 (default): one item per block, the hardware
+ * workgroup dispatcher balancing the load.  target_items (default 16384, 64..2^22): the
+ * number of items each pair kernel aims for, which sets the source-chunk length.  Results
+ * depend on target_items only through the summation order (rounding).  Errors: HSMA_EINVAL. */
+hsma_status hsma_group_tune(hsma_group_t group, int persistent, int target_items);
+
+/* Stage timing: when enabled, every compute call on the group records HIP events on its
+ * stream around its kernel groups (0 schedule/Kelvin images/packing, 1 check sums, 2 fit
+ * apply, 3 evaluation pair sums, 4 final reductions).  hsma_profile_read waits for the
+ * recorded events, returns the summed milliseconds and event-pair counts per stage
+ * (arrays of 5, [host]) and clears the records.  For measurement only: while enabled the
+ * compute calls create events and must not be captured into a graph. */
+hsma_status hsma_profile_enable(hsma_group_t group, int on);
+hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int64_t *count /* [host] 5 */);
+
+/* Synchronise the stream and report a device-side error raised since the last check
+ * (then clear it): HSMA_EDOMAIN for an ion outside the cavity or a non-finite input,
+ * HSMA_EINVAL for device offsets or plan indices inconsistent with the host sizes; for the
+ * plan's single-system calls, or for a group's batched calls. */
 hsma_status hsma_stream_check(hsma_plan_t plan, hipStream_t stream);
+hsma_status hsma_group_stream_check(hsma_group_t group, hipStream_t stream);
 
 const char *hsma_status_string(hsma_status s);
 int hsma_version(void);

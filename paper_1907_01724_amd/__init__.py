@@ -62,8 +62,8 @@ def load_library(path: str | None = None):
     L.hsma_plan_get_info.argtypes = [_VP, C.POINTER(PlanInfo)]
     L.hsma_workspace_bytes.argtypes = [_VP, C.c_int64]
     L.hsma_workspace_bytes.restype = C.c_size_t
-    L.hsma_potential.argtypes = [_VP, C.c_int64] + [_VP] * 5 + [_VP, _VP]
-    L.hsma_energy.argtypes = [_VP, C.c_int64] + [_VP] * 6 + [_VP, _VP]
+    L.hsma_potential.argtypes = [_VP, C.c_int64] + [_VP] * 5 + [_VP, C.c_size_t, _VP]
+    L.hsma_energy.argtypes = [_VP, C.c_int64] + [_VP] * 6 + [_VP, C.c_size_t, _VP]
     L.hsma_debug_intermediates.argtypes = [_VP, C.c_int64, _VP, _VP, _DP, _DP, _DP, _DP]
     L.hsma_stream_check.argtypes = [_VP, _VP]
     L.hsma_status_string.argtypes = [C.c_int]
@@ -71,9 +71,20 @@ def load_library(path: str | None = None):
     L.hsma_version.restype = C.c_int
     L.hsma_profile_enable.argtypes = [_VP, C.c_int]
     L.hsma_profile_read.argtypes = [_VP, _DP, C.POINTER(C.c_int64)]
+    L.hsma_group_create.argtypes = [C.c_int, C.POINTER(_VP), C.POINTER(_VP)]
+    L.hsma_group_destroy.argtypes = [_VP]
+    L.hsma_plan_group.argtypes = [_VP]
+    L.hsma_plan_group.restype = _VP
+    L.hsma_batched_workspace_bytes.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
+    L.hsma_batched_workspace_bytes.restype = C.c_size_t
+    L.hsma_energy_batched.argtypes = [_VP, C.c_int, _VP, _VP, C.c_int64, C.c_int64] + [_VP] * 6 + [_VP, C.c_size_t,
+                                                                                                   _VP]
+    L.hsma_group_stream_check.argtypes = [_VP, _VP]
+    L.hsma_group_tune.argtypes = [_VP, C.c_int, C.c_int]
     for name in ("hsma_plan", "hsma_plan_ex", "hsma_plan_destroy", "hsma_plan_get_info", "hsma_potential",
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
-                 "hsma_profile_read"):
+                 "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
+                 "hsma_group_stream_check", "hsma_group_tune"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -110,13 +121,27 @@ def _stream_ptr(stream):
     return s.cuda_stream
 
 
-def workspace(nbytes: int, device=None):
-    """A 256-byte aligned device buffer of at least nbytes (a uint8 tensor and its pointer)."""
-    torch = _torch()
-    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device or "cuda")
-    ptr = buf.data_ptr()
-    off = (-ptr) % 256
-    return buf, ptr + off
+class Workspace:
+    """A 256-byte aligned device buffer of at least nbytes (backed by a uint8 tensor)."""
+
+    def __init__(self, nbytes: int, device=None):
+        torch = _torch()
+        self.nbytes = int(nbytes)
+        self.buf = torch.empty(max(self.nbytes, 1) + 256, dtype=torch.uint8, device=device or "cuda")
+        p = self.buf.data_ptr()
+        self.ptr = p + (-p) % 256
+
+
+def workspace(nbytes: int, device=None) -> Workspace:
+    return Workspace(nbytes, device)
+
+
+def _ensure(cache: dict, key, nbytes: int, device) -> Workspace:
+    w = cache.get(key)
+    if w is None or w.nbytes < nbytes:
+        w = Workspace(nbytes, device)
+        cache[key] = w
+    return w
 
 
 class Plan:
@@ -163,33 +188,31 @@ class Plan:
     def workspace_bytes(self, N: int) -> int:
         return int(load_library().hsma_workspace_bytes(self._h, int(N)))
 
-    def _workspace(self, N: int, device):
-        key = (int(N), str(device))
-        if key not in self._ws:
-            self._ws[key] = workspace(self.workspace_bytes(N), device)
-        return self._ws[key]
+    def _workspace(self, N: int, device) -> Workspace:
+        return _ensure(self._ws, (int(N), str(device)), self.workspace_bytes(N), device)
 
-    def potential(self, x, y, z, q, phi=None, stream=None, ws=None):
+    def potential(self, x, y, z, q, phi=None, stream=None, ws: Workspace | None = None):
         torch = _torch()
         N = x.numel()
         if phi is None:
             phi = torch.empty(N, dtype=torch.float64, device=x.device)
-        ws_ptr = ws if ws is not None else self._workspace(N, x.device)[1]
+        w = ws if ws is not None else self._workspace(N, x.device)
         _check(load_library().hsma_potential(self._h, N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N),
                                              _dev_ptr(z, "z", N), _dev_ptr(q, "q", N), _dev_ptr(phi, "phi", N),
-                                             ws_ptr, _stream_ptr(stream)), "hsma_potential")
+                                             w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_potential")
         return phi
 
-    def energy(self, x, y, z, q, phi=None, E=None, stream=None, ws=None):
+    def energy(self, x, y, z, q, phi=None, E=None, stream=None, ws: Workspace | None = None):
         torch = _torch()
         N = x.numel()
         if E is None:
             E = torch.empty(1, dtype=torch.float64, device=x.device)
-        ws_ptr = ws if ws is not None else self._workspace(N, x.device)[1]
+        w = ws if ws is not None else self._workspace(N, x.device)
         _check(load_library().hsma_energy(self._h, N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N),
                                           _dev_ptr(z, "z", N), _dev_ptr(q, "q", N),
                                           _dev_ptr(phi, "phi", N) if phi is not None else None,
-                                          _dev_ptr(E, "E", 1), ws_ptr, _stream_ptr(stream)), "hsma_energy")
+                                          _dev_ptr(E, "E", 1), w.ptr, w.nbytes, _stream_ptr(stream)),
+               "hsma_energy")
         return E
 
     def intermediates(self, N: int, device, stream=None):
@@ -200,26 +223,108 @@ class Plan:
         v = np.zeros(inf["M"])
         Q = np.zeros(inf["P"])
         D = np.zeros(inf["P"])
-        ws_ptr = self._workspace(N, device)[1]
+        ws_ptr = self._workspace(N, device).ptr
         p = lambda a: a.ctypes.data_as(_DP)  # noqa: E731
         _check(load_library().hsma_debug_intermediates(self._h, int(N), ws_ptr, _stream_ptr(stream), p(u), p(v),
                                                        p(Q), p(D)), "hsma_debug_intermediates")
         return u, v, Q, D
 
-    STAGES = ("pack", "check", "fit", "eval", "finish")
+    @property
+    def group(self):
+        """Handle of the one-plan group this plan owns (for profiling)."""
+        return load_library().hsma_plan_group(self._h)
+
+    def tune(self, persistent: bool = False, target_items: int = 16384):
+        _check(load_library().hsma_group_tune(self.group, 1 if persistent else 0, int(target_items)),
+               "hsma_group_tune")
 
     def profile(self, on: bool = True):
-        _check(load_library().hsma_profile_enable(self._h, 1 if on else 0), "hsma_profile_enable")
+        _profile(self.group, on)
 
     def profile_read(self) -> dict:
-        ms = (C.c_double * 5)()
-        cnt = (C.c_int64 * 5)()
-        _check(load_library().hsma_profile_read(self._h, ms, cnt), "hsma_profile_read")
-        return {s: (ms[i], cnt[i]) for i, s in enumerate(self.STAGES)}
+        return _profile_read(self.group)
 
     def stream_check(self, stream=None) -> int:
         """Synchronise; return 0 or the status code (2 = an ion outside the cavity)."""
         return int(load_library().hsma_stream_check(self._h, _stream_ptr(stream)))
+
+
+STAGES = ("pack", "check", "fit", "eval", "finish")
+
+
+def _profile(group_handle, on: bool):
+    _check(load_library().hsma_profile_enable(group_handle, 1 if on else 0), "hsma_profile_enable")
+
+
+def _profile_read(group_handle) -> dict:
+    ms = (C.c_double * 5)()
+    cnt = (C.c_int64 * 5)()
+    _check(load_library().hsma_profile_read(group_handle, ms, cnt), "hsma_profile_read")
+    return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+
+class Group:
+    """Plans sharing one discretisation, evaluated together over many ion configurations."""
+
+    def __init__(self, plans):
+        L = load_library()
+        self.plans = list(plans)
+        arr = (_VP * len(self.plans))(*[p.handle for p in self.plans])
+        h = _VP()
+        _check(L.hsma_group_create(len(self.plans), arr, C.byref(h)), "hsma_group_create")
+        self._h = h
+        self._ws = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().hsma_group_destroy(self._h)
+            self._h = None
+            self._ws = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, nsys: int, total_n: int, max_n: int) -> int:
+        return int(load_library().hsma_batched_workspace_bytes(self._h, int(nsys), int(total_n), int(max_n)))
+
+    def energy(self, offsets, x, y, z, q, total_n: int, max_n: int, plan_of=None, phi=None, E=None, stream=None,
+               ws=None):
+        """Potentials and energies of nsys systems; offsets: int64 device tensor of nsys + 1."""
+        torch = _torch()
+        nsys = offsets.numel() - 1
+        if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise TypeError("offsets must be a contiguous int64 device tensor")
+        if plan_of is not None and (plan_of.dtype != torch.int32 or not plan_of.is_cuda or plan_of.numel() != nsys):
+            raise TypeError("plan_of must be an int32 device tensor of nsys entries")
+        if E is None:
+            E = torch.empty(nsys, dtype=torch.float64, device=x.device)
+        w = ws if ws is not None else _ensure(self._ws, (nsys, int(total_n), int(max_n), str(x.device)),
+                                              self.workspace_bytes(nsys, total_n, max_n), x.device)
+        _check(load_library().hsma_energy_batched(
+            self._h, nsys, offsets.data_ptr(), plan_of.data_ptr() if plan_of is not None else None, int(total_n),
+            int(max_n), _dev_ptr(x, "x", total_n), _dev_ptr(y, "y", total_n), _dev_ptr(z, "z", total_n),
+            _dev_ptr(q, "q", total_n), _dev_ptr(phi, "phi", total_n) if phi is not None else None,
+            _dev_ptr(E, "E", nsys), w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_energy_batched")
+        return E
+
+    def tune(self, persistent: bool = False, target_items: int = 16384):
+        _check(load_library().hsma_group_tune(self._h, 1 if persistent else 0, int(target_items)), "hsma_group_tune")
+
+    def profile(self, on: bool = True):
+        _profile(self._h, on)
+
+    def profile_read(self) -> dict:
+        return _profile_read(self._h)
+
+    def stream_check(self, stream=None) -> int:
+        return int(load_library().hsma_group_stream_check(self._h, _stream_ptr(stream)))
 
 
 def status_string(code: int) -> str:

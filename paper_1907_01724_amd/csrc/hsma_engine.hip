@@ -1,0 +1,1127 @@
+// Hot path of the HSMA reaction potential (Algorithm 1, steps 2-5) for gfx950, for one
+// or many ion configurations ("systems") in one set of launches.
+//
+//   k_schedule     per-system item counts and prefix sums from the ion offsets
+//   k_fill         item -> system maps
+//   k_pack         Kelvin images (Sec. 2.4: r_K = (a/r)^2 x, q_K), exact FP64 own-image term,
+//                  packed sources/targets in the pair precision, domain check
+//   k_check        check fields u_k = sum_i q_i G0(c_k, x_i), v_k = sum_i q_i (r_i/a) G0(c_k, x_i)
+//                  (Algorithm 1, step 2): persistent, items = (system, 64 check points, source chunk)
+//   k_check_finish fixed-order sum of the chunk partials
+//   fit            alpha' = pinv u, beta' = pinv v; h = f . alpha' + g . beta';
+//                  Q' = Lhat (n . h), D' = -Lhat h (steps 3-4: the fixed least-squares fit and
+//                  Green's second identity on the Fibonacci nodes); GEMVs for a few systems,
+//                  FP32 MFMA GEMMs across many
+//   k_eval         Phi_i = sum_{j != i} q_K,j / |x_i - r_K,j| + sum_s [Q'_s + D'_s (d.y_s)/|d|^2]/|d|
+//                  (eq. "phirffinall", step 5): persistent, items = (system, 64 ions, source chunk)
+//   k_finish       Phi_i = own-image term + fixed-order sum of chunk partials; block energy partials
+//   k_energy       E_b = 1/2 sum_i q_i Phi_i per system, fixed order
+//
+// Pair kernels: a target per lane; the four waves of a block take four slices of the item's
+// source chunk (read at wave-uniform addresses, i.e. scalar loads, no LDS traffic) and are
+// combined through LDS in a fixed order.  One v_rsq per pair; FP32 sums over 32-source tiles
+// are folded into FP64 (compensated mode).
+#include <math.h>
+#include <stdlib.h>
+
+#include "hsma_internal.h"
+
+namespace hsma {
+namespace {
+
+constexpr int WAVES = 4;
+constexpr int TPB = 64 * WAVES;  // threads per block in the pair kernels
+constexpr int GRP = 64;          // targets per item
+constexpr int TILE = 32;         // sources per FP32 partial sum before folding into FP64
+constexpr int FINB = 256;        // ions per finish block
+constexpr int SCHED_T = 1024;    // threads of the schedule kernel
+constexpr int BLOCKS_PER_CU = 8; // persistent blocks per CU (32 waves per CU)
+
+template <int MODE>
+struct PT {
+  using T = float;
+  using T2 = float2;
+  using T4 = float4;
+};
+template <>
+struct PT<HSMA_PAIR_FP64> {
+  using T = double;
+  using T2 = double2;
+  using T4 = double4;
+};
+
+__device__ __forceinline__ float rinv(float r2) { return __builtin_amdgcn_rsqf(r2); }
+
+// 1/sqrt(r2) in FP64: the FP32 hardware estimate (relative error ~1e-7) refined by one
+// Newton step y <- y + y (1 - r2 y^2) / 2 (relative error ~2e-14).
+__device__ __forceinline__ double rinv(double r2) {
+  const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+  const double t = r2 * y;
+  const double e = fma(-t, y, 1.0);
+  return fma(y * 0.5, e, y);
+}
+
+template <typename T4>
+__device__ __forceinline__ T4 make4(double x, double y, double z, double w);
+template <>
+__device__ __forceinline__ float4 make4<float4>(double x, double y, double z, double w) {
+  return make_float4((float)x, (float)y, (float)z, (float)w);
+}
+template <>
+__device__ __forceinline__ double4 make4<double4>(double x, double y, double z, double w) {
+  return make_double4(x, y, z, w);
+}
+
+template <int MODE>
+__device__ __forceinline__ const typename PT<MODE>::T4 *chk_of(const PlanDev &p) {
+  if constexpr (MODE == HSMA_PAIR_FP64) return p.chk64; else return p.chk32;
+}
+template <int MODE>
+__device__ __forceinline__ const typename PT<MODE>::T4 *nodes_of(const PlanDev &p) {
+  if constexpr (MODE == HSMA_PAIR_FP64) return p.nodes64; else return p.nodes32;
+}
+
+__device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------------
+// Schedule.  sched (int64) holds, each with nsys + 1 entries:
+//   [0] ion offsets  [1] check-item prefix  [2] eval-item prefix  [3] finish-block prefix
+//   [4] check partial-slot prefix  [5] eval partial-slot prefix
+// followed by 8 words: [0] check item counter, [1] eval item counter.
+// ---------------------------------------------------------------------------------
+struct Sched {
+  int64_t *off, *ic, *ie, *fb, *pc, *pe, *ctr;
+  __host__ __device__ Sched(int64_t *base, int nsys) {
+    const int64_t s = nsys + 1;
+    off = base;
+    ic = base + s;
+    ie = base + 2 * s;
+    fb = base + 3 * s;
+    pc = base + 4 * s;
+    pe = base + 5 * s;
+    ctr = base + 6 * s;
+  }
+};
+
+// Bounds the host sized the workspace with; the schedule refuses work beyond them.
+struct Bounds {
+  int64_t total_n, max_n, items_c, items_e, fin, parts_c, parts_e;
+  int nplans;
+};
+
+__global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *__restrict__ offsets,
+                                                      const int32_t *__restrict__ plan_of, Bounds bd, int M, int P,
+                                                      int chc, int che, int64_t grid_c, int64_t grid_e,
+                                                      int64_t *__restrict__ base, int *__restrict__ flag) {
+  Sched S(base, nsys);
+  __shared__ int64_t sc[5][SCHED_T];
+  const int t = threadIdx.x, nt = blockDim.x;  // nt <= SCHED_T, a multiple of 64
+  const int seg = (nsys + nt - 1) / nt;
+  const int b0 = t * seg, b1 = min(nsys, b0 + seg);
+  const int64_t Gc = cdiv64(M, GRP);
+  const int64_t n_single = bd.total_n;
+  // the device offsets and plan indices must agree with what the host sized the work by
+  int bad = 0;
+  for (int b = b0; b < b1; ++b) {
+    const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
+    if (lo < 0 || hi < lo || hi > bd.total_n || hi - lo > bd.max_n) bad = 1;
+    if (b == 0 && lo != 0) bad = 1;
+    if (b == nsys - 1 && hi != bd.total_n) bad = 1;
+    if (plan_of && (plan_of[b] < 0 || plan_of[b] >= bd.nplans)) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  int64_t acc[5] = {0, 0, 0, 0, 0};
+  for (int b = b0; b < b1 && !bad; ++b) {
+    const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
+    const int64_t n = hi - lo;
+    const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
+    const int64_t chunks_e = n > 0 ? cdiv64(n + P, che) : 0;
+    acc[0] += Gc * chunks_c;
+    acc[1] += cdiv64(n, GRP) * chunks_e;
+    acc[2] += cdiv64(n, FINB);
+    acc[3] += Gc * chunks_c * GRP;
+    acc[4] += cdiv64(n, GRP) * chunks_e * GRP;
+  }
+  for (int k = 0; k < 5; ++k) sc[k][t] = acc[k];
+  __syncthreads();
+  // inclusive Hillis-Steele scan over the thread totals
+  for (int o = 1; o < nt; o <<= 1) {
+    int64_t v[5];
+    for (int k = 0; k < 5; ++k) v[k] = t >= o ? sc[k][t - o] : 0;
+    __syncthreads();
+    for (int k = 0; k < 5; ++k) sc[k][t] += v[k];
+    __syncthreads();
+  }
+  int64_t run[5];
+  for (int k = 0; k < 5; ++k) run[k] = sc[k][t] - acc[k];  // exclusive start of this segment
+  for (int b = b0; b < b1 && !bad; ++b) {
+    const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
+    const int64_t n = hi - lo;
+    const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
+    const int64_t chunks_e = n > 0 ? cdiv64(n + P, che) : 0;
+    S.off[b] = lo;
+    S.ic[b] = run[0];
+    S.ie[b] = run[1];
+    S.fb[b] = run[2];
+    S.pc[b] = run[3];
+    S.pe[b] = run[4];
+    run[0] += Gc * chunks_c;
+    run[1] += cdiv64(n, GRP) * chunks_e;
+    run[2] += cdiv64(n, FINB);
+    run[3] += Gc * chunks_c * GRP;
+    run[4] += cdiv64(n, GRP) * chunks_e * GRP;
+  }
+  if (t == nt - 1) {
+    S.off[nsys] = offsets ? offsets[nsys] : n_single;
+    S.ic[nsys] = sc[0][t];
+    S.ie[nsys] = sc[1][t];
+    S.fb[nsys] = sc[2][t];
+    S.pc[nsys] = sc[3][t];
+    S.pe[nsys] = sc[4][t];
+    for (int k = 0; k < 8; ++k) S.ctr[k] = 0;
+    S.ctr[0] = grid_c;  // items below the grid size are taken by block index
+    S.ctr[1] = grid_e;
+    const bool fits = sc[0][t] <= bd.items_c && sc[1][t] <= bd.items_e && sc[2][t] <= bd.fin &&
+                      sc[3][t] <= bd.parts_c && sc[4][t] <= bd.parts_e;
+    const bool ok = !bad && fits;
+    S.ctr[2] = ok ? 1 : 0;  // every later kernel of the call does nothing unless set
+    if (!ok) atomicOr(flag, 2);
+  }
+}
+
+__device__ __forceinline__ bool sched_ok(const Sched &S) { return S.ctr[2] != 0; }
+
+// item -> system maps, one block per system
+__global__ __launch_bounds__(256) void k_fill(int nsys, const int64_t *__restrict__ base, int *__restrict__ sys_c,
+                                              int *__restrict__ sys_e, int *__restrict__ sys_f) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;
+  const int b = blockIdx.x;
+  for (int64_t i = S.ic[b] + threadIdx.x; i < S.ic[b + 1]; i += 256) sys_c[i] = b;
+  for (int64_t i = S.ie[b] + threadIdx.x; i < S.ie[b + 1]; i += 256) sys_e[i] = b;
+  for (int64_t i = S.fb[b] + threadIdx.x; i < S.fb[b + 1]; i += 256) sys_f[i] = b;
+}
+
+// ---------------------------------------------------------------------------------
+// Kelvin images and packing: one finish block (256 ions of one system) per block.
+// ---------------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restrict__ base, const int *__restrict__ sys_f,
+                                              const PlanDev *__restrict__ plans, const int32_t *__restrict__ plan_of,
+                                              const double *__restrict__ x, const double *__restrict__ y,
+                                              const double *__restrict__ z, const double *__restrict__ q,
+                                              typename PT<MODE>::T4 *__restrict__ img,
+                                              typename PT<MODE>::T4 *__restrict__ tgt,
+                                              typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
+                                              int *__restrict__ flag) {
+  using T4 = typename PT<MODE>::T4;
+  using T = typename PT<MODE>::T;
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;
+  const int64_t f = blockIdx.x;
+  if (f >= S.fb[nsys]) return;
+  const int b = sys_f[f];
+  const int64_t il = (f - S.fb[b]) * FINB + threadIdx.x;
+  const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
+  if (il >= n) return;
+  const int64_t i = lo + il;
+  const PlanDev c = plans[plan_of ? plan_of[b] : 0];
+  const double xi = x[i], yi = y[i], zi = z[i], qi = q[i];
+  const double r2 = xi * xi + yi * yi + zi * zi;
+  const double r = sqrt(r2);
+  const bool ok = isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(qi) && r < c.a;
+  if (!ok) {
+    atomicOr(flag, 1);
+    img[i] = make4<T4>(0.0, 0.0, 2.0 * c.far, 0.0);
+    tgt[i] = make4<T4>(0.0, 0.0, 0.0, 0.0);
+    srcw[i] = (T)0;
+    self[i] = 0.0;
+    return;
+  }
+  const double qp = qi * c.c0;  // q / (4 pi eps1)
+  double kx, ky, kz, qk;
+  if (r >= c.rmin) {
+    const double fk = c.a2 / r2;  // r_K = (a/r)^2 x
+    kx = fk * xi;
+    ky = fk * yi;
+    kz = fk * zi;
+    const double rK = c.a2 / r;
+    qk = qp / c.a * (c.gamma * rK + c.dbar * (c.Rtau - rK) * 0.5);
+  } else {
+    // image at infinity: q_K / |x - r_K| -> q (gamma - dbar/2) / a for every target;
+    // represented by a point at distance `far` with the matching strength
+    const double ux = r > 0.0 ? xi / r : 0.0, uy = r > 0.0 ? yi / r : 0.0, uz = r > 0.0 ? zi / r : 1.0;
+    kx = c.far * ux;
+    ky = c.far * uy;
+    kz = c.far * uz;
+    qk = qp * (c.gamma - 0.5 * c.dbar) * c.far / c.a;
+  }
+  // own image: q_K / (4 pi eps1 |x - r_K|) with |x - r_K| = (a^2 - r^2) / r, written so that it
+  // stays regular at r = 0 and keeps FP64 accuracy as r -> a
+  self[i] = qp / c.a * (c.gamma * c.a2 + 0.5 * c.dbar * (c.Rtau * r - c.a2)) / ((c.a - r) * (c.a + r));
+  img[i] = make4<T4>(kx, ky, kz, qk);
+  tgt[i] = make4<T4>(xi, yi, zi, qp);
+  srcw[i] = (T)(qp * r / c.a);
+}
+
+// ---------------------------------------------------------------------------------
+// Item loop.  The first item of a block is its block index; in the persistent form the
+// following items come from a device counter that the schedule kernel starts at the grid
+// size.  A relaxed read of the counter lets a block that finds the queue drained leave
+// without an atomic, so same-address atomics only serve items that exist.  The item index
+// is made wave-uniform (readfirstlane) so that everything derived from it stays in scalar
+// registers and the source loads remain scalar loads.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ bool next_item(bool persistent, bool first, int64_t total, int64_t *ctr, int64_t *slot,
+                                          int64_t &item) {
+  if (first) {
+    item = (int64_t)blockIdx.x;
+    return item < total;
+  }
+  if (!persistent) return false;
+  __syncthreads();  // every wave is done with the previous item's shared data
+  if (threadIdx.x == 0) {
+    const int64_t cur = (int64_t)__hip_atomic_load((unsigned long long *)ctr, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    *slot = cur >= total ? cur : (int64_t)atomicAdd((unsigned long long *)ctr, 1ULL);
+  }
+  __syncthreads();
+  item = uniform64(*slot);
+  return item < total;
+}
+
+// wave index within the block, as a wave-uniform value
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// ---------------------------------------------------------------------------------
+// Check sums.
+// ---------------------------------------------------------------------------------
+template <int MODE>
+__device__ __forceinline__ void check_range(const typename PT<MODE>::T4 &ck, const typename PT<MODE>::T4 *__restrict__ src,
+                                            const typename PT<MODE>::T *__restrict__ srcw, int64_t j0, int64_t j1,
+                                            double &au, double &av) {
+  using T = typename PT<MODE>::T;
+  using T4 = typename PT<MODE>::T4;
+  if constexpr (MODE == HSMA_PAIR_FP32) {
+    T su = 0, sv = 0;
+    for (int64_t j = j0; j < j1; ++j) {
+      const T4 s = src[j];
+      const T dx = ck.x - s.x, dy = ck.y - s.y, dz = ck.z - s.z;
+      const T ri = rinv(dx * dx + dy * dy + dz * dz);
+      su = fma(s.w, ri, su);
+      sv = fma(srcw[j], ri, sv);
+    }
+    au = su;
+    av = sv;
+  } else {
+    au = 0.0;
+    av = 0.0;
+    int64_t jb = j0;
+    for (; jb + TILE <= j1; jb += TILE) {
+      T su = 0, sv = 0;
+#pragma unroll 8
+      for (int t = 0; t < TILE; ++t) {
+        const T4 s = src[jb + t];
+        const T dx = ck.x - s.x, dy = ck.y - s.y, dz = ck.z - s.z;
+        const T ri = rinv(dx * dx + dy * dy + dz * dz);
+        su = fma(s.w, ri, su);
+        sv = fma(srcw[jb + t], ri, sv);
+      }
+      au += (double)su;
+      av += (double)sv;
+    }
+    T su = 0, sv = 0;
+    for (int64_t j = jb; j < j1; ++j) {
+      const T4 s = src[j];
+      const T dx = ck.x - s.x, dy = ck.y - s.y, dz = ck.z - s.z;
+      const T ri = rinv(dx * dx + dy * dy + dz * dz);
+      su = fma(s.w, ri, su);
+      sv = fma(srcw[j], ri, sv);
+    }
+    au += (double)su;
+    av += (double)sv;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_check(int persistent, int nsys, int M, int chc, const int64_t *__restrict__ base,
+                                               const int *__restrict__ sys_c, const PlanDev *__restrict__ plans,
+                                               const int32_t *__restrict__ plan_of,
+                                               const typename PT<MODE>::T4 *__restrict__ src,
+                                               const typename PT<MODE>::T *__restrict__ srcw, int64_t parts_bound,
+                                               double *__restrict__ part) {
+  using T4 = typename PT<MODE>::T4;
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ int64_t s_item;
+  __shared__ double red[2][WAVES][GRP];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (!sched_ok(S)) return;
+  const int64_t total = S.ic[nsys];
+  const int64_t Gc = cdiv64(M, GRP);
+  int64_t item;
+  for (bool first = true; next_item(persistent, first, total, &S.ctr[0], &s_item, item); first = false) {
+    const int b = sys_c[item];
+    const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
+    const int64_t loc = item - S.ic[b];
+    const int64_t chunks = cdiv64(n, chc);
+    const int64_t c = loc / Gc, g = loc % Gc;  // items sharing a source chunk are adjacent
+    const PlanDev pd = plans[plan_of ? plan_of[b] : 0];
+    const T4 *chk = chk_of<MODE>(pd);
+    const int64_t k = g * GRP + lane;
+    const T4 ck = chk[k < M ? k : M - 1];
+    const int sub = chc / WAVES;
+    const int64_t cs = c * chc + (int64_t)w * sub;
+    const int64_t j0 = lo + (cs < n ? cs : n);
+    const int64_t ce = cs + sub;
+    const int64_t j1 = lo + (ce < n ? ce : n);
+    double au = 0.0, av = 0.0;
+    if (j0 < j1) check_range<MODE>(ck, src, srcw, j0, j1, au, av);
+    red[0][w][lane] = au;
+    red[1][w][lane] = av;
+    __syncthreads();
+    if (w == 0) {
+      double su = red[0][0][lane], sv = red[1][0][lane];
+      for (int ww = 1; ww < WAVES; ++ww) {
+        su += red[0][ww][lane];
+        sv += red[1][ww][lane];
+      }
+      const int64_t slot = S.pc[b] + (g * chunks + c) * GRP + lane;
+      part[slot] = su;
+      part[parts_bound + slot] = sv;
+    }
+  }
+}
+
+// u, v of every system: fixed-order sum of the chunk partials.  uv[(2b)*M + k] = u, [(2b+1)*M + k] = v.
+__global__ __launch_bounds__(256) void k_check_finish(int nsys, int M, int chc, const int64_t *__restrict__ base,
+                                                      int64_t parts_bound, const double *__restrict__ part,
+                                                      double *__restrict__ uv, float *__restrict__ uv32) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)nsys * M) return;
+  const int b = (int)(t / M);
+  const int k = (int)(t % M);
+  const int64_t n = S.off[b + 1] - S.off[b];
+  const int64_t chunks = n > 0 ? cdiv64(n, chc) : 0;
+  const int64_t g = k / GRP, lane = k % GRP;
+  double u = 0.0, v = 0.0;
+  for (int64_t c = 0; c < chunks; ++c) {
+    const int64_t slot = S.pc[b] + (g * chunks + c) * GRP + lane;
+    u += part[slot];
+    v += part[parts_bound + slot];
+  }
+  uv[(2 * (int64_t)b) * M + k] = u;
+  uv[(2 * (int64_t)b + 1) * M + k] = v;
+  if (uv32) {
+    uv32[(2 * (int64_t)b) * M + k] = (float)u;
+    uv32[(2 * (int64_t)b + 1) * M + k] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Fit apply, few systems: one wave64 per output row and system.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename TM>
+__global__ __launch_bounds__(256) void k_fit_moments(int K, int M, const TM *__restrict__ pinv,
+                                                     const double *__restrict__ uv, double *__restrict__ ab) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  if (row >= K) return;
+  const TM *pr = pinv + (size_t)row * M;
+  const double *u = uv + (size_t)(2 * b) * M;
+  const double *v = u + M;
+  double su = 0.0, sv = 0.0;
+  for (int m = lane; m < M; m += 64) {
+    const double wgt = (double)pr[m];
+    su = fma(wgt, u[m], su);
+    sv = fma(wgt, v[m], sv);
+  }
+  su = wave_sum(su);
+  sv = wave_sum(sv);
+  if (lane == 0) {
+    ab[(size_t)(2 * b) * K + row] = su;
+    ab[(size_t)(2 * b + 1) * K + row] = sv;
+  }
+}
+
+template <typename TM, typename T2>
+__global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__restrict__ base, int P, int K,
+                                                     const TM *__restrict__ lhat, const PlanDev *__restrict__ plans,
+                                                     const int32_t *__restrict__ plan_of, const int *__restrict__ nidx,
+                                                     const double *__restrict__ ab, T2 *__restrict__ qd) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;  // plan_of was checked by the schedule
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  if (s >= P) return;
+  const double *fg = plans[plan_of ? plan_of[b] : 0].fg;
+  const TM *lr = lhat + (size_t)s * K;
+  const double *al = ab + (size_t)(2 * b) * K;
+  const double *be = al + K;
+  double sq = 0.0, sd = 0.0;
+  for (int k = lane; k < K; k += 64) {
+    const double h = fg[k] * al[k] + fg[K + k] * be[k];
+    const double l = (double)lr[k];
+    sq = fma(l * (double)nidx[k], h, sq);
+    sd = fma(l, h, sd);
+  }
+  sq = wave_sum(sq);
+  sd = wave_sum(sd);
+  if (lane == 0) {
+    T2 o;
+    o.x = sq;
+    o.y = -sd;
+    qd[(size_t)b * P + s] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Fit apply, many systems: C[col][row] = sum_k A[row][k] B[col][k] with FP32 MFMA
+// (v_mfma_f32_16x16x4f32).  Block tile 64 rows x 64 cols, four waves of 32 x 32,
+// k staged through LDS 16 at a time.
+// ---------------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// The MFMA accumulators are FP32; they are folded into FP64 registers after every 64
+// values of k, so the sum over k = 1536-9600 terms loses no more than a 64-term FP32 sum.
+__global__ __launch_bounds__(256) void k_gemm_nt(int nrows, int ncols, int kdim, const float *__restrict__ A,
+                                                 const float *__restrict__ B, float *__restrict__ C) {
+  __shared__ float As[64][17];
+  __shared__ float Bs[64][17];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+  floatx4 acc[2][2];
+  double dacc[2][2][4];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int r = 0; r < 4; ++r) dacc[i][j][r] = 0.0;
+    }
+  int step = 0;
+  for (int k0 = 0; k0 < kdim; k0 += 16) {
+    for (int e = t; e < 64 * 16; e += 256) {
+      const int r = e >> 4, kk = e & 15;
+      const int gr = row0 + r, gc = col0 + r, gk = k0 + kk;
+      As[r][kk] = (gr < nrows && gk < kdim) ? A[(size_t)gr * kdim + gk] : 0.0f;
+      Bs[r][kk] = (gc < ncols && gk < kdim) ? B[(size_t)gc * kdim + gk] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kl = kk + (lane >> 4);
+      float a[2], bb[2];
+      for (int i = 0; i < 2; ++i) a[i] = As[wr * 32 + i * 16 + (lane & 15)][kl];
+      for (int j = 0; j < 2; ++j) bb[j] = Bs[wc * 32 + j * 16 + (lane & 15)][kl];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (++step == 4 || k0 + 16 >= kdim) {
+      step = 0;
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          for (int r = 0; r < 4; ++r) dacc[i][j][r] += (double)acc[i][j][r];
+          acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int col = col0 + wc * 32 + j * 16 + (lane & 15);
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < nrows && col < ncols) C[(size_t)col * nrows + row] = (float)dacc[i][j][r];
+      }
+    }
+}
+
+// h = f . alpha' + g . beta' from the first GEMM's output ab32 [2 nsys][K]; writes the
+// second GEMM's operand h32 [2 nsys][K]: row 2b = n . h, row 2b+1 = h.
+__global__ __launch_bounds__(256) void k_fit_h(int nsys, const int64_t *__restrict__ base, int K,
+                                               const float *__restrict__ ab32, const PlanDev *__restrict__ plans,
+                                               const int32_t *__restrict__ plan_of, const int *__restrict__ nidx,
+                                               float *__restrict__ h32) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;  // plan_of was checked by the schedule
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)nsys * K) return;
+  const int b = (int)(t / K), k = (int)(t % K);
+  const double *fg = plans[plan_of ? plan_of[b] : 0].fg;
+  const double h = fg[k] * (double)ab32[(size_t)(2 * b) * K + k] + fg[K + k] * (double)ab32[(size_t)(2 * b + 1) * K + k];
+  h32[(size_t)(2 * b) * K + k] = (float)(h * (double)nidx[k]);
+  h32[(size_t)(2 * b + 1) * K + k] = (float)h;
+}
+
+// qd[b][s] = (C[2b][s], -C[2b+1][s]) from the second GEMM's output [2 nsys][P].
+template <typename T2>
+__global__ __launch_bounds__(256) void k_fit_qd(int nsys, int P, const float *__restrict__ Cq, T2 *__restrict__ qd) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)nsys * P) return;
+  const int b = (int)(t / P), s = (int)(t % P);
+  T2 o;
+  o.x = Cq[(size_t)(2 * b) * P + s];
+  o.y = -Cq[(size_t)(2 * b + 1) * P + s];
+  qd[t] = o;
+}
+
+// ---------------------------------------------------------------------------------
+// Evaluation sums.
+// ---------------------------------------------------------------------------------
+template <int MODE, bool DIAG>
+__device__ __forceinline__ double kelvin_range(const typename PT<MODE>::T4 &t, int64_t i,
+                                               const typename PT<MODE>::T4 *__restrict__ img, int64_t j0,
+                                               int64_t j1) {
+  using T = typename PT<MODE>::T;
+  using T4 = typename PT<MODE>::T4;
+  if constexpr (MODE != HSMA_PAIR_FP32_COMP) {
+    T s = 0;
+#pragma unroll 8
+    for (int64_t j = j0; j < j1; ++j) {
+      const T4 v = img[j];
+      const T dx = t.x - v.x, dy = t.y - v.y, dz = t.z - v.z;
+      T ri = rinv(dx * dx + dy * dy + dz * dz);
+      if (DIAG) ri = (j == i) ? (T)0 : ri;
+      s = fma(v.w, ri, s);
+    }
+    return (double)s;
+  } else {
+    double acc = 0.0;
+    int64_t jb = j0;
+    for (; jb + TILE <= j1; jb += TILE) {
+      float s = 0.0f;
+#pragma unroll 8
+      for (int u = 0; u < TILE; ++u) {
+        const float4 v = img[jb + u];
+        const float dx = t.x - v.x, dy = t.y - v.y, dz = t.z - v.z;
+        float ri = rinv(dx * dx + dy * dy + dz * dz);
+        if (DIAG) ri = (jb + u == i) ? 0.0f : ri;
+        s = fmaf(v.w, ri, s);
+      }
+      acc += (double)s;
+    }
+    float s = 0.0f;
+    for (int64_t j = jb; j < j1; ++j) {
+      const float4 v = img[j];
+      const float dx = t.x - v.x, dy = t.y - v.y, dz = t.z - v.z;
+      float ri = rinv(dx * dx + dy * dy + dz * dz);
+      if (DIAG) ri = (j == i) ? 0.0f : ri;
+      s = fmaf(v.w, ri, s);
+    }
+    return acc + (double)s;
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ double surface_range(const typename PT<MODE>::T4 &t,
+                                                const typename PT<MODE>::T4 *__restrict__ nodes,
+                                                const typename PT<MODE>::T2 *__restrict__ qd, int s0, int s1) {
+  using T = typename PT<MODE>::T;
+  using T2 = typename PT<MODE>::T2;
+  using T4 = typename PT<MODE>::T4;
+  double acc = 0.0;
+  for (int sb = s0; sb < s1; sb += TILE) {
+    const int se = sb + TILE < s1 ? sb + TILE : s1;
+    T s = 0;
+    for (int k = sb; k < se; ++k) {
+      const T4 yv = nodes[k];
+      const T2 wv = qd[k];
+      const T dx = t.x - yv.x, dy = t.y - yv.y, dz = t.z - yv.z;
+      const T ri = rinv(dx * dx + dy * dy + dz * dz);
+      const T dot = dx * yv.x + dy * yv.y + dz * yv.z;  // (x - y_s) . y_s = R_tau (x - y_s) . y^_s
+      s = fma(ri, fma(wv.y * dot, ri * ri, wv.x), s);
+    }
+    if constexpr (MODE == HSMA_PAIR_FP32) {
+      acc = (double)((T)acc + s);
+    } else {
+      acc += (double)s;
+    }
+  }
+  return acc;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, int che, const int64_t *__restrict__ base,
+                                              const int *__restrict__ sys_e, const PlanDev *__restrict__ plans,
+                                              const int32_t *__restrict__ plan_of,
+                                              const typename PT<MODE>::T4 *__restrict__ tgt,
+                                              const typename PT<MODE>::T4 *__restrict__ img,
+                                              const typename PT<MODE>::T2 *__restrict__ qd, double *__restrict__ part) {
+  using T4 = typename PT<MODE>::T4;
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ int64_t s_item;
+  __shared__ double red[WAVES][GRP];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (!sched_ok(S)) return;
+  const int64_t total = S.ie[nsys];
+  int64_t item;
+  for (bool first = true; next_item(persistent, first, total, &S.ctr[1], &s_item, item); first = false) {
+    const int b = sys_e[item];
+    const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
+    const int64_t loc = item - S.ie[b];
+    const int64_t G = cdiv64(n, GRP);
+    const int64_t chunks = cdiv64(n + P, che);
+    const int64_t c = loc / G, g = loc % G;  // items sharing a source chunk are adjacent
+    const int64_t il = g * GRP + lane;       // local target index
+    const T4 t = tgt[lo + (il < n ? il : n - 1)];
+    const int sub = che / WAVES;
+    const int64_t tot = n + P;
+    const int64_t cs = c * che + (int64_t)w * sub;
+    const int64_t j0 = cs < tot ? cs : tot;
+    const int64_t j1 = (cs + sub) < tot ? (cs + sub) : tot;
+    double acc = 0.0;
+    const int64_t k1 = j1 < n ? j1 : n;
+    if (j0 < k1) {
+      const int64_t t0 = g * GRP;
+      const bool diag = (t0 < k1) && (t0 + GRP > j0);
+      acc = diag ? kelvin_range<MODE, true>(t, il, img + lo, j0, k1) : kelvin_range<MODE, false>(t, il, img + lo, j0, k1);
+    }
+    const int64_t s0 = (j0 > n ? j0 : n) - n, s1 = j1 - n;
+    if (s0 < s1) {
+      const PlanDev pd = plans[plan_of ? plan_of[b] : 0];
+      acc += surface_range<MODE>(t, nodes_of<MODE>(pd), qd + (size_t)b * P, (int)s0, (int)s1);
+    }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0) {
+      double s = red[0][lane];
+      for (int ww = 1; ww < WAVES; ++ww) s += red[ww][lane];
+      part[S.pe[b] + (g * chunks + c) * GRP + lane] = s;
+    }
+  }
+}
+
+// Phi_i = own-image term + fixed-order sum of the chunk partials; block partial of 1/2 sum q Phi.
+__global__ __launch_bounds__(FINB) void k_finish(int nsys, int P, int che, const int64_t *__restrict__ base,
+                                                 const int *__restrict__ sys_f, const double *__restrict__ part,
+                                                 const double *__restrict__ self, const double *__restrict__ q,
+                                                 double *__restrict__ phi, double *__restrict__ epart) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ double red[FINB];
+  const int64_t f = blockIdx.x;
+  if (!sched_ok(S) || f >= S.fb[nsys]) return;  // uniform across the block
+  const int b = sys_f[f];
+  const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
+  const int64_t il = (f - S.fb[b]) * FINB + threadIdx.x;
+  double e = 0.0;
+  if (il < n) {
+    const int64_t chunks = cdiv64(n + P, che);
+    const int64_t g = il / GRP, lane = il % GRP;
+    const double *pp = part + S.pe[b] + g * chunks * GRP + lane;
+    double s = self[lo + il];
+    for (int64_t c = 0; c < chunks; ++c) s += pp[c * GRP];
+    phi[lo + il] = s;
+    e = 0.5 * q[lo + il] * s;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = FINB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) epart[f] = red[0];
+}
+
+// E_b = sum of the block partials of system b, lane-strided then a shuffle tree (fixed order).
+__global__ __launch_bounds__(64) void k_energy(int nsys, const int64_t *__restrict__ base,
+                                               const double *__restrict__ epart, double *__restrict__ E) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int64_t f = S.fb[b] + threadIdx.x; f < S.fb[b + 1]; f += 64) s += epart[f];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) E[b] = s;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int round_up(int64_t v, int m) { return (int)((v + m - 1) / m * m); }
+
+template <int MODE>
+hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, const int32_t *plan_of, int64_t n1,
+                   const double *x, const double *y, const double *z, const double *q, double *phi, double *E,
+                   char *ws, hipStream_t st) {
+  using T = typename PT<MODE>::T;
+  using T2 = typename PT<MODE>::T2;
+  using T4 = typename PT<MODE>::T4;
+  const Geometry *g = grp->geo;
+  const int M = g->M, P = g->P, K = g->K, nsys = L.nsys;
+  int64_t *base = (int64_t *)(ws + L.sched);
+  int *sys_c = (int *)(ws + L.item_sys_c);
+  int *sys_e = (int *)(ws + L.item_sys_e);
+  int *sys_f = (int *)(ws + L.fin_sys);
+  T4 *img = (T4 *)(ws + L.img);
+  T4 *tgt = (T4 *)(ws + L.tgt);
+  T *srcw = (T *)(ws + L.srcw);
+  double *self = (double *)(ws + L.self);
+  double *chk_part = (double *)(ws + L.chk_part);
+  double *uv = (double *)(ws + L.uv);
+  float *uv32 = L.mfma ? (float *)(ws + L.uv32) : nullptr;
+  double *ab = (double *)(ws + L.ab);
+  T2 *qd = (T2 *)(ws + L.qd);
+  double *eval_part = (double *)(ws + L.eval_part);
+  double *epart = (double *)(ws + L.epart);
+  const PlanDev *plans = grp->dev;
+  const int persistent = grp->tune.persistent;
+  const int64_t pgrid = (int64_t)g->ncu * BLOCKS_PER_CU;
+  const int64_t grid_c = persistent ? (L.items_c < pgrid ? L.items_c : pgrid) : L.items_c;
+  const int64_t grid_e = persistent ? (L.items_e < pgrid ? L.items_e : pgrid) : L.items_e;
+
+  hipEvent_t pr = prof_begin(grp, ST_PACK, st);
+  const int sched_t = nsys >= SCHED_T ? SCHED_T : (int)((nsys + 63) / 64 * 64);
+  Bounds bd;
+  bd.total_n = n1;
+  bd.max_n = L.max_n;
+  bd.items_c = L.items_c;
+  bd.items_e = L.items_e;
+  bd.fin = L.fin;
+  bd.parts_c = L.parts_c;
+  bd.parts_e = L.parts_e;
+  bd.nplans = grp->nplans;
+  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, P, L.chc, L.che, grid_c, grid_e, base, grp->flag);
+  k_fill<<<nsys, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f);
+  if (L.fin > 0)
+    k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_f, plans, plan_of, x, y, z, q, img, tgt, srcw, self,
+                                             grp->flag);
+  prof_end(pr, st);
+
+  pr = prof_begin(grp, ST_CHECK, st);
+  if (L.items_c > 0)
+    k_check<MODE><<<(unsigned)grid_c, TPB, 0, st>>>(persistent, nsys, M, L.chc, base, sys_c, plans, plan_of, tgt, srcw,
+                                                    L.parts_c, chk_part);
+  k_check_finish<<<(int)cdiv((int64_t)nsys * M, 256), 256, 0, st>>>(nsys, M, L.chc, base, L.parts_c, chk_part, uv,
+                                                                     uv32);
+  prof_end(pr, st);
+
+  pr = prof_begin(grp, ST_FIT, st);
+  if (L.mfma) {
+    float *ab32 = (float *)(ws + L.ab);  // the FP32 path keeps alpha', beta' in FP32
+    float *h32 = (float *)(ws + L.h32);
+    float *c2 = (float *)(ws + L.gemm2);
+    dim3 g1((unsigned)cdiv(K, 64), (unsigned)cdiv(2 * (int64_t)nsys, 64));
+    k_gemm_nt<<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->pinv32, uv32, ab32);
+    k_fit_h<<<(int)cdiv((int64_t)nsys * K, 256), 256, 0, st>>>(nsys, base, K, ab32, plans, plan_of, g->nidx, h32);
+    dim3 g2((unsigned)cdiv(P, 64), (unsigned)cdiv(2 * (int64_t)nsys, 64));
+    k_gemm_nt<<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->lhat32, h32, c2);
+    k_fit_qd<T2><<<(int)cdiv((int64_t)nsys * P, 256), 256, 0, st>>>(nsys, P, c2, qd);
+  } else if constexpr (MODE == HSMA_PAIR_FP64) {
+    k_fit_moments<double><<<dim3((unsigned)cdiv(K, 4), nsys), 256, 0, st>>>(K, M, g->pinv64, uv, ab);
+    k_fit_surface<double, T2><<<dim3((unsigned)cdiv(P, 4), nsys), 256, 0, st>>>(nsys, base, P, K, g->lhat64, plans,
+                                                                                plan_of, g->nidx, ab, qd);
+  } else {
+    k_fit_moments<float><<<dim3((unsigned)cdiv(K, 4), nsys), 256, 0, st>>>(K, M, g->pinv32, uv, ab);
+    k_fit_surface<float, T2><<<dim3((unsigned)cdiv(P, 4), nsys), 256, 0, st>>>(nsys, base, P, K, g->lhat32, plans,
+                                                                               plan_of, g->nidx, ab, qd);
+  }
+  prof_end(pr, st);
+
+  pr = prof_begin(grp, ST_EVAL, st);
+  if (L.items_e > 0)
+    k_eval<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(persistent, nsys, P, L.che, base, sys_e, plans, plan_of, tgt, img,
+                                                   qd, eval_part);
+  prof_end(pr, st);
+
+  pr = prof_begin(grp, ST_FINISH, st);
+  if (L.fin > 0)
+    k_finish<<<(int)L.fin, FINB, 0, st>>>(nsys, P, L.che, base, sys_f, eval_part, self, q, phi, epart);
+  if (E) k_energy<<<nsys, 64, 0, st>>>(nsys, base, epart, E);
+  prof_end(pr, st);
+  HSMA_HIP(hipGetLastError());
+  return HSMA_OK;
+}
+
+}  // namespace
+
+// Item sizes are chosen from upper bounds known on the host (system count, total and
+// largest system size): the check chunk aims at about 8192 items, the evaluation chunk at
+// about 8192 items of the largest possible pair count; both multiples of 4 waves x 32.
+Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n) {
+  Layout L;
+  const Geometry *g = grp->geo;
+  const int64_t M = g->M, P = g->P, K = g->K;
+  const bool fp64 = grp->pair_prec == HSMA_PAIR_FP64;
+  L.nsys = nsys;
+  L.total_n = total_n;
+  L.max_n = max_n;
+  const int64_t target_items = grp->tune.target_items;
+  const int64_t Gc = cdiv(M, GRP);
+  int64_t chc = cdiv(Gc * total_n, target_items);
+  chc = chc < 512 ? 512 : (chc > 65536 ? 65536 : chc);
+  L.chc = round_up(chc, WAVES * TILE);
+  const double pairs_bound = (double)total_n * (double)(max_n + P);
+  int64_t che = (int64_t)(pairs_bound / (double)(GRP * target_items)) + 1;
+  che = che < 1024 ? 1024 : (che > 65536 ? 65536 : che);
+  L.che = round_up(che, WAVES * TILE);
+  // bounds: sum over systems of ceil(a_b / c) <= sum a_b / c + nsys
+  L.items_c = total_n > 0 ? Gc * (total_n / L.chc + nsys) : 0;
+  L.parts_c = L.items_c * GRP;
+  const int64_t gt = total_n / GRP + nsys;                      // target groups
+  const int64_t chunks_max = (max_n + P) / L.che + 1;           // chunks of the largest system
+  L.items_e = total_n > 0 ? gt * chunks_max : 0;
+  L.parts_e = L.items_e * GRP;
+  L.fin = total_n > 0 ? total_n / FINB + nsys : 0;
+  L.mfma = !fp64 && nsys >= 8;
+  const size_t t4 = fp64 ? sizeof(double4) : sizeof(float4);
+  const size_t t1 = fp64 ? sizeof(double) : sizeof(float);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.sched = take(sizeof(int64_t) * (6 * (size_t)(nsys + 1) + 8));
+  L.item_sys_c = take(sizeof(int) * (size_t)L.items_c);
+  L.item_sys_e = take(sizeof(int) * (size_t)L.items_e);
+  L.fin_sys = take(sizeof(int) * (size_t)L.fin);
+  L.img = take(t4 * (size_t)total_n);
+  L.tgt = take(t4 * (size_t)total_n);
+  L.srcw = take(t1 * (size_t)total_n);
+  L.self = take(sizeof(double) * (size_t)total_n);
+  L.chk_part = take(sizeof(double) * 2 * (size_t)L.parts_c);
+  L.uv = take(sizeof(double) * 2 * (size_t)M * nsys);
+  L.uv32 = L.mfma ? take(sizeof(float) * 2 * (size_t)M * nsys) : 0;
+  L.ab = take(sizeof(double) * 2 * (size_t)K * nsys);
+  L.h32 = L.mfma ? take(sizeof(float) * 2 * (size_t)K * nsys) : 0;
+  L.gemm2 = L.mfma ? take(sizeof(float) * 2 * (size_t)P * nsys) : 0;
+  L.qd = take(sizeof(double2) * (size_t)P * nsys);
+  L.eval_part = take(sizeof(double) * (size_t)L.parts_e);
+  L.phi = take(sizeof(double) * (size_t)total_n);
+  L.epart = take(sizeof(double) * (size_t)(L.fin + 1));
+  L.E = take(sizeof(double) * (size_t)nsys);
+  L.total = o;
+  return L;
+}
+
+hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, const int32_t *plan_of, int64_t total_n,
+                        int64_t max_n, const double *x, const double *y, const double *z, const double *q,
+                        double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!grp || nsys < 1 || total_n < 0 || max_n < 0 || max_n > total_n || !ws) return HSMA_EINVAL;
+  if (total_n > ((int64_t)1 << 31) - 1) return HSMA_EINVAL;
+  if (total_n > 0 && (!x || !y || !z || !q)) return HSMA_EINVAL;
+  if (((uintptr_t)ws & 255) != 0) return HSMA_EINVAL;
+  if (nsys > 1 && !offsets) return HSMA_EINVAL;
+  int dev = -1;
+  HSMA_HIP(hipGetDevice(&dev));
+  if (dev != grp->device) return HSMA_ESTATE;
+  const Layout L = layout(grp, nsys, total_n, max_n);
+  if (ws_bytes < L.total) return HSMA_EINVAL;  // workspace sized for other sizes or launch parameters
+  char *w = (char *)ws;
+  if (!phi) phi = (double *)(w + L.phi);
+  switch (grp->pair_prec) {
+    case HSMA_PAIR_FP32:
+      return launch<HSMA_PAIR_FP32>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
+    case HSMA_PAIR_FP32_COMP:
+      return launch<HSMA_PAIR_FP32_COMP>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
+    case HSMA_PAIR_FP64:
+      return launch<HSMA_PAIR_FP64>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
+    default:
+      return HSMA_EINVAL;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Stage timing.
+// ---------------------------------------------------------------------------------
+hipEvent_t prof_begin(hsma_group_s *grp, int stage, hipStream_t st) {
+  if (!grp->prof_on) return nullptr;
+  Profile *p = (Profile *)grp->prof;
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->n == p->cap) {
+    const int nc = p->cap ? 2 * p->cap : 256;
+    ProfRec *r = (ProfRec *)realloc(p->recs, sizeof(ProfRec) * nc);
+    if (!r) return nullptr;
+    p->recs = r;
+    p->cap = nc;
+  }
+  ProfRec *r = &p->recs[p->n];
+  if (hipEventCreate(&r->a) != hipSuccess) return nullptr;
+  if (hipEventCreate(&r->b) != hipSuccess) {
+    (void)hipEventDestroy(r->a);
+    return nullptr;
+  }
+  r->stage = stage;
+  p->n++;
+  (void)hipEventRecord(r->a, st);
+  return r->b;
+}
+
+void prof_end(hipEvent_t end, hipStream_t st) {
+  if (end) (void)hipEventRecord(end, st);
+}
+
+void prof_free(hsma_group_s *grp) {
+  Profile *p = (Profile *)grp->prof;
+  if (!p) return;
+  for (int i = 0; i < p->n; ++i) {
+    (void)hipEventDestroy(p->recs[i].a);
+    (void)hipEventDestroy(p->recs[i].b);
+  }
+  free(p->recs);
+  delete p;
+  grp->prof = nullptr;
+}
+
+}  // namespace hsma
+
+using namespace hsma;
+
+// ---------------------------------------------------------------------------------
+// C ABI.
+// ---------------------------------------------------------------------------------
+extern "C" size_t hsma_workspace_bytes(hsma_plan_t pl, int64_t N) {
+  if (!pl || N < 0) return 0;
+  return layout(pl->self, 1, N, N).total;
+}
+
+extern "C" hsma_status hsma_potential(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
+                                      const double *q, double *phi, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!pl || (N > 0 && !phi)) return HSMA_EINVAL;
+  return run_batched(pl->self, 1, nullptr, nullptr, N, N, x, y, z, q, phi, nullptr, ws, ws_bytes, st);
+}
+
+extern "C" hsma_status hsma_energy(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
+                                   const double *q, double *phi, double *E, void *ws, size_t ws_bytes,
+                                   hipStream_t st) {
+  if (!pl || !E) return HSMA_EINVAL;
+  return run_batched(pl->self, 1, nullptr, nullptr, N, N, x, y, z, q, phi, E, ws, ws_bytes, st);
+}
+
+extern "C" size_t hsma_batched_workspace_bytes(hsma_group_t grp, int nsys, int64_t total_n, int64_t max_n) {
+  if (!grp || nsys < 1 || total_n < 0 || max_n < 0) return 0;
+  return layout(grp, nsys, total_n, max_n).total;
+}
+
+extern "C" hsma_status hsma_energy_batched(hsma_group_t grp, int nsys, const int64_t *offsets, const int32_t *plan_of,
+                                           int64_t total_n, int64_t max_n, const double *x, const double *y,
+                                           const double *z, const double *q, double *phi, double *E, void *ws,
+                                           size_t ws_bytes, hipStream_t st) {
+  if (!grp || !offsets) return HSMA_EINVAL;
+  return run_batched(grp, nsys, offsets, plan_of, total_n, max_n, x, y, z, q, phi, E, ws, ws_bytes, st);
+}
+
+extern "C" hsma_status hsma_group_tune(hsma_group_t grp, int persistent, int target_items) {
+  if (!grp || (persistent != 0 && persistent != 1) || target_items < 64 || target_items > (1 << 22))
+    return HSMA_EINVAL;
+  grp->tune.persistent = persistent;
+  grp->tune.target_items = target_items;
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_debug_intermediates(hsma_plan_t pl, int64_t N, const void *ws, hipStream_t st, double *u,
+                                                double *v, double *Q, double *D) {
+  if (!pl || !ws || N < 0) return HSMA_EINVAL;
+  const Layout L = layout(pl->self, 1, N, N);
+  const char *w = (const char *)ws;
+  const int M = pl->geo->M, P = pl->geo->P;
+  HSMA_HIP(hipStreamSynchronize(st));
+  if (u) HSMA_HIP(hipMemcpy(u, w + L.uv, sizeof(double) * M, hipMemcpyDeviceToHost));
+  if (v) HSMA_HIP(hipMemcpy(v, w + L.uv + sizeof(double) * M, sizeof(double) * M, hipMemcpyDeviceToHost));
+  if (Q || D) {
+    if (pl->self->pair_prec == HSMA_PAIR_FP64) {
+      double2 *h = new double2[P];
+      hipError_t e = hipMemcpy(h, w + L.qd, sizeof(double2) * P, hipMemcpyDeviceToHost);
+      if (e == hipSuccess)
+        for (int s = 0; s < P; ++s) {
+          if (Q) Q[s] = h[s].x;
+          if (D) D[s] = h[s].y;
+        }
+      delete[] h;
+      if (e != hipSuccess) return HSMA_EDEVICE;
+    } else {
+      float2 *h = new float2[P];
+      hipError_t e = hipMemcpy(h, w + L.qd, sizeof(float2) * P, hipMemcpyDeviceToHost);
+      if (e == hipSuccess)
+        for (int s = 0; s < P; ++s) {
+          if (Q) Q[s] = h[s].x;
+          if (D) D[s] = h[s].y;
+        }
+      delete[] h;
+      if (e != hipSuccess) return HSMA_EDEVICE;
+    }
+  }
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_profile_enable(hsma_group_t grp, int on) {
+  if (!grp) return HSMA_EINVAL;
+  if (!grp->prof) grp->prof = new Profile();
+  grp->prof_on = on ? 1 : 0;
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_profile_read(hsma_group_t grp, double *ms, int64_t *count) {
+  if (!grp || !ms || !count) return HSMA_EINVAL;
+  for (int s = 0; s < ST_COUNT; ++s) {
+    ms[s] = 0.0;
+    count[s] = 0;
+  }
+  Profile *p = (Profile *)grp->prof;
+  if (!p) return HSMA_OK;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hsma_status rc = HSMA_OK;
+  for (int i = 0; i < p->n; ++i) {
+    ProfRec &r = p->recs[i];
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) rc = HSMA_EDEVICE;
+    ms[r.stage] += t;
+    count[r.stage] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  p->n = 0;
+  return rc;
+}
+
+// flag bit 1: an ion outside the cavity or a non-finite input; bit 2: device offsets or plan
+// indices inconsistent with the host sizes (the call did no work).
+static hsma_status flag_check(hsma_group_s *grp, hipStream_t st) {
+  HSMA_HIP(hipStreamSynchronize(st));
+  int f = 0;
+  HSMA_HIP(hipMemcpy(&f, grp->flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (f) {
+    HSMA_HIP(hipMemset(grp->flag, 0, sizeof(int)));
+    return (f & 2) ? HSMA_EINVAL : HSMA_EDOMAIN;
+  }
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_stream_check(hsma_plan_t pl, hipStream_t st) {
+  if (!pl) return HSMA_EINVAL;
+  return flag_check(pl->self, st);
+}
+
+extern "C" hsma_status hsma_group_stream_check(hsma_group_t grp, hipStream_t st) {
+  if (!grp) return HSMA_EINVAL;
+  return flag_check(grp, st);
+}
+
+extern "C" const char *hsma_status_string(hsma_status s) {
+  switch (s) {
+    case HSMA_OK: return "ok";
+    case HSMA_EINVAL: return "invalid argument";
+    case HSMA_EDOMAIN: return "ion outside the cavity or non-finite input";
+    case HSMA_ENOMEM: return "out of memory";
+    case HSMA_EBUSY: return "busy";
+    case HSMA_EDEVICE: return "HIP runtime error";
+    case HSMA_ESTATE: return "wrong state or device";
+  }
+  return "unknown status";
+}
+
+extern "C" int hsma_version(void) { return 200; }

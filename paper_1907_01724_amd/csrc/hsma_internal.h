@@ -11,10 +11,10 @@
 #define HSMA_PI 3.14159265358979323846
 
 // Return HSMA_EDEVICE from the enclosing function when a HIP call fails.
-#define HSMA_HIP(call)                                        \
-  do {                                                        \
-    hipError_t e_ = (call);                                   \
-    if (e_ != hipSuccess) return HSMA_EDEVICE;                \
+#define HSMA_HIP(call)                         \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) return HSMA_EDEVICE; \
   } while (0)
 
 namespace hsma {
@@ -25,6 +25,7 @@ struct Geometry {
   int p, K, P, M, F1, F2;
   double tau, rc_over_a;
   int device;
+  int ncu;             // compute units of the device (persistent grid size)
   double *unit_check;  // M x 3 unit vectors of the check points
   double *unit_nodes;  // P x 3 unit vectors of the Fibonacci nodes
   double *what;        // P Fibonacci weights on the unit sphere (sum 4 pi)
@@ -36,42 +37,75 @@ struct Geometry {
   int refs;
 };
 
-// Scalars of one plan, passed to kernels by value.
-struct Consts {
-  double a, a2, eps1, gamma, sigma, dbar, Rtau, rc, c0;  // c0 = 1 / (4 pi eps1)
-  double far;                                            // distance used for an image at infinity
-  double rmin;                                           // below this radius an ion's image is at infinity
+// Per-plan scalars and pointers, stored on the device (one per plan of a group) and
+// also kept on the host for kernel arguments.
+struct PlanDev {
+  double a, a2, c0;           // radius, radius^2, 1 / (4 pi eps1)
+  double gamma, sigma, dbar;  // constants of eq. "Anuapp"
+  double Rtau, rc;            // auxiliary-sphere and check-point radii
+  double far, rmin;           // an ion with r < rmin has its image at infinity (distance `far`)
+  const double *fg;           // 2K: f_nm then g_nm (the per-plan diagonals of the fit operator)
+  const float4 *chk32;        // M check points at radius rc
+  const double4 *chk64;
+  const float4 *nodes32;      // P surface nodes at radius R_tau
+  const double4 *nodes64;
 };
 
 }  // namespace hsma
+
+// Launch-shape parameters of the pair kernels (see hsma_group_tune).
+struct hsma_tune_s {
+  int persistent;    // 1: persistent blocks taking items from a device counter; 0: one item per block
+  int target_items;  // items each pair kernel aims to create (sets the source-chunk sizes)
+};
+
+struct hsma_group_s {
+  hsma_tune_s tune;
+  int nplans;
+  hsma::Geometry *geo;   // shared by every plan of the group
+  hsma::PlanDev *dev;    // nplans entries on the device
+  int pair_prec;
+  int device;
+  int *flag;             // device-side domain flag
+  int prof_on;           // record HIP events around each stage
+  void *prof;            // hsma::Profile
+  int owned_by_plan;     // the internal one-plan group of a plan
+};
 
 struct hsma_plan_s {
   double a, eps1, eps2, kappa;
   hsma_plan_opts opts;
   hsma::Geometry *geo;
-  hsma::Consts c;
-  double *fg;          // 2K: f_nm then g_nm (the per-plan diagonals of the fit operator)
-  float4 *chk32;       // M check points at radius rc (w unused)
+  hsma::PlanDev host;    // the same values as the device copy
+  double *fg;            // 2K
+  float4 *chk32;
   double4 *chk64;
-  float4 *nodes32;     // P surface nodes at radius R_tau (w unused)
+  float4 *nodes32;
   double4 *nodes64;
-  int *flag;           // device-side domain flag
+  hsma_group_s *self;    // one-plan group used by the single-system entry points
   int device;
-  int prof_on;         // record HIP events around each stage
-  void *prof;          // hsma::Profile
 };
 
 namespace hsma {
 
 hsma_status geometry_acquire(int p, int P, int M, int F1, double tau, double rc_over_a, Geometry **out);
 void geometry_release(Geometry *g);
+hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan, hsma_group_s **out);
+void group_free(hsma_group_s *g);
 
-// Workspace layout for one system of N ions (offsets in bytes from ws).
-struct Workspace {
-  size_t img, tgt, srcw, self, chk_part, uv, ab, qd, eval_part, phi, e_part, total;
-  int chk_chunks, chk_chunk, eval_chunks, eval_chunk, e_blocks;
+// Workspace layout of one batched call (offsets in bytes from the workspace base).
+struct Layout {
+  int nsys;
+  int64_t total_n, max_n;
+  int chc, che;                  // sources per item (check / evaluation), multiples of 128
+  int64_t items_c, items_e, fin; // upper bounds of the item and finish-block counts
+  int64_t parts_c, parts_e;      // upper bounds of the partial-sum slots
+  size_t sched, item_sys_c, item_sys_e, fin_sys;
+  size_t img, tgt, srcw, self, chk_part, uv, uv32, ab, h32, gemm2, qd, eval_part, phi, epart, E;
+  size_t total;
+  bool mfma;                     // fit applied as MFMA GEMMs
 };
-Workspace workspace_layout(const hsma_plan_s *plan, int64_t N);
+Layout layout(const hsma_group_s *g, int nsys, int64_t total_n, int64_t max_n);
 
 // Stage timing with HIP events recorded on the launch stream (off unless enabled).
 enum Stage { ST_PACK = 0, ST_CHECK = 1, ST_FIT = 2, ST_EVAL = 3, ST_FINISH = 4, ST_COUNT = 5 };
@@ -86,8 +120,14 @@ struct Profile {
 };
 // Records the start event of a stage and returns its end event (to pass to prof_end),
 // or nullptr when profiling is off.
-hipEvent_t prof_begin(hsma_plan_s *plan, int stage, hipStream_t st);
+hipEvent_t prof_begin(hsma_group_s *g, int stage, hipStream_t st);
 void prof_end(hipEvent_t end, hipStream_t st);
-void prof_free(hsma_plan_s *plan);
+void prof_free(hsma_group_s *g);
+
+// The batched hot path; offsets is a device array of nsys + 1 entries, or nullptr for
+// a single system of total_n ions.  E may be nullptr.
+hsma_status run_batched(hsma_group_s *g, int nsys, const int64_t *offsets, const int32_t *plan_of, int64_t total_n,
+                        int64_t max_n, const double *x, const double *y, const double *z, const double *q,
+                        double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st);
 
 }  // namespace hsma
