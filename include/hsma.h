@@ -186,6 +186,32 @@ hsma_status hsma_group_tune(hsma_group_t group, int persistent, int target_items
 hsma_status hsma_profile_enable(hsma_group_t group, int on);
 hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int64_t *count /* [host] 5 */);
 
+/* Resident system (a Monte Carlo state): copies x, y, z, q ([device], N >= 1 ions) and keeps
+ * on the device what a single-ion move needs: the positions, the surface strengths s and
+ * surface rows w = sum_i q_i S(x_i) of the HSMA energy, and the energy itself, all from a
+ * full evaluation in FP64 pairs.  Synchronises; the plan must outlive the system.
+ *
+ * hsma_delta_energy: the change of the energy E = (1/2) sum_i q_i Phi_RF(x_i) when ion k
+ * moves to (xk, yk, zk) ([host] scalars, |x| < a), written to dE ([device] one double),
+ * without changing the state.  The energy is a bilinear form in the charges (the Kelvin
+ * images of Sec. 2.4 and the fitted surface images of eq. "phicorrfinall"), so the change
+ * is evaluated exactly from the row and column of ion k: O(N) image pairs, O(M + P)
+ * check/surface pairs and two GEMVs of the fixed fit operator, in FP64, in four launches.
+ * hsma_system_commit: apply that move (positions, s, w and the stored energy).
+ * hsma_system_energy: the stored energy (initial value plus committed changes) to E
+ * ([device]).  hsma_system_positions: copy the current positions ([device] N each).
+ * Errors: HSMA_EINVAL (k out of range, non-finite or |x| >= a), HSMA_EDOMAIN (an initial
+ * ion outside the cavity), HSMA_ESTATE (wrong device), HSMA_ENOMEM, HSMA_EDEVICE.
+ * A system is not thread safe: its calls must be ordered (one stream). */
+hsma_status hsma_system_create(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
+                               const double *q, hipStream_t stream, hsma_system_t *out);
+hsma_status hsma_delta_energy(hsma_system_t sys, int64_t k, double xk, double yk, double zk, double *dE,
+                              hipStream_t stream);
+hsma_status hsma_system_commit(hsma_system_t sys, int64_t k, double xk, double yk, double zk, hipStream_t stream);
+hsma_status hsma_system_energy(hsma_system_t sys, double *E, hipStream_t stream);
+hsma_status hsma_system_positions(hsma_system_t sys, double *x, double *y, double *z, hipStream_t stream);
+hsma_status hsma_system_destroy(hsma_system_t sys);
+
 /* Synchronise the stream and report a device-side error raised since the last check
  * (then clear it): HSMA_EDOMAIN for an ion outside the cavity or a non-finite input,
  * HSMA_EINVAL for device offsets or plan indices inconsistent with the host sizes; for the

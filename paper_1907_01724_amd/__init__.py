@@ -81,10 +81,17 @@ def load_library(path: str | None = None):
                                                                                                    _VP]
     L.hsma_group_stream_check.argtypes = [_VP, _VP]
     L.hsma_group_tune.argtypes = [_VP, C.c_int, C.c_int]
+    L.hsma_system_create.argtypes = [_VP, C.c_int64] + [_VP] * 4 + [_VP, C.POINTER(_VP)]
+    L.hsma_delta_energy.argtypes = [_VP, C.c_int64, C.c_double, C.c_double, C.c_double, _VP, _VP]
+    L.hsma_system_commit.argtypes = [_VP, C.c_int64, C.c_double, C.c_double, C.c_double, _VP]
+    L.hsma_system_energy.argtypes = [_VP, _VP, _VP]
+    L.hsma_system_positions.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.hsma_system_destroy.argtypes = [_VP]
     for name in ("hsma_plan", "hsma_plan_ex", "hsma_plan_destroy", "hsma_plan_get_info", "hsma_potential",
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
-                 "hsma_group_stream_check", "hsma_group_tune"):
+                 "hsma_group_stream_check", "hsma_group_tune", "hsma_system_create", "hsma_delta_energy",
+                 "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -325,6 +332,63 @@ class Group:
 
     def stream_check(self, stream=None) -> int:
         return int(load_library().hsma_group_stream_check(self._h, _stream_ptr(stream)))
+
+
+class System:
+    """A resident ion configuration for single-ion-move energy changes (Monte Carlo)."""
+
+    def __init__(self, plan: Plan, x, y, z, q, stream=None):
+        L = load_library()
+        self.plan = plan
+        self.n = x.numel()
+        h = _VP()
+        _check(L.hsma_system_create(plan.handle, self.n, _dev_ptr(x, "x", self.n), _dev_ptr(y, "y", self.n),
+                                    _dev_ptr(z, "z", self.n), _dev_ptr(q, "q", self.n), _stream_ptr(stream),
+                                    C.byref(h)), "hsma_system_create")
+        self._h = h
+        self.device = x.device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def delta_energy(self, k: int, pos, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(load_library().hsma_delta_energy(self._h, int(k), float(pos[0]), float(pos[1]), float(pos[2]),
+                                                _dev_ptr(out, "dE"), _stream_ptr(stream)), "hsma_delta_energy")
+        return out
+
+    def commit(self, k: int, pos, stream=None):
+        _check(load_library().hsma_system_commit(self._h, int(k), float(pos[0]), float(pos[1]), float(pos[2]),
+                                                 _stream_ptr(stream)), "hsma_system_commit")
+
+    def energy(self, out=None, stream=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(load_library().hsma_system_energy(self._h, _dev_ptr(out, "E"), _stream_ptr(stream)),
+               "hsma_system_energy")
+        return out
+
+    def positions(self, stream=None):
+        torch = _torch()
+        xyz = [torch.empty(self.n, dtype=torch.float64, device=self.device) for _ in range(3)]
+        _check(load_library().hsma_system_positions(self._h, *[t.data_ptr() for t in xyz], _stream_ptr(stream)),
+               "hsma_system_positions")
+        return xyz
+
+    def close(self):
+        if self._h:
+            load_library().hsma_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status_string(code: int) -> str:

@@ -1,0 +1,446 @@
+// Resident ion configurations and single-ion-move energy changes (FP64 throughout).
+//
+// The HSMA energy E = 1/2 sum_i q_i Phi_RF(x_i) (Sec. 4.1, eq. "phirffinall") is a bilinear
+// form in the charges:
+//   E = 1/2 sum_ij q_i q_j g(x_i, x_j) + 1/2 w . s,
+// with g(x, x') = kappa_K(|x'|) c0 / |x - r_K(x')| the modified Kelvin image of a unit charge
+// at x' seen at x (g(x, x) is the ion's own image), w = sum_i q_i S(x_i) the surface kernel
+// rows (S(x) = (1/|x - y_s|, (x - y_s).y_s / |x - y_s|^3) over the P nodes) and s = T c the
+// surface strengths, c = sum_i q_i C(x_i) the check fields and T the fixed fit operator
+// (Algorithm 1, steps 2-4).  Moving ion k from x to x' therefore changes E by
+//   dE = 1/2 [q_k sum_{j != k} q_j (g(x', x_j) - g(x, x_j) + g(x_j, x') - g(x_j, x)) + q_k^2 (g(x', x') - g(x, x))]
+//      + 1/2 [dw . s + (w + dw) . ds],   dw = q_k (S(x') - S(x)),  ds = T q_k (C(x') - C(x)),
+// which costs O(N + M + P) pairs and two small GEMVs instead of a full evaluation.
+#include <math.h>
+#include <string.h>
+
+#include "hsma_internal.h"
+
+namespace hsma {
+
+// Device descriptor of one resident system.
+struct SysDev {
+  PlanDev pl;
+  const double *pinv64, *lhat64;
+  const int *nidx;
+  int K, M, P;
+  int64_t n;
+  double *x, *y, *z, *q;
+  double *s;   // 2P: Q' then D' (the strengths the evaluation kernel uses)
+  double *w;   // 2P: sum_i q_i S(x_i)
+  double *E;   // 1: current energy
+  double *dc;  // 2M scratch: check-field change (u then v)
+  double *ab;  // 2K scratch
+  double *ds;  // 2P scratch
+  double *dw;  // 2P scratch
+  double *partA;  // ceil(n / 256) scratch
+  double *partE;  // P scratch
+};
+
+// One single-ion-move request.
+struct DeReq {
+  int sys;
+  int commit;
+  int64_t k;
+  double x, y, z;
+  double *dE;  // [device] output, or nullptr
+};
+
+}  // namespace hsma
+
+struct hsma_system_s {
+  hsma_plan_t plan;
+  hsma_group_s *g64;     // FP64 group over the plan (full evaluations)
+  hsma::SysDev h;        // host copy of the descriptor
+  hsma::SysDev *d;       // device copy
+  int64_t n;
+  void *ws;              // workspace of the full evaluation
+  size_t ws_bytes;
+  int device;
+};
+
+namespace hsma {
+namespace {
+
+constexpr int DB = 256;
+
+__device__ __forceinline__ double rinv64(double r2) { return 1.0 / sqrt(r2); }
+
+// Image strength per unit charge times c0, and the image position, of an ion at (x, y, z):
+// q_K / q = (1/a)[gamma r_K + dbar (R_tau - r_K)/2] with r_K = a^2 / r (Sec. 2.4).  For r below
+// rmin the image is at infinity; its potential tends to (gamma - dbar/2) c0 / a everywhere.
+struct Img {
+  double X, Y, Z, s;  // position and c0 * strength per unit charge
+  bool inf;           // at infinity: potential = s everywhere
+};
+
+__device__ __forceinline__ Img image_of(const PlanDev &c, double x, double y, double z) {
+  Img m;
+  const double r2 = x * x + y * y + z * z, r = sqrt(r2);
+  if (r < c.rmin) {
+    m.inf = true;
+    m.X = m.Y = m.Z = 0.0;
+    m.s = c.c0 * (c.gamma - 0.5 * c.dbar) / c.a;
+    return m;
+  }
+  m.inf = false;
+  const double f = c.a2 / r2;
+  m.X = f * x;
+  m.Y = f * y;
+  m.Z = f * z;
+  const double rK = c.a2 / r;
+  m.s = c.c0 / c.a * (c.gamma * rK + c.dbar * (c.Rtau - rK) * 0.5);
+  return m;
+}
+
+__device__ __forceinline__ double img_pot(const Img &m, double x, double y, double z) {
+  if (m.inf) return m.s;
+  const double dx = x - m.X, dy = y - m.Y, dz = z - m.Z;
+  return m.s * rinv64(dx * dx + dy * dy + dz * dz);
+}
+
+// g(x, x) of a unit charge: its own image, regular at r = 0 (as in the packing kernel).
+__device__ __forceinline__ double self_g(const PlanDev &c, double x, double y, double z) {
+  const double r = sqrt(x * x + y * y + z * z);
+  return c.c0 / c.a * (c.gamma * c.a2 + 0.5 * c.dbar * (c.Rtau * r - c.a2)) / ((c.a - r) * (c.a + r));
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = DB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Stage 1: Kelvin row/column sums (blocks [0, nA)), check-field changes (next nB blocks),
+// surface-row changes (last nD blocks).  grid.y = request.
+__global__ __launch_bounds__(DB) void k_de_pairs(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
+                                                 DeReq one, int nA, int nB) {
+  __shared__ double red[DB];
+  const DeReq r = reqs ? reqs[blockIdx.y] : one;
+  const SysDev &S = systems[r.sys];
+  const PlanDev &c = S.pl;
+  const double x0 = S.x[r.k], y0 = S.y[r.k], z0 = S.z[r.k], qk = S.q[r.k];
+  const double x1 = r.x, y1 = r.y, z1 = r.z;
+  const int blk = blockIdx.x;
+  if (blk < nA) {
+    const Img ik0 = image_of(c, x0, y0, z0), ik1 = image_of(c, x1, y1, z1);
+    const int64_t j = (int64_t)blk * DB + threadIdx.x;
+    double v = 0.0;
+    if (j < S.n && j != r.k) {
+      const double xj = S.x[j], yj = S.y[j], zj = S.z[j];
+      const Img ij = image_of(c, xj, yj, zj);
+      // row: ion k at its new and old place in the field of j's image; column: j in the field
+      // of k's new and old image
+      v = S.q[j] * ((img_pot(ij, x1, y1, z1) - img_pot(ij, x0, y0, z0)) +
+                    (img_pot(ik1, xj, yj, zj) - img_pot(ik0, xj, yj, zj)));
+    }
+    const double b = block_sum(v, red);
+    if (threadIdx.x == 0) S.partA[blk] = b;
+    return;
+  }
+  if (blk < nA + nB) {
+    const int m = (blk - nA) * DB + threadIdx.x;
+    if (m < S.M) {
+      const double4 ck = c.chk64[m];
+      const double dx1 = ck.x - x1, dy1 = ck.y - y1, dz1 = ck.z - z1;
+      const double dx0 = ck.x - x0, dy0 = ck.y - y0, dz0 = ck.z - z0;
+      const double g1 = c.c0 * rinv64(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
+      const double g0 = c.c0 * rinv64(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+      const double r1 = sqrt(x1 * x1 + y1 * y1 + z1 * z1) / c.a, r0 = sqrt(x0 * x0 + y0 * y0 + z0 * z0) / c.a;
+      S.dc[m] = qk * (g1 - g0);
+      S.dc[S.M + m] = qk * (r1 * g1 - r0 * g0);
+    }
+    return;
+  }
+  const int s = (blk - nA - nB) * DB + threadIdx.x;
+  if (s < S.P) {
+    const double4 yv = c.nodes64[s];
+    const double dx1 = x1 - yv.x, dy1 = y1 - yv.y, dz1 = z1 - yv.z;
+    const double dx0 = x0 - yv.x, dy0 = y0 - yv.y, dz0 = z0 - yv.z;
+    const double i1 = rinv64(dx1 * dx1 + dy1 * dy1 + dz1 * dz1), i0 = rinv64(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+    const double t1 = (dx1 * yv.x + dy1 * yv.y + dz1 * yv.z) * i1 * i1 * i1;
+    const double t0 = (dx0 * yv.x + dy0 * yv.y + dz0 * yv.z) * i0 * i0 * i0;
+    S.dw[s] = qk * (i1 - i0);
+    S.dw[S.P + s] = qk * (t1 - t0);
+  }
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Stage 2: alpha'' = pinv du, beta'' = pinv dv; one wave per coefficient row.
+__global__ __launch_bounds__(256) void k_de_fit1(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
+                                                 DeReq one) {
+  const DeReq r = reqs ? reqs[blockIdx.y] : one;
+  const SysDev &S = systems[r.sys];
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= S.K) return;
+  const double *pr = S.pinv64 + (size_t)row * S.M;
+  double a = 0.0, b = 0.0;
+  for (int m = lane; m < S.M; m += 64) {
+    a = fma(pr[m], S.dc[m], a);
+    b = fma(pr[m], S.dc[S.M + m], b);
+  }
+  a = wave_sum64(a);
+  b = wave_sum64(b);
+  if (lane == 0) {
+    S.ab[row] = a;
+    S.ab[S.K + row] = b;
+  }
+}
+
+// Stage 3: ds = (Lhat (n . h), -Lhat h), h = f . alpha'' + g . beta''; per node also the
+// energy terms dw . s + (w + dw) . ds.
+__global__ __launch_bounds__(256) void k_de_fit2(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
+                                                 DeReq one) {
+  const DeReq r = reqs ? reqs[blockIdx.y] : one;
+  const SysDev &S = systems[r.sys];
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (s >= S.P) return;
+  const double *lr = S.lhat64 + (size_t)s * S.K;
+  const double *fg = S.pl.fg;
+  double sq = 0.0, sd = 0.0;
+  for (int k = lane; k < S.K; k += 64) {
+    const double h = fg[k] * S.ab[k] + fg[S.K + k] * S.ab[S.K + k];
+    sq = fma(lr[k] * (double)S.nidx[k], h, sq);
+    sd = fma(lr[k], h, sd);
+  }
+  sq = wave_sum64(sq);
+  sd = wave_sum64(sd);
+  if (lane == 0) {
+    const double dq = sq, dd = -sd;
+    S.ds[s] = dq;
+    S.ds[S.P + s] = dd;
+    const double dwq = S.dw[s], dwd = S.dw[S.P + s];
+    S.partE[s] = dwq * S.s[s] + dwd * S.s[S.P + s] + (S.w[s] + dwq) * dq + (S.w[S.P + s] + dwd) * dd;
+  }
+}
+
+// Stage 4 (one block per request): dE in a fixed order; with commit, apply the move.
+__global__ __launch_bounds__(DB) void k_de_final(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
+                                                 DeReq one, int nA) {
+  __shared__ double red[DB];
+  const DeReq r = reqs ? reqs[blockIdx.x] : one;
+  const SysDev &S = systems[r.sys];
+  const PlanDev &c = S.pl;
+  const double x0 = S.x[r.k], y0 = S.y[r.k], z0 = S.z[r.k], qk = S.q[r.k];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nA; i += DB) a += S.partA[i];
+  double e = 0.0;
+  for (int i = threadIdx.x; i < S.P; i += DB) e += S.partE[i];
+  const double sa = block_sum(a, red);
+  const double se = block_sum(e, red);
+  const double dself = self_g(c, r.x, r.y, r.z) - self_g(c, x0, y0, z0);
+  const double dE = 0.5 * (qk * sa + qk * qk * dself) + 0.5 * se;
+  if (threadIdx.x == 0 && r.dE) *r.dE = dE;
+  if (r.commit) {
+    __syncthreads();  // every thread has read the old position
+    for (int i = threadIdx.x; i < 2 * S.P; i += DB) {
+      S.s[i] += S.ds[i];
+      S.w[i] += S.dw[i];
+    }
+    if (threadIdx.x == 0) {
+      S.x[r.k] = r.x;
+      S.y[r.k] = r.y;
+      S.z[r.k] = r.z;
+      *S.E += dE;
+    }
+  }
+}
+
+// w = sum_i q_i S(x_i) over the nodes: one block per node, fixed order.
+__global__ __launch_bounds__(DB) void k_sys_w(SysDev *__restrict__ sd) {
+  __shared__ double red[DB];
+  const SysDev &S = *sd;
+  const int s = blockIdx.x;
+  const double4 yv = S.pl.nodes64[s];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < S.n; i += DB) {
+    const double dx = S.x[i] - yv.x, dy = S.y[i] - yv.y, dz = S.z[i] - yv.z;
+    const double ir = rinv64(dx * dx + dy * dy + dz * dz);
+    a += S.q[i] * ir;
+    b += S.q[i] * (dx * yv.x + dy * yv.y + dz * yv.z) * ir * ir * ir;
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    S.w[s] = a;
+    S.w[S.P + s] = b;
+  }
+}
+
+// s from the full evaluation's strengths (double2 per node) into the Q', D' layout.
+__global__ void k_sys_s(int P, const double2 *__restrict__ qd, double *__restrict__ s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  s[i] = qd[i].x;
+  s[P + i] = qd[i].y;
+}
+
+}  // namespace
+}  // namespace hsma
+
+using namespace hsma;
+
+static void system_free(hsma_system_s *sys) {
+  if (!sys) return;
+  SysDev &h = sys->h;
+  double *bufs[] = {h.x, h.y, h.z, h.q, h.s, h.w, h.E, h.dc, h.ab, h.ds, h.dw, h.partA, h.partE};
+  for (double *b : bufs) (void)hipFree(b);
+  (void)hipFree(sys->d);
+  (void)hipFree(sys->ws);
+  if (sys->g64) group_free(sys->g64);
+  delete sys;
+}
+
+extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
+                                          const double *q, hipStream_t st, hsma_system_t *out) {
+  if (!pl || !out || N < 1 || N > ((int64_t)1 << 31) - 1 || !x || !y || !z || !q) return HSMA_EINVAL;
+  *out = nullptr;
+  int dev = -1;
+  HSMA_HIP(hipGetDevice(&dev));
+  if (dev != pl->device) return HSMA_ESTATE;
+  hsma_system_s *sys = new hsma_system_s();
+  memset(sys, 0, sizeof(*sys));
+  sys->plan = pl;
+  sys->n = N;
+  sys->device = dev;
+  const Geometry *g = pl->geo;
+  const int K = g->K, M = g->M, P = g->P;
+  SysDev &h = sys->h;
+  h.pl = pl->host;
+  h.pinv64 = g->pinv64;
+  h.lhat64 = g->lhat64;
+  h.nidx = g->nidx;
+  h.K = K;
+  h.M = M;
+  h.P = P;
+  h.n = N;
+  hsma_status rc = group_build(1, &pl, 1, &sys->g64);
+  if (rc != HSMA_OK) {
+    system_free(sys);
+    return rc;
+  }
+  sys->g64->pair_prec = HSMA_PAIR_FP64;  // full evaluations of the state in FP64
+  const size_t nb = sizeof(double) * (size_t)N;
+  const int nA = (int)((N + DB - 1) / DB);
+  double *phi = nullptr;
+  Layout L = layout(sys->g64, 1, N, N);
+  sys->ws_bytes = L.total;
+#define HSMA_TRY(call)          \
+  do {                          \
+    if ((call) != hipSuccess) { \
+      rc = HSMA_EDEVICE;        \
+      goto fail;                \
+    }                           \
+  } while (0)
+  HSMA_TRY(hipMalloc(&h.x, nb));
+  HSMA_TRY(hipMalloc(&h.y, nb));
+  HSMA_TRY(hipMalloc(&h.z, nb));
+  HSMA_TRY(hipMalloc(&h.q, nb));
+  HSMA_TRY(hipMalloc(&h.s, sizeof(double) * 2 * P));
+  HSMA_TRY(hipMalloc(&h.w, sizeof(double) * 2 * P));
+  HSMA_TRY(hipMalloc(&h.E, sizeof(double)));
+  HSMA_TRY(hipMalloc(&h.dc, sizeof(double) * 2 * M));
+  HSMA_TRY(hipMalloc(&h.ab, sizeof(double) * 2 * K));
+  HSMA_TRY(hipMalloc(&h.ds, sizeof(double) * 2 * P));
+  HSMA_TRY(hipMalloc(&h.dw, sizeof(double) * 2 * P));
+  HSMA_TRY(hipMalloc(&h.partA, sizeof(double) * nA));
+  HSMA_TRY(hipMalloc(&h.partE, sizeof(double) * P));
+  HSMA_TRY(hipMalloc(&sys->d, sizeof(SysDev)));
+  HSMA_TRY(hipMalloc(&sys->ws, sys->ws_bytes));
+  HSMA_TRY(hipMemcpyAsync(h.x, x, nb, hipMemcpyDeviceToDevice, st));
+  HSMA_TRY(hipMemcpyAsync(h.y, y, nb, hipMemcpyDeviceToDevice, st));
+  HSMA_TRY(hipMemcpyAsync(h.z, z, nb, hipMemcpyDeviceToDevice, st));
+  HSMA_TRY(hipMemcpyAsync(h.q, q, nb, hipMemcpyDeviceToDevice, st));
+  HSMA_TRY(hipMemcpyAsync(sys->d, &h, sizeof(SysDev), hipMemcpyHostToDevice, st));
+  phi = (double *)((char *)sys->ws + L.phi);
+  rc = run_batched(sys->g64, 1, nullptr, nullptr, N, N, h.x, h.y, h.z, h.q, phi, h.E, sys->ws, sys->ws_bytes, st);
+  if (rc != HSMA_OK) goto fail;
+  k_sys_s<<<(P + 255) / 256, 256, 0, st>>>(P, (const double2 *)((char *)sys->ws + L.qd), h.s);
+  k_sys_w<<<P, DB, 0, st>>>(sys->d);
+  HSMA_TRY(hipGetLastError());
+  HSMA_TRY(hipStreamSynchronize(st));
+  {
+    int f = 0;
+    HSMA_TRY(hipMemcpy(&f, sys->g64->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (f) {
+      rc = (f & 2) ? HSMA_EINVAL : HSMA_EDOMAIN;
+      goto fail;
+    }
+  }
+  *out = sys;
+  return HSMA_OK;
+fail:
+#undef HSMA_TRY
+  (void)hipStreamSynchronize(st);
+  system_free(sys);
+  return rc;
+}
+
+static hsma_status delta(hsma_system_t sys, int64_t k, double xk, double yk, double zk, double *dE, int commit,
+                         hipStream_t st) {
+  if (!sys || k < 0 || k >= sys->n) return HSMA_EINVAL;
+  if (!(isfinite(xk) && isfinite(yk) && isfinite(zk))) return HSMA_EINVAL;
+  if (!(sqrt(xk * xk + yk * yk + zk * zk) < sys->h.pl.a)) return HSMA_EINVAL;
+  int dev = -1;
+  HSMA_HIP(hipGetDevice(&dev));
+  if (dev != sys->device) return HSMA_ESTATE;
+  DeReq r;
+  r.sys = 0;
+  r.commit = commit;
+  r.k = k;
+  r.x = xk;
+  r.y = yk;
+  r.z = zk;
+  r.dE = dE;
+  const int nA = (int)((sys->n + DB - 1) / DB), nB = (sys->h.M + DB - 1) / DB, nD = (sys->h.P + DB - 1) / DB;
+  k_de_pairs<<<dim3(nA + nB + nD, 1), DB, 0, st>>>(sys->d, nullptr, r, nA, nB);
+  k_de_fit1<<<dim3((sys->h.K + 3) / 4, 1), 256, 0, st>>>(sys->d, nullptr, r);
+  k_de_fit2<<<dim3((sys->h.P + 3) / 4, 1), 256, 0, st>>>(sys->d, nullptr, r);
+  k_de_final<<<1, DB, 0, st>>>(sys->d, nullptr, r, nA);
+  HSMA_HIP(hipGetLastError());
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_delta_energy(hsma_system_t sys, int64_t k, double xk, double yk, double zk, double *dE,
+                                         hipStream_t st) {
+  if (!dE) return HSMA_EINVAL;
+  return delta(sys, k, xk, yk, zk, dE, 0, st);
+}
+
+extern "C" hsma_status hsma_system_commit(hsma_system_t sys, int64_t k, double xk, double yk, double zk,
+                                          hipStream_t st) {
+  return delta(sys, k, xk, yk, zk, nullptr, 1, st);
+}
+
+extern "C" hsma_status hsma_system_energy(hsma_system_t sys, double *E, hipStream_t st) {
+  if (!sys || !E) return HSMA_EINVAL;
+  HSMA_HIP(hipMemcpyAsync(E, sys->h.E, sizeof(double), hipMemcpyDeviceToDevice, st));
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_system_positions(hsma_system_t sys, double *x, double *y, double *z, hipStream_t st) {
+  if (!sys || !x || !y || !z) return HSMA_EINVAL;
+  const size_t nb = sizeof(double) * (size_t)sys->n;
+  HSMA_HIP(hipMemcpyAsync(x, sys->h.x, nb, hipMemcpyDeviceToDevice, st));
+  HSMA_HIP(hipMemcpyAsync(y, sys->h.y, nb, hipMemcpyDeviceToDevice, st));
+  HSMA_HIP(hipMemcpyAsync(z, sys->h.z, nb, hipMemcpyDeviceToDevice, st));
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_system_destroy(hsma_system_t sys) {
+  if (!sys) return HSMA_EINVAL;
+  (void)hipDeviceSynchronize();
+  system_free(sys);
+  return HSMA_OK;
+}
