@@ -211,6 +211,65 @@ hsma_status hsma_system_commit(hsma_system_t sys, int64_t k, double xk, double y
 hsma_status hsma_system_energy(hsma_system_t sys, double *E, hipStream_t stream);
 hsma_status hsma_system_positions(hsma_system_t sys, double *x, double *y, double *z, hipStream_t stream);
 hsma_status hsma_system_destroy(hsma_system_t sys);
+/* A fresh FP64 full evaluation of the system's current energy (E [device]), with a
+ * caller workspace of ws_bytes >= hsma_system_workspace_bytes(sys); the state is unchanged. */
+size_t hsma_system_workspace_bytes(hsma_system_t sys);
+hsma_status hsma_system_full_energy(hsma_system_t sys, double *E, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Request server over resident systems.
+ *
+ * Systems are admitted against a device-memory budget (hsma_server_add_system returns
+ * HSMA_EBUSY when the system's resident bytes would exceed it; 0 = half the free memory
+ * at creation).  Requests -- a single-ion move (energy change, optionally committed) or a
+ * fresh FP64 full energy -- are queued by hsma_server_submit (thread safe) and served by a
+ * scheduler thread with continuous batching: whenever one of delta_slots batch slots is
+ * free, it launches every waiting move whose system is idle, in arrival order (each system
+ * sees its requests in order), up to max_batch; full energies use energy_slots streams of
+ * their own.  New batches start while earlier ones run, and a request's result does not
+ * depend on the batch it lands in.  Results, with submit/start/done times in seconds since
+ * the server's creation, are collected with hsma_server_poll.  Requests that name an
+ * unknown system, an ion out of range or a position outside the cavity complete at once
+ * with status HSMA_EINVAL.  hsma_server_run_load submits reqs[i] at arrival[i] seconds
+ * (open-loop load) and returns when all are done, with times relative to its start. */
+typedef struct hsma_server_s *hsma_server_t;
+enum { HSMA_REQ_DELTA = 0, HSMA_REQ_ENERGY = 1 };
+typedef struct {
+  int type;      /* HSMA_REQ_DELTA or HSMA_REQ_ENERGY */
+  int sys;       /* system id from hsma_server_add_system */
+  int commit;    /* HSMA_REQ_DELTA: apply the move after evaluating it */
+  int64_t k;     /* HSMA_REQ_DELTA: ion index */
+  double x, y, z;/* HSMA_REQ_DELTA: new position */
+  uint64_t tag;  /* caller's identifier, returned with the result */
+} hsma_request;
+typedef struct {
+  uint64_t tag;
+  int type, sys;
+  int status;    /* hsma_status */
+  double value;  /* energy change or energy */
+  double t_submit, t_start, t_done;
+} hsma_result;
+typedef struct {
+  size_t memory_budget; /* bytes; 0 = half of the free device memory */
+  int max_systems, max_batch, delta_slots, energy_slots;
+} hsma_server_opts;
+typedef struct {
+  size_t memory_used, memory_budget;
+  int64_t pending;
+  uint64_t completed, batches, batched_requests;
+  int systems;
+  double now;
+} hsma_server_info;
+hsma_server_opts hsma_server_opts_default(void);
+hsma_status hsma_server_create(const hsma_server_opts *opts /* [host], NULL = defaults */, hsma_server_t *out);
+hsma_status hsma_server_destroy(hsma_server_t server);
+hsma_status hsma_server_add_system(hsma_server_t server, hsma_plan_t plan, int64_t N, const double *x,
+                                   const double *y, const double *z, const double *q /* [device] */, int *id);
+hsma_status hsma_server_remove_system(hsma_server_t server, int id);
+hsma_status hsma_server_submit(hsma_server_t server, const hsma_request *reqs /* [host] */, int n);
+int hsma_server_poll(hsma_server_t server, hsma_result *out /* [host] */, int max);
+hsma_status hsma_server_stats(hsma_server_t server, hsma_server_info *info /* [host] */);
+hsma_status hsma_server_run_load(hsma_server_t server, const hsma_request *reqs, const double *arrival, int n,
+                                 hsma_result *out /* all [host] */);
 
 /* Synchronise the stream and report a device-side error raised since the last check
  * (then clear it): HSMA_EDOMAIN for an ion outside the cavity or a non-finite input,

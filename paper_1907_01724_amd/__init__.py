@@ -40,6 +40,30 @@ class PlanInfo(C.Structure):
                 ("M", C.c_int), ("F1", C.c_int), ("F2", C.c_int), ("pair_prec", C.c_int), ("device", C.c_int)]
 
 
+class Request(C.Structure):
+    _fields_ = [("type", C.c_int), ("sys", C.c_int), ("commit", C.c_int), ("k", C.c_int64), ("x", C.c_double),
+                ("y", C.c_double), ("z", C.c_double), ("tag", C.c_uint64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("type", C.c_int), ("sys", C.c_int), ("status", C.c_int), ("value", C.c_double),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("memory_budget", C.c_size_t), ("max_systems", C.c_int), ("max_batch", C.c_int),
+                ("delta_slots", C.c_int), ("energy_slots", C.c_int)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("memory_used", C.c_size_t), ("memory_budget", C.c_size_t), ("pending", C.c_int64),
+                ("completed", C.c_uint64), ("batches", C.c_uint64), ("batched_requests", C.c_uint64),
+                ("systems", C.c_int), ("now", C.c_double)]
+
+
+REQ_DELTA = 0
+REQ_ENERGY = 1
+
 _lib = None
 _VP = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -87,11 +111,26 @@ def load_library(path: str | None = None):
     L.hsma_system_energy.argtypes = [_VP, _VP, _VP]
     L.hsma_system_positions.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.hsma_system_destroy.argtypes = [_VP]
+    L.hsma_system_workspace_bytes.argtypes = [_VP]
+    L.hsma_system_workspace_bytes.restype = C.c_size_t
+    L.hsma_system_full_energy.argtypes = [_VP, _VP, _VP, C.c_size_t, _VP]
+    L.hsma_server_opts_default.restype = ServerOpts
+    L.hsma_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(_VP)]
+    L.hsma_server_destroy.argtypes = [_VP]
+    L.hsma_server_add_system.argtypes = [_VP, _VP, C.c_int64] + [_VP] * 4 + [C.POINTER(C.c_int)]
+    L.hsma_server_remove_system.argtypes = [_VP, C.c_int]
+    L.hsma_server_submit.argtypes = [_VP, C.POINTER(Request), C.c_int]
+    L.hsma_server_poll.argtypes = [_VP, C.POINTER(Result), C.c_int]
+    L.hsma_server_poll.restype = C.c_int
+    L.hsma_server_stats.argtypes = [_VP, C.POINTER(ServerInfo)]
+    L.hsma_server_run_load.argtypes = [_VP, C.POINTER(Request), C.POINTER(C.c_double), C.c_int, C.POINTER(Result)]
     for name in ("hsma_plan", "hsma_plan_ex", "hsma_plan_destroy", "hsma_plan_get_info", "hsma_potential",
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_system_create", "hsma_delta_energy",
-                 "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy"):
+                 "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
+                 "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
+                 "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -372,6 +411,18 @@ class System:
                "hsma_system_energy")
         return out
 
+    def full_energy(self, out=None, stream=None):
+        """A fresh FP64 full evaluation of the current energy (state unchanged)."""
+        torch = _torch()
+        L = load_library()
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        ws = Workspace(int(L.hsma_system_workspace_bytes(self._h)), self.device)
+        _check(L.hsma_system_full_energy(self._h, _dev_ptr(out, "E"), ws.ptr, ws.nbytes, _stream_ptr(stream)),
+               "hsma_system_full_energy")
+        torch.cuda.synchronize()
+        return out
+
     def positions(self, stream=None):
         torch = _torch()
         xyz = [torch.empty(self.n, dtype=torch.float64, device=self.device) for _ in range(3)]
@@ -382,6 +433,78 @@ class System:
     def close(self):
         if self._h:
             load_library().hsma_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def requests_array(reqs) -> "C.Array":
+    """reqs: iterable of (type, sys, commit, k, x, y, z) tuples -> ctypes array of Request."""
+    reqs = list(reqs)
+    arr = (Request * max(len(reqs), 1))()
+    for i, r in enumerate(reqs):
+        t, sys_id, commit, k, x, y, z = r
+        arr[i] = Request(int(t), int(sys_id), int(commit), int(k), float(x), float(y), float(z), i)
+    return arr
+
+
+class Server:
+    """Continuous-batching request server over resident systems (see hsma_server_* in hsma.h)."""
+
+    def __init__(self, memory_budget: int = 0, max_systems: int = 1024, max_batch: int = 256, delta_slots: int = 3,
+                 energy_slots: int = 2):
+        L = load_library()
+        o = ServerOpts(int(memory_budget), int(max_systems), int(max_batch), int(delta_slots), int(energy_slots))
+        h = _VP()
+        _check(L.hsma_server_create(C.byref(o), C.byref(h)), "hsma_server_create")
+        self._h = h
+        self._plans = []
+
+    def add_system(self, plan: Plan, x, y, z, q) -> int:
+        n = x.numel()
+        i = C.c_int(-1)
+        _check(load_library().hsma_server_add_system(self._h, plan.handle, n, _dev_ptr(x, "x", n), _dev_ptr(y, "y", n),
+                                                     _dev_ptr(z, "z", n), _dev_ptr(q, "q", n), C.byref(i)),
+               "hsma_server_add_system")
+        self._plans.append(plan)  # plans must outlive the server's systems
+        return i.value
+
+    def remove_system(self, sys_id: int):
+        _check(load_library().hsma_server_remove_system(self._h, int(sys_id)), "hsma_server_remove_system")
+
+    def submit(self, reqs):
+        n = len(reqs)
+        if n == 0:
+            return
+        arr = reqs if isinstance(reqs, C.Array) else requests_array(reqs)
+        _check(load_library().hsma_server_submit(self._h, arr, n), "hsma_server_submit")
+
+    def poll(self, max_results: int = 4096):
+        buf = (Result * max_results)()
+        n = load_library().hsma_server_poll(self._h, buf, max_results)
+        return [buf[i] for i in range(n)]
+
+    def stats(self) -> dict:
+        inf = ServerInfo()
+        _check(load_library().hsma_server_stats(self._h, C.byref(inf)), "hsma_server_stats")
+        return {k: getattr(inf, k) for k, _ in ServerInfo._fields_}
+
+    def run_load(self, reqs, arrival):
+        """Open-loop load: request i submitted at arrival[i] s; returns the results in order."""
+        arr = requests_array(reqs)
+        n = len(reqs)
+        times = (C.c_double * max(n, 1))(*[float(t) for t in arrival])
+        out = (Result * max(n, 1))()
+        _check(load_library().hsma_server_run_load(self._h, arr, times, n, out), "hsma_server_run_load")
+        return [out[i] for i in range(n)]
+
+    def close(self):
+        if self._h:
+            load_library().hsma_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

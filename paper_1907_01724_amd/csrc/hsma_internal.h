@@ -51,6 +51,56 @@ struct PlanDev {
   const double4 *nodes64;
 };
 
+// Device descriptor of one resident system (single-ion-move state).
+struct SysDev {
+  PlanDev pl;
+  const double *pinv64, *lhat64;
+  const int *nidx;
+  int K, M, P;
+  int64_t n;
+  double *x, *y, *z, *q;
+  double *s;      // 2P: Q' then D' (the strengths the evaluation kernel uses)
+  double *w;      // 2P: sum_i q_i S(x_i)
+  double *E;      // 1: current energy
+  double *dc;     // 2M scratch: check-field change (u then v)
+  double *ab;     // 2K scratch
+  double *ds;     // 2P scratch
+  double *dw;     // 2P scratch
+  double *partA;  // ceil(n / 256) scratch
+  double *partE;  // P scratch
+};
+
+// One single-ion-move request.
+struct DeReq {
+  int sys;      // index into the descriptor array
+  int commit;   // apply the move after evaluating it
+  int64_t k;
+  double x, y, z;
+  double *dE;   // [device] output, or nullptr
+};
+
+}  // namespace hsma
+
+struct hsma_system_s {
+  hsma_plan_t plan;
+  hsma_group_s *g64;     // FP64 group over the plan (full evaluations)
+  hsma::SysDev h;        // host copy of the descriptor
+  hsma::SysDev *d;       // device copy
+  int64_t n;
+  void *ws;              // workspace of the initial full evaluation (freed after creation)
+  size_t ws_bytes;
+  size_t footprint;      // resident device bytes
+  int device;
+};
+
+namespace hsma {
+// Single-ion-move pipeline for nreq requests (reqs on the device, or `one` when nreq = 1 and
+// reqs is null); max_* bound the systems the requests refer to.  Each system may have at
+// most one request in a batch.
+hsma_status launch_delta(const SysDev *systems, const DeReq *reqs, DeReq one, int nreq, int64_t max_n, int max_M,
+                         int max_P, int max_K, hipStream_t st);
+hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t ws_bytes, hipStream_t st);
+size_t system_workspace_bytes(const hsma_system_s *sys);
 }  // namespace hsma
 
 // Launch-shape parameters of the pair kernels (see hsma_group_tune).

@@ -1,0 +1,519 @@
+// Request server over resident systems: continuous batching of single-ion-move energy
+// changes and full-energy evaluations, admission of systems by device memory, per-request
+// timestamps.  Host code only; the device work is the batched single-ion-move pipeline
+// (launch_delta) and the FP64 full evaluation of a system.
+//
+// Scheduling: a host thread keeps a FIFO of pending requests.  Whenever a batch slot is free
+// it takes, in arrival order, every pending single-ion-move request whose system has no work
+// on the device and no earlier request still waiting (so each system sees its requests in
+// order), up to max_batch, and launches them as one batch on that slot's stream.  Full-energy
+// requests take energy slots (their own streams and workspaces).  Several slots let new
+// batches start while earlier ones are still running, so work that arrives while the device
+// is busy overlaps with it.  A request's result is independent of the batch it lands in:
+// every request of a batch runs on its own grid row with its system's own reduction order.
+#include <string.h>
+
+#include <atomic>
+#include <cmath>
+#include <chrono>
+#include <deque>
+#include <thread>
+#include <vector>
+
+#include "hsma_internal.h"
+
+using namespace hsma;
+
+namespace {
+
+struct Pending {
+  hsma_request r;
+  double t_submit;
+};
+
+struct DeltaSlot {
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  DeReq *h_reqs = nullptr;  // pinned
+  DeReq *d_reqs = nullptr;
+  double *d_dE = nullptr;
+  double *h_dE = nullptr;   // pinned
+  std::vector<Pending> reqs;
+  double t_start = 0.0;
+  bool busy = false;
+};
+
+struct EnergySlot {
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  double *d_E = nullptr;
+  double *h_E = nullptr;  // pinned
+  Pending req;
+  double t_start = 0.0;
+  bool busy = false;
+};
+
+}  // namespace
+
+struct hsma_server_s {
+  int device = 0;
+  hsma_server_opts opts;
+  std::mutex mu;
+  std::deque<Pending> pending;
+  std::vector<hsma_result> done;
+  std::vector<hsma_system_s *> systems;  // by id; nullptr once removed
+  std::vector<int> busy;                 // 1 while the system has work on the device
+  SysDev *d_sys = nullptr;               // descriptors by id
+  size_t used = 0, budget = 0;
+  std::vector<DeltaSlot> dslots;
+  std::vector<EnergySlot> eslots;
+  std::thread th;
+  std::atomic<bool> stop{false};
+  std::chrono::steady_clock::time_point t0;
+  hipStream_t admin = nullptr;  // system creation
+  // statistics
+  uint64_t n_done = 0, n_batches = 0, n_batched_reqs = 0;
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+void finish(hsma_server_s *S, const Pending &p, int status, double value, double t_start, double t_done) {
+  hsma_result r;
+  r.tag = p.r.tag;
+  r.type = p.r.type;
+  r.sys = p.r.sys;
+  r.status = status;
+  r.value = value;
+  r.t_submit = p.t_submit;
+  r.t_start = t_start;
+  r.t_done = t_done;
+  S->done.push_back(r);
+  S->n_done++;
+}
+
+bool valid_request(hsma_server_s *S, const hsma_request &r) {
+  if (r.sys < 0 || r.sys >= (int)S->systems.size() || !S->systems[r.sys]) return false;
+  if (r.type == HSMA_REQ_ENERGY) return true;
+  if (r.type != HSMA_REQ_DELTA) return false;
+  const hsma_system_s *sys = S->systems[r.sys];
+  if (r.k < 0 || r.k >= sys->n) return false;
+  if (!(std::isfinite(r.x) && std::isfinite(r.y) && std::isfinite(r.z))) return false;
+  return std::sqrt(r.x * r.x + r.y * r.y + r.z * r.z) < sys->h.pl.a;
+}
+
+// One pass of the scheduler; returns true when anything happened.  Called with S->mu held.
+bool schedule_once(hsma_server_s *S) {
+  bool did = false;
+  // completions
+  for (DeltaSlot &d : S->dslots) {
+    if (!d.busy || hipEventQuery(d.ev) != hipSuccess) continue;
+    const double t = S->now();
+    for (size_t i = 0; i < d.reqs.size(); ++i) {
+      finish(S, d.reqs[i], HSMA_OK, d.h_dE[i], d.t_start, t);
+      S->busy[d.reqs[i].r.sys] = 0;
+    }
+    d.reqs.clear();
+    d.busy = false;
+    did = true;
+  }
+  for (EnergySlot &e : S->eslots) {
+    if (!e.busy || hipEventQuery(e.ev) != hipSuccess) continue;
+    finish(S, e.req, HSMA_OK, *e.h_E, e.t_start, S->now());
+    S->busy[e.req.r.sys] = 0;
+    e.busy = false;
+    did = true;
+  }
+  if (S->pending.empty()) return did;
+  // a scan in arrival order; a system with an earlier request left waiting is blocked
+  std::vector<char> blocked(S->systems.size(), 0);
+  DeltaSlot *ds = nullptr;
+  for (DeltaSlot &d : S->dslots)
+    if (!d.busy) {
+      ds = &d;
+      break;
+    }
+  int64_t max_n = 0;
+  int max_M = 0, max_P = 0, max_K = 0;
+  for (auto it = S->pending.begin(); it != S->pending.end();) {
+    const hsma_request &r = it->r;
+    if (blocked[r.sys] || S->busy[r.sys]) {
+      blocked[r.sys] = 1;
+      ++it;
+      continue;
+    }
+    if (r.type == HSMA_REQ_ENERGY) {
+      EnergySlot *es = nullptr;
+      for (EnergySlot &e : S->eslots)
+        if (!e.busy) {
+          es = &e;
+          break;
+        }
+      if (!es) {
+        blocked[r.sys] = 1;
+        ++it;
+        continue;
+      }
+      hsma_system_s *sys = S->systems[r.sys];
+      const size_t need = system_workspace_bytes(sys);
+      bool ok = true;
+      if (es->ws_bytes < need) {
+        (void)hipFree(es->ws);
+        S->used -= es->ws_bytes;
+        es->ws = nullptr;
+        es->ws_bytes = 0;
+        if (hipMalloc(&es->ws, need) == hipSuccess) {
+          es->ws_bytes = need;
+          S->used += need;
+        } else {
+          ok = false;
+        }
+      }
+      const Pending p = *it;
+      it = S->pending.erase(it);
+      if (!ok) {
+        finish(S, p, HSMA_ENOMEM, 0.0, S->now(), S->now());
+        continue;
+      }
+      es->req = p;
+      es->t_start = S->now();
+      S->busy[p.r.sys] = 1;  // (r referred to the erased element)
+      blocked[p.r.sys] = 1;
+      hsma_status rc = system_full_energy(sys, es->d_E, es->ws, es->ws_bytes, es->st);
+      if (rc == HSMA_OK && hipMemcpyAsync(es->h_E, es->d_E, sizeof(double), hipMemcpyDeviceToHost, es->st) != hipSuccess)
+        rc = HSMA_EDEVICE;
+      if (rc == HSMA_OK && hipEventRecord(es->ev, es->st) != hipSuccess) rc = HSMA_EDEVICE;
+      if (rc != HSMA_OK) {
+        (void)hipStreamSynchronize(es->st);
+        S->busy[p.r.sys] = 0;
+        finish(S, p, rc, 0.0, es->t_start, S->now());
+        continue;
+      }
+      es->busy = true;
+      did = true;
+      continue;
+    }
+    // single-ion move
+    if (!ds || (int)ds->reqs.size() >= S->opts.max_batch) {
+      blocked[r.sys] = 1;
+      ++it;
+      continue;
+    }
+    const hsma_system_s *sys = S->systems[r.sys];
+    DeReq &q = ds->h_reqs[ds->reqs.size()];
+    q.sys = r.sys;
+    q.commit = r.commit ? 1 : 0;
+    q.k = r.k;
+    q.x = r.x;
+    q.y = r.y;
+    q.z = r.z;
+    q.dE = ds->d_dE + ds->reqs.size();
+    ds->reqs.push_back(*it);
+    if (sys->n > max_n) max_n = sys->n;
+    if (sys->h.M > max_M) max_M = sys->h.M;
+    if (sys->h.P > max_P) max_P = sys->h.P;
+    if (sys->h.K > max_K) max_K = sys->h.K;
+    S->busy[r.sys] = 1;
+    blocked[r.sys] = 1;
+    it = S->pending.erase(it);
+  }
+  if (ds && !ds->reqs.empty()) {
+    const int n = (int)ds->reqs.size();
+    ds->t_start = S->now();
+    hsma_status rc = HSMA_OK;
+    if (hipMemcpyAsync(ds->d_reqs, ds->h_reqs, sizeof(DeReq) * n, hipMemcpyHostToDevice, ds->st) != hipSuccess)
+      rc = HSMA_EDEVICE;
+    if (rc == HSMA_OK) rc = launch_delta(S->d_sys, ds->d_reqs, DeReq(), n, max_n, max_M, max_P, max_K, ds->st);
+    if (rc == HSMA_OK && hipMemcpyAsync(ds->h_dE, ds->d_dE, sizeof(double) * n, hipMemcpyDeviceToHost, ds->st) !=
+                             hipSuccess)
+      rc = HSMA_EDEVICE;
+    if (rc == HSMA_OK && hipEventRecord(ds->ev, ds->st) != hipSuccess) rc = HSMA_EDEVICE;
+    if (rc != HSMA_OK) {
+      (void)hipStreamSynchronize(ds->st);
+      for (const Pending &p : ds->reqs) {
+        S->busy[p.r.sys] = 0;
+        finish(S, p, rc, 0.0, ds->t_start, S->now());
+      }
+      ds->reqs.clear();
+    } else {
+      ds->busy = true;
+      S->n_batches++;
+      S->n_batched_reqs += n;
+    }
+    did = true;
+  }
+  return did;
+}
+
+void run_loop(hsma_server_s *S) {
+  (void)hipSetDevice(S->device);
+  while (!S->stop.load()) {
+    bool did;
+    bool idle;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      did = schedule_once(S);
+      idle = S->pending.empty();
+      if (idle)
+        for (const DeltaSlot &d : S->dslots) idle = idle && !d.busy;
+      if (idle)
+        for (const EnergySlot &e : S->eslots) idle = idle && !e.busy;
+    }
+    if (!did) std::this_thread::sleep_for(std::chrono::microseconds(idle ? 200 : 5));
+  }
+}
+
+void server_free(hsma_server_s *S) {
+  if (S->th.joinable()) {
+    S->stop.store(true);
+    S->th.join();
+  }
+  for (DeltaSlot &d : S->dslots) {
+    if (d.st) (void)hipStreamSynchronize(d.st);
+    (void)hipHostFree(d.h_reqs);
+    (void)hipHostFree(d.h_dE);
+    (void)hipFree(d.d_reqs);
+    (void)hipFree(d.d_dE);
+    if (d.ev) (void)hipEventDestroy(d.ev);
+    if (d.st) (void)hipStreamDestroy(d.st);
+  }
+  for (EnergySlot &e : S->eslots) {
+    if (e.st) (void)hipStreamSynchronize(e.st);
+    (void)hipFree(e.ws);
+    (void)hipFree(e.d_E);
+    (void)hipHostFree(e.h_E);
+    if (e.ev) (void)hipEventDestroy(e.ev);
+    if (e.st) (void)hipStreamDestroy(e.st);
+  }
+  for (hsma_system_s *s : S->systems)
+    if (s) hsma_system_destroy(s);
+  (void)hipFree(S->d_sys);
+  if (S->admin) (void)hipStreamDestroy(S->admin);
+  delete S;
+}
+
+// resident bytes of a system of N ions on a plan (the footprint hsma_system_create reports)
+size_t footprint_of(hsma_plan_t pl, int64_t N) {
+  const Geometry *g = pl->geo;
+  const size_t nb = sizeof(double) * (size_t)N;
+  const size_t nA = (size_t)((N + 255) / 256);
+  return 4 * nb + sizeof(double) * (6 * (size_t)g->P + 2 * (size_t)g->M + 2 * (size_t)g->K + 1 + nA + g->P) +
+         sizeof(SysDev);
+}
+
+}  // namespace
+
+extern "C" hsma_server_opts hsma_server_opts_default(void) {
+  hsma_server_opts o;
+  o.memory_budget = 0;
+  o.max_systems = 1024;
+  o.max_batch = 256;
+  o.delta_slots = 3;
+  o.energy_slots = 2;
+  return o;
+}
+
+extern "C" hsma_status hsma_server_create(const hsma_server_opts *opts, hsma_server_t *out) {
+  if (!out) return HSMA_EINVAL;
+  *out = nullptr;
+  hsma_server_opts o = opts ? *opts : hsma_server_opts_default();
+  if (o.max_systems < 1 || o.max_batch < 1 || o.max_batch > 65535 || o.delta_slots < 1 || o.energy_slots < 1)
+    return HSMA_EINVAL;
+  hsma_server_s *S = new hsma_server_s();
+  S->opts = o;
+  S->t0 = std::chrono::steady_clock::now();
+  hsma_status rc = HSMA_OK;
+  if (hipGetDevice(&S->device) != hipSuccess) rc = HSMA_EDEVICE;
+  size_t fre = 0, tot = 0;
+  if (rc == HSMA_OK && hipMemGetInfo(&fre, &tot) != hipSuccess) rc = HSMA_EDEVICE;
+  S->budget = o.memory_budget ? o.memory_budget : fre / 2;
+  if (rc == HSMA_OK && (hipMalloc(&S->d_sys, sizeof(SysDev) * o.max_systems) != hipSuccess ||
+                        hipStreamCreateWithFlags(&S->admin, hipStreamNonBlocking) != hipSuccess))
+    rc = HSMA_EDEVICE;
+  S->dslots.resize(o.delta_slots);
+  for (DeltaSlot &d : S->dslots) {
+    if (rc != HSMA_OK) break;
+    if (hipStreamCreateWithFlags(&d.st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&d.ev, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&d.h_reqs, sizeof(DeReq) * o.max_batch, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&d.h_dE, sizeof(double) * o.max_batch, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&d.d_reqs, sizeof(DeReq) * o.max_batch) != hipSuccess ||
+        hipMalloc(&d.d_dE, sizeof(double) * o.max_batch) != hipSuccess)
+      rc = HSMA_ENOMEM;
+  }
+  S->eslots.resize(o.energy_slots);
+  for (EnergySlot &e : S->eslots) {
+    if (rc != HSMA_OK) break;
+    if (hipStreamCreateWithFlags(&e.st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&e.d_E, sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&e.h_E, sizeof(double), hipHostMallocDefault) != hipSuccess)
+      rc = HSMA_ENOMEM;
+  }
+  if (rc != HSMA_OK) {
+    server_free(S);
+    return rc;
+  }
+  S->th = std::thread(run_loop, S);
+  *out = S;
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_server_destroy(hsma_server_t S) {
+  if (!S) return HSMA_EINVAL;
+  server_free(S);
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, int64_t N, const double *x,
+                                              const double *y, const double *z, const double *q, int *id) {
+  if (!S || !pl || !id || N < 1) return HSMA_EINVAL;
+  const size_t fp = footprint_of(pl, N);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if ((int)S->systems.size() >= S->opts.max_systems) {
+      // reuse a removed id if any
+      bool free_id = false;
+      for (hsma_system_s *s : S->systems) free_id = free_id || !s;
+      if (!free_id) return HSMA_EBUSY;
+    }
+    if (S->used + fp > S->budget) return HSMA_EBUSY;
+    S->used += fp;  // reserved while the system is built
+  }
+  hsma_system_t sys = nullptr;
+  hsma_status rc = hsma_system_create(pl, N, x, y, z, q, S->admin, &sys);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (rc != HSMA_OK) {
+    S->used -= fp;
+    return rc;
+  }
+  S->used += sys->footprint;
+  S->used -= fp;
+  int slot = -1;
+  for (size_t i = 0; i < S->systems.size(); ++i)
+    if (!S->systems[i]) {
+      slot = (int)i;
+      break;
+    }
+  if (slot < 0) {
+    slot = (int)S->systems.size();
+    S->systems.push_back(nullptr);
+    S->busy.push_back(0);
+  }
+  if (hipMemcpy(S->d_sys + slot, &sys->h, sizeof(SysDev), hipMemcpyHostToDevice) != hipSuccess) {
+    S->used -= sys->footprint;
+    hsma_system_destroy(sys);
+    return HSMA_EDEVICE;
+  }
+  S->systems[slot] = sys;
+  S->busy[slot] = 0;
+  *id = slot;
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_server_remove_system(hsma_server_t S, int id) {
+  if (!S) return HSMA_EINVAL;
+  for (;;) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (id < 0 || id >= (int)S->systems.size() || !S->systems[id]) return HSMA_EINVAL;
+      bool waiting = S->busy[id] != 0;
+      for (const Pending &p : S->pending) waiting = waiting || p.r.sys == id;
+      if (!waiting) {
+        hsma_system_s *sys = S->systems[id];
+        S->systems[id] = nullptr;
+        S->used -= sys->footprint;
+        hsma_system_destroy(sys);
+        return HSMA_OK;
+      }
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+}
+
+extern "C" hsma_status hsma_server_submit(hsma_server_t S, const hsma_request *reqs, int n) {
+  if (!S || (n > 0 && !reqs) || n < 0) return HSMA_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  const double t = S->now();
+  for (int i = 0; i < n; ++i) {
+    Pending p;
+    p.r = reqs[i];
+    p.t_submit = t;
+    if (!valid_request(S, reqs[i])) {
+      finish(S, p, HSMA_EINVAL, 0.0, t, t);
+      continue;
+    }
+    S->pending.push_back(p);
+  }
+  return HSMA_OK;
+}
+
+extern "C" int hsma_server_poll(hsma_server_t S, hsma_result *out, int max) {
+  if (!S || !out || max <= 0) return 0;
+  std::lock_guard<std::mutex> lk(S->mu);
+  const int n = (int)(S->done.size() < (size_t)max ? S->done.size() : (size_t)max);
+  for (int i = 0; i < n; ++i) out[i] = S->done[i];
+  S->done.erase(S->done.begin(), S->done.begin() + n);
+  return n;
+}
+
+extern "C" hsma_status hsma_server_stats(hsma_server_t S, hsma_server_info *info) {
+  if (!S || !info) return HSMA_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  info->memory_used = S->used;
+  info->memory_budget = S->budget;
+  info->pending = (int64_t)S->pending.size();
+  info->completed = S->n_done;
+  info->batches = S->n_batches;
+  info->batched_requests = S->n_batched_reqs;
+  int live = 0;
+  for (hsma_system_s *s : S->systems) live += s != nullptr;
+  info->systems = live;
+  info->now = S->now();
+  return HSMA_OK;
+}
+
+// Open-loop load: request i is submitted at arrival[i] seconds after the call starts (a
+// busy-waiting injector thread); returns when every request has a result, in out[i]
+// (matched by position; tags are overwritten with the request index).
+extern "C" hsma_status hsma_server_run_load(hsma_server_t S, const hsma_request *reqs, const double *arrival, int n,
+                                            hsma_result *out) {
+  if (!S || n < 0 || (n > 0 && (!reqs || !arrival || !out))) return HSMA_EINVAL;
+  const double t_begin = S->now();
+  std::thread inj([&]() {
+    for (int i = 0; i < n; ++i) {
+      const double due = t_begin + arrival[i];
+      while (S->now() < due) {
+        const double wait = due - S->now();
+        if (wait > 2e-4) std::this_thread::sleep_for(std::chrono::microseconds(50));
+      }
+      hsma_request r = reqs[i];
+      r.tag = (uint64_t)i;
+      hsma_server_submit(S, &r, 1);
+    }
+  });
+  int got = 0;
+  std::vector<hsma_result> buf(1024);
+  while (got < n) {
+    const int k = hsma_server_poll(S, buf.data(), (int)buf.size());
+    for (int i = 0; i < k; ++i) {
+      const uint64_t t = buf[i].tag;
+      if (t < (uint64_t)n) {
+        out[t] = buf[i];
+        ++got;
+      }
+    }
+    if (k == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  inj.join();
+  for (int i = 0; i < n; ++i) {  // times relative to the start of the load
+    out[i].t_submit -= t_begin;
+    out[i].t_start -= t_begin;
+    out[i].t_done -= t_begin;
+  }
+  return HSMA_OK;
+}

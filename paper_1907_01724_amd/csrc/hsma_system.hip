@@ -17,49 +17,6 @@
 #include "hsma_internal.h"
 
 namespace hsma {
-
-// Device descriptor of one resident system.
-struct SysDev {
-  PlanDev pl;
-  const double *pinv64, *lhat64;
-  const int *nidx;
-  int K, M, P;
-  int64_t n;
-  double *x, *y, *z, *q;
-  double *s;   // 2P: Q' then D' (the strengths the evaluation kernel uses)
-  double *w;   // 2P: sum_i q_i S(x_i)
-  double *E;   // 1: current energy
-  double *dc;  // 2M scratch: check-field change (u then v)
-  double *ab;  // 2K scratch
-  double *ds;  // 2P scratch
-  double *dw;  // 2P scratch
-  double *partA;  // ceil(n / 256) scratch
-  double *partE;  // P scratch
-};
-
-// One single-ion-move request.
-struct DeReq {
-  int sys;
-  int commit;
-  int64_t k;
-  double x, y, z;
-  double *dE;  // [device] output, or nullptr
-};
-
-}  // namespace hsma
-
-struct hsma_system_s {
-  hsma_plan_t plan;
-  hsma_group_s *g64;     // FP64 group over the plan (full evaluations)
-  hsma::SysDev h;        // host copy of the descriptor
-  hsma::SysDev *d;       // device copy
-  int64_t n;
-  void *ws;              // workspace of the full evaluation
-  size_t ws_bytes;
-  int device;
-};
-
-namespace hsma {
 namespace {
 
 constexpr int DB = 256;
@@ -129,6 +86,7 @@ __global__ __launch_bounds__(DB) void k_de_pairs(const SysDev *__restrict__ syst
   const double x1 = r.x, y1 = r.y, z1 = r.z;
   const int blk = blockIdx.x;
   if (blk < nA) {
+    if ((int64_t)blk * DB >= S.n) return;  // nA covers the largest system of the batch
     const Img ik0 = image_of(c, x0, y0, z0), ik1 = image_of(c, x1, y1, z1);
     const int64_t j = (int64_t)blk * DB + threadIdx.x;
     double v = 0.0;
@@ -145,7 +103,7 @@ __global__ __launch_bounds__(DB) void k_de_pairs(const SysDev *__restrict__ syst
     return;
   }
   if (blk < nA + nB) {
-    const int m = (blk - nA) * DB + threadIdx.x;
+    const int m = (blk - nA) * DB + threadIdx.x;  // nB covers the largest M of the batch
     if (m < S.M) {
       const double4 ck = c.chk64[m];
       const double dx1 = ck.x - x1, dy1 = ck.y - y1, dz1 = ck.z - z1;
@@ -227,12 +185,13 @@ __global__ __launch_bounds__(256) void k_de_fit2(const SysDev *__restrict__ syst
 
 // Stage 4 (one block per request): dE in a fixed order; with commit, apply the move.
 __global__ __launch_bounds__(DB) void k_de_final(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
-                                                 DeReq one, int nA) {
+                                                 DeReq one) {
   __shared__ double red[DB];
   const DeReq r = reqs ? reqs[blockIdx.x] : one;
   const SysDev &S = systems[r.sys];
   const PlanDev &c = S.pl;
   const double x0 = S.x[r.k], y0 = S.y[r.k], z0 = S.z[r.k], qk = S.q[r.k];
+  const int nA = (int)((S.n + DB - 1) / DB);  // this system's own blocks: the order does not depend on the batch
   double a = 0.0;
   for (int i = threadIdx.x; i < nA; i += DB) a += S.partA[i];
   double e = 0.0;
@@ -287,6 +246,25 @@ __global__ void k_sys_s(int P, const double2 *__restrict__ qd, double *__restric
 }
 
 }  // namespace
+
+hsma_status launch_delta(const SysDev *systems, const DeReq *reqs, DeReq one, int nreq, int64_t max_n, int max_M,
+                         int max_P, int max_K, hipStream_t st) {
+  const int nA = (int)((max_n + DB - 1) / DB), nB = (max_M + DB - 1) / DB, nD = (max_P + DB - 1) / DB;
+  k_de_pairs<<<dim3(nA + nB + nD, nreq), DB, 0, st>>>(systems, reqs, one, nA, nB);
+  k_de_fit1<<<dim3((max_K + 3) / 4, nreq), 256, 0, st>>>(systems, reqs, one);
+  k_de_fit2<<<dim3((max_P + 3) / 4, nreq), 256, 0, st>>>(systems, reqs, one);
+  k_de_final<<<nreq, DB, 0, st>>>(systems, reqs, one);
+  HSMA_HIP(hipGetLastError());
+  return HSMA_OK;
+}
+
+hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
+  return run_batched(sys->g64, 1, nullptr, nullptr, sys->n, sys->n, sys->h.x, sys->h.y, sys->h.z, sys->h.q, nullptr,
+                     E, ws, ws_bytes, st);
+}
+
+size_t system_workspace_bytes(const hsma_system_s *sys) { return layout(sys->g64, 1, sys->n, sys->n).total; }
+
 }  // namespace hsma
 
 using namespace hsma;
@@ -333,6 +311,8 @@ extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const doubl
   sys->g64->pair_prec = HSMA_PAIR_FP64;  // full evaluations of the state in FP64
   const size_t nb = sizeof(double) * (size_t)N;
   const int nA = (int)((N + DB - 1) / DB);
+  sys->footprint = 4 * nb + sizeof(double) * (6 * (size_t)P + 2 * (size_t)M + 2 * (size_t)K + 1 + (size_t)nA + P) +
+                   sizeof(SysDev);
   double *phi = nullptr;
   Layout L = layout(sys->g64, 1, N, N);
   sys->ws_bytes = L.total;
@@ -378,6 +358,9 @@ extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const doubl
       goto fail;
     }
   }
+  (void)hipFree(sys->ws);  // the resident state is small; full evaluations bring their own workspace
+  sys->ws = nullptr;
+  sys->ws_bytes = 0;
   *out = sys;
   return HSMA_OK;
 fail:
@@ -385,6 +368,14 @@ fail:
   (void)hipStreamSynchronize(st);
   system_free(sys);
   return rc;
+}
+
+extern "C" size_t hsma_system_workspace_bytes(hsma_system_t sys) { return sys ? system_workspace_bytes(sys) : 0; }
+
+extern "C" hsma_status hsma_system_full_energy(hsma_system_t sys, double *E, void *ws, size_t ws_bytes,
+                                               hipStream_t st) {
+  if (!sys || !E || !ws) return HSMA_EINVAL;
+  return system_full_energy(sys, E, ws, ws_bytes, st);
 }
 
 static hsma_status delta(hsma_system_t sys, int64_t k, double xk, double yk, double zk, double *dE, int commit,
@@ -403,13 +394,7 @@ static hsma_status delta(hsma_system_t sys, int64_t k, double xk, double yk, dou
   r.y = yk;
   r.z = zk;
   r.dE = dE;
-  const int nA = (int)((sys->n + DB - 1) / DB), nB = (sys->h.M + DB - 1) / DB, nD = (sys->h.P + DB - 1) / DB;
-  k_de_pairs<<<dim3(nA + nB + nD, 1), DB, 0, st>>>(sys->d, nullptr, r, nA, nB);
-  k_de_fit1<<<dim3((sys->h.K + 3) / 4, 1), 256, 0, st>>>(sys->d, nullptr, r);
-  k_de_fit2<<<dim3((sys->h.P + 3) / 4, 1), 256, 0, st>>>(sys->d, nullptr, r);
-  k_de_final<<<1, DB, 0, st>>>(sys->d, nullptr, r, nA);
-  HSMA_HIP(hipGetLastError());
-  return HSMA_OK;
+  return launch_delta(sys->d, nullptr, r, 1, sys->n, sys->h.M, sys->h.P, sys->h.K, st);
 }
 
 extern "C" hsma_status hsma_delta_energy(hsma_system_t sys, int64_t k, double xk, double yk, double zk, double *dE,
