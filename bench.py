@@ -51,6 +51,9 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
+    ap.add_argument("--legs", default="batched,serving",
+                    help="extra workloads after the headline one: batched, serving (comma list, or none)")
+    ap.add_argument("--serving-requests", type=int, default=6000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -203,8 +206,208 @@ def main() -> int:
                 }
         out["rel_err_phi_l2_max"] = worst_phi
         out["rel_err_energy_max"] = worst_e
+    legs = [l for l in args.legs.split(",") if l and l != "none"]
+    if "batched" in legs:
+        out["batched"] = leg_batched(args)
+    if "serving" in legs:
+        out["serving"] = leg_serving(args)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _eval_roofline(pairs_kelvin, pairs_surface, avg_s):
+    t_min = (pairs_kelvin * SLOTS_KELVIN + pairs_surface * SLOTS_SURFACE) / ISSUE_RATE
+    pairs = pairs_kelvin + pairs_surface
+    return {"bound": "alu", "achieved": pairs / avg_s / 1e9, "peak": pairs / t_min / 1e9, "unit": "Gpair/s",
+            "frac": t_min / avg_s, "avg_launch_ms": avg_s * 1e3}
+
+
+def leg_batched(args) -> dict:
+    """4096 configurations (a = 25, eps1 = 1, eps2 = 78.5, kappa = 0.3, P = 1024, M = 1536),
+    N log-uniform in [100, 20000]: one batched call (shared plan, fit as MFMA GEMMs) per step,
+    against the plain per-system path on the same systems."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    wl = W.workload_c4()
+    sizes = np.array([s.n for s in wl.systems], dtype=np.int64)
+    off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cat = [np.concatenate([getattr(s, k) for s in wl.systems]) for k in "xyzq"]
+    log(f"bench[batched]: {len(sizes)} systems, sum N = {off_h[-1]}, generated in {time.perf_counter() - t0:.1f} s")
+    ph = wl.systems[0].phys
+    plan = hs.Plan(ph.a, ph.eps1, ph.eps2, ph.kappa, wl.disc.P, wl.disc.M, pair_prec=args.prec)
+    group = hs.Group([plan])
+    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
+    off = torch.tensor(off_h, dtype=torch.int64, device=dev)
+    nsys, total, max_n = len(sizes), int(off_h[-1]), int(sizes.max())
+    phi = torch.empty(total, dtype=torch.float64, device=dev)
+    E = torch.empty(nsys, dtype=torch.float64, device=dev)
+    ws = hs.workspace(group.workspace_bytes(nsys, total, max_n), dev)
+
+    def call():
+        group.energy(off, xb, yb, zb, qb, total_n=total, max_n=max_n, phi=phi, E=E, ws=ws)
+
+    call()
+    torch.cuda.synchronize()
+    assert group.stream_check() == 0
+    steps = 3
+    group.profile(True)
+    group.profile_read()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / steps
+    st = group.profile_read()
+    group.profile(False)
+    info = plan.info
+    pk = float(np.sum(sizes * (sizes - 1)))
+    ps = float(np.sum(sizes)) * info["P"]
+    pc = float(np.sum(sizes)) * info["M"]
+    # plain per-system path: one single-system call per configuration
+    single_ws = hs.workspace(plan.workspace_bytes(max_n), dev)
+    e1 = torch.empty(1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for b in range(nsys):
+        lo, hi = int(off_h[b]), int(off_h[b + 1])
+        plan.energy(xb[lo:hi], yb[lo:hi], zb[lo:hi], qb[lo:hi], E=e1, ws=single_ws)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t2) * 1e3
+    res = {
+        "workload": "4096 configurations, N log-uniform in [100, 20000], a=25, eps1=1, eps2=78.5, kappa=0.3, "
+                    "P=1024, M=1536, shared plan",
+        "systems": nsys, "total_ions": total, "ms_per_call": ms, "systems_per_s": nsys / (ms * 1e-3),
+        "gpairs_per_s": (pc + pk + ps) / (ms * 1e-3) / 1e9,
+        "per_system_path_ms": ms_single, "per_system_path_systems_per_s": nsys / (ms_single * 1e-3),
+        "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()},
+        "roofline": _eval_roofline(pk, ps, st["eval"][0] / steps * 1e-3),
+    }
+    if not args.no_oracle:
+        import oracle
+        rng = np.random.default_rng(0)
+        pick = rng.choice(np.nonzero(sizes <= 3000)[0], 6, replace=False)
+        phi_h = phi.cpu().numpy()
+        E_h = E.cpu().numpy()
+        prm = oracle.Params(a=info["a"], eps1=info["eps1"], eps2=info["eps2"], kappa=info["kappa"], p=info["p"],
+                            P=info["P"], M=info["M"], tau=info["tau"], rc_over_a=info["rc"] / info["a"], F1=info["F1"])
+        wphi, we = 0.0, 0.0
+        for b in pick:
+            s = wl.systems[b]
+            ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
+            got = phi_h[off_h[b]:off_h[b + 1]]
+            wphi = max(wphi, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+            e_ref = oracle.energy(s.q, ref)
+            we = max(we, abs(E_h[b] - e_ref) / abs(e_ref))
+        res["rel_err_phi_l2_max_sampled"] = wphi
+        res["rel_err_energy_max_sampled"] = we
+        res["sampled_systems"] = [int(b) for b in pick]
+    log(f"bench[batched]: {ms:.2f} ms/call, {res['systems_per_s']:.0f} systems/s "
+        f"(per-system path {res['per_system_path_systems_per_s']:.0f})")
+    return res
+
+
+def leg_serving(args) -> dict:
+    """512 resident configurations (N log-uniform in [500, 50000], a ~ U[15, 40], kappa ~
+    U[0.05, 1], eps1 = 1, eps2 = 78.5, P = 1024, M = 1536); requests 90% single-ion moves
+    (ion and system uniform, displacement U([-1/2, 1/2]^3) kept inside, committed with
+    probability 1/2) and 10% fresh full energies.  Capacity from a burst, then Poisson
+    arrivals at fractions of it; latency = done - submitted."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    wl = W.workload_c5()
+    plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, wl.disc.P, wl.disc.M) for s in wl.systems]
+    server = hs.Server(max_batch=512, delta_slots=3, energy_slots=2)
+    for p, s in zip(plans, wl.systems):
+        t = [torch.tensor(getattr(s, k), dtype=torch.float64, device=dev) for k in "xyzq"]
+        server.add_system(p, *t)
+    torch.cuda.synchronize()
+    log(f"bench[serving]: {len(plans)} systems resident, {server.stats()['memory_used'] / 2**30:.2f} GiB, "
+        f"set up in {time.perf_counter() - t0:.1f} s")
+    rng = np.random.default_rng(1907017244)
+    pos = [np.stack([s.x, s.y, s.z], axis=1).copy() for s in wl.systems]
+
+    def stream(n):
+        reqs = []
+        for _ in range(n):
+            b = int(rng.integers(len(pos)))
+            if rng.random() < 0.1:
+                reqs.append((hs.REQ_ENERGY, b, 0, 0, 0.0, 0.0, 0.0))
+                continue
+            k = int(rng.integers(len(pos[b])))
+            new = W.random_move(rng, pos[b][k], wl.systems[b].phys.a)
+            commit = int(rng.random() < 0.5)
+            if commit:
+                pos[b][k] = new
+            reqs.append((hs.REQ_DELTA, b, commit, k, *new))
+        return reqs
+
+    def summarize(res, reqs, wall):
+        lat = np.array([r.t_done - r.t_submit for r in res]) * 1e3
+        dl = np.array([r.t_done - r.t_submit for r, q in zip(res, reqs) if q[0] == hs.REQ_DELTA]) * 1e3
+        el = np.array([r.t_done - r.t_submit for r, q in zip(res, reqs) if q[0] == hs.REQ_ENERGY]) * 1e3
+        assert all(r.status == 0 for r in res)
+        return {"requests": len(res), "requests_per_s": len(res) / wall, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "delta_p50_ms": float(np.percentile(dl, 50)),
+                "delta_p99_ms": float(np.percentile(dl, 99)), "energy_p50_ms": float(np.percentile(el, 50)),
+                "energy_p99_ms": float(np.percentile(el, 99))}
+
+    n = args.serving_requests
+    server.run_load(stream(500), np.zeros(500))  # warm-up
+    reqs = stream(n)
+    st0 = server.stats()
+    res = server.run_load(reqs, np.zeros(n))
+    st1 = server.stats()
+    wall = max(r.t_done for r in res)
+    burst = summarize(res, reqs, wall)
+    cap = burst["requests_per_s"]
+    out = {"workload": "512 resident configurations, N log-uniform in [500, 50000], a~U[15,40], kappa~U[0.05,1], "
+                       "P=1024, M=1536; 90% single-ion moves (commit p=1/2), 10% fresh FP64 energies",
+           "capacity_requests_per_s": cap, "burst": burst,
+           "mean_batch": (st1["batched_requests"] - st0["batched_requests"]) / max(1, st1["batches"] - st0["batches"]),
+           "loads": []}
+    for f in (0.25, 0.5, 0.75, 0.9):
+        reqs = stream(n)
+        arrival = np.cumsum(rng.exponential(1.0 / (f * cap), n))
+        res = server.run_load(reqs, arrival)
+        wall = max(r.t_done for r in res)
+        d = summarize(res, reqs, wall)
+        d["offered_fraction"] = f
+        d["offered_requests_per_s"] = f * cap
+        out["loads"].append(d)
+        log(f"bench[serving]: load {f:.2f} x capacity: p50 {d['p50_ms']:.3f} ms, p99 {d['p99_ms']:.3f} ms")
+    server.close()
+    # plain per-system path: one synchronous single-ion query at a time on a resident system
+    b = int(np.argmax([len(p) for p in pos]))
+    s = wl.systems[b]
+    t = [torch.tensor(v, dtype=torch.float64, device=dev) for v in (pos[b][:, 0], pos[b][:, 1], pos[b][:, 2], s.q)]
+    one = hs.System(plans[b], *t)
+    dE = torch.empty(1, dtype=torch.float64, device=dev)
+    lat = []
+    for i in range(300):
+        k = int(rng.integers(len(pos[b])))
+        new = W.random_move(rng, pos[b][k], s.phys.a)
+        ta = time.perf_counter()
+        one.delta_energy(k, new, out=dE)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ta)
+    one.close()
+    lat = np.array(lat[20:]) * 1e3
+    out["per_system_path"] = {"system_ions": int(len(pos[b])), "delta_requests_per_s": float(1e3 / lat.mean()),
+                              "delta_p50_ms": float(np.percentile(lat, 50)), "delta_p99_ms": float(np.percentile(lat, 99))}
+    log(f"bench[serving]: capacity {cap:.0f} req/s (burst), per-system path {1e3 / lat.mean():.0f} req/s")
+    return out
 
 
 if __name__ == "__main__":
