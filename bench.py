@@ -54,6 +54,8 @@ def main() -> int:
     ap.add_argument("--legs", default="batched,serving",
                     help="extra workloads after the headline one: batched, serving (comma list, or none)")
     ap.add_argument("--serving-requests", type=int, default=6000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run two device copies of 256 MiB (a known-traffic kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -67,6 +69,14 @@ def main() -> int:
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration: 2 x (256 MiB read + 256 MiB written)")
+        del src, dst
     wl = W.workload_c2()
     d = wl.disc
     systems = wl.systems

@@ -296,6 +296,17 @@ __device__ __forceinline__ bool next_item(bool persistent, bool first, int64_t t
   return item < total;
 }
 
+// The slice of an item's source range [b0, b1) that wave w takes: the range split evenly over
+// the waves in whole 32-source tiles (the last slices may be short or empty).
+__device__ __forceinline__ void wave_slice(int64_t b0, int64_t b1, int w, int64_t &j0, int64_t &j1) {
+  const int64_t len = b1 - b0;
+  const int64_t tiles = (len + TILE - 1) / TILE;
+  const int64_t per = (tiles + WAVES - 1) / WAVES * TILE;
+  const int64_t s0 = b0 + (int64_t)w * per, s1 = s0 + per;
+  j0 = s0 < b1 ? s0 : b1;
+  j1 = s1 < b1 ? s1 : b1;
+}
+
 // wave index within the block, as a wave-uniform value
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
@@ -375,11 +386,10 @@ __global__ __launch_bounds__(TPB) void k_check(int persistent, int nsys, int M, 
     const T4 *chk = chk_of<MODE>(pd);
     const int64_t k = g * GRP + lane;
     const T4 ck = chk[k < M ? k : M - 1];
-    const int sub = chc / WAVES;
-    const int64_t cs = c * chc + (int64_t)w * sub;
-    const int64_t j0 = lo + (cs < n ? cs : n);
-    const int64_t ce = cs + sub;
-    const int64_t j1 = lo + (ce < n ? ce : n);
+    int64_t j0, j1;
+    wave_slice(c * chc, (c + 1) * chc < n ? (c + 1) * chc : n, w, j0, j1);
+    j0 += lo;
+    j1 += lo;
     double au = 0.0, av = 0.0;
     if (j0 < j1) check_range<MODE>(ck, src, srcw, j0, j1, au, av);
     red[0][w][lane] = au;
@@ -679,11 +689,9 @@ __global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, i
     const int64_t c = loc / G, g = loc % G;  // items sharing a source chunk are adjacent
     const int64_t il = g * GRP + lane;       // local target index
     const T4 t = tgt[lo + (il < n ? il : n - 1)];
-    const int sub = che / WAVES;
     const int64_t tot = n + P;
-    const int64_t cs = c * che + (int64_t)w * sub;
-    const int64_t j0 = cs < tot ? cs : tot;
-    const int64_t j1 = (cs + sub) < tot ? (cs + sub) : tot;
+    int64_t j0, j1;
+    wave_slice(c * che, (c + 1) * che < tot ? (c + 1) * che : tot, w, j0, j1);
     double acc = 0.0;
     const int64_t k1 = j1 < n ? j1 : n;
     if (j0 < k1) {
