@@ -170,11 +170,12 @@ hsma_status hsma_energy_batched(hsma_group_t group, int nsys, const int64_t *off
                                 hipStream_t stream);
 
 /* Launch shape of the group's pair kernels (check and evaluation sums).  persistent = 1:
- * one grid of 8 blocks per compute unit whose blocks take (system, 64 targets, source
- * chunk) items from a device counter; 0 (default): one item per block, the hardware
- * workgroup dispatcher balancing the load.  target_items (default 16384, 64..2^22): the
- * number of items each pair kernel aims for, which sets the source-chunk length.  Results
- * depend on target_items only through the summation order (rounding).  Errors: HSMA_EINVAL. */
+ * one grid of resident blocks (the occupancy limit on every compute unit) whose blocks
+ * take (system, 64 targets, source chunk) items from a device counter; 0 (default): one
+ * item per block, the hardware workgroup dispatcher balancing the load.  target_items
+ * (default 16384, 64..2^22): the number of items each pair kernel aims for, which sets the
+ * source-chunk length.  Results depend on the launch shape only through the summation
+ * order (rounding).  Errors: HSMA_EINVAL. */
 hsma_status hsma_group_tune(hsma_group_t group, int persistent, int target_items);
 
 /* Stage timing: when enabled, every compute call on the group records HIP events on its

@@ -35,7 +35,6 @@ constexpr int GRP = 64;          // targets per item
 constexpr int TILE = 32;         // sources per FP32 partial sum before folding into FP64
 constexpr int FINB = 256;        // ions per finish block
 constexpr int SCHED_T = 1024;    // threads of the schedule kernel
-constexpr int BLOCKS_PER_CU = 8; // persistent blocks per CU (32 waves per CU)
 
 template <int MODE>
 struct PT {
@@ -77,8 +76,11 @@ __device__ __forceinline__ const typename PT<MODE>::T4 *chk_of(const PlanDev &p)
   if constexpr (MODE == HSMA_PAIR_FP64) return p.chk64; else return p.chk32;
 }
 template <int MODE>
-__device__ __forceinline__ const typename PT<MODE>::T4 *nodes_of(const PlanDev &p) {
-  if constexpr (MODE == HSMA_PAIR_FP64) return p.nodes64; else return p.nodes32;
+inline const typename PT<MODE>::T4 *group_nodes(const hsma_group_s *g) {
+  if constexpr (MODE == HSMA_PAIR_FP64)
+    return g->nodes64;
+  else
+    return g->nodes32;
 }
 
 __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -315,13 +317,13 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // ---------------------------------------------------------------------------------
 template <int MODE>
 __device__ __forceinline__ void check_range(const typename PT<MODE>::T4 &ck, const typename PT<MODE>::T4 *__restrict__ src,
-                                            const typename PT<MODE>::T *__restrict__ srcw, int64_t j0, int64_t j1,
+                                            const typename PT<MODE>::T *__restrict__ srcw, int j0, int j1,
                                             double &au, double &av) {
   using T = typename PT<MODE>::T;
   using T4 = typename PT<MODE>::T4;
   if constexpr (MODE == HSMA_PAIR_FP32) {
     T su = 0, sv = 0;
-    for (int64_t j = j0; j < j1; ++j) {
+    for (int j = j0; j < j1; ++j) {
       const T4 s = src[j];
       const T dx = ck.x - s.x, dy = ck.y - s.y, dz = ck.z - s.z;
       const T ri = rinv(dx * dx + dy * dy + dz * dz);
@@ -333,7 +335,7 @@ __device__ __forceinline__ void check_range(const typename PT<MODE>::T4 &ck, con
   } else {
     au = 0.0;
     av = 0.0;
-    int64_t jb = j0;
+    int jb = j0;
     for (; jb + TILE <= j1; jb += TILE) {
       T su = 0, sv = 0;
 #pragma unroll 8
@@ -348,7 +350,7 @@ __device__ __forceinline__ void check_range(const typename PT<MODE>::T4 &ck, con
       av += (double)sv;
     }
     T su = 0, sv = 0;
-    for (int64_t j = jb; j < j1; ++j) {
+    for (int j = jb; j < j1; ++j) {
       const T4 s = src[j];
       const T dx = ck.x - s.x, dy = ck.y - s.y, dz = ck.z - s.z;
       const T ri = rinv(dx * dx + dy * dy + dz * dz);
@@ -388,10 +390,8 @@ __global__ __launch_bounds__(TPB) void k_check(int persistent, int nsys, int M, 
     const T4 ck = chk[k < M ? k : M - 1];
     int64_t j0, j1;
     wave_slice(c * chc, (c + 1) * chc < n ? (c + 1) * chc : n, w, j0, j1);
-    j0 += lo;
-    j1 += lo;
     double au = 0.0, av = 0.0;
-    if (j0 < j1) check_range<MODE>(ck, src, srcw, j0, j1, au, av);
+    if (j0 < j1) check_range<MODE>(ck, src + lo, srcw + lo, (int)j0, (int)j1, au, av);
     red[0][w][lane] = au;
     red[1][w][lane] = av;
     __syncthreads();
@@ -594,15 +594,14 @@ __global__ __launch_bounds__(256) void k_fit_qd(int nsys, int P, const float *__
 // Evaluation sums.
 // ---------------------------------------------------------------------------------
 template <int MODE, bool DIAG>
-__device__ __forceinline__ double kelvin_range(const typename PT<MODE>::T4 &t, int64_t i,
-                                               const typename PT<MODE>::T4 *__restrict__ img, int64_t j0,
-                                               int64_t j1) {
+__device__ __forceinline__ double kelvin_range(const typename PT<MODE>::T4 &t, int i,
+                                               const typename PT<MODE>::T4 *__restrict__ img, int j0, int j1) {
   using T = typename PT<MODE>::T;
   using T4 = typename PT<MODE>::T4;
   if constexpr (MODE != HSMA_PAIR_FP32_COMP) {
     T s = 0;
 #pragma unroll 8
-    for (int64_t j = j0; j < j1; ++j) {
+    for (int j = j0; j < j1; ++j) {
       const T4 v = img[j];
       const T dx = t.x - v.x, dy = t.y - v.y, dz = t.z - v.z;
       T ri = rinv(dx * dx + dy * dy + dz * dz);
@@ -612,7 +611,7 @@ __device__ __forceinline__ double kelvin_range(const typename PT<MODE>::T4 &t, i
     return (double)s;
   } else {
     double acc = 0.0;
-    int64_t jb = j0;
+    int jb = j0;
     for (; jb + TILE <= j1; jb += TILE) {
       float s = 0.0f;
 #pragma unroll 8
@@ -626,7 +625,7 @@ __device__ __forceinline__ double kelvin_range(const typename PT<MODE>::T4 &t, i
       acc += (double)s;
     }
     float s = 0.0f;
-    for (int64_t j = jb; j < j1; ++j) {
+    for (int j = jb; j < j1; ++j) {
       const float4 v = img[j];
       const float dx = t.x - v.x, dy = t.y - v.y, dz = t.z - v.z;
       float ri = rinv(dx * dx + dy * dy + dz * dz);
@@ -648,6 +647,7 @@ __device__ __forceinline__ double surface_range(const typename PT<MODE>::T4 &t,
   for (int sb = s0; sb < s1; sb += TILE) {
     const int se = sb + TILE < s1 ? sb + TILE : s1;
     T s = 0;
+#pragma unroll 8
     for (int k = sb; k < se; ++k) {
       const T4 yv = nodes[k];
       const T2 wv = qd[k];
@@ -671,6 +671,7 @@ __global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, i
                                               const int32_t *__restrict__ plan_of,
                                               const typename PT<MODE>::T4 *__restrict__ tgt,
                                               const typename PT<MODE>::T4 *__restrict__ img,
+                                              const typename PT<MODE>::T4 *__restrict__ nodes,
                                               const typename PT<MODE>::T2 *__restrict__ qd, double *__restrict__ part) {
   using T4 = typename PT<MODE>::T4;
   Sched S(const_cast<int64_t *>(base), nsys);
@@ -697,12 +698,13 @@ __global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, i
     if (j0 < k1) {
       const int64_t t0 = g * GRP;
       const bool diag = (t0 < k1) && (t0 + GRP > j0);
-      acc = diag ? kelvin_range<MODE, true>(t, il, img + lo, j0, k1) : kelvin_range<MODE, false>(t, il, img + lo, j0, k1);
+      acc = diag ? kelvin_range<MODE, true>(t, (int)il, img + lo, (int)j0, (int)k1)
+                 : kelvin_range<MODE, false>(t, (int)il, img + lo, (int)j0, (int)k1);
     }
     const int64_t s0 = (j0 > n ? j0 : n) - n, s1 = j1 - n;
     if (s0 < s1) {
-      const PlanDev pd = plans[plan_of ? plan_of[b] : 0];
-      acc += surface_range<MODE>(t, nodes_of<MODE>(pd), qd + (size_t)b * P, (int)s0, (int)s1);
+      const int pl = plan_of ? plan_of[b] : 0;
+      acc += surface_range<MODE>(t, nodes + (size_t)pl * P, qd + (size_t)b * P, (int)s0, (int)s1);
     }
     red[w][lane] = acc;
     __syncthreads();
@@ -787,9 +789,9 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   double *epart = (double *)(ws + L.epart);
   const PlanDev *plans = grp->dev;
   const int persistent = grp->tune.persistent;
-  const int64_t pgrid = (int64_t)g->ncu * BLOCKS_PER_CU;
-  const int64_t grid_c = persistent ? (L.items_c < pgrid ? L.items_c : pgrid) : L.items_c;
-  const int64_t grid_e = persistent ? (L.items_e < pgrid ? L.items_e : pgrid) : L.items_e;
+  const int64_t pgrid_c = (int64_t)g->ncu * grp->tune.occ_check, pgrid_e = (int64_t)g->ncu * grp->tune.occ_eval;
+  const int64_t grid_c = persistent ? (L.items_c < pgrid_c ? L.items_c : pgrid_c) : L.items_c;
+  const int64_t grid_e = persistent ? (L.items_e < pgrid_e ? L.items_e : pgrid_e) : L.items_e;
 
   hipEvent_t pr = prof_begin(grp, ST_PACK, st);
   const int sched_t = nsys >= SCHED_T ? SCHED_T : (int)((nsys + 63) / 64 * 64);
@@ -842,7 +844,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   pr = prof_begin(grp, ST_EVAL, st);
   if (L.items_e > 0)
     k_eval<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(persistent, nsys, P, L.che, base, sys_e, plans, plan_of, tgt, img,
-                                                   qd, eval_part);
+                                                   group_nodes<MODE>(grp), qd, eval_part);
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_FINISH, st);
@@ -920,7 +922,7 @@ hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, con
                         int64_t max_n, const double *x, const double *y, const double *z, const double *q,
                         double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!grp || nsys < 1 || total_n < 0 || max_n < 0 || max_n > total_n || !ws) return HSMA_EINVAL;
-  if (total_n > ((int64_t)1 << 31) - 1) return HSMA_EINVAL;
+  if (total_n + grp->geo->P > ((int64_t)1 << 31) - 1) return HSMA_EINVAL;  // 32-bit source indices
   if (total_n > 0 && (!x || !y || !z || !q)) return HSMA_EINVAL;
   if (((uintptr_t)ws & 255) != 0) return HSMA_EINVAL;
   if (nsys > 1 && !offsets) return HSMA_EINVAL;
@@ -938,6 +940,30 @@ hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, con
       return launch<HSMA_PAIR_FP32_COMP>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
     case HSMA_PAIR_FP64:
       return launch<HSMA_PAIR_FP64>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
+    default:
+      return HSMA_EINVAL;
+  }
+}
+
+template <int MODE>
+hsma_status occupancy_of(int *oc, int *oe) {
+  int a = 0, b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_check<MODE>, TPB, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_eval<MODE>, TPB, 0) != hipSuccess)
+    return HSMA_EDEVICE;
+  *oc = a > 0 ? a : 1;
+  *oe = b > 0 ? b : 1;
+  return HSMA_OK;
+}
+
+hsma_status pair_occupancy(int pair_prec, int *occ_check, int *occ_eval) {
+  switch (pair_prec) {
+    case HSMA_PAIR_FP32:
+      return occupancy_of<HSMA_PAIR_FP32>(occ_check, occ_eval);
+    case HSMA_PAIR_FP32_COMP:
+      return occupancy_of<HSMA_PAIR_FP32_COMP>(occ_check, occ_eval);
+    case HSMA_PAIR_FP64:
+      return occupancy_of<HSMA_PAIR_FP64>(occ_check, occ_eval);
     default:
       return HSMA_EINVAL;
   }

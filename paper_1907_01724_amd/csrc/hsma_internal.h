@@ -99,6 +99,8 @@ namespace hsma {
 // most one request in a batch.
 hsma_status launch_delta(const SysDev *systems, const DeReq *reqs, DeReq one, int nreq, int64_t max_n, int max_M,
                          int max_P, int max_K, hipStream_t st);
+// Resident blocks per compute unit of the check and evaluation kernels for a pair precision.
+hsma_status pair_occupancy(int pair_prec, int *occ_check, int *occ_eval);
 hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t ws_bytes, hipStream_t st);
 size_t system_workspace_bytes(const hsma_system_s *sys);
 }  // namespace hsma
@@ -107,6 +109,8 @@ size_t system_workspace_bytes(const hsma_system_s *sys);
 struct hsma_tune_s {
   int persistent;    // 1: persistent blocks taking items from a device counter; 0: one item per block
   int target_items;  // items each pair kernel aims to create (sets the source-chunk sizes)
+  int occ_check;     // resident blocks per compute unit of the check and evaluation kernels
+  int occ_eval;      // (occupancy API, set when the group is built)
 };
 
 struct hsma_group_s {
@@ -117,6 +121,8 @@ struct hsma_group_s {
   int pair_prec;
   int device;
   int *flag;             // device-side domain flag
+  float4 *nodes32;       // surface nodes of every plan (plan i at i * P), for the evaluation kernel
+  double4 *nodes64;
   int prof_on;           // record HIP events around each stage
   void *prof;            // hsma::Profile
   int owned_by_plan;     // the internal one-plan group of a plan
