@@ -54,8 +54,8 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="batched,serving",
-                    help="extra workloads after the headline one: batched, serving (comma list, or none)")
+    ap.add_argument("--legs", default="batched,serving,sweep",
+                    help="extra workloads after the headline one: batched, serving, sweep (comma list, or none)")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run two device copies of 256 MiB (a known-traffic kernel for counter scaling)")
@@ -243,6 +243,8 @@ def main() -> int:
         out["batched"] = leg_batched(args)
     if "serving" in legs:
         out["serving"] = leg_serving(args)
+    if "sweep" in legs:
+        out["precision_sweep"] = leg_sweep(args)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -359,6 +361,72 @@ def leg_batched(args) -> dict:
         res["sampled_systems"] = [int(b) for b in pick]
     log(f"bench[batched]: {ms:.2f} ms/call, {res['systems_per_s']:.0f} systems/s "
         f"(per-system path {res['per_system_path_systems_per_s']:.0f})")
+    return res
+
+
+def leg_sweep(args) -> dict:
+    """Precision sweep on N = 1e6 ions uniform in a = 200 (charges +-1 and +-2, 2:1), eps1 = 1,
+    eps2 = 80, kappa = 0.1, P = 6400, M = 9600 (p = 40): the whole path with FP32, compensated
+    FP32 and FP64 pair sums (fit applied in FP32 for the FP32 modes, in FP64 for FP64 pairs);
+    the potentials of 256 sampled ions are compared with the oracle's, the energies with the
+    FP64 run's."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.workload_c3()
+    s = wl.systems[0]
+    d = wl.disc
+    N = s.n
+    x, y, z, q = (torch.tensor(v, dtype=torch.float64, device=dev) for v in (s.x, s.y, s.z, s.q))
+    rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 20))
+    idx = np.sort(rng.choice(N, 256, replace=False))
+    idx_d = torch.tensor(idx, dtype=torch.int64, device=dev)
+    pairs = N * d.M + N * (N - 1) + N * d.P
+    res = {"workload": "N=1e6 uniform in a=200, charges +-1/+-2 (2:1), eps1=1, eps2=80, kappa=0.1, "
+                       "P=6400, M=9600, p=40", "pairs_per_call": pairs}
+    phis, Es = {}, {}
+    plan = None
+    for prec in ("fp32", "fp32c", "fp64"):
+        t0 = time.perf_counter()
+        plan = hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=prec)
+        t_plan = time.perf_counter() - t0
+        ws = hs.workspace(plan.workspace_bytes(N), dev)
+        phi = torch.empty(N, dtype=torch.float64, device=dev)
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+        plan.energy(x, y, z, q, phi=phi, E=E, ws=ws)
+        torch.cuda.synchronize()
+        assert plan.stream_check() == 0
+        t1 = time.perf_counter()
+        for _ in range(2):
+            plan.energy(x, y, z, q, phi=phi, E=E, ws=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / 2
+        phis[prec] = phi[idx_d].cpu().numpy()
+        Es[prec] = float(E.cpu().numpy()[0])
+        res[prec] = {"ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9, "plan_s": t_plan, "E": Es[prec]}
+        log(f"bench[sweep]: {prec}: {ms:.1f} ms/call ({pairs / (ms * 1e-3) / 1e9:.0f} GPairs/s), plan {t_plan:.2f} s")
+        del ws, phi
+    for prec in ("fp32", "fp32c"):
+        res[prec]["rel_err_energy_vs_fp64"] = abs(Es[prec] - Es["fp64"]) / abs(Es["fp64"])
+    if not args.no_oracle:
+        import oracle
+        i = plan.info
+        prm = oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
+                            M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"])
+        t0 = time.perf_counter()
+        ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q,
+                               targets=np.stack([s.x[idx], s.y[idx], s.z[idx]], axis=1))
+        res["oracle_s"] = time.perf_counter() - t0
+        for prec in ("fp32", "fp32c", "fp64"):
+            err = phis[prec] - ref
+            res[prec]["rel_err_phi_l2_sampled"] = float(np.linalg.norm(err) / np.linalg.norm(ref))
+            res[prec]["max_err_over_max_phi_sampled"] = float(np.max(np.abs(err)) / np.max(np.abs(ref)))
+        log(f"bench[sweep]: oracle on 256 sampled ions in {res['oracle_s']:.1f} s; rel L2 " +
+            ", ".join(f"{p} {res[p]['rel_err_phi_l2_sampled']:.2e}" for p in ("fp32", "fp32c", "fp64")))
     return res
 
 
