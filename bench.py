@@ -38,6 +38,10 @@ if ROOT not in sys.path:
 CU, LANES, CLOCK = 256, 64, 2.4e9
 ISSUE_RATE = CU * LANES * CLOCK              # lane-instructions / s
 SLOTS_KELVIN, SLOTS_SURFACE = 8, 14
+# The symmetric Kelvin kernel computes each ion pair's reciprocal image distance once for both
+# ions: 3 sub, 3 for |d|^2, v_rsq_f32 and one fma per direction, 9 instructions per unordered
+# pair, i.e. 4.5 per Kelvin pair counted in one direction.
+SLOTS_KELVIN_SYM = 4.5
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hsma_eval_c2_n20000_hbm_traffic.txt")
 ENGINE_SRC = os.path.join(ROOT, "paper_1907_01724_amd", "csrc", "hsma_engine.hip")
 
@@ -177,13 +181,16 @@ def main() -> int:
         ev_ms, ev_n = stages["eval"]
         avg = ev_ms / max(ev_n, 1) * 1e-3               # one launch covers the whole batch
         eval_pairs = (pairs_kelvin + pairs_surface) * nsys
-        t_min = (pairs_kelvin * SLOTS_KELVIN + pairs_surface * SLOTS_SURFACE) * nsys / ISSUE_RATE
+        sym = group.eval_kernel(nsys, nsys * N, N)
+        sk = SLOTS_KELVIN_SYM if sym > 0 else SLOTS_KELVIN
+        t_min = (pairs_kelvin * sk + pairs_surface * SLOTS_SURFACE) * nsys / ISSUE_RATE
         peak = eval_pairs / t_min
         achieved = eval_pairs / avg
         traffic, _ = _measured_traffic(args.prec)
         out["roofline"] = {
             "bound": "alu",
-            "kernel": "k_eval (evaluation pair sums, all systems of the step in one launch)",
+            "kernel": ("k_kelvin_sym (symmetric Kelvin pairs in blocks of %d ions + surface chunks)" % sym if sym > 0
+                       else "k_eval (evaluation pair sums)") + ", all systems of the step in one launch",
             "achieved": achieved / 1e9,
             "peak": peak / 1e9,
             "unit": "Gpair/s",
@@ -193,7 +200,8 @@ def main() -> int:
             "algorithmic_bytes": 40 * N * nsys + 24 * P * nsys,
             "avg_launch_ms": avg * 1e3,
             "pairs_per_launch": eval_pairs,
-            "peak_model": "256 CU x 64 lanes x 2.4 GHz VALU issue, one instruction per cycle; 8 instructions per Kelvin pair, 14 per surface pair",
+            "peak_model": "256 CU x 64 lanes x 2.4 GHz VALU issue, one instruction per cycle; %s instructions per "
+                          "Kelvin pair, 14 per surface pair" % sk,
         }
         out["stage_ms_per_step"] = {k: v[0] / args.steps for k, v in stages.items()}
 
@@ -264,11 +272,11 @@ def _measured_traffic(prec: str):
     return float(kv["k_eval_traffic_bytes_per_launch"]), float(kv["k_eval_algorithmic_bytes_per_launch"])
 
 
-def _eval_roofline(pairs_kelvin, pairs_surface, avg_s):
-    t_min = (pairs_kelvin * SLOTS_KELVIN + pairs_surface * SLOTS_SURFACE) / ISSUE_RATE
+def _eval_roofline(pairs_kelvin, pairs_surface, avg_s, sym=0):
+    t_min = (pairs_kelvin * (SLOTS_KELVIN_SYM if sym > 0 else SLOTS_KELVIN) + pairs_surface * SLOTS_SURFACE) / ISSUE_RATE
     pairs = pairs_kelvin + pairs_surface
     return {"bound": "alu", "achieved": pairs / avg_s / 1e9, "peak": pairs / t_min / 1e9, "unit": "Gpair/s",
-            "frac": t_min / avg_s, "avg_launch_ms": avg_s * 1e3}
+            "frac": t_min / avg_s, "avg_launch_ms": avg_s * 1e3, "symmetric_block": sym}
 
 
 def leg_batched(args) -> dict:
@@ -338,7 +346,7 @@ def leg_batched(args) -> dict:
         "gpairs_per_s": (pc + pk + ps) / (ms * 1e-3) / 1e9,
         "per_system_path_ms": ms_single, "per_system_path_systems_per_s": nsys / (ms_single * 1e-3),
         "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()},
-        "roofline": _eval_roofline(pk, ps, st["eval"][0] / steps * 1e-3),
+        "roofline": _eval_roofline(pk, ps, st["eval"][0] / steps * 1e-3, group.eval_kernel(nsys, total, max_n)),
     }
     if not args.no_oracle:
         import oracle

@@ -178,6 +178,21 @@ hsma_status hsma_energy_batched(hsma_group_t group, int nsys, const int64_t *off
  * order (rounding).  Errors: HSMA_EINVAL. */
 hsma_status hsma_group_tune(hsma_group_t group, int persistent, int target_items);
 
+/* Kelvin sums by the symmetric kernel.  The image distance of an ion pair satisfies
+ * |x_j - r_K,i| = (r_j / r_i) |x_i - r_K,j| (Sec. 2.4 images), so one reciprocal root serves
+ * both ions of a pair.  The kernel works on blocks of 256 or 512 ions and applies to the
+ * compensated FP32 pair precision when its partial sums (8 bytes per ion and block) fit in
+ * 16 GiB.  mode 0: never; 1 (default): blocks of 256, else 512, when it applies and the launch
+ * is large enough (see hsma_group_eval_kernel); 2 / 3: blocks of 256 / 512 whenever they
+ * apply.  Results differ only in rounding.  Errors: HSMA_EINVAL. */
+hsma_status hsma_group_set_symmetric(hsma_group_t group, int mode);
+
+/* Which evaluation kernel hsma_energy_batched would run for these sizes: the ion-block size
+ * (256 or 512) of the symmetric Kelvin kernel, 0 for the one-directional kernel, -1 for invalid
+ * arguments.  In mode 1 the symmetric kernel is chosen when its waves (one per block pair or
+ * surface chunk) at least cover every SIMD of the device. */
+int hsma_group_eval_kernel(hsma_group_t group, int nsys, int64_t total_n, int64_t max_n);
+
 /* Stage timing: when enabled, every compute call on the group records HIP events on its
  * stream around its kernel groups (0 schedule/Kelvin images/packing, 1 check sums, 2 fit
  * apply, 3 evaluation pair sums, 4 final reductions).  hsma_profile_read waits for the

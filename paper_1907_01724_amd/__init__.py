@@ -105,6 +105,9 @@ def load_library(path: str | None = None):
                                                                                                    _VP]
     L.hsma_group_stream_check.argtypes = [_VP, _VP]
     L.hsma_group_tune.argtypes = [_VP, C.c_int, C.c_int]
+    L.hsma_group_set_symmetric.argtypes = [_VP, C.c_int]
+    L.hsma_group_eval_kernel.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
+    L.hsma_group_eval_kernel.restype = C.c_int
     L.hsma_system_create.argtypes = [_VP, C.c_int64] + [_VP] * 4 + [_VP, C.POINTER(_VP)]
     L.hsma_delta_energy.argtypes = [_VP, C.c_int64, C.c_double, C.c_double, C.c_double, _VP, _VP]
     L.hsma_system_commit.argtypes = [_VP, C.c_int64, C.c_double, C.c_double, C.c_double, _VP]
@@ -127,7 +130,7 @@ def load_library(path: str | None = None):
     for name in ("hsma_plan", "hsma_plan_ex", "hsma_plan_destroy", "hsma_plan_get_info", "hsma_potential",
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
-                 "hsma_group_stream_check", "hsma_group_tune", "hsma_system_create", "hsma_delta_energy",
+                 "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel", "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
                  "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
@@ -284,6 +287,14 @@ class Plan:
         _check(load_library().hsma_group_tune(self.group, 1 if persistent else 0, int(target_items)),
                "hsma_group_tune")
 
+    def set_symmetric(self, mode: int = 1):
+        """Symmetric Kelvin kernel: 0 never, 1 for large launches (default), 2 / 3 always with ion
+        blocks of 256 / 512."""
+        _check(load_library().hsma_group_set_symmetric(self.group, int(mode)), "hsma_group_set_symmetric")
+
+    def eval_kernel(self, N: int) -> int:
+        return int(load_library().hsma_group_eval_kernel(self.group, 1, int(N), int(N)))
+
     def profile(self, on: bool = True):
         _profile(self.group, on)
 
@@ -362,6 +373,15 @@ class Group:
 
     def tune(self, persistent: bool = False, target_items: int = 16384):
         _check(load_library().hsma_group_tune(self._h, 1 if persistent else 0, int(target_items)), "hsma_group_tune")
+
+    def set_symmetric(self, mode: int = 1):
+        """Symmetric Kelvin kernel: 0 never, 1 for large launches (default), 2 / 3 always with ion
+        blocks of 256 / 512."""
+        _check(load_library().hsma_group_set_symmetric(self._h, int(mode)), "hsma_group_set_symmetric")
+
+    def eval_kernel(self, nsys: int, total_n: int, max_n: int) -> int:
+        """Ion-block size of the symmetric Kelvin kernel these sizes would use, or 0."""
+        return int(load_library().hsma_group_eval_kernel(self._h, int(nsys), int(total_n), int(max_n)))
 
     def profile(self, on: bool = True):
         _profile(self._h, on)

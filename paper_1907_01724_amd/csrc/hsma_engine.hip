@@ -35,6 +35,8 @@ constexpr int GRP = 64;          // targets per item
 constexpr int TILE = 32;         // sources per FP32 partial sum before folding into FP64
 constexpr int FINB = 256;        // ions per finish block
 constexpr int SCHED_T = 1024;    // threads of the schedule kernel
+constexpr int64_t SYM_MAX_BYTES = (int64_t)16 << 30;  // partial-slot bound above which the symmetric
+                                                       // Kelvin kernel is not used
 
 template <int MODE>
 struct PT {
@@ -111,10 +113,25 @@ struct Bounds {
   int nplans;
 };
 
+__device__ __forceinline__ void eval_counts(int64_t n, int P, int che, int sym_tb, int sch, int64_t &items,
+                                            int64_t &parts) {
+  if (n <= 0) {
+    items = parts = 0;
+  } else if (sym_tb > 0) {  // symmetric Kelvin blocks: pair items I <= J, then surface chunks
+    const int64_t B = cdiv64(n, sym_tb);
+    items = B * (B + 1) / 2 + B * sch;
+    parts = n * (B + sch);
+  } else {
+    items = cdiv64(n, GRP) * cdiv64(n + P, che);
+    parts = items * GRP;
+  }
+}
+
 __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *__restrict__ offsets,
                                                       const int32_t *__restrict__ plan_of, Bounds bd, int M, int P,
-                                                      int chc, int che, int64_t grid_c, int64_t grid_e,
-                                                      int64_t *__restrict__ base, int *__restrict__ flag) {
+                                                      int chc, int che, int sym_tb, int sch, int64_t grid_c,
+                                                      int64_t grid_e, int64_t *__restrict__ base,
+                                                      int *__restrict__ flag) {
   Sched S(base, nsys);
   __shared__ int64_t sc[5][SCHED_T];
   const int t = threadIdx.x, nt = blockDim.x;  // nt <= SCHED_T, a multiple of 64
@@ -137,12 +154,13 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
     const int64_t n = hi - lo;
     const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
-    const int64_t chunks_e = n > 0 ? cdiv64(n + P, che) : 0;
+    int64_t items_e, parts_e;
+    eval_counts(n, P, che, sym_tb, sch, items_e, parts_e);
     acc[0] += Gc * chunks_c;
-    acc[1] += cdiv64(n, GRP) * chunks_e;
+    acc[1] += items_e;
     acc[2] += cdiv64(n, FINB);
     acc[3] += Gc * chunks_c * GRP;
-    acc[4] += cdiv64(n, GRP) * chunks_e * GRP;
+    acc[4] += parts_e;
   }
   for (int k = 0; k < 5; ++k) sc[k][t] = acc[k];
   __syncthreads();
@@ -160,7 +178,8 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
     const int64_t n = hi - lo;
     const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
-    const int64_t chunks_e = n > 0 ? cdiv64(n + P, che) : 0;
+    int64_t items_e, parts_e;
+    eval_counts(n, P, che, sym_tb, sch, items_e, parts_e);
     S.off[b] = lo;
     S.ic[b] = run[0];
     S.ie[b] = run[1];
@@ -168,10 +187,10 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     S.pc[b] = run[3];
     S.pe[b] = run[4];
     run[0] += Gc * chunks_c;
-    run[1] += cdiv64(n, GRP) * chunks_e;
+    run[1] += items_e;
     run[2] += cdiv64(n, FINB);
     run[3] += Gc * chunks_c * GRP;
-    run[4] += cdiv64(n, GRP) * chunks_e * GRP;
+    run[4] += parts_e;
   }
   if (t == nt - 1) {
     S.off[nsys] = offsets ? offsets[nsys] : n_single;
@@ -215,7 +234,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
                                               typename PT<MODE>::T4 *__restrict__ img,
                                               typename PT<MODE>::T4 *__restrict__ tgt,
                                               typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
-                                              int *__restrict__ flag) {
+                                              float2 *__restrict__ wr, int *__restrict__ flag) {
   using T4 = typename PT<MODE>::T4;
   using T = typename PT<MODE>::T;
   Sched S(const_cast<int64_t *>(base), nsys);
@@ -238,11 +257,13 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
     tgt[i] = make4<T4>(0.0, 0.0, 0.0, 0.0);
     srcw[i] = (T)0;
     self[i] = 0.0;
+    if (wr) wr[i] = make_float2(0.0f, 0.0f);
     return;
   }
   const double qp = qi * c.c0;  // q / (4 pi eps1)
-  double kx, ky, kz, qk;
+  double kx, ky, kz, qk, reff;
   if (r >= c.rmin) {
+    reff = r;
     const double fk = c.a2 / r2;  // r_K = (a/r)^2 x
     kx = fk * xi;
     ky = fk * yi;
@@ -257,6 +278,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
     ky = c.far * uy;
     kz = c.far * uz;
     qk = qp * (c.gamma - 0.5 * c.dbar) * c.far / c.a;
+    reff = c.a2 / c.far;  // the radius whose Kelvin point is the stand-in at distance `far`
   }
   // own image: q_K / (4 pi eps1 |x - r_K|) with |x - r_K| = (a^2 - r^2) / r, written so that it
   // stays regular at r = 0 and keeps FP64 accuracy as r -> a
@@ -264,6 +286,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   img[i] = make4<T4>(kx, ky, kz, qk);
   tgt[i] = make4<T4>(xi, yi, zi, qp);
   srcw[i] = (T)(qp * r / c.a);
+  if (wr) wr[i] = make_float2((float)(qk * reff), (float)(1.0 / reff));
 }
 
 // ---------------------------------------------------------------------------------
@@ -716,8 +739,192 @@ __global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, i
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Symmetric Kelvin sums.  For ions i, j of one system, |x_i - r_K,j|^2 (r_j/a)^2 =
+// r_i^2 r_j^2 / a^2 - 2 x_i.x_j + a^2 is symmetric in i and j, so
+//   1 / |x_j - r_K,i| = (r_i / r_j) / |x_i - r_K,j|:
+// one reciprocal root gives both q'_j / |x_i - r_K,j| (to ion i) and
+// (q'_i r_i) / |x_i - r_K,j| / r_j (to ion j), q' = q_K / (4 pi eps1).
+// A system's ions form blocks of TB = 64 R; a wave holds one block as targets (R per lane)
+// and sweeps another block J >= I as wave-uniform sources.  Forward sums stay in the lanes;
+// the reverse contribution to each source is summed over the wave by DPP steps.  Every ion
+// gets one partial slot per partner block (slot K of ion i at K * n + i, K = the other block),
+// written exactly once, then one slot per surface-node chunk.  Diagonal blocks and surface
+// chunks are one-directional.
+// ---------------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ float dpp_read(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO));
+}
+
+// Sum over the 64 lanes of a wave, complete in lane 63.  Row shifts by 1, 2, 4 and 8 with zero
+// fill form the inclusive prefix sum of each row of 16 lanes (its total in the row's lane 15);
+// the row-15 broadcast then adds row r-1's total into row r (lane 31 = rows 0+1, lane 63 =
+// rows 2+3) and the row-31 broadcast adds lane 31 into rows 2 and 3.  Only lane 63 is used.
+__device__ __forceinline__ float wave_total_lane63(float v) {
+  v += dpp_read<0x111, 0xf, 0xf, true>(v);  // row_shr:1
+  v += dpp_read<0x112, 0xf, 0xf, true>(v);  // row_shr:2
+  v += dpp_read<0x114, 0xf, 0xf, true>(v);  // row_shr:4
+  v += dpp_read<0x118, 0xf, 0xf, true>(v);  // row_shr:8
+  v += dpp_read<0x142, 0xf, 0xf, true>(v);  // row_bcast:15
+  v += dpp_read<0x143, 0xf, 0xf, true>(v);  // row_bcast:31
+  return v;
+}
+
+template <int R>
+__global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, const int64_t *__restrict__ base,
+                                                    const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
+                                                    const float4 *__restrict__ tgt, const float4 *__restrict__ img,
+                                                    const float2 *__restrict__ wr, const float4 *__restrict__ nodes,
+                                                    const float2 *__restrict__ qd, double *__restrict__ part) {
+  constexpr int TB = 64 * R;
+  constexpr float FAR_TARGET = 3.0e18f;  // stand-in position of an empty target lane
+  Sched S(const_cast<int64_t *>(base), nsys);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (!sched_ok(S)) return;
+  const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);  // one item per wave
+  if (item >= S.ie[nsys]) return;
+  const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
+  const int64_t lo = S.off[b];
+  const int n = (int)(S.off[b + 1] - lo);
+  const int64_t B = cdiv64(n, TB);
+  const int64_t npair = B * (B + 1) / 2;
+  const int64_t loc = item - S.ie[b];
+  double *pb = part + S.pe[b];
+  const float4 *im = img + lo;
+  int I, J;
+  bool surface = false;
+  int c = 0;
+  if (loc < npair) {
+    // rows I = 0..B-1 of the triangle J = I..B-1 start at I B - I (I - 1) / 2
+    const double bb = 2.0 * (double)B + 1.0;
+    int64_t r = (int64_t)((bb - sqrt(bb * bb - 8.0 * (double)loc)) * 0.5);
+    r = r < 0 ? 0 : (r > B - 1 ? B - 1 : r);
+    while (r > 0 && r * B - r * (r - 1) / 2 > loc) --r;
+    while (r + 1 < B && (r + 1) * B - (r + 1) * r / 2 <= loc) ++r;
+    I = (int)r;
+    J = (int)(I + (loc - (r * B - r * (r - 1) / 2)));
+  } else {
+    surface = true;
+    const int64_t t = loc - npair;
+    I = (int)(t / sch);
+    c = (int)(t % sch);
+    J = 0;
+  }
+  I = __builtin_amdgcn_readfirstlane(I);
+  J = __builtin_amdgcn_readfirstlane(J);
+  const int t0 = I * TB;
+  float tx[R], ty[R], tz[R], tw[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int i = t0 + k * 64 + lane;
+    if (i < n) {
+      const float4 t = tgt[lo + i];
+      tx[k] = t.x;
+      ty[k] = t.y;
+      tz[k] = t.z;
+      tw[k] = wr[lo + i].x;
+    } else {
+      tx[k] = FAR_TARGET;
+      ty[k] = 0.0f;
+      tz[k] = 0.0f;
+      tw[k] = 0.0f;
+    }
+  }
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  int slot;
+  if (surface) {
+    const int per = (P + sch - 1) / sch;
+    const int s0 = c * per, s1 = s0 + per < P ? s0 + per : P;
+    const int pl = plan_of ? plan_of[b] : 0;
+    const float4 *nd = nodes + (size_t)pl * P;
+    const float2 *qb = qd + (size_t)b * P;
+    for (int sb = s0; sb < s1; sb += TILE) {
+      const int se = sb + TILE < s1 ? sb + TILE : s1;
+      float sum[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) sum[k] = 0.0f;
+      for (int m = sb; m < se; ++m) {
+        const float4 yv = nd[m];
+        const float2 wv = qb[m];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const float dx = tx[k] - yv.x, dy = ty[k] - yv.y, dz = tz[k] - yv.z;
+          const float ri = rinv(dx * dx + dy * dy + dz * dz);
+          const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
+          sum[k] = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc[k] += (double)sum[k];
+    }
+    slot = (int)B + c;
+  } else {
+    const int j0 = J * TB, j1 = j0 + TB < n ? j0 + TB : n;
+    if (I == J) {
+      // diagonal block: one-directional, the ion's own image excluded (it is the analytic term)
+      for (int jb = j0; jb < j1; jb += TILE) {
+        const int je = jb + TILE < j1 ? jb + TILE : j1;
+        float sum[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) sum[k] = 0.0f;
+        for (int j = jb; j < je; ++j) {
+          const float4 v = im[j];
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const float dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
+            float ri = rinv(dx * dx + dy * dy + dz * dz);
+            ri = (j == t0 + k * 64 + lane) ? 0.0f : ri;
+            sum[k] = fmaf(v.w, ri, sum[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += (double)sum[k];
+      }
+    } else {
+      for (int jg = j0; jg < j1; jg += 64) {
+        const int ge = jg + 64 < j1 ? jg + 64 : j1;
+        float rb = 0.0f;  // lane l: reverse total of source jg + l
+        for (int jb = jg; jb < ge; jb += TILE) {
+          const int je = jb + TILE < ge ? jb + TILE : ge;
+          float sum[R];
+#pragma unroll
+          for (int k = 0; k < R; ++k) sum[k] = 0.0f;
+          for (int j = jb; j < je; ++j) {
+            const float4 v = im[j];
+            float rev = 0.0f;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+              const float dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
+              const float ri = rinv(dx * dx + dy * dy + dz * dz);
+              sum[k] = fmaf(v.w, ri, sum[k]);
+              rev = fmaf(tw[k], ri, rev);
+            }
+            rev = wave_total_lane63(rev);
+            const float tot = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rev), 63));
+            rb = (lane == j - jg) ? tot : rb;
+          }
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] += (double)sum[k];
+        }
+        const int js = jg + lane;
+        if (js < ge) pb[(size_t)I * n + js] = (double)rb * (double)wr[lo + js].y;  // slot I of ion js
+      }
+    }
+    slot = J;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int i = t0 + k * 64 + lane;
+    if (i < n) pb[(size_t)slot * n + i] = acc[k];
+  }
+}
+
 // Phi_i = own-image term + fixed-order sum of the chunk partials; block partial of 1/2 sum q Phi.
-__global__ __launch_bounds__(FINB) void k_finish(int nsys, int P, int che, const int64_t *__restrict__ base,
+__global__ __launch_bounds__(FINB) void k_finish(int nsys, int P, int che, int sym_tb, int sch,
+                                                 const int64_t *__restrict__ base,
                                                  const int *__restrict__ sys_f, const double *__restrict__ part,
                                                  const double *__restrict__ self, const double *__restrict__ q,
                                                  double *__restrict__ phi, double *__restrict__ epart) {
@@ -730,11 +937,19 @@ __global__ __launch_bounds__(FINB) void k_finish(int nsys, int P, int che, const
   const int64_t il = (f - S.fb[b]) * FINB + threadIdx.x;
   double e = 0.0;
   if (il < n) {
-    const int64_t chunks = cdiv64(n + P, che);
-    const int64_t g = il / GRP, lane = il % GRP;
-    const double *pp = part + S.pe[b] + g * chunks * GRP + lane;
     double s = self[lo + il];
-    for (int64_t c = 0; c < chunks; ++c) s += pp[c * GRP];
+    if (sym_tb > 0) {  // one slot per partner block, then the surface chunks: slot K of ion i at K * n + i
+      const int slots = (int)(cdiv64(n, sym_tb) + sch);
+      const double *pp = part + S.pe[b] + il;
+#pragma unroll 8
+      for (int k = 0; k < slots; ++k) s += pp[(int64_t)k * n];
+    } else {
+      const int64_t chunks = cdiv64(n + P, che);
+      const int64_t g = il / GRP, lane = il % GRP;
+      const double *pp = part + S.pe[b] + g * chunks * GRP + lane;
+#pragma unroll 8
+      for (int64_t c = 0; c < chunks; ++c) s += pp[c * GRP];
+    }
     phi[lo + il] = s;
     e = 0.5 * q[lo + il] * s;
   }
@@ -804,11 +1019,12 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   bd.parts_c = L.parts_c;
   bd.parts_e = L.parts_e;
   bd.nplans = grp->nplans;
-  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, P, L.chc, L.che, grid_c, grid_e, base, grp->flag);
+  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, P, L.chc, L.che, L.sym_tb, L.sch, grid_c, grid_e,
+                                    base, grp->flag);
   k_fill<<<nsys, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f);
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_f, plans, plan_of, x, y, z, q, img, tgt, srcw, self,
-                                             grp->flag);
+                                             (float2 *)(ws + L.wr), grp->flag);
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_CHECK, st);
@@ -842,14 +1058,29 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_EVAL, st);
-  if (L.items_e > 0)
+  bool done = false;
+  if constexpr (MODE == HSMA_PAIR_FP32_COMP) {
+    if (L.sym_tb > 0 && L.items_e > 0) {
+      const unsigned gs = (unsigned)cdiv(L.items_e, WAVES);
+      const float2 *wr = (const float2 *)(ws + L.wr);
+      if (L.sym_tb == 256)
+        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wr, grp->nodes32, qd,
+                                            eval_part);
+      else
+        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wr, grp->nodes32, qd,
+                                            eval_part);
+      done = true;
+    }
+  }
+  if (!done && L.items_e > 0)
     k_eval<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(persistent, nsys, P, L.che, base, sys_e, plans, plan_of, tgt, img,
                                                    group_nodes<MODE>(grp), qd, eval_part);
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_FINISH, st);
   if (L.fin > 0)
-    k_finish<<<(int)L.fin, FINB, 0, st>>>(nsys, P, L.che, base, sys_f, eval_part, self, q, phi, epart);
+    k_finish<<<(int)L.fin, FINB, 0, st>>>(nsys, P, L.che, L.sym_tb, L.sch, base, sys_f, eval_part, self, q, phi,
+                                          epart);
   if (E) k_energy<<<nsys, 64, 0, st>>>(nsys, base, epart, E);
   prof_end(pr, st);
   HSMA_HIP(hipGetLastError());
@@ -885,6 +1116,29 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n)
   const int64_t chunks_max = (max_n + P) / L.che + 1;           // chunks of the largest system
   L.items_e = total_n > 0 ? gt * chunks_max : 0;
   L.parts_e = L.items_e * GRP;
+  // Symmetric Kelvin kernel: ion blocks of 256 (4 targets per lane) where they fit, else 512.
+  // Each wave works on a whole block pair or surface chunk, so in the automatic mode it is used
+  // only when its waves at least cover every SIMD of the device.
+  L.sym_tb = 0;
+  L.sch = 0;
+  const int mode = grp->tune.symmetric;
+  if (grp->pair_prec == HSMA_PAIR_FP32_COMP && mode != 0 && total_n > 0) {
+    for (int r = 4; r <= 8; r *= 2) {
+      if ((mode == 2 && r != 4) || (mode == 3 && r != 8)) continue;
+      const int64_t tb = 64 * r;
+      const int64_t bmax = cdiv(max_n, tb);
+      const int64_t sch = cdiv(P, (2 * tb) / 3);     // surface chunks of about 2/3 of a block's cost
+      const int64_t parts = total_n * (bmax + sch);  // >= sum_b n_b (B_b + sch)
+      const int64_t sb = total_n / tb + nsys;        // >= sum_b B_b
+      const int64_t waves = sb * (bmax + 1) / 2 + sb * sch;
+      if (parts * (int64_t)sizeof(double) > SYM_MAX_BYTES || (mode == 1 && waves < 4 * (int64_t)g->ncu)) continue;
+      L.sym_tb = (int)tb;
+      L.sch = (int)sch;
+      L.items_e = waves + 1;  // >= sum_b B_b (B_b + 1) / 2 + B_b sch
+      L.parts_e = parts;
+      break;
+    }
+  }
   L.fin = total_n > 0 ? total_n / FINB + nsys : 0;
   L.mfma = !fp64 && nsys >= 8;
   const size_t t4 = fp64 ? sizeof(double4) : sizeof(float4);
@@ -903,6 +1157,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n)
   L.tgt = take(t4 * (size_t)total_n);
   L.srcw = take(t1 * (size_t)total_n);
   L.self = take(sizeof(double) * (size_t)total_n);
+  L.wr = take(sizeof(float2) * (size_t)total_n);
   L.chk_part = take(sizeof(double) * 2 * (size_t)L.parts_c);
   L.uv = take(sizeof(double) * 2 * (size_t)M * nsys);
   L.uv32 = L.mfma ? take(sizeof(float) * 2 * (size_t)M * nsys) : 0;
@@ -1054,6 +1309,17 @@ extern "C" hsma_status hsma_group_tune(hsma_group_t grp, int persistent, int tar
     return HSMA_EINVAL;
   grp->tune.persistent = persistent;
   grp->tune.target_items = target_items;
+  return HSMA_OK;
+}
+
+extern "C" int hsma_group_eval_kernel(hsma_group_t grp, int nsys, int64_t total_n, int64_t max_n) {
+  if (!grp || nsys < 1 || total_n < 0 || max_n < 0 || max_n > total_n) return -1;
+  return layout(grp, nsys, total_n, max_n).sym_tb;
+}
+
+extern "C" hsma_status hsma_group_set_symmetric(hsma_group_t grp, int on) {
+  if (!grp || on < 0 || on > 3) return HSMA_EINVAL;
+  grp->tune.symmetric = on;
   return HSMA_OK;
 }
 

@@ -111,6 +111,8 @@ struct hsma_tune_s {
   int target_items;  // items each pair kernel aims to create (sets the source-chunk sizes)
   int occ_check;     // resident blocks per compute unit of the check and evaluation kernels
   int occ_eval;      // (occupancy API, set when the group is built)
+  int symmetric;     // symmetric Kelvin kernel: 0 never, 1 for large launches, 2 / 3 whenever it
+                     // applies with ion blocks of 256 / 512
 };
 
 struct hsma_group_s {
@@ -154,10 +156,11 @@ struct Layout {
   int nsys;
   int64_t total_n, max_n;
   int chc, che;                  // sources per item (check / evaluation), multiples of 128
+  int sym_tb, sch;               // symmetric Kelvin kernel: ions per block and surface chunks (0: off)
   int64_t items_c, items_e, fin; // upper bounds of the item and finish-block counts
   int64_t parts_c, parts_e;      // upper bounds of the partial-sum slots
   size_t sched, item_sys_c, item_sys_e, fin_sys;
-  size_t img, tgt, srcw, self, chk_part, uv, uv32, ab, h32, gemm2, qd, eval_part, phi, epart, E;
+  size_t img, tgt, srcw, self, wr, chk_part, uv, uv32, ab, h32, gemm2, qd, eval_part, phi, epart, E;
   size_t total;
   bool mfma;                     // fit applied as MFMA GEMMs
 };
