@@ -30,18 +30,18 @@ if ROOT not in sys.path:
 
 # Derived ALU ceiling of the evaluation kernel: 256 CUs x 4 SIMDs x 16 lanes issue
 # 256 * 64 FP32 lane-instructions per cycle at 2.4 GHz (78.6 TFLOP/s of FMA; packed FP32
-# is not used), one VALU instruction per issue cycle at best.  A Kelvin-image pair needs 8
-# VALU instructions: 3 sub, 1 mul + 2 fma for |d|^2, v_rsq_f32 and 1 fma to accumulate; a
-# surface-node pair 14: 3 sub, 3 for |d|^2, v_rsq_f32, 3 for d.y_s, 4 for the
-# monopole+dipole.  The transcendental v_rsq_f32 is counted twice by the SQ busy counters,
-# so the attainable rate lies somewhat below this bound.
+# is not used).  Only the non-transcendental VALU instructions are counted, one issue cycle
+# each; how the transcendental v_rsq_f32 overlaps with them is left out, so the peak is an
+# upper bound.  One-directional Kelvin pair: 3 sub, 1 mul + 2 fma for |d|^2, 1 fma to
+# accumulate = 7; surface-node pair: 3 sub, 3 for |d|^2, 3 for d.y_s, 4 for the
+# monopole+dipole = 13.
 CU, LANES, CLOCK = 256, 64, 2.4e9
 ISSUE_RATE = CU * LANES * CLOCK              # lane-instructions / s
-SLOTS_KELVIN, SLOTS_SURFACE = 8, 14
+SLOTS_KELVIN, SLOTS_SURFACE = 7, 13
 # The symmetric Kelvin kernel computes each ion pair's reciprocal image distance once for both
-# ions: 3 sub, 3 for |d|^2, v_rsq_f32 and one fma per direction, 9 instructions per unordered
-# pair, i.e. 4.5 per Kelvin pair counted in one direction.
-SLOTS_KELVIN_SYM = 4.5
+# ions: 3 sub, 3 for |d|^2 and one fma per direction, 8 instructions per unordered pair, i.e. 4
+# per Kelvin pair counted in one direction.
+SLOTS_KELVIN_SYM = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hsma_eval_c2_n20000_hbm_traffic.txt")
 ENGINE_SRC = os.path.join(ROOT, "paper_1907_01724_amd", "csrc", "hsma_engine.hip")
 
@@ -186,7 +186,8 @@ def main() -> int:
         t_min = (pairs_kelvin * sk + pairs_surface * SLOTS_SURFACE) * nsys / ISSUE_RATE
         peak = eval_pairs / t_min
         achieved = eval_pairs / avg
-        traffic, _ = _measured_traffic(args.prec)
+        traffic = _measured_traffic(args.prec, "k_kelvin_sym<%d>" % (sym // 64) if sym > 0 else "k_eval<%d>" % {
+            "fp32": 0, "fp32c": 1, "fp64": 2}[args.prec])
         out["roofline"] = {
             "bound": "alu",
             "kernel": ("k_kelvin_sym (symmetric Kelvin pairs in blocks of %d ions + surface chunks)" % sym if sym > 0
@@ -200,8 +201,8 @@ def main() -> int:
             "algorithmic_bytes": 40 * N * nsys + 24 * P * nsys,
             "avg_launch_ms": avg * 1e3,
             "pairs_per_launch": eval_pairs,
-            "peak_model": "256 CU x 64 lanes x 2.4 GHz VALU issue, one instruction per cycle; %s instructions per "
-                          "Kelvin pair, 14 per surface pair" % sk,
+            "peak_model": "256 CU x 64 lanes x 2.4 GHz VALU issue, one instruction per cycle; %s non-transcendental "
+                          "VALU instructions per Kelvin pair, 13 per surface pair" % sk,
         }
         out["stage_ms_per_step"] = {k: v[0] / args.steps for k, v in stages.items()}
 
@@ -257,19 +258,20 @@ def main() -> int:
     return 0
 
 
-def _measured_traffic(prec: str):
-    """HBM bytes per launch of the batched evaluation kernel from the committed PMC summary,
-    or None when the kernel source (or the pair precision) differs from what was counted."""
+def _measured_traffic(prec: str, kernel: str):
+    """HBM bytes per launch of the batched evaluation kernel from the committed PMC summary, or
+    None when the kernel, its source (hash) or the pair precision differ from the counted run."""
     import hashlib
     try:
         kv = dict(l.split(None, 1) for l in open(TRAFFIC_FILE) if l.strip() and not l.startswith((" ", "#")))
         with open(ENGINE_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
-        return None, None
-    if kv.get("engine_source_sha256", "").strip() != sha or kv.get("k_eval_pair_precision", "").strip() != prec:
-        return None, None
-    return float(kv["k_eval_traffic_bytes_per_launch"]), float(kv["k_eval_algorithmic_bytes_per_launch"])
+        return None
+    if (kv.get("engine_source_sha256", "").strip() != sha or kv.get("pair_precision", "").strip() != prec
+            or kv.get("kernel", "").strip() != kernel):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def _eval_roofline(pairs_kelvin, pairs_surface, avg_s, sym=0):

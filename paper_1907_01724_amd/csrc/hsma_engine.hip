@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
                                               typename PT<MODE>::T4 *__restrict__ img,
                                               typename PT<MODE>::T4 *__restrict__ tgt,
                                               typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
-                                              float2 *__restrict__ wr, int *__restrict__ flag) {
+                                              float *__restrict__ wk, double *__restrict__ rk, int *__restrict__ flag) {
   using T4 = typename PT<MODE>::T4;
   using T = typename PT<MODE>::T;
   Sched S(const_cast<int64_t *>(base), nsys);
@@ -257,7 +257,10 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
     tgt[i] = make4<T4>(0.0, 0.0, 0.0, 0.0);
     srcw[i] = (T)0;
     self[i] = 0.0;
-    if (wr) wr[i] = make_float2(0.0f, 0.0f);
+    if (wk) {
+      wk[i] = 0.0f;
+      rk[i] = 0.0;
+    }
     return;
   }
   const double qp = qi * c.c0;  // q / (4 pi eps1)
@@ -286,7 +289,10 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   img[i] = make4<T4>(kx, ky, kz, qk);
   tgt[i] = make4<T4>(xi, yi, zi, qp);
   srcw[i] = (T)(qp * r / c.a);
-  if (wr) wr[i] = make_float2((float)(qk * reff), (float)(1.0 / reff));
+  if (wk) {
+    wk[i] = (float)(qk * reff);  // c0 q_K r: the ion's image strength times its radius
+    rk[i] = 1.0 / reff;
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -445,6 +451,7 @@ __global__ __launch_bounds__(256) void k_check_finish(int nsys, int M, int chc, 
   const int64_t chunks = n > 0 ? cdiv64(n, chc) : 0;
   const int64_t g = k / GRP, lane = k % GRP;
   double u = 0.0, v = 0.0;
+#pragma unroll 8
   for (int64_t c = 0; c < chunks; ++c) {
     const int64_t slot = S.pc[b] + (g * chunks + c) * GRP + lane;
     u += part[slot];
@@ -775,7 +782,8 @@ template <int R>
 __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, const int64_t *__restrict__ base,
                                                     const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
                                                     const float4 *__restrict__ tgt, const float4 *__restrict__ img,
-                                                    const float2 *__restrict__ wr, const float4 *__restrict__ nodes,
+                                                    const float *__restrict__ wk, const double *__restrict__ rk,
+                                                    const float4 *__restrict__ nodes,
                                                     const float2 *__restrict__ qd, double *__restrict__ part) {
   constexpr int TB = 64 * R;
   constexpr float FAR_TARGET = 3.0e18f;  // stand-in position of an empty target lane
@@ -823,7 +831,7 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
       tx[k] = t.x;
       ty[k] = t.y;
       tz[k] = t.z;
-      tw[k] = wr[lo + i].x;
+      tw[k] = wk[lo + i];
     } else {
       tx[k] = FAR_TARGET;
       ty[k] = 0.0f;
@@ -910,7 +918,7 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
           for (int k = 0; k < R; ++k) acc[k] += (double)sum[k];
         }
         const int js = jg + lane;
-        if (js < ge) pb[(size_t)I * n + js] = (double)rb * (double)wr[lo + js].y;  // slot I of ion js
+        if (js < ge) pb[(size_t)I * n + js] = (double)rb * rk[lo + js];  // slot I of ion js
       }
     }
     slot = J;
@@ -1024,7 +1032,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   k_fill<<<nsys, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f);
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_f, plans, plan_of, x, y, z, q, img, tgt, srcw, self,
-                                             (float2 *)(ws + L.wr), grp->flag);
+                                             (float *)(ws + L.wk), (double *)(ws + L.rk), grp->flag);
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_CHECK, st);
@@ -1062,12 +1070,13 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   if constexpr (MODE == HSMA_PAIR_FP32_COMP) {
     if (L.sym_tb > 0 && L.items_e > 0) {
       const unsigned gs = (unsigned)cdiv(L.items_e, WAVES);
-      const float2 *wr = (const float2 *)(ws + L.wr);
+      const float *wk = (const float *)(ws + L.wk);
+      const double *rk = (const double *)(ws + L.rk);
       if (L.sym_tb == 256)
-        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wr, grp->nodes32, qd,
+        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
                                             eval_part);
       else
-        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wr, grp->nodes32, qd,
+        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
                                             eval_part);
       done = true;
     }
@@ -1157,7 +1166,8 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n)
   L.tgt = take(t4 * (size_t)total_n);
   L.srcw = take(t1 * (size_t)total_n);
   L.self = take(sizeof(double) * (size_t)total_n);
-  L.wr = take(sizeof(float2) * (size_t)total_n);
+  L.wk = take(sizeof(float) * (size_t)total_n);
+  L.rk = take(sizeof(double) * (size_t)total_n);
   L.chk_part = take(sizeof(double) * 2 * (size_t)L.parts_c);
   L.uv = take(sizeof(double) * 2 * (size_t)M * nsys);
   L.uv32 = L.mfma ? take(sizeof(float) * 2 * (size_t)M * nsys) : 0;

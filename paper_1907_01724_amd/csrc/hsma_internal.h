@@ -160,7 +160,7 @@ struct Layout {
   int64_t items_c, items_e, fin; // upper bounds of the item and finish-block counts
   int64_t parts_c, parts_e;      // upper bounds of the partial-sum slots
   size_t sched, item_sys_c, item_sys_e, fin_sys;
-  size_t img, tgt, srcw, self, wr, chk_part, uv, uv32, ab, h32, gemm2, qd, eval_part, phi, epart, E;
+  size_t img, tgt, srcw, self, wk, rk, chk_part, uv, uv32, ab, h32, gemm2, qd, eval_part, phi, epart, E;
   size_t total;
   bool mfma;                     // fit applied as MFMA GEMMs
 };
