@@ -485,6 +485,7 @@ __global__ __launch_bounds__(256) void k_fit_moments(int K, int M, const TM *__r
   const double *u = uv + (size_t)(2 * b) * M;
   const double *v = u + M;
   double su = 0.0, sv = 0.0;
+#pragma unroll 8
   for (int m = lane; m < M; m += 64) {
     const double wgt = (double)pr[m];
     su = fma(wgt, u[m], su);
@@ -514,6 +515,7 @@ __global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__
   const double *al = ab + (size_t)(2 * b) * K;
   const double *be = al + K;
   double sq = 0.0, sd = 0.0;
+#pragma unroll 4
   for (int k = lane; k < K; k += 64) {
     const double h = fg[k] * al[k] + fg[K + k] * be[k];
     const double l = (double)lr[k];
@@ -894,7 +896,10 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
     } else {
       for (int jg = j0; jg < j1; jg += 64) {
         const int ge = jg + 64 < j1 ? jg + 64 : j1;
-        float rb = 0.0f;  // lane l: reverse total of source jg + l
+        // Reverse totals of the group's sources: each source's total arrives in lane 63 and the
+        // buffer moves down one lane per source (wave_shl:1, lane i reads lane i + 1), so after
+        // the g = ge - jg sources lane 64 - g + t holds source jg + t.
+        float rb = 0.0f;
         for (int jb = jg; jb < ge; jb += TILE) {
           const int je = jb + TILE < ge ? jb + TILE : ge;
           float sum[R];
@@ -911,14 +916,16 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
               rev = fmaf(tw[k], ri, rev);
             }
             rev = wave_total_lane63(rev);
-            const float tot = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rev), 63));
-            rb = (lane == j - jg) ? tot : rb;
+            // wave_shl:1 without zero fill: lane 63 has no source lane and keeps the old value,
+            // which is the new total
+            rb = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(rev), __float_as_int(rb), 0x130, 0xf, 0xf,
+                                                            false));
           }
 #pragma unroll
           for (int k = 0; k < R; ++k) acc[k] += (double)sum[k];
         }
-        const int js = jg + lane;
-        if (js < ge) pb[(size_t)I * n + js] = (double)rb * rk[lo + js];  // slot I of ion js
+        const int js = jg + lane - (64 - (ge - jg));
+        if (js >= jg) pb[(size_t)I * n + js] = (double)rb * rk[lo + js];  // slot I of ion js
       }
     }
     slot = J;
