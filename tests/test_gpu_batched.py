@@ -133,10 +133,14 @@ def test_plans_with_different_cavities(dev):
     _check_systems(group, [plans[w] for w in which], systems, off, phi.cpu().numpy(), E.cpu().numpy(), "fp32c", dev)
 
 
-def test_graph_replay_matches_eager(dev):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_graph_replay_matches_eager(dev, mode):
+    """Mode 2 forces the symmetric Kelvin kernel, whose block pairs run on the group's second
+    stream: the captured graph then holds the fork and join between the two streams."""
     a = 25.0
     plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536)
     group = hs.Group([plan])
+    group.set_symmetric(mode)
     systems = _uneven_systems(a, [100, 2000, 0, 513, 1500, 64, 1, 900, 3000], 900)
     off, off_d, t = _batch(systems, dev)
     n = int(off[-1])
@@ -151,6 +155,7 @@ def test_graph_replay_matches_eager(dev):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         group.energy(off_d, *t, total_n=n, max_n=3000, phi=phi, E=E, stream=s, ws=ws)
+    assert group.eval_kernel(len(systems), n, 3000) == (256 if mode == 2 else 0)
     for rep in range(4):
         phi.zero_()
         E.zero_()
