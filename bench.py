@@ -61,6 +61,8 @@ def main() -> int:
     ap.add_argument("--legs", default="batched,serving,sweep",
                     help="extra workloads after the headline one: batched, serving, sweep (comma list, or none)")
     ap.add_argument("--serving-requests", type=int, default=6000)
+    ap.add_argument("--serving-slots", default="1,2",
+                    help="request server: concurrent single-ion-move batches and full energies")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run two device copies of 256 MiB (a known-traffic kernel for counter scaling)")
     args = ap.parse_args()
@@ -456,7 +458,8 @@ def leg_serving(args) -> dict:
     t0 = time.perf_counter()
     wl = W.workload_c5()
     plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, wl.disc.P, wl.disc.M) for s in wl.systems]
-    server = hs.Server(max_batch=512, delta_slots=3, energy_slots=2)
+    dsl, esl = (int(v) for v in args.serving_slots.split(","))
+    server = hs.Server(max_batch=512, delta_slots=dsl, energy_slots=esl)
     for p, s in zip(plans, wl.systems):
         t = [torch.tensor(getattr(s, k), dtype=torch.float64, device=dev) for k in "xyzq"]
         server.add_system(p, *t)
@@ -502,6 +505,7 @@ def leg_serving(args) -> dict:
     cap = burst["requests_per_s"]
     out = {"workload": "512 resident configurations, N log-uniform in [500, 50000], a~U[15,40], kappa~U[0.05,1], "
                        "P=1024, M=1536; 90% single-ion moves (commit p=1/2), 10% fresh FP64 energies",
+           "slots": {"moves": dsl, "energies": esl},
            "capacity_requests_per_s": cap, "burst": burst,
            "mean_batch": (st1["batched_requests"] - st0["batched_requests"]) / max(1, st1["batches"] - st0["batches"]),
            "loads": []}

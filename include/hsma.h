@@ -235,14 +235,16 @@ hsma_status hsma_system_full_energy(hsma_system_t sys, double *E, void *ws, size
 /* Request server over resident systems.
  *
  * Systems are admitted against a device-memory budget (hsma_server_add_system returns
- * HSMA_EBUSY when the system's resident bytes would exceed it; 0 = half the free memory
- * at creation).  Requests -- a single-ion move (energy change, optionally committed) or a
+ * HSMA_EBUSY when the system's resident bytes, plus any growth of the shared full-energy
+ * workspaces to its size, would exceed it; 0 = half the free memory at creation).  Requests -- a single-ion move (energy change, optionally committed) or a
  * fresh FP64 full energy -- are queued by hsma_server_submit (thread safe) and served by a
  * scheduler thread with continuous batching: whenever one of delta_slots batch slots is
  * free, it launches every waiting move whose system is idle, in arrival order (each system
  * sees its requests in order), up to max_batch; full energies use energy_slots streams of
- * their own.  New batches start while earlier ones run, and a request's result does not
- * depend on the batch it lands in.  Results, with submit/start/done times in seconds since
+ * their own (defaults: 1 and 2; more move slots raise throughput under bursts and lengthen
+ * the latency tail, since streams share the device's hardware queues with the long energy
+ * evaluations).  New batches start while earlier ones run, and a request's result does not
+ * depend on the batch it lands in.  The scheduler sleeps while idle and is woken by submits.  Results, with submit/start/done times in seconds since
  * the server's creation, are collected with hsma_server_poll.  Requests that name an
  * unknown system, an ion out of range or a position outside the cavity complete at once
  * with status HSMA_EINVAL.  hsma_server_run_load submits reqs[i] at arrival[i] seconds

@@ -475,7 +475,7 @@ def requests_array(reqs) -> "C.Array":
 class Server:
     """Continuous-batching request server over resident systems (see hsma_server_* in hsma.h)."""
 
-    def __init__(self, memory_budget: int = 0, max_systems: int = 1024, max_batch: int = 256, delta_slots: int = 3,
+    def __init__(self, memory_budget: int = 0, max_systems: int = 1024, max_batch: int = 256, delta_slots: int = 1,
                  energy_slots: int = 2):
         L = load_library()
         o = ServerOpts(int(memory_budget), int(max_systems), int(max_batch), int(delta_slots), int(energy_slots))

@@ -16,6 +16,7 @@
 #include <atomic>
 #include <cmath>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <thread>
 #include <vector>
@@ -61,6 +62,7 @@ struct hsma_server_s {
   int device = 0;
   hsma_server_opts opts;
   std::mutex mu;
+  std::condition_variable wake;  // signalled on submit and stop: the idle scheduler sleeps on it
   std::deque<Pending> pending;
   std::vector<hsma_result> done;
   std::vector<hsma_system_s *> systems;  // by id; nullptr once removed
@@ -249,27 +251,36 @@ bool schedule_once(hsma_server_s *S) {
   return did;
 }
 
+// The scheduler thread: while requests are pending or on the device it polls (yielding the CPU
+// between passes, since timed sleeps are far coarser than a request); with nothing to do it
+// sleeps until a submit or stop signals it.
 void run_loop(hsma_server_s *S) {
   (void)hipSetDevice(S->device);
   while (!S->stop.load()) {
-    bool did;
-    bool idle;
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      did = schedule_once(S);
-      idle = S->pending.empty();
-      if (idle)
-        for (const DeltaSlot &d : S->dslots) idle = idle && !d.busy;
-      if (idle)
-        for (const EnergySlot &e : S->eslots) idle = idle && !e.busy;
+    std::unique_lock<std::mutex> lk(S->mu);
+    const bool did = schedule_once(S);
+    bool idle = S->pending.empty();
+    if (idle)
+      for (const DeltaSlot &d : S->dslots) idle = idle && !d.busy;
+    if (idle)
+      for (const EnergySlot &e : S->eslots) idle = idle && !e.busy;
+    if (idle) {
+      S->wake.wait_for(lk, std::chrono::milliseconds(100),
+                       [S] { return S->stop.load() || !S->pending.empty(); });
+      continue;
     }
-    if (!did) std::this_thread::sleep_for(std::chrono::microseconds(idle ? 200 : 5));
+    lk.unlock();
+    if (!did) std::this_thread::yield();
   }
 }
 
 void server_free(hsma_server_s *S) {
   if (S->th.joinable()) {
-    S->stop.store(true);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stop.store(true);
+    }
+    S->wake.notify_all();
     S->th.join();
   }
   for (DeltaSlot &d : S->dslots) {
@@ -312,7 +323,7 @@ extern "C" hsma_server_opts hsma_server_opts_default(void) {
   o.memory_budget = 0;
   o.max_systems = 1024;
   o.max_batch = 256;
-  o.delta_slots = 3;
+  o.delta_slots = 1;
   o.energy_slots = 2;
   return o;
 }
@@ -393,6 +404,16 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
   }
   S->used += sys->footprint;
   S->used -= fp;
+  // the full-energy workspaces must grow to this system's size: that memory counts too
+  const size_t need = system_workspace_bytes(sys);
+  size_t grow = 0;
+  for (const EnergySlot &e : S->eslots)
+    if (e.ws_bytes < need) grow += need - e.ws_bytes;
+  if (S->used + grow > S->budget) {
+    S->used -= sys->footprint;
+    hsma_system_destroy(sys);
+    return HSMA_EBUSY;
+  }
   int slot = -1;
   for (size_t i = 0; i < S->systems.size(); ++i)
     if (!S->systems[i]) {
@@ -411,6 +432,19 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
   }
   S->systems[slot] = sys;
   S->busy[slot] = 0;
+  // Full-energy workspaces grow here, at admission, rather than in the scheduler, where freeing
+  // device memory would stall every request in flight (a slot busy now grows when next used).
+  for (EnergySlot &e : S->eslots) {
+    if (e.busy || e.ws_bytes >= need) continue;
+    (void)hipFree(e.ws);
+    S->used -= e.ws_bytes;
+    e.ws = nullptr;
+    e.ws_bytes = 0;
+    if (hipMalloc(&e.ws, need) == hipSuccess) {
+      e.ws_bytes = need;
+      S->used += need;
+    }
+  }
   *id = slot;
   return HSMA_OK;
 }
@@ -449,6 +483,7 @@ extern "C" hsma_status hsma_server_submit(hsma_server_t S, const hsma_request *r
     }
     S->pending.push_back(p);
   }
+  S->wake.notify_one();
   return HSMA_OK;
 }
 

@@ -108,12 +108,18 @@ def test_mix_equals_alone(dev):
 
 
 def test_admission_by_memory(dev):
+    """Each system's resident state counts against the budget, and so do the full-energy
+    workspaces, which are shared and sized by the largest system admitted."""
     items = _make(3, 21, dev, 1000, 1001)
     probe = hs.Server()
     probe.add_system(items[0][0], *items[0][2])
-    per = probe.stats()["memory_used"]
+    one = probe.stats()["memory_used"]
+    probe.add_system(items[1][0], *items[1][2])
+    per = probe.stats()["memory_used"] - one      # one more system of the same size
+    shared = one - per                            # the workspaces
     probe.close()
-    server = hs.Server(memory_budget=int(2.5 * per))
+    assert per > 0 and shared > 0
+    server = hs.Server(memory_budget=int(shared + 2.5 * per))
     a = server.add_system(items[0][0], *items[0][2])
     server.add_system(items[1][0], *items[1][2])
     with pytest.raises(hs.HsmaError) as ei:
