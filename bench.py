@@ -379,9 +379,10 @@ def leg_batched(args) -> dict:
 def leg_sweep(args) -> dict:
     """Precision sweep on N = 1e6 ions uniform in a = 200 (charges +-1 and +-2, 2:1), eps1 = 1,
     eps2 = 80, kappa = 0.1, P = 6400, M = 9600 (p = 40): the whole path with FP32, compensated
-    FP32 and FP64 pair sums (fit applied in FP32 for the FP32 modes, in FP64 for FP64 pairs);
-    the potentials of 256 sampled ions are compared with the oracle's, the energies with the
-    FP64 run's."""
+    FP32 and FP64 pair sums (fit applied with FP32 GEMVs for the FP32 modes, FP64 GEMVs for FP64
+    pairs), and the compensated FP32 path again with the fit applied as FP32 MFMA GEMMs and as
+    split-BF16x3 and split-BF16x6 MFMA GEMMs.  The potentials of 256 sampled ions are compared with the oracle's,
+    the energies with the FP64 run's; each run also reports its fit-stage time."""
     import numpy as np
     import torch
 
@@ -400,12 +401,18 @@ def leg_sweep(args) -> dict:
     pairs = N * d.M + N * (N - 1) + N * d.P
     res = {"workload": "N=1e6 uniform in a=200, charges +-1/+-2 (2:1), eps1=1, eps2=80, kappa=0.1, "
                        "P=6400, M=9600, p=40", "pairs_per_call": pairs}
+    runs = (("fp32", "fp32", 0), ("fp32c", "fp32c", 0), ("fp32c_fit_mfma_fp32", "fp32c", 2),
+            ("fp32c_fit_mfma_bf16x3", "fp32c", 3), ("fp32c_fit_mfma_bf16x6", "fp32c", 4), ("fp64", "fp64", 0))
+    route_name = {1: "gemv", 2: "mfma_fp32", 3: "mfma_bf16x3", 4: "mfma_bf16x6"}
     phis, Es = {}, {}
-    plan = None
-    for prec in ("fp32", "fp32c", "fp64"):
+    plans = {}
+    for label, prec, fit in runs:
         t0 = time.perf_counter()
-        plan = hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=prec)
+        if prec not in plans:
+            plans[prec] = hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=prec)
+        plan = plans[prec]
         t_plan = time.perf_counter() - t0
+        plan.set_fit(fit)
         ws = hs.workspace(plan.workspace_bytes(N), dev)
         phi = torch.empty(N, dtype=torch.float64, device=dev)
         E = torch.empty(1, dtype=torch.float64, device=dev)
@@ -417,28 +424,37 @@ def leg_sweep(args) -> dict:
             plan.energy(x, y, z, q, phi=phi, E=E, ws=ws)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t1) * 1e3 / 2
-        phis[prec] = phi[idx_d].cpu().numpy()
-        Es[prec] = float(E.cpu().numpy()[0])
-        res[prec] = {"ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9, "plan_s": t_plan, "E": Es[prec]}
-        log(f"bench[sweep]: {prec}: {ms:.1f} ms/call ({pairs / (ms * 1e-3) / 1e9:.0f} GPairs/s), plan {t_plan:.2f} s")
+        plan.profile(True)
+        plan.energy(x, y, z, q, phi=phi, E=E, ws=ws)
+        st = plan.profile_read()
+        plan.profile(False)
+        phis[label] = phi[idx_d].cpu().numpy()
+        Es[label] = float(E.cpu().numpy()[0])
+        res[label] = {"ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9, "plan_s": t_plan, "E": Es[label],
+                      "fit": route_name[plan.fit_route()] if prec != "fp64" else "gemv_fp64",
+                      "fit_stage_ms": st["fit"][0]}
+        log(f"bench[sweep]: {label}: {ms:.1f} ms/call ({pairs / (ms * 1e-3) / 1e9:.0f} GPairs/s), "
+            f"fit {res[label]['fit']} {st['fit'][0]:.3f} ms, plan {t_plan:.2f} s")
         del ws, phi
-    for prec in ("fp32", "fp32c"):
-        res[prec]["rel_err_energy_vs_fp64"] = abs(Es[prec] - Es["fp64"]) / abs(Es["fp64"])
+    for label, _, _ in runs[:-1]:
+        res[label]["rel_err_energy_vs_fp64"] = abs(Es[label] - Es["fp64"]) / abs(Es["fp64"])
     if not args.no_oracle:
         import oracle
-        i = plan.info
+        i = plans["fp64"].info
         prm = oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
                             M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"])
         t0 = time.perf_counter()
         ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q,
                                targets=np.stack([s.x[idx], s.y[idx], s.z[idx]], axis=1))
         res["oracle_s"] = time.perf_counter() - t0
-        for prec in ("fp32", "fp32c", "fp64"):
-            err = phis[prec] - ref
-            res[prec]["rel_err_phi_l2_sampled"] = float(np.linalg.norm(err) / np.linalg.norm(ref))
-            res[prec]["max_err_over_max_phi_sampled"] = float(np.max(np.abs(err)) / np.max(np.abs(ref)))
+        for label, _, _ in runs:
+            err = phis[label] - ref
+            res[label]["rel_err_phi_l2_sampled"] = float(np.linalg.norm(err) / np.linalg.norm(ref))
+            res[label]["max_err_over_max_phi_sampled"] = float(np.max(np.abs(err)) / np.max(np.abs(ref)))
         log(f"bench[sweep]: oracle on 256 sampled ions in {res['oracle_s']:.1f} s; rel L2 " +
-            ", ".join(f"{p} {res[p]['rel_err_phi_l2_sampled']:.2e}" for p in ("fp32", "fp32c", "fp64")))
+            ", ".join(f"{lb} {res[lb]['rel_err_phi_l2_sampled']:.2e}" for lb, _, _ in runs))
+    for plan in plans.values():
+        plan.close()
     return res
 
 

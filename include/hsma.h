@@ -193,6 +193,23 @@ hsma_status hsma_group_set_symmetric(hsma_group_t group, int mode);
  * surface chunk) at least cover every SIMD of the device. */
 int hsma_group_eval_kernel(hsma_group_t group, int nsys, int64_t total_n, int64_t max_n);
 
+/* Fit apply (Algorithm 1, steps 3-4: alpha' = Y^+ u, beta' = Y^+ v, then the surface
+ * strengths Q', D' through the fixed operator of eq. "GreenSecond") in the FP32 pair modes.
+ * mode 0 (default): FP32 GEMVs below 8 systems per call, FP32 MFMA GEMMs from 8 systems;
+ * 1: always the GEMVs; 2: always the FP32 MFMA GEMMs; 3: always BF16 MFMA GEMMs with
+ * split-BF16x3 products (each factor split into two BF16 terms, three term products: about
+ * 2^-16 relative per product); 4: the same with split-BF16x6 products (three BF16 terms, six
+ * term products: about 2^-24, as FP32).  The fit amplifies the rounding of the check fields
+ * and of the operators strongly (balanced charges cancel in u, v), so mode 3 can miss the 1e-6
+ * potential target where the surface term is a large share of the potential; modes 1, 2 and
+ * 4 hold it.  The FP64 pair mode always applies the fit with FP64 GEMVs.
+ * Errors: HSMA_EINVAL (mode outside 0..4). */
+hsma_status hsma_group_set_fit(hsma_group_t group, int mode);
+
+/* Which fit route hsma_energy_batched would take for nsys systems: 1 GEMV, 2 FP32 MFMA,
+ * 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA; -1 for invalid arguments. */
+int hsma_group_fit_route(hsma_group_t group, int nsys);
+
 /* Stage timing: when enabled, every compute call on the group records HIP events on its
  * stream around its kernel groups (0 schedule/Kelvin images/packing, 1 check sums, 2 fit
  * apply, 3 evaluation pair sums, 4 final reductions).  hsma_profile_read waits for the

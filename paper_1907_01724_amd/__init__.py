@@ -108,6 +108,9 @@ def load_library(path: str | None = None):
     L.hsma_group_set_symmetric.argtypes = [_VP, C.c_int]
     L.hsma_group_eval_kernel.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
     L.hsma_group_eval_kernel.restype = C.c_int
+    L.hsma_group_set_fit.argtypes = [_VP, C.c_int]
+    L.hsma_group_fit_route.argtypes = [_VP, C.c_int]
+    L.hsma_group_fit_route.restype = C.c_int
     L.hsma_system_create.argtypes = [_VP, C.c_int64] + [_VP] * 4 + [_VP, C.POINTER(_VP)]
     L.hsma_delta_energy.argtypes = [_VP, C.c_int64, C.c_double, C.c_double, C.c_double, _VP, _VP]
     L.hsma_system_commit.argtypes = [_VP, C.c_int64, C.c_double, C.c_double, C.c_double, _VP]
@@ -130,7 +133,8 @@ def load_library(path: str | None = None):
     for name in ("hsma_plan", "hsma_plan_ex", "hsma_plan_destroy", "hsma_plan_get_info", "hsma_potential",
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
-                 "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel", "hsma_system_create", "hsma_delta_energy",
+                 "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
+                 "hsma_group_set_fit", "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
                  "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
@@ -295,6 +299,15 @@ class Plan:
     def eval_kernel(self, N: int) -> int:
         return int(load_library().hsma_group_eval_kernel(self.group, 1, int(N), int(N)))
 
+    def set_fit(self, mode: int = 0):
+        """Fit apply: 0 automatic, 1 GEMV, 2 FP32 MFMA, 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA
+        (FP32 pair modes)."""
+        _check(load_library().hsma_group_set_fit(self.group, int(mode)), "hsma_group_set_fit")
+
+    def fit_route(self) -> int:
+        """1 GEMV, 2 FP32 MFMA, 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA."""
+        return int(load_library().hsma_group_fit_route(self.group, 1))
+
     def profile(self, on: bool = True):
         _profile(self.group, on)
 
@@ -382,6 +395,15 @@ class Group:
     def eval_kernel(self, nsys: int, total_n: int, max_n: int) -> int:
         """Ion-block size of the symmetric Kelvin kernel these sizes would use, or 0."""
         return int(load_library().hsma_group_eval_kernel(self._h, int(nsys), int(total_n), int(max_n)))
+
+    def set_fit(self, mode: int = 0):
+        """Fit apply: 0 automatic, 1 GEMV, 2 FP32 MFMA, 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA
+        (FP32 pair modes)."""
+        _check(load_library().hsma_group_set_fit(self._h, int(mode)), "hsma_group_set_fit")
+
+    def fit_route(self, nsys: int) -> int:
+        """1 GEMV, 2 FP32 MFMA, 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA."""
+        return int(load_library().hsma_group_fit_route(self._h, int(nsys)))
 
     def profile(self, on: bool = True):
         _profile(self._h, on)

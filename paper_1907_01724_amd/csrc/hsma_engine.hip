@@ -593,6 +593,113 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int nrows, int ncols, int kdim,
     }
 }
 
+// Fit apply on BF16 MFMA with split products.  Every factor x is taken as a sum of BF16
+// terms b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1), and the product of two
+// factors as the sum of the term products whose orders add to at most NS - 1:
+//   NS = 2 (split-BF16x3): a0 c0 + a0 c1 + a1 c0; the two-term split leaves up to 2^-16 |x|,
+//           so a product carries up to 3 * 2^-16 relative error;
+//   NS = 3 (split-BF16x6): also a0 c2 + a2 c0 + a1 c1, leaving about 2^-24, as FP32.
+// C[col][row] = sum_k A[row][k] B[col][k]; A comes pre-split (plane t of nrows rows, row
+// stride kp = kdim rounded up to 32, zero padding), B is FP32 with row stride kdim and is
+// split while it is staged.  v_mfma_f32_16x16x32_bf16: a lane holds 8 consecutive k of one row
+// (A) or column (B); both operands use the same k order, so the contraction does not depend
+// on it.  Block tile 64 x 64, four waves of 32 x 32, k staged 32 at a time; the smallest
+// products are accumulated first, and the FP32 accumulators are folded into FP64 every 64 k,
+// as in k_gemm_nt.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline uint32_t bf16_rne_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_gemm_bf(int nrows, int ncols, int kdim, int kp,
+                                                 const uint16_t *__restrict__ A, const float *__restrict__ B,
+                                                 float *__restrict__ C) {
+  __shared__ __align__(16) uint16_t As[NS][64][40];
+  __shared__ __align__(16) uint16_t Bs[NS][64][40];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+  const int sr = t >> 2, sc = (t & 3) * 8;  // staging: row / column sr, k offset sc
+  floatx4 acc[2][2];
+  double dacc[2][2][4];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int r = 0; r < 4; ++r) dacc[i][j][r] = 0.0;
+    }
+  int step = 0;
+  for (int k0 = 0; k0 < kdim; k0 += 32) {
+    {
+      const int gr = row0 + sr;
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        uint4 h = make_uint4(0, 0, 0, 0);
+        if (gr < nrows)  // k0 + sc + 7 < kp: the padded rows cover every staged k
+          h = *(const uint4 *)(A + ((size_t)p * nrows + gr) * kp + k0 + sc);
+        *(uint4 *)&As[p][sr][sc] = h;
+      }
+      const int gc = col0 + sr;
+      uint32_t bb[NS][8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + sc + e;
+        float v = (gc < ncols && gk < kdim) ? B[(size_t)gc * kdim + gk] : 0.0f;
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+          bb[p][e] = bf16_rne_bits(v);
+          v -= __uint_as_float(bb[p][e] << 16);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NS; ++p)
+        *(uint4 *)&Bs[p][sr][sc] = make_uint4(bb[p][0] | bb[p][1] << 16, bb[p][2] | bb[p][3] << 16,
+                                              bb[p][4] | bb[p][5] << 16, bb[p][6] | bb[p][7] << 16);
+    }
+    __syncthreads();
+    const int kl = 8 * (lane >> 4);
+    bf16x8 af[NS][2], bf[NS][2];
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+      for (int i = 0; i < 2; ++i) {
+        af[p][i] = *(const bf16x8 *)&As[p][wr * 32 + i * 16 + (lane & 15)][kl];
+        bf[p][i] = *(const bf16x8 *)&Bs[p][wc * 32 + i * 16 + (lane & 15)][kl];
+      }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        floatx4 c = acc[i][j];
+        if constexpr (NS == 3) {
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bf[1][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bf[0][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[2][j], c, 0, 0, 0);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bf[0][j], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[1][j], c, 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bf[0][j], c, 0, 0, 0);
+      }
+    __syncthreads();
+    if (++step == 2 || k0 + 32 >= kdim) {
+      step = 0;
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          for (int r = 0; r < 4; ++r) dacc[i][j][r] += (double)acc[i][j][r];
+          acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int col = col0 + wc * 32 + j * 16 + (lane & 15);
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < nrows && col < ncols) C[(size_t)col * nrows + row] = (float)dacc[i][j][r];
+      }
+    }
+}
+
 // h = f . alpha' + g . beta' from the first GEMM's output ab32 [2 nsys][K]; writes the
 // second GEMM's operand h32 [2 nsys][K]: row 2b = n . h, row 2b+1 = h.
 __global__ __launch_bounds__(256) void k_fit_h(int nsys, const int64_t *__restrict__ base, int K,
@@ -1056,10 +1163,20 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
     float *h32 = (float *)(ws + L.h32);
     float *c2 = (float *)(ws + L.gemm2);
     dim3 g1((unsigned)cdiv(K, 64), (unsigned)cdiv(2 * (int64_t)nsys, 64));
-    k_gemm_nt<<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->pinv32, uv32, ab32);
+    if (L.bf_terms == 2)
+      k_gemm_bf<2><<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->Mp, g->pinv_bf, uv32, ab32);
+    else if (L.bf_terms == 3)
+      k_gemm_bf<3><<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->Mp, g->pinv_bf, uv32, ab32);
+    else
+      k_gemm_nt<<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->pinv32, uv32, ab32);
     k_fit_h<<<(int)cdiv((int64_t)nsys * K, 256), 256, 0, st>>>(nsys, base, K, ab32, plans, plan_of, g->nidx, h32);
     dim3 g2((unsigned)cdiv(P, 64), (unsigned)cdiv(2 * (int64_t)nsys, 64));
-    k_gemm_nt<<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->lhat32, h32, c2);
+    if (L.bf_terms == 2)
+      k_gemm_bf<2><<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->Kp, g->lhat_bf, h32, c2);
+    else if (L.bf_terms == 3)
+      k_gemm_bf<3><<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->Kp, g->lhat_bf, h32, c2);
+    else
+      k_gemm_nt<<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->lhat32, h32, c2);
     k_fit_qd<T2><<<(int)cdiv((int64_t)nsys * P, 256), 256, 0, st>>>(nsys, P, c2, qd);
   } else if constexpr (MODE == HSMA_PAIR_FP64) {
     k_fit_moments<double><<<dim3((unsigned)cdiv(K, 4), nsys), 256, 0, st>>>(K, M, g->pinv64, uv, ab);
@@ -1156,7 +1273,9 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n)
     }
   }
   L.fin = total_n > 0 ? total_n / FINB + nsys : 0;
-  L.mfma = !fp64 && nsys >= 8;
+  const int fit = grp->tune.fit;
+  L.mfma = !fp64 && (fit >= 2 || (fit == 0 && nsys >= 8));
+  L.bf_terms = fp64 ? 0 : fit == 3 ? 2 : fit == 4 ? 3 : 0;
   const size_t t4 = fp64 ? sizeof(double4) : sizeof(float4);
   const size_t t1 = fp64 ? sizeof(double) : sizeof(float);
   size_t o = 0;
@@ -1338,6 +1457,18 @@ extern "C" hsma_status hsma_group_set_symmetric(hsma_group_t grp, int on) {
   if (!grp || on < 0 || on > 3) return HSMA_EINVAL;
   grp->tune.symmetric = on;
   return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_group_set_fit(hsma_group_t grp, int mode) {
+  if (!grp || mode < 0 || mode > 4) return HSMA_EINVAL;
+  grp->tune.fit = mode;
+  return HSMA_OK;
+}
+
+extern "C" int hsma_group_fit_route(hsma_group_t grp, int nsys) {
+  if (!grp || nsys < 1) return -1;
+  const Layout L = layout(grp, nsys, 0, 0);
+  return L.bf_terms == 3 ? 4 : L.bf_terms == 2 ? 3 : L.mfma ? 2 : 1;
 }
 
 extern "C" hsma_status hsma_debug_intermediates(hsma_plan_t pl, int64_t N, const void *ws, hipStream_t st, double *u,

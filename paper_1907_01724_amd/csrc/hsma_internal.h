@@ -33,6 +33,12 @@ struct Geometry {
   float *pinv32;       // same, FP32
   double *lhat64;      // P x K: what_s (1 + tau)^n Y_nm(y_s) / (4 pi)
   float *lhat32;       // same, FP32
+  // The two operators split into three BF16 terms x ~ b0 + b1 + b2 (b0 = bf16(x),
+  // b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)) for the split-BF16 MFMA fits: the b0 plane,
+  // then b1, then b2, each row zero-padded to a multiple of 32 columns.
+  uint16_t *pinv_bf;   // 3 x K x Mp, Mp = M rounded up to 32
+  uint16_t *lhat_bf;   // 3 x P x Kp, Kp = K rounded up to 32
+  int Mp, Kp;
   int *nidx;           // K: degree n of each coefficient index
   int refs;
 };
@@ -113,6 +119,8 @@ struct hsma_tune_s {
   int occ_eval;      // (occupancy API, set when the group is built)
   int symmetric;     // symmetric Kelvin kernel: 0 never, 1 for large launches, 2 / 3 whenever it
                      // applies with ion blocks of 256 / 512
+  int fit;           // fit apply in the FP32 pair modes: 0 automatic, 1 GEMV, 2 FP32 MFMA,
+                     // 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA
 };
 
 struct hsma_group_s {
@@ -163,6 +171,7 @@ struct Layout {
   size_t img, tgt, srcw, self, wk, rk, chk_part, uv, uv32, ab, h32, gemm2, qd, eval_part, phi, epart, E;
   size_t total;
   bool mfma;                     // fit applied as MFMA GEMMs
+  int bf_terms;                  // ... with products of BF16 splits of 2 (x3) or 3 (x6) terms; 0: FP32
 };
 Layout layout(const hsma_group_s *g, int nsys, int64_t total_n, int64_t max_n);
 
