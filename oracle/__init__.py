@@ -72,6 +72,10 @@ def lib():
         L.orc_hsma_eval.argtypes = [P, C.c_long, _DP, _DP, _DP, _DP, C.c_long, _DP, _DP, _DP, _DP,
                                     C.POINTER(_Diag)]
         L.orc_hsma_eval.restype = C.c_int
+        L.orc_hsma_field.argtypes = [P, C.c_long, _DP, _DP, _DP, _DP, C.c_long, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
+        L.orc_hsma_field.restype = C.c_int
+        L.orc_surface_field.argtypes = [P, _DP, _DP, _DP, C.c_long, _DP, _DP, _DP, _DP, _DP, _DP]
+        L.orc_kelvin_field.argtypes = [P, C.c_long, _DP, _DP, _DP, _DP, C.c_long, _DP, _DP, _DP, _DP, _DP, _DP]
         L.orc_kirkwood_eval.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_long,
                                         _DP, _DP, _DP, _DP, C.c_long, _DP, _DP, _DP, C.c_int, C.c_int,
                                         C.c_double, _DP, _DP]
@@ -232,6 +236,17 @@ def surface_potential(prm: Params, nodes, Q, D, targets):
     return out
 
 
+def surface_field(prm: Params, nodes, Q, D, targets):
+    """Field -grad of the surface images' potential at ``targets`` (nt, 3)."""
+    t = _f64(targets)
+    tx, ty, tz = (_f64(t[:, k]) for k in range(3))
+    ex, ey, ez = np.zeros(len(tx)), np.zeros(len(tx)), np.zeros(len(tx))
+    cp = prm.c()
+    lib().orc_surface_field(C.byref(cp), _p(_f64(nodes)), _p(_f64(Q)), _p(_f64(D)), len(tx), _p(tx), _p(ty), _p(tz),
+                            _p(ex), _p(ey), _p(ez))
+    return np.stack([ex, ey, ez], axis=1)
+
+
 def kelvin_potential(prm: Params, x, y, z, q, targets):
     x, y, z, q = map(_f64, (x, y, z, q))
     t = _f64(targets)
@@ -268,6 +283,26 @@ def hsma_eval(prm: Params, x, y, z, q, targets=None, diag: bool = False):
     if st != 0:
         raise ValueError(f"oracle HSMA failed with status {st}")
     return (phi, d) if diag else phi
+
+
+def hsma_field(prm: Params, x, y, z, q, targets=None):
+    """O1 reaction potential and field E = -grad Phi_RF at ``targets`` (default: at the ions),
+    every image held fixed (Algorithm 1, step 5).  Returns (phi, E) with E of shape (nt, 3)."""
+    x, y, z, q = map(_f64, (x, y, z, q))
+    if targets is None:
+        tx, ty, tz = x, y, z
+    else:
+        t = _f64(targets)
+        tx, ty, tz = (_f64(t[:, k]) for k in range(3))
+    nt = len(tx)
+    phi = np.zeros(nt)
+    ex, ey, ez = np.zeros(nt), np.zeros(nt), np.zeros(nt)
+    cp = prm.c()
+    st = lib().orc_hsma_field(C.byref(cp), len(x), _p(x), _p(y), _p(z), _p(q), nt, _p(tx), _p(ty), _p(tz),
+                              _p(phi), _p(ex), _p(ey), _p(ez))
+    if st != 0:
+        raise ValueError(f"oracle HSMA field failed with status {st}")
+    return phi, np.stack([ex, ey, ez], axis=1)
 
 
 def kirkwood_eval(a, eps1, eps2, kappa, x, y, z, q, targets=None, order: int = 0, nmax: int = 200000,

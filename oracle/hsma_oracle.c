@@ -472,6 +472,139 @@ done:
 }
 
 /* ------------------------------------------------------------------------- */
+/* Field at the targets (Algorithm 1, step 5: "potential/field").                */
+/* ------------------------------------------------------------------------- */
+
+/* E = -grad Phi at the target with every source held fixed: for an image charge c at
+ * position s, the field c (x - s) / |x - s|^3 in units of the potential's prefactor.
+ * Kelvin images (Sec. 2.4): c = q_K,i / (4 pi eps1) at r_K,i; an ion at the centre
+ * has its image at infinity and adds a constant potential, hence no field.        */
+void orc_kelvin_field(const orc_params *pp, long N, const double *x, const double *y, const double *z,
+                      const double *q, long nt, const double *tx, const double *ty, const double *tz,
+                      double *ex, double *ey, double *ez) {
+  double eps = pp->eps1 / pp->eps2, mu = pp->kappa * pp->a, Rt = (1.0 + pp->tau) * pp->a;
+  double g3[3];
+  orc_image_constants(eps, mu, g3);
+  double a = pp->a, c0 = 1.0 / (4.0 * ORC_PI * pp->eps1);
+#pragma omp parallel for schedule(static)
+  for (long t = 0; t < nt; t++) {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (long i = 0; i < N; i++) {
+      double ri = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+      if (ri == 0.0) continue;
+      double f = (a / ri) * (a / ri);
+      double rK = a * a / ri;
+      double qK = q[i] / a * (g3[0] * rK + g3[2] * (Rt - rK) / 2.0);
+      double dx = tx[t] - f * x[i], dy = ty[t] - f * y[i], dz = tz[t] - f * z[i];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double c = c0 * qK / (r * r * r);
+      fx += c * dx;
+      fy += c * dy;
+      fz += c * dz;
+    }
+    ex[t] = fx;
+    ey[t] = fy;
+    ez[t] = fz;
+  }
+}
+
+/* Field of the surface images (eq. "GreenSecond" discretised by the Fibonacci rule).
+ * Monopole Q at y: Q d / (4 pi |d|^3), d = x - y.  Exact dipole (dipole = 0), potential
+ * D (d . u) / (4 pi |d|^3) with u the outward unit normal: its negative gradient is
+ * D [3 (d . u) d / |d|^5 - u / |d|^3] / (4 pi).  Paper form (dipole = 1): the two point
+ * charges -D/dy at (R_tau - dy/2) u and +D/dy at (R_tau + dy/2) u (eq. "threeintegrals"). */
+void orc_surface_field(const orc_params *pp, const double *nodes, const double *Q, const double *D, long nt,
+                       const double *tx, const double *ty, const double *tz, double *ex, double *ey, double *ez) {
+  double Rt = (1.0 + pp->tau) * pp->a;
+  double dy = pp->dy_over_Rtau * Rt;
+  double k4 = 1.0 / (4.0 * ORC_PI);
+#pragma omp parallel for schedule(static)
+  for (long t = 0; t < nt; t++) {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int k = 0; k < pp->P; k++) {
+      double ux = nodes[3 * k] / Rt, uy = nodes[3 * k + 1] / Rt, uz = nodes[3 * k + 2] / Rt;
+      double dx = tx[t] - nodes[3 * k], dyy = ty[t] - nodes[3 * k + 1], dz = tz[t] - nodes[3 * k + 2];
+      double r = sqrt(dx * dx + dyy * dyy + dz * dz);
+      double r3 = r * r * r;
+      double c = k4 * Q[k] / r3;
+      fx += c * dx;
+      fy += c * dyy;
+      fz += c * dz;
+      if (pp->dipole == 0) {
+        double du = dx * ux + dyy * uy + dz * uz;
+        double cd = k4 * D[k] * 3.0 * du / (r3 * r * r), cu = k4 * D[k] / r3;
+        fx += cd * dx - cu * ux;
+        fy += cd * dyy - cu * uy;
+        fz += cd * dz - cu * uz;
+      } else {
+        double rm = Rt - 0.5 * dy, rp = Rt + 0.5 * dy;
+        double mx = tx[t] - rm * ux, my = ty[t] - rm * uy, mz = tz[t] - rm * uz;
+        double px = tx[t] - rp * ux, py = ty[t] - rp * uy, pz = tz[t] - rp * uz;
+        double rmm = sqrt(mx * mx + my * my + mz * mz), rpp = sqrt(px * px + py * py + pz * pz);
+        double cm = k4 * (-D[k] / dy) / (rmm * rmm * rmm), cp = k4 * (D[k] / dy) / (rpp * rpp * rpp);
+        fx += cm * mx + cp * px;
+        fy += cm * my + cp * py;
+        fz += cm * mz + cp * pz;
+      }
+    }
+    ex[t] = fx;
+    ey[t] = fy;
+    ez[t] = fz;
+  }
+}
+
+/* O1 with the field: Algorithm 1 as in orc_hsma_eval (steps 1-4 give the images and
+ * the surface strengths), then step 5 evaluates both the potential and the field
+ * E = -grad Phi_RF at the targets, every image held fixed.  Return codes as
+ * orc_hsma_eval.                                                                */
+int orc_hsma_field(const orc_params *pp, long N, const double *x, const double *y, const double *z,
+                   const double *q, long nt, const double *tx, const double *ty, const double *tz,
+                   double *phi, double *ex, double *ey, double *ez) {
+  if (!orc_params_ok(pp)) return -1;
+  for (long i = 0; i < N; i++)
+    if (!(sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]) < pp->a)) return -2;
+  int p = pp->p, K = (p + 1) * (p + 1), M = pp->M, P = pp->P, F2 = P / 2 - 1;
+  double Rt = (1.0 + pp->tau) * pp->a;
+  size_t n1 = (size_t)(nt > 0 ? nt : 1);
+  double *chk = (double *)malloc(sizeof(double) * 3 * (size_t)M);
+  double *u = (double *)malloc(sizeof(double) * (size_t)M);
+  double *v = (double *)malloc(sizeof(double) * (size_t)M);
+  double *al = (double *)malloc(sizeof(double) * (size_t)K);
+  double *be = (double *)malloc(sizeof(double) * (size_t)K);
+  double *Ah = (double *)malloc(sizeof(double) * (size_t)K);
+  double *nodes = (double *)malloc(sizeof(double) * 3 * (size_t)P);
+  double *w = (double *)malloc(sizeof(double) * (size_t)P);
+  double *Q = (double *)malloc(sizeof(double) * (size_t)P);
+  double *D = (double *)malloc(sizeof(double) * (size_t)P);
+  double *pk = (double *)malloc(sizeof(double) * n1);
+  double *ps = (double *)malloc(sizeof(double) * n1);
+  double *fk = (double *)malloc(sizeof(double) * 3 * n1);
+  double *fs = (double *)malloc(sizeof(double) * 3 * n1);
+  int st = 0;
+
+  orc_check_lattice(M, pp->rc_over_a * pp->a, chk);                       /* step 1 */
+  orc_check_fields(pp, N, x, y, z, q, chk, u, v);                          /* step 2 */
+  if (orc_fit_moments(pp, chk, u, v, al, be) != 0) { st = -3; goto done; } /* step 3 */
+  orc_correction_coeffs(pp, al, be, Ah);
+  orc_fibonacci_nodes(pp->F1, F2, Rt, nodes, w);                           /* step 4 */
+  orc_surface_strengths(pp, Ah, nodes, w, Q, D);
+  orc_kelvin_potential(pp, N, x, y, z, q, nt, tx, ty, tz, pk);             /* step 5 */
+  orc_surface_potential(pp, nodes, Q, D, nt, tx, ty, tz, ps);
+  orc_kelvin_field(pp, N, x, y, z, q, nt, tx, ty, tz, fk, fk + n1, fk + 2 * n1);
+  orc_surface_field(pp, nodes, Q, D, nt, tx, ty, tz, fs, fs + n1, fs + 2 * n1);
+  for (long t = 0; t < nt; t++) {
+    phi[t] = pk[t] + ps[t];
+    ex[t] = fk[t] + fs[t];
+    ey[t] = fk[n1 + t] + fs[n1 + t];
+    ez[t] = fk[2 * n1 + t] + fs[2 * n1 + t];
+  }
+done:
+  free(chk); free(u); free(v); free(al); free(be); free(Ah);
+  free(nodes); free(w); free(Q); free(D); free(pk); free(ps); free(fk); free(fs);
+  return st;
+}
+
+/* ------------------------------------------------------------------------- */
 /* O2: the Kirkwood series (Sec. 2.2).                                          */
 /* ------------------------------------------------------------------------- */
 
