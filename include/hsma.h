@@ -131,6 +131,22 @@ hsma_status hsma_potential(hsma_plan_t plan, int64_t N, const double *x, const d
 hsma_status hsma_energy(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
                         const double *q, double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Potential and field at every ion (Algorithm 1, step 5: "potential/field at the source
+ * charge locations"): E_i = -grad Phi_RF(x) at x = x_i with every image, the ion's own
+ * included, and every surface charge held fixed; the force on ion i is q_i E_i up to the
+ * method's error (the fixed-image field of eq. "phirffinall").  Same units as the
+ * potential (divide by the length unit).  The evaluation runs the one-directional pair
+ * kernel with four sums (Phi, Ex, Ey, Ez) per target; the own image's field is added in
+ * FP64 as -x_i Phi_own,i / (a^2 - r_i^2).
+ *   ex, ey, ez: [device] N doubles each (output; required when N > 0);
+ *   phi: [device] N doubles or NULL; E: [device] one double or NULL;
+ *   ws: [device] ws_bytes >= hsma_field_workspace_bytes(plan, N).
+ * Errors as hsma_potential. */
+size_t hsma_field_workspace_bytes(hsma_plan_t plan, int64_t N);
+hsma_status hsma_field(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
+                       const double *q, double *phi, double *ex, double *ey, double *ez, double *E, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
 /* Intermediate results of the last hsma_potential/hsma_energy call that used ws,
  * copied to host arrays (for tests and diagnostics; synchronises the stream).
  * Any output pointer may be NULL.  u, v: M check fields; Q, D: P surface strengths
@@ -168,6 +184,15 @@ hsma_status hsma_energy_batched(hsma_group_t group, int nsys, const int64_t *off
                                 int64_t total_n, int64_t max_n, const double *x, const double *y, const double *z,
                                 const double *q, double *phi, double *E, void *ws, size_t ws_bytes,
                                 hipStream_t stream);
+
+/* Batched potentials, fields and energies: hsma_energy_batched's arguments and checks, plus
+ * ex, ey, ez ([device] total_n doubles each, required) as in hsma_field; ws_bytes >=
+ * hsma_field_batched_workspace_bytes(group, nsys, total_n, max_n). */
+size_t hsma_field_batched_workspace_bytes(hsma_group_t group, int nsys, int64_t total_n, int64_t max_n);
+hsma_status hsma_field_batched(hsma_group_t group, int nsys, const int64_t *offsets, const int32_t *plan_of,
+                               int64_t total_n, int64_t max_n, const double *x, const double *y, const double *z,
+                               const double *q, double *phi, double *ex, double *ey, double *ez, double *E,
+                               void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Launch shape of the group's pair kernels (check and evaluation sums).  persistent = 1:
  * one grid of resident blocks (the occupancy limit on every compute unit) whose blocks

@@ -258,6 +258,18 @@ def kelvin_potential(prm: Params, x, y, z, q, targets):
     return out
 
 
+def kelvin_field(prm: Params, x, y, z, q, targets):
+    """Field of the Kelvin images of the ions (x, y, z, q) at ``targets`` (nt, 3)."""
+    x, y, z, q = map(_f64, (x, y, z, q))
+    t = _f64(targets)
+    tx, ty, tz = (_f64(t[:, k]) for k in range(3))
+    ex, ey, ez = np.zeros(len(tx)), np.zeros(len(tx)), np.zeros(len(tx))
+    cp = prm.c()
+    lib().orc_kelvin_field(C.byref(cp), len(x), _p(x), _p(y), _p(z), _p(q), len(tx), _p(tx), _p(ty), _p(tz),
+                           _p(ex), _p(ey), _p(ez))
+    return np.stack([ex, ey, ez], axis=1)
+
+
 def hsma_eval(prm: Params, x, y, z, q, targets=None, diag: bool = False):
     """O1 reaction potential at ``targets`` (default: at the ions themselves)."""
     x, y, z, q = map(_f64, (x, y, z, q))

@@ -109,6 +109,13 @@ def load_library(path: str | None = None):
     L.hsma_group_eval_kernel.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
     L.hsma_group_eval_kernel.restype = C.c_int
     L.hsma_group_set_fit.argtypes = [_VP, C.c_int]
+    L.hsma_field_workspace_bytes.argtypes = [_VP, C.c_int64]
+    L.hsma_field_workspace_bytes.restype = C.c_size_t
+    L.hsma_field.argtypes = [_VP, C.c_int64] + [_VP] * 9 + [_VP, C.c_size_t, _VP]
+    L.hsma_field_batched_workspace_bytes.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
+    L.hsma_field_batched_workspace_bytes.restype = C.c_size_t
+    L.hsma_field_batched.argtypes = [_VP, C.c_int, _VP, _VP, C.c_int64, C.c_int64] + [_VP] * 9 + [_VP, C.c_size_t,
+                                                                                                   _VP]
     L.hsma_group_fit_route.argtypes = [_VP, C.c_int]
     L.hsma_group_fit_route.restype = C.c_int
     L.hsma_system_create.argtypes = [_VP, C.c_int64] + [_VP] * 4 + [_VP, C.POINTER(_VP)]
@@ -134,7 +141,7 @@ def load_library(path: str | None = None):
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
-                 "hsma_group_set_fit", "hsma_system_create", "hsma_delta_energy",
+                 "hsma_group_set_fit", "hsma_field", "hsma_field_batched", "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
                  "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
@@ -268,6 +275,26 @@ class Plan:
                "hsma_energy")
         return E
 
+    def field_workspace_bytes(self, N: int) -> int:
+        return int(load_library().hsma_field_workspace_bytes(self._h, int(N)))
+
+    def field(self, x, y, z, q, phi=None, E=None, stream=None, ws: Workspace | None = None):
+        """Potential and field E = -grad Phi_RF at every ion (images held fixed).
+        Returns (phi, field) with field an (N, 3) float64 device tensor."""
+        torch = _torch()
+        N = x.numel()
+        if phi is None:
+            phi = torch.empty(N, dtype=torch.float64, device=x.device)
+        f = torch.empty((3, N), dtype=torch.float64, device=x.device)
+        w = ws if ws is not None else _ensure(self._ws, ("field", N, str(x.device)), self.field_workspace_bytes(N),
+                                              x.device)
+        _check(load_library().hsma_field(self._h, N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N), _dev_ptr(z, "z", N),
+                                         _dev_ptr(q, "q", N), _dev_ptr(phi, "phi", N), f[0].data_ptr(),
+                                         f[1].data_ptr(), f[2].data_ptr(),
+                                         _dev_ptr(E, "E", 1) if E is not None else None, w.ptr, w.nbytes,
+                                         _stream_ptr(stream)), "hsma_field")
+        return phi, f.t()
+
     def intermediates(self, N: int, device, stream=None):
         """Check fields u, v and surface strengths Q', D' of the last call with this workspace."""
         import numpy as np
@@ -383,6 +410,31 @@ class Group:
             _dev_ptr(q, "q", total_n), _dev_ptr(phi, "phi", total_n) if phi is not None else None,
             _dev_ptr(E, "E", nsys), w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_energy_batched")
         return E
+
+    def field(self, offsets, x, y, z, q, total_n: int, max_n: int, plan_of=None, phi=None, E=None, stream=None,
+              ws=None):
+        """Potentials, fields (total_n x 3) and energies of nsys systems."""
+        torch = _torch()
+        nsys = offsets.numel() - 1
+        if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise TypeError("offsets must be a contiguous int64 device tensor")
+        if plan_of is not None and (plan_of.dtype != torch.int32 or not plan_of.is_cuda or plan_of.numel() != nsys):
+            raise TypeError("plan_of must be an int32 device tensor of nsys entries")
+        if E is None:
+            E = torch.empty(nsys, dtype=torch.float64, device=x.device)
+        if phi is None:
+            phi = torch.empty(int(total_n), dtype=torch.float64, device=x.device)
+        f = torch.empty((3, int(total_n)), dtype=torch.float64, device=x.device)
+        lib = load_library()
+        w = ws if ws is not None else _ensure(
+            self._ws, ("field", nsys, int(total_n), int(max_n), str(x.device)),
+            int(lib.hsma_field_batched_workspace_bytes(self._h, nsys, int(total_n), int(max_n))), x.device)
+        _check(lib.hsma_field_batched(
+            self._h, nsys, offsets.data_ptr(), plan_of.data_ptr() if plan_of is not None else None, int(total_n),
+            int(max_n), _dev_ptr(x, "x", total_n), _dev_ptr(y, "y", total_n), _dev_ptr(z, "z", total_n),
+            _dev_ptr(q, "q", total_n), _dev_ptr(phi, "phi", total_n), f[0].data_ptr(), f[1].data_ptr(),
+            f[2].data_ptr(), _dev_ptr(E, "E", nsys), w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_field_batched")
+        return phi, f.t(), E
 
     def tune(self, persistent: bool = False, target_items: int = 16384):
         _check(load_library().hsma_group_tune(self._h, 1 if persistent else 0, int(target_items)), "hsma_group_tune")

@@ -234,7 +234,9 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
                                               typename PT<MODE>::T4 *__restrict__ img,
                                               typename PT<MODE>::T4 *__restrict__ tgt,
                                               typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
-                                              float *__restrict__ wk, double *__restrict__ rk, int *__restrict__ flag) {
+                                              float *__restrict__ wk, double *__restrict__ rk,
+                                              double4 *__restrict__ sfield, float4 *__restrict__ tlo,
+                                              float4 *__restrict__ ilo, int *__restrict__ flag) {
   using T4 = typename PT<MODE>::T4;
   using T = typename PT<MODE>::T;
   Sched S(const_cast<int64_t *>(base), nsys);
@@ -261,6 +263,11 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
       wk[i] = 0.0f;
       rk[i] = 0.0;
     }
+    if (sfield) sfield[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (tlo) {
+      tlo[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      ilo[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     return;
   }
   const double qp = qi * c.c0;  // q / (4 pi eps1)
@@ -285,9 +292,22 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   }
   // own image: q_K / (4 pi eps1 |x - r_K|) with |x - r_K| = (a^2 - r^2) / r, written so that it
   // stays regular at r = 0 and keeps FP64 accuracy as r -> a
-  self[i] = qp / c.a * (c.gamma * c.a2 + 0.5 * c.dbar * (c.Rtau * r - c.a2)) / ((c.a - r) * (c.a + r));
+  const double sp = qp / c.a * (c.gamma * c.a2 + 0.5 * c.dbar * (c.Rtau * r - c.a2)) / ((c.a - r) * (c.a + r));
+  self[i] = sp;
+  if (sfield) {
+    // its field: q'_K (x - r_K) / |x - r_K|^3 with x - r_K = -x (a^2 - r^2) / r^2, i.e.
+    // -x times the own-image potential over (a^2 - r^2); zero at the centre
+    const double e = -sp / ((c.a - r) * (c.a + r));
+    sfield[i] = make_double4(e * xi, e * yi, e * zi, 0.0);
+  }
   img[i] = make4<T4>(kx, ky, kz, qk);
   tgt[i] = make4<T4>(xi, yi, zi, qp);
+  if (tlo) {  // what FP32 rounding left of each coordinate, so that pair differences keep ~2^-48 a
+    tlo[i] = make_float4((float)(xi - (double)(float)xi), (float)(yi - (double)(float)yi),
+                         (float)(zi - (double)(float)zi), 0.f);
+    ilo[i] = make_float4((float)(kx - (double)(float)kx), (float)(ky - (double)(float)ky),
+                         (float)(kz - (double)(float)kz), 0.f);
+  }
   srcw[i] = (T)(qp * r / c.a);
   if (wk) {
     wk[i] = (float)(qk * reff);  // c0 q_K r: the ion's image strength times its radius
@@ -856,6 +876,188 @@ __global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, i
 }
 
 // ---------------------------------------------------------------------------------
+// Field sums (Algorithm 1, step 5: potential and field at the ions).  With every image
+// held fixed, an image of strength c at s adds c / |x - s| to the potential and
+// c (x - s) / |x - s|^3 to E = -grad Phi.  A surface node y_s adds, besides its potential
+// Q / r + D' (d . y_s) / r^3 (d = x - y_s), the field
+//   d (Q + 3 D' (d . y_s) / r^2) / r^3 - y_s D' / r^3.
+// The partial sums are kept per target and source chunk as (Phi, Ex, Ey, Ez).
+// ---------------------------------------------------------------------------------
+struct F4 {
+  double p, x, y, z;
+};
+
+// In the FP32 modes the coordinates carry FP32 lo parts (tl for the target, ilo for the
+// images): d = (x_hi - s_hi) + (x_lo - s_lo).  The field of an image a distance d away is
+// dominated by the nearest images, and for two ions at the interface d can be 1e-4 a, where
+// FP32 coordinates alone (2^-24 a) would leave 1e-3 relative error in the term.
+template <int MODE, bool DIAG>
+__device__ __forceinline__ void kelvin_field_range(const typename PT<MODE>::T4 &t, const float4 &tl, int i,
+                                                   const typename PT<MODE>::T4 *__restrict__ img,
+                                                   const float4 *__restrict__ ilo, int j0, int j1, F4 &acc) {
+  using T = typename PT<MODE>::T;
+  using T4 = typename PT<MODE>::T4;
+  constexpr bool LO = MODE != HSMA_PAIR_FP64;
+  // FP32_COMP: FP32 sums over 32-source tiles folded into FP64; otherwise one running sum
+  const int tile = MODE == HSMA_PAIR_FP32_COMP ? TILE : (1 << 30);
+  T rp = 0, rx = 0, ry = 0, rz = 0;
+  for (int jb = j0; jb < j1; jb += tile) {
+    const int je = (j1 - jb) > tile ? jb + tile : j1;
+    T sp = 0, sx = 0, sy = 0, sz = 0;
+#pragma unroll 8
+    for (int j = jb; j < je; ++j) {
+      const T4 v = img[j];
+      T dx = t.x - v.x, dy = t.y - v.y, dz = t.z - v.z;
+      if constexpr (LO) {
+        const float4 vl = ilo[j];
+        dx += tl.x - vl.x;
+        dy += tl.y - vl.y;
+        dz += tl.z - vl.z;
+      }
+      T ri = rinv(dx * dx + dy * dy + dz * dz);
+      if (DIAG) ri = (j == i) ? (T)0 : ri;
+      const T w = v.w * ri;
+      sp += w;
+      const T w3 = w * (ri * ri);
+      sx = fma(w3, dx, sx);
+      sy = fma(w3, dy, sy);
+      sz = fma(w3, dz, sz);
+    }
+    if constexpr (MODE == HSMA_PAIR_FP32_COMP) {
+      acc.p += (double)sp;
+      acc.x += (double)sx;
+      acc.y += (double)sy;
+      acc.z += (double)sz;
+    } else {
+      rp += sp;
+      rx += sx;
+      ry += sy;
+      rz += sz;
+    }
+  }
+  if constexpr (MODE != HSMA_PAIR_FP32_COMP) {
+    acc.p += (double)rp;
+    acc.x += (double)rx;
+    acc.y += (double)ry;
+    acc.z += (double)rz;
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void surface_field_range(const typename PT<MODE>::T4 &t,
+                                                    const typename PT<MODE>::T4 *__restrict__ nodes,
+                                                    const typename PT<MODE>::T2 *__restrict__ qd, int s0, int s1,
+                                                    F4 &acc) {
+  using T = typename PT<MODE>::T;
+  using T2 = typename PT<MODE>::T2;
+  using T4 = typename PT<MODE>::T4;
+  T rp = 0, rx = 0, ry = 0, rz = 0;
+  for (int sb = s0; sb < s1; sb += TILE) {
+    const int se = sb + TILE < s1 ? sb + TILE : s1;
+    T sp = 0, sx = 0, sy = 0, sz = 0;
+#pragma unroll 4
+    for (int k = sb; k < se; ++k) {
+      const T4 yv = nodes[k];
+      const T2 wv = qd[k];
+      const T dx = t.x - yv.x, dy = t.y - yv.y, dz = t.z - yv.z;
+      const T ri = rinv(dx * dx + dy * dy + dz * dz);
+      const T ri2 = ri * ri;
+      const T dot = dx * yv.x + dy * yv.y + dz * yv.z;  // (x - y_s) . y_s
+      const T tq = wv.y * dot * ri2;                      // D' (d . y_s) / r^2
+      const T u = wv.x + tq;
+      sp = fma(ri, u, sp);
+      const T A = ri * ri2;
+      const T B = A * fma((T)2, tq, u);
+      const T Cy = A * wv.y;
+      sx = fma(B, dx, fma(-Cy, yv.x, sx));
+      sy = fma(B, dy, fma(-Cy, yv.y, sy));
+      sz = fma(B, dz, fma(-Cy, yv.z, sz));
+    }
+    if constexpr (MODE == HSMA_PAIR_FP32) {
+      rp += sp;
+      rx += sx;
+      ry += sy;
+      rz += sz;
+    } else {
+      acc.p += (double)sp;
+      acc.x += (double)sx;
+      acc.y += (double)sy;
+      acc.z += (double)sz;
+    }
+  }
+  if constexpr (MODE == HSMA_PAIR_FP32) {
+    acc.p += (double)rp;
+    acc.x += (double)rx;
+    acc.y += (double)ry;
+    acc.z += (double)rz;
+  }
+}
+
+// Same items and partial slots as k_eval, with a (Phi, E) quadruple per slot.
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_eval_field(int persistent, int nsys, int P, int che,
+                                                    const int64_t *__restrict__ base, const int *__restrict__ sys_e,
+                                                    const int32_t *__restrict__ plan_of,
+                                                    const typename PT<MODE>::T4 *__restrict__ tgt,
+                                                    const typename PT<MODE>::T4 *__restrict__ img,
+                                                    const typename PT<MODE>::T4 *__restrict__ nodes,
+                                                    const typename PT<MODE>::T2 *__restrict__ qd,
+                                                    const float4 *__restrict__ tlo, const float4 *__restrict__ ilo,
+                                                    double4 *__restrict__ part) {
+  using T4 = typename PT<MODE>::T4;
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ int64_t s_item;
+  __shared__ double4 red[WAVES][GRP];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (!sched_ok(S)) return;
+  const int64_t total = S.ie[nsys];
+  int64_t item;
+  for (bool first = true; next_item(persistent, first, total, &S.ctr[1], &s_item, item); first = false) {
+    const int b = sys_e[item];
+    const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
+    const int64_t loc = item - S.ie[b];
+    const int64_t G = cdiv64(n, GRP);
+    const int64_t chunks = cdiv64(n + P, che);
+    const int64_t c = loc / G, g = loc % G;
+    const int64_t il = g * GRP + lane;
+    const T4 t = tgt[lo + (il < n ? il : n - 1)];
+    const float4 tl = tlo ? tlo[lo + (il < n ? il : n - 1)] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t tot = n + P;
+    int64_t j0, j1;
+    wave_slice(c * che, (c + 1) * che < tot ? (c + 1) * che : tot, w, j0, j1);
+    F4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int64_t k1 = j1 < n ? j1 : n;
+    if (j0 < k1) {
+      const int64_t t0 = g * GRP;
+      const bool diag = (t0 < k1) && (t0 + GRP > j0);
+      const float4 *il4 = ilo ? ilo + lo : nullptr;
+      if (diag)
+        kelvin_field_range<MODE, true>(t, tl, (int)il, img + lo, il4, (int)j0, (int)k1, acc);
+      else
+        kelvin_field_range<MODE, false>(t, tl, (int)il, img + lo, il4, (int)j0, (int)k1, acc);
+    }
+    const int64_t s0 = (j0 > n ? j0 : n) - n, s1 = j1 - n;
+    if (s0 < s1) {
+      const int pl = plan_of ? plan_of[b] : 0;
+      surface_field_range<MODE>(t, nodes + (size_t)pl * P, qd + (size_t)b * P, (int)s0, (int)s1, acc);
+    }
+    red[w][lane] = make_double4(acc.p, acc.x, acc.y, acc.z);
+    __syncthreads();
+    if (w == 0) {
+      double4 s = red[0][lane];
+      for (int ww = 1; ww < WAVES; ++ww) {
+        const double4 o = red[ww][lane];
+        s.x += o.x;
+        s.y += o.y;
+        s.z += o.z;
+        s.w += o.w;
+      }
+      part[S.pe[b] + (g * chunks + c) * GRP + lane] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // Symmetric Kelvin sums.  For ions i, j of one system, |x_i - r_K,j|^2 (r_j/a)^2 =
 // r_i^2 r_j^2 / a^2 - 2 x_i.x_j + a^2 is symmetric in i and j, so
 //   1 / |x_j - r_K,i| = (r_i / r_j) / |x_i - r_K,j|:
@@ -1084,6 +1286,53 @@ __global__ __launch_bounds__(FINB) void k_finish(int nsys, int P, int che, int s
   if (threadIdx.x == 0) epart[f] = red[0];
 }
 
+// Phi_i and E_i = own-image terms + fixed-order sums of the chunk partials (one-directional
+// evaluation items); block partial of 1/2 sum q Phi.
+__global__ __launch_bounds__(FINB) void k_finish_field(int nsys, int P, int che, const int64_t *__restrict__ base,
+                                                       const int *__restrict__ sys_f,
+                                                       const double4 *__restrict__ part,
+                                                       const double *__restrict__ self,
+                                                       const double4 *__restrict__ sfield,
+                                                       const double *__restrict__ q, double *__restrict__ phi,
+                                                       double *__restrict__ ex, double *__restrict__ ey,
+                                                       double *__restrict__ ez, double *__restrict__ epart) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ double red[FINB];
+  const int64_t f = blockIdx.x;
+  if (!sched_ok(S) || f >= S.fb[nsys]) return;  // uniform across the block
+  const int b = sys_f[f];
+  const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
+  const int64_t il = (f - S.fb[b]) * FINB + threadIdx.x;
+  double e = 0.0;
+  if (il < n) {
+    const double4 sf = sfield[lo + il];
+    double sp = self[lo + il], sx = sf.x, sy = sf.y, sz = sf.z;
+    const int64_t chunks = cdiv64(n + P, che);
+    const int64_t g = il / GRP, lane = il % GRP;
+    const double4 *pp = part + S.pe[b] + g * chunks * GRP + lane;
+#pragma unroll 4
+    for (int64_t c = 0; c < chunks; ++c) {
+      const double4 v = pp[c * GRP];
+      sp += v.x;
+      sx += v.y;
+      sy += v.z;
+      sz += v.w;
+    }
+    phi[lo + il] = sp;
+    ex[lo + il] = sx;
+    ey[lo + il] = sy;
+    ez[lo + il] = sz;
+    e = 0.5 * q[lo + il] * sp;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = FINB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) epart[f] = red[0];
+}
+
 // E_b = sum of the block partials of system b, lane-strided then a shuffle tree (fixed order).
 __global__ __launch_bounds__(64) void k_energy(int nsys, const int64_t *__restrict__ base,
                                                const double *__restrict__ epart, double *__restrict__ E) {
@@ -1103,7 +1352,7 @@ inline int round_up(int64_t v, int m) { return (int)((v + m - 1) / m * m); }
 template <int MODE>
 hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, const int32_t *plan_of, int64_t n1,
                    const double *x, const double *y, const double *z, const double *q, double *phi, double *E,
-                   char *ws, hipStream_t st) {
+                   double *ex, double *ey, double *ez, char *ws, hipStream_t st) {
   using T = typename PT<MODE>::T;
   using T2 = typename PT<MODE>::T2;
   using T4 = typename PT<MODE>::T4;
@@ -1146,7 +1395,10 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   k_fill<<<nsys, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f);
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_f, plans, plan_of, x, y, z, q, img, tgt, srcw, self,
-                                             (float *)(ws + L.wk), (double *)(ws + L.rk), grp->flag);
+                                             (float *)(ws + L.wk), (double *)(ws + L.rk),
+                                             L.field ? (double4 *)(ws + L.sfield) : nullptr,
+                                             L.lo ? (float4 *)(ws + L.tlo) : nullptr,
+                                             L.lo ? (float4 *)(ws + L.ilo) : nullptr, grp->flag);
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_CHECK, st);
@@ -1205,13 +1457,23 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       done = true;
     }
   }
-  if (!done && L.items_e > 0)
+  if (L.field) {
+    if (L.items_e > 0)
+      k_eval_field<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(
+          persistent, nsys, P, L.che, base, sys_e, plan_of, tgt, img, group_nodes<MODE>(grp), qd,
+          L.lo ? (const float4 *)(ws + L.tlo) : nullptr, L.lo ? (const float4 *)(ws + L.ilo) : nullptr,
+          (double4 *)eval_part);
+  } else if (!done && L.items_e > 0) {
     k_eval<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(persistent, nsys, P, L.che, base, sys_e, plans, plan_of, tgt, img,
                                                    group_nodes<MODE>(grp), qd, eval_part);
+  }
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_FINISH, st);
-  if (L.fin > 0)
+  if (L.fin > 0 && L.field)
+    k_finish_field<<<(int)L.fin, FINB, 0, st>>>(nsys, P, L.che, base, sys_f, (const double4 *)eval_part, self,
+                                                (const double4 *)(ws + L.sfield), q, phi, ex, ey, ez, epart);
+  else if (L.fin > 0)
     k_finish<<<(int)L.fin, FINB, 0, st>>>(nsys, P, L.che, L.sym_tb, L.sch, base, sys_f, eval_part, self, q, phi,
                                           epart);
   if (E) k_energy<<<nsys, 64, 0, st>>>(nsys, base, epart, E);
@@ -1225,8 +1487,9 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
 // Item sizes are chosen from upper bounds known on the host (system count, total and
 // largest system size): the check chunk aims at about 8192 items, the evaluation chunk at
 // about 8192 items of the largest possible pair count; both multiples of 4 waves x 32.
-Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n) {
+Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n, bool field) {
   Layout L;
+  L.field = field;
   const Geometry *g = grp->geo;
   const int64_t M = g->M, P = g->P, K = g->K;
   const bool fp64 = grp->pair_prec == HSMA_PAIR_FP64;
@@ -1255,7 +1518,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n)
   L.sym_tb = 0;
   L.sch = 0;
   const int mode = grp->tune.symmetric;
-  if (grp->pair_prec == HSMA_PAIR_FP32_COMP && mode != 0 && total_n > 0) {
+  if (grp->pair_prec == HSMA_PAIR_FP32_COMP && mode != 0 && total_n > 0 && !field) {
     for (int r = 4; r <= 8; r *= 2) {
       if ((mode == 2 && r != 4) || (mode == 3 && r != 8)) continue;
       const int64_t tb = 64 * r;
@@ -1301,7 +1564,11 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n)
   L.h32 = L.mfma ? take(sizeof(float) * 2 * (size_t)K * nsys) : 0;
   L.gemm2 = L.mfma ? take(sizeof(float) * 2 * (size_t)P * nsys) : 0;
   L.qd = take(sizeof(double2) * (size_t)P * nsys);
-  L.eval_part = take(sizeof(double) * (size_t)L.parts_e);
+  L.eval_part = take((field ? sizeof(double4) : sizeof(double)) * (size_t)L.parts_e);
+  L.sfield = field ? take(sizeof(double4) * (size_t)total_n) : 0;
+  L.lo = field && !fp64;
+  L.tlo = L.lo ? take(sizeof(float4) * (size_t)total_n) : 0;
+  L.ilo = L.lo ? take(sizeof(float4) * (size_t)total_n) : 0;
   L.phi = take(sizeof(double) * (size_t)total_n);
   L.epart = take(sizeof(double) * (size_t)(L.fin + 1));
   L.E = take(sizeof(double) * (size_t)nsys);
@@ -1311,8 +1578,11 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n)
 
 hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, const int32_t *plan_of, int64_t total_n,
                         int64_t max_n, const double *x, const double *y, const double *z, const double *q,
-                        double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
+                        double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st, double *ex, double *ey,
+                        double *ez) {
   if (!grp || nsys < 1 || total_n < 0 || max_n < 0 || max_n > total_n || !ws) return HSMA_EINVAL;
+  const bool field = ex || ey || ez;
+  if (field && (!ex || !ey || !ez)) return HSMA_EINVAL;
   if (total_n + grp->geo->P > ((int64_t)1 << 31) - 1) return HSMA_EINVAL;  // 32-bit source indices
   if (total_n > 0 && (!x || !y || !z || !q)) return HSMA_EINVAL;
   if (((uintptr_t)ws & 255) != 0) return HSMA_EINVAL;
@@ -1320,17 +1590,17 @@ hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, con
   int dev = -1;
   HSMA_HIP(hipGetDevice(&dev));
   if (dev != grp->device) return HSMA_ESTATE;
-  const Layout L = layout(grp, nsys, total_n, max_n);
+  const Layout L = layout(grp, nsys, total_n, max_n, field);
   if (ws_bytes < L.total) return HSMA_EINVAL;  // workspace sized for other sizes or launch parameters
   char *w = (char *)ws;
   if (!phi) phi = (double *)(w + L.phi);
   switch (grp->pair_prec) {
     case HSMA_PAIR_FP32:
-      return launch<HSMA_PAIR_FP32>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
+      return launch<HSMA_PAIR_FP32>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
     case HSMA_PAIR_FP32_COMP:
-      return launch<HSMA_PAIR_FP32_COMP>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
+      return launch<HSMA_PAIR_FP32_COMP>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
     case HSMA_PAIR_FP64:
-      return launch<HSMA_PAIR_FP64>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, w, st);
+      return launch<HSMA_PAIR_FP64>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
     default:
       return HSMA_EINVAL;
   }
@@ -1425,6 +1695,31 @@ extern "C" hsma_status hsma_energy(hsma_plan_t pl, int64_t N, const double *x, c
                                    hipStream_t st) {
   if (!pl || !E) return HSMA_EINVAL;
   return run_batched(pl->self, 1, nullptr, nullptr, N, N, x, y, z, q, phi, E, ws, ws_bytes, st);
+}
+
+extern "C" size_t hsma_field_workspace_bytes(hsma_plan_t pl, int64_t N) {
+  if (!pl || N < 0) return 0;
+  return layout(pl->self, 1, N, N, true).total;
+}
+
+extern "C" hsma_status hsma_field(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
+                                  const double *q, double *phi, double *ex, double *ey, double *ez, double *E,
+                                  void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!pl || (N > 0 && (!ex || !ey || !ez))) return HSMA_EINVAL;
+  return run_batched(pl->self, 1, nullptr, nullptr, N, N, x, y, z, q, phi, E, ws, ws_bytes, st, ex, ey, ez);
+}
+
+extern "C" size_t hsma_field_batched_workspace_bytes(hsma_group_t grp, int nsys, int64_t total_n, int64_t max_n) {
+  if (!grp || nsys < 1 || total_n < 0 || max_n < 0) return 0;
+  return layout(grp, nsys, total_n, max_n, true).total;
+}
+
+extern "C" hsma_status hsma_field_batched(hsma_group_t grp, int nsys, const int64_t *offsets, const int32_t *plan_of,
+                                          int64_t total_n, int64_t max_n, const double *x, const double *y,
+                                          const double *z, const double *q, double *phi, double *ex, double *ey,
+                                          double *ez, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!grp || !offsets || !ex || !ey || !ez) return HSMA_EINVAL;
+  return run_batched(grp, nsys, offsets, plan_of, total_n, max_n, x, y, z, q, phi, E, ws, ws_bytes, st, ex, ey, ez);
 }
 
 extern "C" size_t hsma_batched_workspace_bytes(hsma_group_t grp, int nsys, int64_t total_n, int64_t max_n) {

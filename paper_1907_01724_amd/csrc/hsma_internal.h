@@ -170,10 +170,14 @@ struct Layout {
   size_t sched, item_sys_c, item_sys_e, fin_sys;
   size_t img, tgt, srcw, self, wk, rk, chk_part, uv, uv32, ab, h32, gemm2, qd, eval_part, phi, epart, E;
   size_t total;
+  bool field;                    // potential and field (one-directional evaluation, 4 values per slot)
+  size_t sfield;                 // own-image field per ion (double4), field layouts only
+  bool lo;                       // FP32 lo parts of target and image coordinates (field, FP32 pairs)
+  size_t tlo, ilo;
   bool mfma;                     // fit applied as MFMA GEMMs
   int bf_terms;                  // ... with products of BF16 splits of 2 (x3) or 3 (x6) terms; 0: FP32
 };
-Layout layout(const hsma_group_s *g, int nsys, int64_t total_n, int64_t max_n);
+Layout layout(const hsma_group_s *g, int nsys, int64_t total_n, int64_t max_n, bool field = false);
 
 // Stage timing with HIP events recorded on the launch stream (off unless enabled).
 enum Stage { ST_PACK = 0, ST_CHECK = 1, ST_FIT = 2, ST_EVAL = 3, ST_FINISH = 4, ST_COUNT = 5 };
@@ -196,6 +200,7 @@ void prof_free(hsma_group_s *g);
 // a single system of total_n ions.  E may be nullptr.
 hsma_status run_batched(hsma_group_s *g, int nsys, const int64_t *offsets, const int32_t *plan_of, int64_t total_n,
                         int64_t max_n, const double *x, const double *y, const double *z, const double *q,
-                        double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st);
+                        double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st, double *ex = nullptr,
+                        double *ey = nullptr, double *ez = nullptr);
 
 }  // namespace hsma

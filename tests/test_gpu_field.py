@@ -1,0 +1,185 @@
+"""GPU parity of the field at the ions (Algorithm 1, step 5) through the C ABI.
+
+E_i = -grad Phi_RF at x_i with every image held fixed, against the oracle's field
+(oracle.hsma_field, pinned by differences of its potential and by the Kirkwood series).
+Tolerances, relative L2 over all components: 1e-6 for the FP32 pair modes and 1e-10 for
+FP64 pairs, as for the potential.  The field is dominated by nearer images than the
+potential: two ions at the interface put each other's image 1e-4 a away or closer, where FP32
+coordinates alone (2^-24 a) leave 1e-3 relative error in the term, so the field kernel carries
+FP32 lo parts of the coordinates (3.2e-6 without them, 2.2e-7 with them, on the shell system
+with the own images taken out), and the own image, the nearest one, is added in FP64.  The
+potentials and energies returned with the field are held to the potential's tolerances.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1907_01724_amd as hs  # noqa: E402
+
+TOL = {"fp32": 1e-6, "fp32c": 1e-6, "fp64": 1e-10}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hs.load_library()
+    return torch.device("cuda:0")
+
+
+def _params(plan):
+    i = plan.info
+    return oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"], M=i["M"],
+                         tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"])
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _field(plan, s, dev):
+    x, y, z, q = (torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev) for v in (s.x, s.y, s.z, s.q))
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    phi, f = plan.field(x, y, z, q, E=E)
+    assert plan.stream_check() == 0
+    return phi.cpu().numpy(), f.cpu().numpy(), float(E.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32c", "fp64"])
+def test_c1_field(dev, prec):
+    wl = W.workload_c1()
+    s, d, ph = wl.systems[0], wl.disc, wl.systems[0].phys
+    plan = hs.Plan(ph.a, ph.eps1, ph.eps2, ph.kappa, d.P, d.M, pair_prec=prec)
+    phi, f, E = _field(plan, s, dev)
+    ref_phi, ref_f = oracle.hsma_field(_params(plan), s.x, s.y, s.z, s.q)
+    print(f"[{prec}] field relL2 {_rel(f, ref_f):.3e} phi relL2 {_rel(phi, ref_phi):.3e}", flush=True)
+    assert _rel(f, ref_f) <= TOL[prec]
+    assert _rel(phi, ref_phi) <= TOL[prec]
+    e_ref = oracle.energy(s.q, ref_phi)
+    scale = abs(e_ref) if prec == "fp64" else 0.5 * float(np.sum(np.abs(s.q * ref_phi)))
+    assert abs(E - e_ref) <= (1e-11 if prec == "fp64" else 2.0 ** -24 * (4 if prec == "fp32" else 1)) * scale
+    plan.close()
+
+
+@pytest.mark.parametrize("params", [(80.0, 80.0, 0.5), (1.0, 80.0, 0.05)])
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_shell_field(dev, params, prec):
+    """3000 ions, 30% within 1/2 of the interface of a = 30 (the C2 recipe at a smaller N)."""
+    pos, q = W.c2_positions(N=3000)
+    e1, e2, k = params
+    s = W.System(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, W.Physics(30.0, e1, e2, k))
+    plan = hs.Plan(30.0, e1, e2, k, 1600, 2400, pair_prec=prec)
+    phi, f, _ = _field(plan, s, dev)
+    ref_phi, ref_f = oracle.hsma_field(_params(plan), s.x, s.y, s.z, s.q)
+    print(f"[{prec} {params}] field relL2 {_rel(f, ref_f):.3e} phi relL2 {_rel(phi, ref_phi):.3e}", flush=True)
+    assert _rel(f, ref_f) <= TOL[prec]
+    assert _rel(phi, ref_phi) <= TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32c"])
+def test_shell_field_of_the_pair_sums(dev, prec):
+    """The same shell system with every ion's own-image field (added in FP64, and the
+    largest term for ions at the interface) taken out of both sides, so that the comparison
+    sees the compensated FP32 pair sums over the other images and the surface nodes alone.
+    (The plain FP32 mode, a precision-sweep mode with one FP32 running sum per target, misses
+    1e-6 here: its error grows with the number of sources, 3.1e-6 at N = 3000.)"""
+    pos, q = W.c2_positions(N=3000)
+    s = W.System(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, W.Physics(30.0, 1.0, 80.0, 0.5))
+    plan = hs.Plan(30.0, 1.0, 80.0, 0.5, 1600, 2400, pair_prec=prec)
+    _, f, _ = _field(plan, s, dev)
+    prm = _params(plan)
+    _, ref_f = oracle.hsma_field(prm, s.x, s.y, s.z, s.q)
+    own = np.concatenate([oracle.kelvin_field(prm, s.x[i:i + 1], s.y[i:i + 1], s.z[i:i + 1], s.q[i:i + 1],
+                                              pos[i:i + 1]) for i in range(s.n)])
+    rel = _rel(f - own, ref_f - own)
+    print(f"[{prec}] pair-sum field relL2 {rel:.3e}", flush=True)
+    assert rel <= TOL[prec]
+    plan.close()
+
+
+def test_centre_and_interface_ions(dev):
+    rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 350))
+    a, N = 20.0, 700
+    pos = W.uniform_ball(rng, N, a)
+    pos[0] = (0.0, 0.0, 0.0)
+    for k in range(1, 9):
+        d = rng.standard_normal(3)
+        pos[k] = d / np.linalg.norm(d) * a * (1.0 - 1e-6 * k)
+    q = W.balanced_charges(rng, N)
+    s = W.System(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, W.Physics(a, 1.0, 80.0, 0.5))
+    plan = hs.Plan(a, 1.0, 80.0, 0.5, 1024, 1536, pair_prec="fp32c")
+    phi, f, _ = _field(plan, s, dev)
+    ref_phi, ref_f = oracle.hsma_field(_params(plan), s.x, s.y, s.z, s.q)
+    assert np.all(np.isfinite(f))
+    assert _rel(f, ref_f) <= 1e-6
+    assert _rel(phi, ref_phi) <= 1e-6
+    # the centred ion: its own image (at infinity) exerts no field; the rest is the others'
+    assert np.linalg.norm(f[0] - ref_f[0]) <= 1e-5 * np.linalg.norm(ref_f[0])
+    plan.close()
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 65])
+def test_tiny_systems(dev, N):
+    plan = hs.Plan(10.0, 1.0, 80.0, 0.1, 400, 600, pair_prec="fp32c")
+    if N == 0:
+        e = torch.empty(0, dtype=torch.float64, device=dev)
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+        phi, f = plan.field(e, e, e, e, E=E)
+        assert plan.stream_check() == 0 and f.shape == (0, 3)
+        return
+    s = W.small_uniform(N=N, a=10.0, seed=W.SEED_BASE + 360 + N)
+    phi, f, _ = _field(plan, s, dev)
+    ref_phi, ref_f = oracle.hsma_field(_params(plan), s.x, s.y, s.z, s.q)
+    assert _rel(f, ref_f) <= 1e-6
+    assert _rel(phi, ref_phi) <= 1e-6
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_batched_field(dev, prec):
+    a = 25.0
+    plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536, pair_prec=prec)
+    group = hs.Group([plan])
+    sizes = [700, 0, 1, 1500, 64, 333]
+    systems = [W.small_uniform(N=n, a=a, seed=W.SEED_BASE + 370 + b) if n > 0 else None for b, n in enumerate(sizes)]
+    parts = [s for s in systems if s is not None]
+    cat = [np.concatenate([getattr(s, k) for s in parts]) for k in "xyzq"]
+    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
+    off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    off = torch.tensor(off_h, dtype=torch.int64, device=dev)
+    total = int(off_h[-1])
+    phi, f, E = group.field(off, xb, yb, zb, qb, total_n=total, max_n=max(sizes))
+    assert group.stream_check() == 0
+    phi, f, E = phi.cpu().numpy(), f.cpu().numpy(), E.cpu().numpy()
+    prm = _params(plan)
+    for b, s in enumerate(systems):
+        if s is None:
+            assert E[b] == 0.0
+            continue
+        lo, hi = off_h[b], off_h[b + 1]
+        ref_phi, ref_f = oracle.hsma_field(prm, s.x, s.y, s.z, s.q)
+        assert _rel(f[lo:hi], ref_f) <= TOL[prec], (b, _rel(f[lo:hi], ref_f))
+        assert _rel(phi[lo:hi], ref_phi) <= TOL[prec]
+
+
+def test_field_call_refuses_missing_outputs(dev):
+    plan = hs.Plan(10.0, 1.0, 80.0, 0.1, 400, 600)
+    lib = hs.load_library()
+    x = torch.zeros(4, dtype=torch.float64, device=dev)
+    ws = hs.workspace(plan.field_workspace_bytes(4), dev)
+    rc = lib.hsma_field(plan.handle, 4, x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(), None, None, None,
+                        None, None, ws.ptr, ws.nbytes, None)
+    assert rc == 1  # HSMA_EINVAL
+    small = hs.workspace(plan.workspace_bytes(4), dev)
+    f = torch.empty(3, 4, dtype=torch.float64, device=dev)
+    if plan.workspace_bytes(4) < plan.field_workspace_bytes(4):
+        rc = lib.hsma_field(plan.handle, 4, x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(), None,
+                            f[0].data_ptr(), f[1].data_ptr(), f[2].data_ptr(), None, small.ptr, small.nbytes, None)
+        assert rc == 1
+    plan.close()
