@@ -42,6 +42,10 @@ SLOTS_KELVIN, SLOTS_SURFACE = 7, 13
 # ions: 3 sub, 3 for |d|^2 and one fma per direction, 8 instructions per unordered pair, i.e. 4
 # per Kelvin pair counted in one direction.
 SLOTS_KELVIN_SYM = 4
+# Field kernel (potential and E = -grad Phi together): Kelvin pair with hi/lo coordinates 9 (d) +
+# 3 (|d|^2) + 2 (strength / r, potential) + 2 (1/r^3 factor) + 3 (E); surface node 3 + 3 + 1 (1/r^2)
+# + 3 (d . y) + 2 + 1 + 1 (potential) + 4 (factors) + 6 (E).  rsq not counted, as above.
+SLOTS_FIELD_KELVIN, SLOTS_FIELD_SURFACE = 19, 24
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hsma_eval_c2_n20000_hbm_traffic.txt")
 ENGINE_SRC = os.path.join(ROOT, "paper_1907_01724_amd", "csrc", "hsma_engine.hip")
 
@@ -58,8 +62,9 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="batched,serving,sweep",
-                    help="extra workloads after the headline one: batched, serving, sweep (comma list, or none)")
+    ap.add_argument("--legs", default="batched,serving,sweep,field",
+                    help="extra workloads after the headline one: batched, serving, sweep, field (comma list, or "
+                         "none)")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--serving-slots", default="1,2",
                     help="request server: concurrent single-ion-move batches and full energies")
@@ -256,6 +261,8 @@ def main() -> int:
         out["serving"] = leg_serving(args)
     if "sweep" in legs:
         out["precision_sweep"] = leg_sweep(args)
+    if "field" in legs:
+        out["field"] = leg_field(args)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -281,6 +288,85 @@ def _eval_roofline(pairs_kelvin, pairs_surface, avg_s, sym=0):
     pairs = pairs_kelvin + pairs_surface
     return {"bound": "alu", "achieved": pairs / avg_s / 1e9, "peak": pairs / t_min / 1e9, "unit": "Gpair/s",
             "frac": t_min / avg_s, "avg_launch_ms": avg_s * 1e3, "symmetric_block": sym}
+
+
+def leg_field(args) -> dict:
+    """Potential, field and energy at the ions of the headline workload (N = 20000, a = 30,
+    30% in the shell, P = 1600, M = 2400, the four parameter sets in one batched call):
+    time per call, the field kernel against its ALU roofline, and the relative L2 error of
+    every ion's potential and field per system against the oracle's."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.workload_c2()
+    d, systems = wl.disc, wl.systems
+    N, nsys = systems[0].n, len(systems)
+    plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=args.prec)
+             for s in systems]
+    group = hs.Group(plans)
+    cat = [np.concatenate([getattr(s, k) for s in systems]) for k in "xyzq"]
+    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
+    off = torch.tensor(np.arange(nsys + 1) * N, dtype=torch.int64, device=dev)
+    plan_of = torch.arange(nsys, dtype=torch.int32, device=dev)
+    total = nsys * N
+
+    def call():
+        return group.field(off, xb, yb, zb, qb, total_n=total, max_n=N, plan_of=plan_of)
+
+    call()
+    torch.cuda.synchronize()
+    assert group.stream_check() == 0
+    steps = 10
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        phi, f, E = call()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    group.profile(True)
+    group.profile_read()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    st = group.profile_read()
+    group.profile(False)
+    inf = plans[0].info
+    P, M = inf["P"], inf["M"]
+    pk, ps = N * (N - 1) * nsys, N * P * nsys
+    pairs = pk + ps + N * M * nsys
+    ev = st["eval"][0] / steps * 1e-3
+    t_min = (pk * SLOTS_FIELD_KELVIN + ps * SLOTS_FIELD_SURFACE) / ISSUE_RATE
+    res = {"workload": "N=20000, a=30, 30% in the shell [a-1/2,a), P=1600, M=2400, p=20, 4 (eps1,eps2,kappa) sets, "
+                       "potential + field + energy", "ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9,
+           "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()},
+           "roofline": {"bound": "alu", "kernel": "k_eval_field (potential and field pair sums)",
+                        "achieved": (pk + ps) / ev / 1e9, "peak": (pk + ps) / t_min / 1e9, "unit": "Gpair/s",
+                        "frac": t_min / ev, "avg_launch_ms": ev * 1e3,
+                        "peak_model": "%d / %d non-transcendental VALU instructions per Kelvin / surface pair" % (
+                            SLOTS_FIELD_KELVIN, SLOTS_FIELD_SURFACE)}}
+    if not args.no_oracle:
+        import oracle
+        phi_h, f_h = phi.cpu().numpy(), f.cpu().numpy()
+        wp, wf = 0.0, 0.0
+        for b, (p, s) in enumerate(zip(plans, systems)):
+            i = p.info
+            prm = oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
+                                M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"])
+            rp, rf = oracle.hsma_field(prm, s.x, s.y, s.z, s.q)
+            gp, gf = phi_h[b * N:(b + 1) * N], f_h[b * N:(b + 1) * N]
+            wp = max(wp, float(np.linalg.norm(gp - rp) / np.linalg.norm(rp)))
+            wf = max(wf, float(np.linalg.norm(gf - rf) / np.linalg.norm(rf)))
+        res["rel_err_phi_l2_max"] = wp
+        res["rel_err_field_l2_max"] = wf
+    for p in plans:
+        p.close()
+    log(f"bench[field]: {ms:.3f} ms/call, eval {ev * 1e3:.3f} ms ({res['roofline']['frac']:.2f} of its ALU peak)" +
+        (f", errors phi {res['rel_err_phi_l2_max']:.2e} field {res['rel_err_field_l2_max']:.2e}"
+         if "rel_err_field_l2_max" in res else ""))
+    return res
 
 
 def leg_batched(args) -> dict:
@@ -361,9 +447,10 @@ def leg_batched(args) -> dict:
         prm = oracle.Params(a=info["a"], eps1=info["eps1"], eps2=info["eps2"], kappa=info["kappa"], p=info["p"],
                             P=info["P"], M=info["M"], tau=info["tau"], rc_over_a=info["rc"] / info["a"], F1=info["F1"])
         wphi, we = 0.0, 0.0
+        refs = {}
         for b in pick:
             s = wl.systems[b]
-            ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
+            ref = refs[b] = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
             got = phi_h[off_h[b]:off_h[b + 1]]
             wphi = max(wphi, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
             e_ref = oracle.energy(s.q, ref)
@@ -371,6 +458,35 @@ def leg_batched(args) -> dict:
         res["rel_err_phi_l2_max_sampled"] = wphi
         res["rel_err_energy_max_sampled"] = we
         res["sampled_systems"] = [int(b) for b in pick]
+    # The fit apply by each route on the same call: stage time, rate against the MFMA peak of its
+    # type (the split-BF16 routes count their term products), and the sampled errors.
+    K, P, M = info["K"], info["P"], info["M"]
+    fit_flop = 2.0 * K * M * 2 * nsys + 2.0 * P * K * 2 * nsys
+    routes = {}
+    for mode, name, peak, mult in ((1, "gemv_fp32", None, 1), (2, "mfma_fp32", 157.3, 1),
+                                   (3, "mfma_bf16x3", 2500.0, 3), (4, "mfma_bf16x6", 2500.0, 6)):
+        group.set_fit(mode)
+        call()
+        group.profile(True)
+        group.profile_read()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        fit_ms = group.profile_read()["fit"][0] / steps
+        group.profile(False)
+        r = {"fit_ms": fit_ms}
+        if peak is not None:
+            tf = fit_flop * mult / (fit_ms * 1e-3) / 1e12
+            r.update({"tflops": tf, "peak_tflops": peak, "frac": tf / peak})
+        if not args.no_oracle:
+            phi_h = phi.cpu().numpy()
+            r["rel_err_phi_l2_max_sampled"] = max(
+                float(np.linalg.norm(phi_h[off_h[b]:off_h[b + 1]] - refs[b]) / np.linalg.norm(refs[b])) for b in pick)
+        routes[name] = r
+        log(f"bench[batched]: fit {name}: {fit_ms:.3f} ms" +
+            (f", max sampled rel L2 {r['rel_err_phi_l2_max_sampled']:.2e}" if "rel_err_phi_l2_max_sampled" in r else ""))
+    group.set_fit(0)
+    res["fit_routes"] = {"flop_per_call": fit_flop, **routes}
     log(f"bench[batched]: {ms:.2f} ms/call, {res['systems_per_s']:.0f} systems/s "
         f"(per-system path {res['per_system_path_systems_per_s']:.0f})")
     return res
