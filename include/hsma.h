@@ -147,6 +147,23 @@ hsma_status hsma_field(hsma_plan_t plan, int64_t N, const double *x, const doubl
                        const double *q, double *phi, double *ex, double *ey, double *ez, double *E, void *ws,
                        size_t ws_bytes, hipStream_t stream);
 
+/* The Kirkwood series of Sec. 2.2 (eqs. "phirf", "Anm", "Anuapp1"), the paper's comparison
+ * method, for the plan's cavity (a, eps1, eps2, kappa; its discretisation is not used):
+ *   Phi_i = sum_j q_j / (4 pi eps1 a) sum_{n=0}^{order} M_n t^n P_n(c),
+ *   t = |x_i| |x_j| / a^2, c = cos(angle between x_i and x_j),
+ * truncated after n = order (0 <= order <= HSMA_KIRKWOOD_MAX_ORDER), every source on every
+ * ion including its own term, in FP64, summed in a fixed order.  The series converges like
+ * t^order, i.e. slowly for ions near the interface (Sec. 4.1); it is O(N^2 order).
+ *   x, y, z, q: [device] N doubles; phi: [device] N doubles or NULL; E: [device] one double
+ *   (E = (1/2) sum q_i Phi_i) or NULL; ws: [device] ws_bytes >=
+ *   hsma_kirkwood_workspace_bytes(order, N), 256-byte aligned.
+ * Ions outside the cavity raise the plan's domain flag (hsma_stream_check).  Errors as
+ * hsma_potential. */
+#define HSMA_KIRKWOOD_MAX_ORDER 100000
+size_t hsma_kirkwood_workspace_bytes(int order, int64_t N);
+hsma_status hsma_kirkwood(hsma_plan_t plan, int order, int64_t N, const double *x, const double *y, const double *z,
+                          const double *q, double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Intermediate results of the last hsma_potential/hsma_energy call that used ws,
  * copied to host arrays (for tests and diagnostics; synchronises the stream).
  * Any output pointer may be NULL.  u, v: M check fields; Q, D: P surface strengths

@@ -109,6 +109,9 @@ def load_library(path: str | None = None):
     L.hsma_group_eval_kernel.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
     L.hsma_group_eval_kernel.restype = C.c_int
     L.hsma_group_set_fit.argtypes = [_VP, C.c_int]
+    L.hsma_kirkwood_workspace_bytes.argtypes = [C.c_int, C.c_int64]
+    L.hsma_kirkwood_workspace_bytes.restype = C.c_size_t
+    L.hsma_kirkwood.argtypes = [_VP, C.c_int, C.c_int64] + [_VP] * 6 + [_VP, C.c_size_t, _VP]
     L.hsma_field_workspace_bytes.argtypes = [_VP, C.c_int64]
     L.hsma_field_workspace_bytes.restype = C.c_size_t
     L.hsma_field.argtypes = [_VP, C.c_int64] + [_VP] * 9 + [_VP, C.c_size_t, _VP]
@@ -141,7 +144,7 @@ def load_library(path: str | None = None):
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
-                 "hsma_group_set_fit", "hsma_field", "hsma_field_batched", "hsma_system_create", "hsma_delta_energy",
+                 "hsma_group_set_fit", "hsma_field", "hsma_field_batched", "hsma_kirkwood", "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
                  "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
@@ -294,6 +297,22 @@ class Plan:
                                          _dev_ptr(E, "E", 1) if E is not None else None, w.ptr, w.nbytes,
                                          _stream_ptr(stream)), "hsma_field")
         return phi, f.t()
+
+    def kirkwood(self, x, y, z, q, order: int = 40, phi=None, E=None, stream=None, ws: Workspace | None = None):
+        """The truncated Kirkwood series (Sec. 2.2) for this plan's cavity, in FP64: potentials
+        at the ions (and the energy when E is given).  Returns phi."""
+        torch = _torch()
+        N = x.numel()
+        if phi is None:
+            phi = torch.empty(N, dtype=torch.float64, device=x.device)
+        lib = load_library()
+        w = ws if ws is not None else _ensure(self._ws, ("kirkwood", int(order), N, str(x.device)),
+                                              int(lib.hsma_kirkwood_workspace_bytes(int(order), N)), x.device)
+        _check(lib.hsma_kirkwood(self._h, int(order), N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N), _dev_ptr(z, "z", N),
+                                 _dev_ptr(q, "q", N), _dev_ptr(phi, "phi", N),
+                                 _dev_ptr(E, "E", 1) if E is not None else None, w.ptr, w.nbytes,
+                                 _stream_ptr(stream)), "hsma_kirkwood")
+        return phi
 
     def intermediates(self, N: int, device, stream=None):
         """Check fields u, v and surface strengths Q', D' of the last call with this workspace."""

@@ -212,22 +212,37 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
 
 __device__ __forceinline__ bool sched_ok(const Sched &S) { return S.ctr[2] != 0; }
 
-// item -> system maps, one block per system
-__global__ __launch_bounds__(256) void k_fill(int nsys, const int64_t *__restrict__ base, int *__restrict__ sys_c,
-                                              int *__restrict__ sys_e, int *__restrict__ sys_f) {
-  Sched S(const_cast<int64_t *>(base), nsys);
-  if (!sched_ok(S)) return;
-  const int b = blockIdx.x;
-  for (int64_t i = S.ic[b] + threadIdx.x; i < S.ic[b + 1]; i += 256) sys_c[i] = b;
-  for (int64_t i = S.ie[b] + threadIdx.x; i < S.ie[b + 1]; i += 256) sys_e[i] = b;
-  for (int64_t i = S.fb[b] + threadIdx.x; i < S.fb[b + 1]; i += 256) sys_f[i] = b;
+// The system an item belongs to: the last b with pre[b] <= i in a prefix array of nsys + 1
+// entries (systems without items share their prefix value with the next one).
+__device__ __forceinline__ int system_of(const int64_t *__restrict__ pre, int nsys, int64_t i) {
+  int lo = 0, hi = nsys;  // pre[lo] <= i < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= i)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// item -> system maps of the check, evaluation and finish items, grid-stride over all threads
+__device__ __forceinline__ void fill_maps(const Sched &S, int nsys, int *__restrict__ sys_c, int *__restrict__ sys_e,
+                                          int *__restrict__ sys_f) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < S.ic[nsys]; i += stride) sys_c[i] = system_of(S.ic, nsys, i);
+  for (int64_t i = t0; i < S.ie[nsys]; i += stride) sys_e[i] = system_of(S.ie, nsys, i);
+  for (int64_t i = t0; i < S.fb[nsys]; i += stride) sys_f[i] = system_of(S.fb, nsys, i);
 }
 
 // ---------------------------------------------------------------------------------
 // Kelvin images and packing: one finish block (256 ions of one system) per block.
 // ---------------------------------------------------------------------------------
+// Also fills the item -> system maps the later kernels of the call read.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restrict__ base, const int *__restrict__ sys_f,
+__global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restrict__ base, int *__restrict__ sys_c,
+                                              int *__restrict__ sys_e, int *__restrict__ sys_f,
                                               const PlanDev *__restrict__ plans, const int32_t *__restrict__ plan_of,
                                               const double *__restrict__ x, const double *__restrict__ y,
                                               const double *__restrict__ z, const double *__restrict__ q,
@@ -241,9 +256,10 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   using T = typename PT<MODE>::T;
   Sched S(const_cast<int64_t *>(base), nsys);
   if (!sched_ok(S)) return;
+  fill_maps(S, nsys, sys_c, sys_e, sys_f);
   const int64_t f = blockIdx.x;
   if (f >= S.fb[nsys]) return;
-  const int b = sys_f[f];
+  const int b = system_of(S.fb, nsys, f);
   const int64_t il = (f - S.fb[b]) * FINB + threadIdx.x;
   const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
   if (il >= n) return;
@@ -1392,9 +1408,9 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   bd.nplans = grp->nplans;
   k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, P, L.chc, L.che, L.sym_tb, L.sch, grid_c, grid_e,
                                     base, grp->flag);
-  k_fill<<<nsys, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f);
   if (L.fin > 0)
-    k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_f, plans, plan_of, x, y, z, q, img, tgt, srcw, self,
+    k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f, plans, plan_of, x, y, z, q, img, tgt,
+                                             srcw, self,
                                              (float *)(ws + L.wk), (double *)(ws + L.rk),
                                              L.field ? (double4 *)(ws + L.sfield) : nullptr,
                                              L.lo ? (float4 *)(ws + L.tlo) : nullptr,

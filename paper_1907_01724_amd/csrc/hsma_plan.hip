@@ -27,28 +27,6 @@ namespace {
 // Kirkwood factors.
 // ---------------------------------------------------------------------------------
 
-// S_n = k_n(mu) / (mu k_n'(mu)) from k_n(mu) = pi e^{-mu}/(2 mu) sum_{l<=n} t_l,
-// t_l = (n+l)! / (l! (n-l)!) (2 mu)^{-l}: differentiating term by term,
-// mu k_n' = -pi e^{-mu}/(2 mu) sum_l t_l (mu + l + 1), so S_n = -sum t_l / sum t_l (mu+l+1).
-// The terms are generated by their ratio and rescaled to stay in range.
-__device__ double s_ratio(int n, double mu) {
-  if (mu < 1e-30) return -1.0 / (n + 1.0);
-  double t = 1.0, A = 0.0, B = 0.0;
-  for (int l = 0; l <= n; ++l) {
-    A += t;
-    B += t * (mu + l + 1.0);
-    if (l < n) {
-      t *= (double)(n + l + 1) * (double)(n - l) / ((double)(l + 1) * 2.0 * mu);
-      if (t > 1e200) {
-        t *= 1e-200;
-        A *= 1e-200;
-        B *= 1e-200;
-      }
-    }
-  }
-  return -A / B;
-}
-
 // One thread: M_n, gamma, sigma, dbar and the plan diagonals
 //   f_nm = R_tau (rc/a)^{n+1} (M_n - gamma + dbar/2),  g_nm = R_tau (rc/a)^{n+1} (-dbar R_tau / (2a)),
 // so that R_tau Ahat_nm = f_nm alpha'_nm + g_nm beta'_nm for the fitted alpha' = pinv u,
@@ -68,8 +46,7 @@ __global__ void k_plan_constants(int p, double eps, double mu, double tau, doubl
   const int K = (p + 1) * (p + 1);
   double scale = rc_over_a;  // (rc/a)^{n+1}
   for (int n = 0; n <= p; ++n) {
-    const double S = s_ratio(n, mu);
-    const double Mn = (eps * (n + 1.0) * S + 1.0) / (eps * n * S - 1.0);
+    const double Mn = kirkwood_factor(n, eps, mu);
     out[3 + n] = Mn;
     const double cn = Mn - gamma + 0.5 * dbar;
     for (int m = -n; m <= n; ++m) {
