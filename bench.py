@@ -62,9 +62,9 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="batched,serving,sweep,field",
-                    help="extra workloads after the headline one: batched, serving, sweep, field (comma list, or "
-                         "none)")
+    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood",
+                    help="extra workloads after the headline one: batched, serving, sweep, field, kirkwood (comma "
+                         "list, or none)")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--serving-slots", default="1,2",
                     help="request server: concurrent single-ion-move batches and full energies")
@@ -263,6 +263,8 @@ def main() -> int:
         out["precision_sweep"] = leg_sweep(args)
     if "field" in legs:
         out["field"] = leg_field(args)
+    if "kirkwood" in legs:
+        out["kirkwood"] = leg_kirkwood(args)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -366,6 +368,67 @@ def leg_field(args) -> dict:
     log(f"bench[field]: {ms:.3f} ms/call, eval {ev * 1e3:.3f} ms ({res['roofline']['frac']:.2f} of its ALU peak)" +
         (f", errors phi {res['rel_err_phi_l2_max']:.2e} field {res['rel_err_field_l2_max']:.2e}"
          if "rel_err_field_l2_max" in res else ""))
+    return res
+
+
+def leg_kirkwood(args) -> dict:
+    """The paper's comparison (Sec. 4.1) on the GPU: the C1 system (N = 200 uniform in a = 10,
+    eps1 = 1, eps2 = 80, kappa = 0.1) by HSMA (FP64 pairs; P = 400, p = 10 and P = 1600, p = 20)
+    and by the Kirkwood series truncated at order 40, each against the converged series
+    (the oracle's O2, not timed); then the time of the order-40 series on the N = 20000 shell
+    system of the headline workload (first parameter set) beside HSMA's."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.workload_c1()
+    s, ph = wl.systems[0], wl.systems[0].phys
+    t = [torch.tensor(v, dtype=torch.float64, device=dev) for v in (s.x, s.y, s.z, s.q)]
+    res = {"workload": "C1: N=200 uniform in a=10, eps1=1, eps2=80, kappa=0.1; timing on N=20000, a=30, "
+                       "30% in the shell, eps1=eps2=80, kappa=0.05"}
+    out = {}
+    for P, M in ((400, 600), (1600, 2400)):
+        plan = hs.Plan(ph.a, ph.eps1, ph.eps2, ph.kappa, P, M, pair_prec="fp64")
+        phi = torch.empty(s.n, dtype=torch.float64, device=dev)
+        plan.energy(*t, phi=phi)
+        assert plan.stream_check() == 0
+        out[f"hsma_p{plan.info['p']}_P{P}"] = phi.cpu().numpy()
+        if P == 400:
+            out["kirkwood_order40"] = plan.kirkwood(*t, order=40).cpu().numpy()
+            assert plan.stream_check() == 0
+        plan.close()
+    if not args.no_oracle:
+        import oracle
+        truth = oracle.kirkwood_eval(ph.a, ph.eps1, ph.eps2, ph.kappa, s.x, s.y, s.z, s.q)
+        res["rel_err_l2_vs_converged_series"] = {k: float(np.linalg.norm(v - truth) / np.linalg.norm(truth))
+                                                 for k, v in out.items()}
+        r = np.sqrt(s.x ** 2 + s.y ** 2 + s.z ** 2)
+        inner = r < 0.9 * ph.a
+        res["rel_err_l2_inner_ions_r_below_0.9a"] = {
+            k: float(np.linalg.norm(v[inner] - truth[inner]) / np.linalg.norm(truth[inner])) for k, v in out.items()}
+    wl2 = W.workload_c2()
+    s2 = wl2.systems[0]
+    p2 = hs.Plan(s2.phys.a, s2.phys.eps1, s2.phys.eps2, s2.phys.kappa, wl2.disc.P, wl2.disc.M)
+    t2 = [torch.tensor(v, dtype=torch.float64, device=dev) for v in (s2.x, s2.y, s2.z, s2.q)]
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    times = {}
+    for name, fn in (("kirkwood_order40_fp64", lambda: p2.kirkwood(*t2, order=40, E=E)),
+                     ("hsma_fp32c", lambda: p2.energy(*t2, E=E))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) * 1e3 / 5
+    assert p2.stream_check() == 0
+    p2.close()
+    res["ms_per_call_n20000"] = times
+    log("bench[kirkwood]: " + (", ".join(f"{k} err {v:.2e}" for k, v in res.get("rel_err_l2_vs_converged_series", {}).items()))
+        + "; N=20000: " + ", ".join(f"{k} {v:.2f} ms" for k, v in times.items()))
     return res
 
 
