@@ -35,7 +35,8 @@ def build(force: bool = True) -> str:
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("eps1", C.c_double), ("eps2", C.c_double), ("kappa", C.c_double),
                 ("tau", C.c_double), ("rc_over_a", C.c_double), ("p", C.c_int), ("P", C.c_int),
-                ("M", C.c_int), ("F1", C.c_int), ("dipole", C.c_int), ("dy_over_Rtau", C.c_double)]
+                ("M", C.c_int), ("F1", C.c_int), ("dipole", C.c_int), ("dy_over_Rtau", C.c_double),
+                ("check_set", C.c_int)]
 
 
 class _Diag(C.Structure):
@@ -59,6 +60,8 @@ def lib():
         L.orc_real_sh.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _DP]
         L.orc_fibonacci_nodes.argtypes = [C.c_int, C.c_int, C.c_double, _DP, _DP]
         L.orc_check_lattice.argtypes = [C.c_int, C.c_double, _DP]
+        L.orc_gl_nodes.argtypes = [C.c_int, _DP, _DP]
+        L.orc_check_gl.argtypes = [C.c_int, C.c_double, _DP, _DP]
         L.orc_lstsq.argtypes = [C.c_int, C.c_int, _DP, C.c_int, _DP, _DP]
         L.orc_lstsq.restype = C.c_int
         P = C.POINTER(_Params)
@@ -111,6 +114,7 @@ class Params:
     F1: int | None = None
     dipole: int = 0
     dy_over_Rtau: float = 1e-5
+    check_set: int = 0  # 0 golden-angle lattice, 1 the Gauss-Legendre grid, 2p x (2p + 1) (M = 2p (2p + 1))
 
     @property
     def K(self) -> int:
@@ -125,7 +129,7 @@ class Params:
 
     def c(self) -> _Params:
         return _Params(self.a, self.eps1, self.eps2, self.kappa, self.tau, self.rc_over_a, self.p, self.P,
-                       self.M, self.f1(), self.dipole, self.dy_over_Rtau)
+                       self.M, self.f1(), self.dipole, self.dy_over_Rtau, self.check_set)
 
 
 def fibonacci_f1(F2: int) -> int:
@@ -177,6 +181,22 @@ def check_lattice(M: int, rc: float) -> np.ndarray:
     xyz = np.zeros((M, 3))
     lib().orc_check_lattice(M, rc, _p(xyz))
     return xyz
+
+
+def gl_nodes(n: int):
+    """Gauss-Legendre nodes (decreasing) and weights on [-1, 1]."""
+    x, w = np.zeros(n), np.zeros(n)
+    lib().orc_gl_nodes(n, _p(x), _p(w))
+    return x, w
+
+
+def check_gl(p: int, rc: float):
+    """The check grid of Algorithm 1 step 1 (2p Gauss-Legendre nodes x 2p + 1 azimuths) on
+    radius rc, and its quadrature weights on the unit sphere."""
+    xyz = np.zeros((2 * p * (2 * p + 1), 3))
+    wq = np.zeros(2 * p * (2 * p + 1))
+    lib().orc_check_gl(p, rc, _p(xyz), _p(wq))
+    return xyz, wq
 
 
 def lstsq(A: np.ndarray, B: np.ndarray) -> np.ndarray:

@@ -163,6 +163,67 @@ void orc_check_lattice(int M, double rc, double *xyz) {
   }
 }
 
+/* Gauss-Legendre rule of n nodes on [-1, 1]: the roots of P_n, found by Newton's method
+ * from cos(pi (i + 3/4) / (n + 1/2)), with weights 2 / ((1 - x^2) P_n'(x)^2).  P_n and its
+ * derivative come from the three-term recurrence and (1 - x^2) P_n' = n (P_{n-1} - x P_n).
+ * Nodes are returned in decreasing order.                                       */
+void orc_gl_nodes(int n, double *x, double *w) {
+  for (int i = 0; i < n; i++) {
+    double z = cos(ORC_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; it++) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; k++) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) p0 = 1.0;
+      dp = n * (p0 - z * p1) / (1.0 - z * z);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    /* derivative at the converged root */
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; k++) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) p0 = 1.0;
+    dp = n * (p0 - z * p1) / (1.0 - z * z);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+/* Algorithm 1, step 1: 2p Gauss-Legendre nodes in cos(theta) times equispaced azimuths on the
+ * sphere of radius rc.  The paper takes 2p azimuths; at phi_j = pi j / p the harmonic
+ * sin(p phi) vanishes, so degree p could not be fitted.  Here 2p + 1 azimuths
+ * phi_j = 2 pi j / (2p + 1) are taken (M = 2p (2p + 1)), which resolve every order |m| <= p.
+ * Point k = i (2p + 1) + j.  wq (optional, M): the quadrature weights w_i 2 pi / (2p + 1) of
+ * the grid on the unit sphere, exact for products of harmonics of degree <= p.            */
+void orc_check_gl(int p, double rc, double *xyz, double *wq) {
+  int n = 2 * p, nph = 2 * p + 1;
+  double *x = (double *)malloc(sizeof(double) * (size_t)n);
+  double *w = (double *)malloc(sizeof(double) * (size_t)n);
+  orc_gl_nodes(n, x, w);
+  for (int i = 0; i < n; i++) {
+    double st = sqrt(fmax(0.0, 1.0 - x[i] * x[i]));
+    for (int j = 0; j < nph; j++) {
+      int k = i * nph + j;
+      double ph = 2.0 * ORC_PI * j / nph;
+      xyz[3 * k + 0] = rc * st * cos(ph);
+      xyz[3 * k + 1] = rc * st * sin(ph);
+      xyz[3 * k + 2] = rc * x[i];
+      if (wq) wq[k] = w[i] * 2.0 * ORC_PI / nph;
+    }
+  }
+  free(x);
+  free(w);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Dense least squares by Householder QR.                                       */
 /* ------------------------------------------------------------------------- */
@@ -230,6 +291,7 @@ typedef struct {
   int F1;                      /* Fibonacci F1 (F2 = P/2 - 1) */
   int dipole;                  /* 0 exact normal dipole, 1 central-difference point pair */
   double dy_over_Rtau;         /* central-difference step / R_tau (dipole = 1) */
+  int check_set;               /* 0 golden-angle lattice of M points, 1 the Gauss-Legendre grid (M = 2p (2p+1)) */
 } orc_params;
 
 /* Optional intermediate outputs; any pointer may be NULL. */
@@ -245,9 +307,18 @@ typedef struct {
 
 static int orc_params_ok(const orc_params *pp) {
   if (!(pp->a > 0.0 && pp->eps1 > 0.0 && pp->eps2 > 0.0 && pp->kappa >= 0.0)) return 0;
-  if (!(pp->tau > 0.0 && pp->rc_over_a > 1.0)) return 0;
+  if (!(pp->tau > 0.0 && pp->rc_over_a >= 1.0)) return 0;
   if (pp->p < 0 || pp->P < 4 || (pp->P & 1) || pp->M < (pp->p + 1) * (pp->p + 1)) return 0;
+  if (pp->check_set != 0 && (pp->check_set != 1 || pp->M != 2 * pp->p * (2 * pp->p + 1))) return 0;
   return 1;
+}
+
+/* Step 1 of Algorithm 1: the check points of the chosen set on the sphere of radius rc. */
+static void orc_check_points(const orc_params *pp, double *chk) {
+  if (pp->check_set == 1)
+    orc_check_gl(pp->p, pp->rc_over_a * pp->a, chk, NULL);
+  else
+    orc_check_lattice(pp->M, pp->rc_over_a * pp->a, chk);
 }
 
 /* Step S2 of Algorithm 1, realised at check points: the potential of the sources
@@ -442,7 +513,7 @@ int orc_hsma_eval(const orc_params *pp, long N, const double *x, const double *y
   double *ps = (double *)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
   int st = 0;
 
-  orc_check_lattice(M, pp->rc_over_a * pp->a, chk);                       /* step 1 */
+  orc_check_points(pp, chk);                                               /* step 1 */
   orc_check_fields(pp, N, x, y, z, q, chk, u, v);                          /* step 2 */
   if (orc_fit_moments(pp, chk, u, v, al, be) != 0) { st = -3; goto done; } /* step 3 */
   orc_correction_coeffs(pp, al, be, Ah);
@@ -582,7 +653,7 @@ int orc_hsma_field(const orc_params *pp, long N, const double *x, const double *
   double *fs = (double *)malloc(sizeof(double) * 3 * n1);
   int st = 0;
 
-  orc_check_lattice(M, pp->rc_over_a * pp->a, chk);                       /* step 1 */
+  orc_check_points(pp, chk);                                               /* step 1 */
   orc_check_fields(pp, N, x, y, z, q, chk, u, v);                          /* step 2 */
   if (orc_fit_moments(pp, chk, u, v, al, be) != 0) { st = -3; goto done; } /* step 3 */
   orc_correction_coeffs(pp, al, be, Ah);
