@@ -82,9 +82,14 @@ typedef struct hsma_system_s *hsma_system_t;
 typedef struct {
   int p;            /* spherical-harmonic truncation order (eq. "phim"); < 0: default */
   double tau;       /* auxiliary sphere R_tau = (1 + tau) a, tau > 0 (Sec. 2.4) */
-  double rc_over_a; /* radius of the check points / a, > 1; <= 0: 1 + tau */
+  double rc_over_a; /* radius of the check points / a, >= 1; <= 0: 1 + tau */
   int F1;           /* Fibonacci-rule F1 (Sec. 2.4), 0 < F1 < F2; 0: default */
   int pair_prec;    /* hsma_pair_precision */
+  int check_set;    /* check points: 0 golden-angle lattice of M points (default); 1 the
+                       Gauss-Legendre grid of Algorithm 1 step 1: 2p nodes in cos(theta) times
+                       2p + 1 equispaced azimuths (the paper's 2p azimuths are zeros of
+                       sin(p phi) and cannot fit degree p), so M must be 2p (2p + 1).  Set
+                       rc_over_a = 1 for the paper's placement on the interface. */
 } hsma_plan_opts;
 
 /* Read-only description of a plan (for callers and tests). */
@@ -95,6 +100,7 @@ typedef struct {
   int p, K, P, M, F1, F2;          /* K = (p+1)^2 fitted coefficients; P = 2 (F2 + 1) */
   int pair_prec;
   int device;
+  int check_set;
 } hsma_plan_info;
 
 hsma_plan_opts hsma_plan_opts_default(void);

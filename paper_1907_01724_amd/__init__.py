@@ -30,14 +30,15 @@ class HsmaError(RuntimeError):
 
 class PlanOpts(C.Structure):
     _fields_ = [("p", C.c_int), ("tau", C.c_double), ("rc_over_a", C.c_double), ("F1", C.c_int),
-                ("pair_prec", C.c_int)]
+                ("pair_prec", C.c_int), ("check_set", C.c_int)]
 
 
 class PlanInfo(C.Structure):
     _fields_ = [("a", C.c_double), ("eps1", C.c_double), ("eps2", C.c_double), ("kappa", C.c_double),
                 ("tau", C.c_double), ("R_tau", C.c_double), ("rc", C.c_double), ("gamma", C.c_double),
                 ("sigma", C.c_double), ("dbar", C.c_double), ("p", C.c_int), ("K", C.c_int), ("P", C.c_int),
-                ("M", C.c_int), ("F1", C.c_int), ("F2", C.c_int), ("pair_prec", C.c_int), ("device", C.c_int)]
+                ("M", C.c_int), ("F1", C.c_int), ("F2", C.c_int), ("pair_prec", C.c_int), ("device", C.c_int),
+                ("check_set", C.c_int)]
 
 
 class Request(C.Structure):
@@ -212,7 +213,7 @@ class Plan:
 
     def __init__(self, a: float, eps1: float, eps2: float, kappa: float, P: int, M: int, p: int | None = None,
                  tau: float = 0.1, rc_over_a: float | None = None, F1: int | None = None,
-                 pair_prec: str | int = "fp32c"):
+                 pair_prec: str | int = "fp32c", check_set: int = 0):
         L = load_library()
         o = L.hsma_plan_opts_default()
         if p is not None:
@@ -223,6 +224,7 @@ class Plan:
         if F1 is not None:
             o.F1 = int(F1)
         o.pair_prec = PAIR_PREC[pair_prec] if isinstance(pair_prec, str) else int(pair_prec)
+        o.check_set = int(check_set)
         h = _VP()
         _check(L.hsma_plan_ex(float(a), float(eps1), float(eps2), float(kappa), int(P), int(M), C.byref(o),
                               C.byref(h)), "hsma_plan_ex")

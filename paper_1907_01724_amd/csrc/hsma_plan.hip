@@ -95,6 +95,36 @@ __global__ void k_check_lattice(int M, double *pts) {
   pts[3 * k + 2] = zk;
 }
 
+// Algorithm 1, step 1: 2p Gauss-Legendre nodes in cos(theta) times 2p + 1 equispaced
+// azimuths 2 pi j / (2p + 1) on the unit sphere, point k = i (2p + 1) + j.  Node i is the
+// i-th root of P_2p in decreasing order, found by Newton's method from
+// cos(pi (i + 3/4) / (2p + 1/2)) with P_2p and P_2p' from the three-term recurrence and
+// (1 - x^2) P_n' = n (P_{n-1} - x P_n).  One thread per point.
+__global__ void k_check_gl(int p, double *pts) {
+  const int n = 2 * p, nph = 2 * p + 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n * nph) return;
+  const int i = k / nph, j = k % nph;
+  double z = cos(HSMA_PI * (i + 0.75) / (n + 0.5));
+  for (int it = 0; it < 100; ++it) {
+    double p0 = 1.0, p1 = z;
+    for (int l = 2; l <= n; ++l) {
+      const double p2 = ((2.0 * l - 1.0) * z * p1 - (l - 1.0) * p0) / l;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double dp = n * (p0 - z * p1) / (1.0 - z * z);
+    const double dz = p1 / dp;
+    z -= dz;
+    if (fabs(dz) < 1e-16) break;
+  }
+  const double st = sqrt(fmax(0.0, 1.0 - z * z));
+  const double ph = 2.0 * HSMA_PI * j / nph;
+  pts[3 * k + 0] = st * cos(ph);
+  pts[3 * k + 1] = st * sin(ph);
+  pts[3 * k + 2] = z;
+}
+
 // ---------------------------------------------------------------------------------
 // Real orthonormal spherical harmonics of a unit vector (x, y, z), degree <= p.
 // Y_nm = N_nm P_n^m(z) times cos(m phi) (m > 0, with sqrt 2) or sin(|m| phi) (m < 0).
@@ -326,7 +356,7 @@ __global__ void k_scale_points(int n, const double *unit, double r, float4 *p32,
 // Geometry cache.
 // ---------------------------------------------------------------------------------
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, double, double, int>, Geometry *> g_cache;
+std::map<std::tuple<int, int, int, int, double, double, int, int>, Geometry *> g_cache;
 
 inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -375,7 +405,10 @@ hsma_status geometry_build(Geometry *g) {
   HSMA_TRY(hipMemsetAsync(bad, 0, sizeof(int), st));
   HSMA_TRY(hipMemsetAsync(G, 0, sizeof(double) * (size_t)K * K, st));
 
-  k_check_lattice<<<blocks(M, 256), 256, 0, st>>>(M, g->unit_check);
+  if (g->check_set == 1)
+    k_check_gl<<<blocks(M, 256), 256, 0, st>>>(p, g->unit_check);
+  else
+    k_check_lattice<<<blocks(M, 256), 256, 0, st>>>(M, g->unit_check);
   k_fibonacci<<<blocks(P, 256), 256, 0, st>>>(g->F1, g->F2, g->unit_nodes, g->what);
   k_degree_index<<<blocks(K, 256), 256, 0, st>>>(K, g->nidx);
   k_surface_basis<<<blocks(P, 64), 64, 0, st>>>(p, P, g->tau, g->unit_nodes, g->what, g->lhat64, g->lhat32);
@@ -416,10 +449,11 @@ out:
 
 }  // namespace
 
-hsma_status geometry_acquire(int p, int P, int M, int F1, double tau, double rc_over_a, Geometry **out) {
+hsma_status geometry_acquire(int p, int P, int M, int F1, double tau, double rc_over_a, int check_set,
+                             Geometry **out) {
   int dev = 0;
   HSMA_HIP(hipGetDevice(&dev));
-  auto key = std::make_tuple(p, P, M, F1, tau, rc_over_a, dev);
+  auto key = std::make_tuple(p, P, M, F1, tau, rc_over_a, dev, check_set);
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_cache.find(key);
   if (it != g_cache.end()) {
@@ -437,6 +471,7 @@ hsma_status geometry_acquire(int p, int P, int M, int F1, double tau, double rc_
   g->F2 = P / 2 - 1;
   g->tau = tau;
   g->rc_over_a = rc_over_a;
+  g->check_set = check_set;
   g->device = dev;
   g->ncu = 0;
   if (hipDeviceGetAttribute(&g->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || g->ncu <= 0)
@@ -501,6 +536,7 @@ extern "C" hsma_plan_opts hsma_plan_opts_default(void) {
   o.rc_over_a = 0.0;
   o.F1 = 0;
   o.pair_prec = HSMA_PAIR_FP32_COMP;
+  o.check_set = 0;
   return o;
 }
 
@@ -518,7 +554,8 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   if (P < 8 || (P & 1)) return HSMA_EINVAL;
   if (!(isfinite(o.tau) && o.tau > 0.0 && o.tau < 10.0)) return HSMA_EINVAL;
   if (o.rc_over_a <= 0.0) o.rc_over_a = 1.0 + o.tau;
-  if (!(isfinite(o.rc_over_a) && o.rc_over_a > 1.0 && o.rc_over_a < 10.0)) return HSMA_EINVAL;
+  if (!(isfinite(o.rc_over_a) && o.rc_over_a >= 1.0 && o.rc_over_a < 10.0)) return HSMA_EINVAL;
+  if (o.check_set != 0 && o.check_set != 1) return HSMA_EINVAL;
   if (o.p < 0) {
     int s = (int)floor(sqrt((double)P));
     while ((long)(s + 1) * (s + 1) <= P) ++s;
@@ -528,13 +565,14 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   if (o.p > 120) return HSMA_EINVAL;
   const int K = (o.p + 1) * (o.p + 1);
   if ((long)2 * M < 3L * K) return HSMA_EINVAL;  // M >= 1.5 K
+  if (o.check_set == 1 && (o.p < 1 || M != 2 * o.p * (2 * o.p + 1))) return HSMA_EINVAL;
   const int F2 = P / 2 - 1;
   if (o.F1 == 0) o.F1 = default_f1(F2);
   if (o.F1 <= 0 || o.F1 >= F2) return HSMA_EINVAL;
   if (o.pair_prec < HSMA_PAIR_FP32 || o.pair_prec > HSMA_PAIR_FP64) return HSMA_EINVAL;
 
   Geometry *g = nullptr;
-  hsma_status rc = geometry_acquire(o.p, P, M, o.F1, o.tau, o.rc_over_a, &g);
+  hsma_status rc = geometry_acquire(o.p, P, M, o.F1, o.tau, o.rc_over_a, o.check_set, &g);
   if (rc != HSMA_OK) return rc;
 
   hsma_plan_s *pl = new hsma_plan_s();
@@ -636,6 +674,7 @@ extern "C" hsma_status hsma_plan_get_info(hsma_plan_t pl, hsma_plan_info *info) 
   info->F2 = pl->geo->F2;
   info->pair_prec = pl->opts.pair_prec;
   info->device = pl->device;
+  info->check_set = pl->geo->check_set;
   return HSMA_OK;
 }
 
