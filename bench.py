@@ -642,7 +642,7 @@ def leg_serving(args) -> dict:
     U[0.05, 1], eps1 = 1, eps2 = 78.5, P = 1024, M = 1536); requests 90% single-ion moves
     (ion and system uniform, displacement U([-1/2, 1/2]^3) kept inside, committed with
     probability 1/2) and 10% fresh full energies.  Capacity from a burst, then Poisson
-    arrivals at fractions of it; latency = done - submitted."""
+    arrivals at 0.25, 0.5, 0.75, 0.9 and 1.1 of it; latency = done - submitted."""
     import numpy as np
     import torch
 
@@ -704,7 +704,7 @@ def leg_serving(args) -> dict:
            "capacity_requests_per_s": cap, "burst": burst,
            "mean_batch": (st1["batched_requests"] - st0["batched_requests"]) / max(1, st1["batches"] - st0["batches"]),
            "loads": []}
-    for f in (0.25, 0.5, 0.75, 0.9):
+    for f in (0.25, 0.5, 0.75, 0.9, 1.1):  # 1.1: overload, the queue grows over the run
         reqs = stream(n)
         arrival = np.cumsum(rng.exponential(1.0 / (f * cap), n))
         res = server.run_load(reqs, arrival)
@@ -713,7 +713,8 @@ def leg_serving(args) -> dict:
         d["offered_fraction"] = f
         d["offered_requests_per_s"] = f * cap
         out["loads"].append(d)
-        log(f"bench[serving]: load {f:.2f} x capacity: p50 {d['p50_ms']:.3f} ms, p99 {d['p99_ms']:.3f} ms")
+        log(f"bench[serving]: load {f:.2f} x capacity: p50 {d['p50_ms']:.3f} ms, p99 {d['p99_ms']:.3f} ms "
+            f"(moves {d['delta_p50_ms']:.3f} / {d['delta_p99_ms']:.3f} ms)")
     server.close()
     # plain per-system path: one synchronous single-ion query at a time on a resident system
     b = int(np.argmax([len(p) for p in pos]))
