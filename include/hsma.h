@@ -286,6 +286,15 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  * A system is not thread safe: its calls must be ordered (one stream). */
 hsma_status hsma_system_create(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
                                const double *q, hipStream_t stream, hsma_system_t *out);
+/* As hsma_system_create, with flags: HSMA_SYSTEM_COULOMB makes the system's energy the total
+ * E_RF + E_C, where E_C = (1/2) sum_{i != j} q_i q_j / (4 pi eps1 |x_i - x_j|) is the direct
+ * Coulomb energy of the ions in the cavity (eq. "phicoul"); hsma_delta_energy, commits,
+ * hsma_system_energy and hsma_system_full_energy then all refer to the total.  E_C is summed
+ * directly in FP64 (O(N^2) at creation and in full evaluations, O(N) per move).  Other flag
+ * bits: HSMA_EINVAL. */
+#define HSMA_SYSTEM_COULOMB 1
+hsma_status hsma_system_create_ex(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
+                                  const double *q, int flags, hipStream_t stream, hsma_system_t *out);
 hsma_status hsma_delta_energy(hsma_system_t sys, int64_t k, double xk, double yk, double zk, double *dE,
                               hipStream_t stream);
 hsma_status hsma_system_commit(hsma_system_t sys, int64_t k, double xk, double yk, double zk, hipStream_t stream);

@@ -83,6 +83,8 @@ def lib():
                                         _DP, _DP, _DP, _DP, C.c_long, _DP, _DP, _DP, C.c_int, C.c_int,
                                         C.c_double, _DP, _DP]
         L.orc_kirkwood_eval.restype = C.c_int
+        L.orc_coulomb_energy.argtypes = [C.c_double, C.c_long, _DP, _DP, _DP, _DP]
+        L.orc_coulomb_energy.restype = C.c_double
         _lib = L
     return _lib
 
@@ -353,6 +355,12 @@ def kirkwood_eval(a, eps1, eps2, kappa, x, y, z, q, targets=None, order: int = 0
     if st != 0:
         raise ValueError("oracle Kirkwood failed")
     return (phi, tail.value) if return_tail else phi
+
+
+def coulomb_energy(eps1: float, x, y, z, q) -> float:
+    """Direct Coulomb energy (1/2) sum_{i != j} q_i q_j / (4 pi eps1 |x_i - x_j|)."""
+    x, y, z, q = map(_f64, (x, y, z, q))
+    return float(lib().orc_coulomb_energy(float(eps1), len(x), _p(x), _p(y), _p(z), _p(q)))
 
 
 def energy(q, phi) -> float:

@@ -675,6 +675,24 @@ done:
   return st;
 }
 
+/* Direct Coulomb energy of the ions in medium eps1 (eq. "phicoul"):
+ * E_C = (1/2) sum_{i != j} q_i q_j / (4 pi eps1 |x_i - x_j|), the definition summed in FP64. */
+double orc_coulomb_energy(double eps1, long N, const double *x, const double *y, const double *z,
+                          const double *q) {
+  double e = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : e)
+  for (long i = 0; i < N; i++) {
+    double s = 0.0;
+    for (long j = 0; j < N; j++) {
+      if (j == i) continue;
+      double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+      s += q[j] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    e += q[i] * s;
+  }
+  return 0.5 * e / (4.0 * ORC_PI * eps1);
+}
+
 /* ------------------------------------------------------------------------- */
 /* O2: the Kirkwood series (Sec. 2.2).                                          */
 /* ------------------------------------------------------------------------- */

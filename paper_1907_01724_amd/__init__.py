@@ -110,6 +110,7 @@ def load_library(path: str | None = None):
     L.hsma_group_eval_kernel.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
     L.hsma_group_eval_kernel.restype = C.c_int
     L.hsma_group_set_fit.argtypes = [_VP, C.c_int]
+    L.hsma_system_create_ex.argtypes = [_VP, C.c_int64] + [_VP] * 4 + [C.c_int, _VP, C.POINTER(_VP)]
     L.hsma_kirkwood_workspace_bytes.argtypes = [C.c_int, C.c_int64]
     L.hsma_kirkwood_workspace_bytes.restype = C.c_size_t
     L.hsma_kirkwood.argtypes = [_VP, C.c_int, C.c_int64] + [_VP] * 6 + [_VP, C.c_size_t, _VP]
@@ -145,7 +146,8 @@ def load_library(path: str | None = None):
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
-                 "hsma_group_set_fit", "hsma_field", "hsma_field_batched", "hsma_kirkwood", "hsma_system_create", "hsma_delta_energy",
+                 "hsma_group_set_fit", "hsma_field", "hsma_field_batched", "hsma_kirkwood", "hsma_system_create_ex",
+                 "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
                  "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
@@ -491,14 +493,16 @@ class Group:
 class System:
     """A resident ion configuration for single-ion-move energy changes (Monte Carlo)."""
 
-    def __init__(self, plan: Plan, x, y, z, q, stream=None):
+    def __init__(self, plan: Plan, x, y, z, q, stream=None, coulomb: bool = False):
+        """coulomb: the energy (and every move's change) also holds the direct Coulomb energy
+        of the ions in the cavity."""
         L = load_library()
         self.plan = plan
         self.n = x.numel()
         h = _VP()
-        _check(L.hsma_system_create(plan.handle, self.n, _dev_ptr(x, "x", self.n), _dev_ptr(y, "y", self.n),
-                                    _dev_ptr(z, "z", self.n), _dev_ptr(q, "q", self.n), _stream_ptr(stream),
-                                    C.byref(h)), "hsma_system_create")
+        _check(L.hsma_system_create_ex(plan.handle, self.n, _dev_ptr(x, "x", self.n), _dev_ptr(y, "y", self.n),
+                                       _dev_ptr(z, "z", self.n), _dev_ptr(q, "q", self.n), 1 if coulomb else 0,
+                                       _stream_ptr(stream), C.byref(h)), "hsma_system_create_ex")
         self._h = h
         self.device = x.device
 

@@ -11,6 +11,11 @@
 //   dE = 1/2 [q_k sum_{j != k} q_j (g(x', x_j) - g(x, x_j) + g(x_j, x') - g(x_j, x)) + q_k^2 (g(x', x') - g(x, x))]
 //      + 1/2 [dw . s + (w + dw) . ds],   dw = q_k (S(x') - S(x)),  ds = T q_k (C(x') - C(x)),
 // which costs O(N + M + P) pairs and two small GEMVs instead of a full evaluation.
+//
+// Optionally (HSMA_SYSTEM_COULOMB) the state's energy also holds the direct Coulomb energy of
+// the ions inside the cavity, E_C = 1/2 sum_{i != j} q_i q_j c0 / |x_i - x_j| (eq. "phicoul"),
+// so that a move's change is the total one: dE_C = q_k sum_{j != k} q_j c0 (1/|x' - x_j| -
+// 1/|x - x_j|), summed in the same pass over j as the image terms.
 #include <math.h>
 #include <string.h>
 
@@ -95,8 +100,13 @@ __global__ __launch_bounds__(DB) void k_de_pairs(const SysDev *__restrict__ syst
       const Img ij = image_of(c, xj, yj, zj);
       // row: ion k at its new and old place in the field of j's image; column: j in the field
       // of k's new and old image
-      v = S.q[j] * ((img_pot(ij, x1, y1, z1) - img_pot(ij, x0, y0, z0)) +
-                    (img_pot(ik1, xj, yj, zj) - img_pot(ik0, xj, yj, zj)));
+      double t = (img_pot(ij, x1, y1, z1) - img_pot(ij, x0, y0, z0)) +
+                 (img_pot(ik1, xj, yj, zj) - img_pot(ik0, xj, yj, zj));
+      if (S.coulomb) {  // 2 c0 (1/r' - 1/r): the final 1/2 q_k makes it q_k q_j c0 (1/r' - 1/r)
+        const double ax = x1 - xj, ay = y1 - yj, az = z1 - zj, bx = x0 - xj, by = y0 - yj, bz = z0 - zj;
+        t += 2.0 * c.c0 * (rinv64(ax * ax + ay * ay + az * az) - rinv64(bx * bx + by * by + bz * bz));
+      }
+      v = S.q[j] * t;
     }
     const double b = block_sum(v, red);
     if (threadIdx.x == 0) S.partA[blk] = b;
@@ -245,6 +255,91 @@ __global__ void k_sys_s(int P, const double2 *__restrict__ qd, double *__restric
   s[P + i] = qd[i].y;
 }
 
+// Direct Coulomb energy in FP64: partials of sum_{j != i} q_j / |x_i - x_j| per target and
+// source chunk (one target per thread, wave-uniform sources), then per block
+// 1/2 c0 sum_i q_i (chunk sum in chunk order), then one block adds the block partials in
+// order to E.
+constexpr int CB = 256;
+
+__global__ __launch_bounds__(CB) void k_coul_pairs(int64_t N, int64_t chunk, const double *__restrict__ x,
+                                                   const double *__restrict__ y, const double *__restrict__ z,
+                                                   const double *__restrict__ q, double *__restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  const int64_t ii = i < N ? i : N - 1;
+  const double xi = x[ii], yi = y[ii], zi = z[ii];
+  const int64_t j0 = c * chunk, j1 = j0 + chunk < N ? j0 + chunk : N;
+  double s = 0.0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const double dx = xi - x[j], dy = yi - y[j], dz = zi - z[j];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    s += (j == ii) ? 0.0 : q[j] * rinv64(r2);
+  }
+  if (i < N) part[c * N + i] = s;
+}
+
+__global__ __launch_bounds__(CB) void k_coul_finish(int64_t N, int nchunks, const double *__restrict__ part,
+                                                    const double *__restrict__ q, double c0,
+                                                    double *__restrict__ epart) {
+  __shared__ double red[CB];
+  const int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x;
+  double e = 0.0;
+  if (i < N) {
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[(int64_t)c * N + i];
+    e = 0.5 * c0 * q[i] * s;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = CB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(CB) void k_coul_add(int nb, const double *__restrict__ epart, double *__restrict__ E) {
+  __shared__ double red[CB];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += CB) s += epart[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = CB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *E += red[0];
+}
+
+inline int coul_chunks(int64_t N) {
+  const int64_t tb = (N + CB - 1) / CB;
+  int64_t nc = (2048 + tb - 1) / tb;
+  nc = nc < 1 ? 1 : (nc > 64 ? 64 : nc);
+  const int64_t most = (N + 255) / 256;  // at least 256 sources per chunk
+  return (int)(nc > most ? (most < 1 ? 1 : most) : nc);
+}
+
+inline size_t align256s(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Bytes of the Coulomb scratch, placed at the end of a full-evaluation workspace.
+size_t coul_bytes(int64_t N) {
+  return align256s(sizeof(double) * (size_t)N * coul_chunks(N)) + align256s(sizeof(double) * (size_t)((N + CB - 1) / CB));
+}
+
+// E += E_C of the system's current positions, with scratch at ws.
+hsma_status add_coulomb(const SysDev &h, int64_t N, double *E, char *ws, hipStream_t st) {
+  const int nc = coul_chunks(N);
+  const int64_t chunk = (N + nc - 1) / nc;
+  double *part = (double *)ws;
+  double *epart = (double *)(ws + align256s(sizeof(double) * (size_t)N * nc));
+  const int nb = (int)((N + CB - 1) / CB);
+  k_coul_pairs<<<dim3((unsigned)nb, (unsigned)nc), CB, 0, st>>>(N, chunk, h.x, h.y, h.z, h.q, part);
+  k_coul_finish<<<nb, CB, 0, st>>>(N, nc, part, h.q, h.pl.c0, epart);
+  k_coul_add<<<1, CB, 0, st>>>(nb, epart, E);
+  HSMA_HIP(hipGetLastError());
+  return HSMA_OK;
+}
+
 }  // namespace
 
 hsma_status launch_delta(const SysDev *systems, const DeReq *reqs, DeReq one, int nreq, int64_t max_n, int max_M,
@@ -259,11 +354,17 @@ hsma_status launch_delta(const SysDev *systems, const DeReq *reqs, DeReq one, in
 }
 
 hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
-  return run_batched(sys->g64, 1, nullptr, nullptr, sys->n, sys->n, sys->h.x, sys->h.y, sys->h.z, sys->h.q, nullptr,
-                     E, ws, ws_bytes, st);
+  if (ws_bytes < system_workspace_bytes(sys)) return HSMA_EINVAL;
+  const size_t lt = layout(sys->g64, 1, sys->n, sys->n).total;
+  hsma_status rc = run_batched(sys->g64, 1, nullptr, nullptr, sys->n, sys->n, sys->h.x, sys->h.y, sys->h.z, sys->h.q,
+                               nullptr, E, ws, lt, st);
+  if (rc != HSMA_OK || !sys->h.coulomb) return rc;
+  return add_coulomb(sys->h, sys->n, E, (char *)ws + lt, st);
 }
 
-size_t system_workspace_bytes(const hsma_system_s *sys) { return layout(sys->g64, 1, sys->n, sys->n).total; }
+size_t system_workspace_bytes(const hsma_system_s *sys) {
+  return layout(sys->g64, 1, sys->n, sys->n).total + (sys->h.coulomb ? coul_bytes(sys->n) : 0);
+}
 
 }  // namespace hsma
 
@@ -280,9 +381,11 @@ static void system_free(hsma_system_s *sys) {
   delete sys;
 }
 
-extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
-                                          const double *q, hipStream_t st, hsma_system_t *out) {
+extern "C" hsma_status hsma_system_create_ex(hsma_plan_t pl, int64_t N, const double *x, const double *y,
+                                             const double *z, const double *q, int flags, hipStream_t st,
+                                             hsma_system_t *out) {
   if (!pl || !out || N < 1 || N > ((int64_t)1 << 31) - 1 || !x || !y || !z || !q) return HSMA_EINVAL;
+  if (flags & ~HSMA_SYSTEM_COULOMB) return HSMA_EINVAL;
   *out = nullptr;
   int dev = -1;
   HSMA_HIP(hipGetDevice(&dev));
@@ -303,6 +406,7 @@ extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const doubl
   h.M = M;
   h.P = P;
   h.n = N;
+  h.coulomb = (flags & HSMA_SYSTEM_COULOMB) ? 1 : 0;
   hsma_status rc = group_build(1, &pl, 1, &sys->g64);
   if (rc != HSMA_OK) {
     system_free(sys);
@@ -315,7 +419,7 @@ extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const doubl
                    sizeof(SysDev);
   double *phi = nullptr;
   Layout L = layout(sys->g64, 1, N, N);
-  sys->ws_bytes = L.total;
+  sys->ws_bytes = L.total + (h.coulomb ? coul_bytes(N) : 0);
 #define HSMA_TRY(call)          \
   do {                          \
     if ((call) != hipSuccess) { \
@@ -344,8 +448,12 @@ extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const doubl
   HSMA_TRY(hipMemcpyAsync(h.q, q, nb, hipMemcpyDeviceToDevice, st));
   HSMA_TRY(hipMemcpyAsync(sys->d, &h, sizeof(SysDev), hipMemcpyHostToDevice, st));
   phi = (double *)((char *)sys->ws + L.phi);
-  rc = run_batched(sys->g64, 1, nullptr, nullptr, N, N, h.x, h.y, h.z, h.q, phi, h.E, sys->ws, sys->ws_bytes, st);
+  rc = run_batched(sys->g64, 1, nullptr, nullptr, N, N, h.x, h.y, h.z, h.q, phi, h.E, sys->ws, L.total, st);
   if (rc != HSMA_OK) goto fail;
+  if (h.coulomb) {
+    rc = add_coulomb(h, N, h.E, (char *)sys->ws + L.total, st);
+    if (rc != HSMA_OK) goto fail;
+  }
   k_sys_s<<<(P + 255) / 256, 256, 0, st>>>(P, (const double2 *)((char *)sys->ws + L.qd), h.s);
   k_sys_w<<<P, DB, 0, st>>>(sys->d);
   HSMA_TRY(hipGetLastError());
@@ -368,6 +476,11 @@ fail:
   (void)hipStreamSynchronize(st);
   system_free(sys);
   return rc;
+}
+
+extern "C" hsma_status hsma_system_create(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
+                                          const double *q, hipStream_t st, hsma_system_t *out) {
+  return hsma_system_create_ex(pl, N, x, y, z, q, 0, st, out);
 }
 
 extern "C" size_t hsma_system_workspace_bytes(hsma_system_t sys) { return sys ? system_workspace_bytes(sys) : 0; }

@@ -116,3 +116,47 @@ def test_invalid_moves(dev):
             sysm.delta_energy(k, new)
         assert ei.value.code == 1
     sysm.close()
+
+
+def test_total_energy_with_coulomb(dev):
+    """HSMA_SYSTEM_COULOMB: the energy and every move's change hold the direct Coulomb energy of
+    the ions too; the reference is (E_RF + E_C)(x') - (E_RF + E_C)(x) from the oracle, with
+    E_C the FP64 pair sum of its definition."""
+    a = 15.0
+    plan = hs.Plan(a, 1.0, 78.5, 0.5, 1024, 1536, pair_prec="fp64")
+    prm = _oparams(plan)
+    s = W.small_uniform(700, a, seed=123)
+    pos = np.stack([s.x, s.y, s.z], axis=1)
+    t = [torch.tensor(getattr(s, k), dtype=torch.float64, device=dev) for k in "xyzq"]
+    sysm = hs.System(plan, *t, coulomb=True)
+    plain = hs.System(plan, *t)
+
+    def total(p):
+        return _energy(prm, p, s.q) + oracle.coulomb_energy(1.0, p[:, 0], p[:, 1], p[:, 2], s.q)
+
+    e0 = total(pos)
+    assert abs(float(sysm.energy().cpu()[0]) - e0) <= 1e-11 * abs(e0)
+    rng = np.random.default_rng(29)
+    for step in range(12):
+        k = int(rng.integers(700))
+        new = W.random_move(rng, pos[k], a)
+        dE = float(sysm.delta_energy(k, new).cpu()[0])
+        moved = pos.copy()
+        moved[k] = new
+        ref = total(moved) - total(pos)
+        assert abs(dE - ref) <= 1e-12 * abs(e0) + 1e-9 * abs(ref), (k, dE, ref)
+        # the reaction-only system's change differs by exactly the Coulomb change
+        d_rf = float(plain.delta_energy(k, new).cpu()[0])
+        dc = (oracle.coulomb_energy(1.0, moved[:, 0], moved[:, 1], moved[:, 2], s.q) -
+              oracle.coulomb_energy(1.0, pos[:, 0], pos[:, 1], pos[:, 2], s.q))
+        assert abs((dE - d_rf) - dc) <= 1e-12 * abs(e0) + 1e-9 * abs(dc)
+        if step % 2 == 0:
+            sysm.commit(k, new)
+            plain.commit(k, new)
+            pos = moved
+    torch.cuda.synchronize()
+    fresh = total(pos)
+    assert abs(float(sysm.energy().cpu()[0]) - fresh) <= 1e-11 * abs(fresh)
+    assert abs(float(sysm.full_energy().cpu()[0]) - fresh) <= 1e-11 * abs(fresh)
+    sysm.close()
+    plain.close()

@@ -238,3 +238,13 @@ def test_kirkwood_truncated_converges():
     errs = [abs(oracle.kirkwood_eval(1.0, 2.0, 80.0, 5.0, x, y, z, q, order=o)[0] - ref) for o in (10, 20, 40, 80)]
     assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:]))
     assert errs[-1] < 1e-14
+
+
+def test_coulomb_energy_closed_forms():
+    """Two charges: q1 q2 / (4 pi eps1 r); a unit square of alternating charges: four nearest
+    pairs at distance 1 and two diagonal pairs at sqrt 2."""
+    e = oracle.coulomb_energy(2.0, [0.0, 3.0], [0.0, 0.0], [0.0, 4.0], [1.5, -2.0])
+    assert abs(e - 1.5 * -2.0 / (4 * math.pi * 2.0 * 5.0)) <= 1e-16
+    xs, ys = [0.0, 1.0, 1.0, 0.0], [0.0, 0.0, 1.0, 1.0]
+    e = oracle.coulomb_energy(1.0, xs, ys, [0.0] * 4, [1.0, -1.0, 1.0, -1.0])
+    assert abs(e - (-4.0 + 2.0 / math.sqrt(2.0)) / (4 * math.pi)) <= 1e-15
