@@ -90,6 +90,11 @@ typedef struct {
                        2p + 1 equispaced azimuths (the paper's 2p azimuths are zeros of
                        sin(p phi) and cannot fit degree p), so M must be 2p (2p + 1).  Set
                        rc_over_a = 1 for the paper's placement on the interface. */
+  int dipole;       /* surface dipoles (eq. "GreenSecond"): 0 exact normal dipoles (default);
+                       1 the paper's pair of point charges -+D/dy at R_tau -+ dy/2 along the
+                       normal (eq. "approxG"); the pair cancels about log10(R_tau/dy) digits, so
+                       it is meant for FP64 pairs or a large dy */
+  double dy_over_Rtau; /* dy / R_tau for dipole = 1, in (0, 0.1); <= 0: 1e-5 */
 } hsma_plan_opts;
 
 /* Read-only description of a plan (for callers and tests). */
@@ -101,6 +106,8 @@ typedef struct {
   int pair_prec;
   int device;
   int check_set;
+  int dipole;
+  double dy_over_Rtau;
 } hsma_plan_info;
 
 hsma_plan_opts hsma_plan_opts_default(void);

@@ -30,7 +30,7 @@ class HsmaError(RuntimeError):
 
 class PlanOpts(C.Structure):
     _fields_ = [("p", C.c_int), ("tau", C.c_double), ("rc_over_a", C.c_double), ("F1", C.c_int),
-                ("pair_prec", C.c_int), ("check_set", C.c_int)]
+                ("pair_prec", C.c_int), ("check_set", C.c_int), ("dipole", C.c_int), ("dy_over_Rtau", C.c_double)]
 
 
 class PlanInfo(C.Structure):
@@ -38,7 +38,7 @@ class PlanInfo(C.Structure):
                 ("tau", C.c_double), ("R_tau", C.c_double), ("rc", C.c_double), ("gamma", C.c_double),
                 ("sigma", C.c_double), ("dbar", C.c_double), ("p", C.c_int), ("K", C.c_int), ("P", C.c_int),
                 ("M", C.c_int), ("F1", C.c_int), ("F2", C.c_int), ("pair_prec", C.c_int), ("device", C.c_int),
-                ("check_set", C.c_int)]
+                ("check_set", C.c_int), ("dipole", C.c_int), ("dy_over_Rtau", C.c_double)]
 
 
 class Request(C.Structure):
@@ -215,7 +215,8 @@ class Plan:
 
     def __init__(self, a: float, eps1: float, eps2: float, kappa: float, P: int, M: int, p: int | None = None,
                  tau: float = 0.1, rc_over_a: float | None = None, F1: int | None = None,
-                 pair_prec: str | int = "fp32c", check_set: int = 0):
+                 pair_prec: str | int = "fp32c", check_set: int = 0, dipole: int = 0,
+                 dy_over_Rtau: float | None = None):
         L = load_library()
         o = L.hsma_plan_opts_default()
         if p is not None:
@@ -227,6 +228,9 @@ class Plan:
             o.F1 = int(F1)
         o.pair_prec = PAIR_PREC[pair_prec] if isinstance(pair_prec, str) else int(pair_prec)
         o.check_set = int(check_set)
+        o.dipole = int(dipole)
+        if dy_over_Rtau is not None:
+            o.dy_over_Rtau = float(dy_over_Rtau)
         h = _VP()
         _check(L.hsma_plan_ex(float(a), float(eps1), float(eps2), float(kappa), int(P), int(M), C.byref(o),
                               C.byref(h)), "hsma_plan_ex")

@@ -535,8 +535,35 @@ __global__ __launch_bounds__(256) void k_fit_moments(int K, int M, const TM *__r
   }
 }
 
+// The evaluation's surface sources of node s of system b: (Q', D') at s with exact dipoles
+// (Pe = P); with the paper's point pairs (Pe = 3P) the monopole (Q', 0) at 3s and the charges
+// (-D' R_tau/dy, 0), (+D' R_tau/dy, 0) at its inner and outer point (3s + 1, 3s + 2), whose
+// potential D' (R_tau/dy)(1/|x - y+| - 1/|x - y-|) tends to the dipole's D' (x - y).y / |x - y|^3.
+template <typename T2>
+__device__ __forceinline__ void store_strengths(T2 *__restrict__ qd, int b, int s, int P, int Pe, double q,
+                                                double d, double dyc) {
+  if (Pe == P) {
+    T2 o;
+    o.x = q;
+    o.y = d;
+    qd[(size_t)b * P + s] = o;
+  } else {
+    T2 o0, o1, o2;
+    o0.x = q;
+    o0.y = 0;
+    o1.x = -d * dyc;
+    o1.y = 0;
+    o2.x = d * dyc;
+    o2.y = 0;
+    T2 *e = qd + (size_t)b * Pe + 3 * (size_t)s;
+    e[0] = o0;
+    e[1] = o1;
+    e[2] = o2;
+  }
+}
+
 template <typename TM, typename T2>
-__global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__restrict__ base, int P, int K,
+__global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__restrict__ base, int P, int Pe, int K,
                                                      const TM *__restrict__ lhat, const PlanDev *__restrict__ plans,
                                                      const int32_t *__restrict__ plan_of, const int *__restrict__ nidx,
                                                      const double *__restrict__ ab, T2 *__restrict__ qd) {
@@ -560,12 +587,7 @@ __global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__
   }
   sq = wave_sum(sq);
   sd = wave_sum(sd);
-  if (lane == 0) {
-    T2 o;
-    o.x = sq;
-    o.y = -sd;
-    qd[(size_t)b * P + s] = o;
-  }
+  if (lane == 0) store_strengths(qd, b, s, P, Pe, sq, -sd, plans[plan_of ? plan_of[b] : 0].dyc);
 }
 
 // ---------------------------------------------------------------------------------
@@ -755,14 +777,14 @@ __global__ __launch_bounds__(256) void k_fit_h(int nsys, const int64_t *__restri
 
 // qd[b][s] = (C[2b][s], -C[2b+1][s]) from the second GEMM's output [2 nsys][P].
 template <typename T2>
-__global__ __launch_bounds__(256) void k_fit_qd(int nsys, int P, const float *__restrict__ Cq, T2 *__restrict__ qd) {
+__global__ __launch_bounds__(256) void k_fit_qd(int nsys, int P, int Pe, const PlanDev *__restrict__ plans,
+                                                const int32_t *__restrict__ plan_of, const float *__restrict__ Cq,
+                                                T2 *__restrict__ qd) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)nsys * P) return;
   const int b = (int)(t / P), s = (int)(t % P);
-  T2 o;
-  o.x = Cq[(size_t)(2 * b) * P + s];
-  o.y = -Cq[(size_t)(2 * b + 1) * P + s];
-  qd[t] = o;
+  store_strengths(qd, b, s, P, Pe, (double)Cq[(size_t)(2 * b) * P + s], -(double)Cq[(size_t)(2 * b + 1) * P + s],
+                  plans[plan_of ? plan_of[b] : 0].dyc);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1374,6 +1396,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   using T4 = typename PT<MODE>::T4;
   const Geometry *g = grp->geo;
   const int M = g->M, P = g->P, K = g->K, nsys = L.nsys;
+  const int Pe = grp->P_ev;  // surface sources of the evaluation
   int64_t *base = (int64_t *)(ws + L.sched);
   int *sys_c = (int *)(ws + L.item_sys_c);
   int *sys_e = (int *)(ws + L.item_sys_e);
@@ -1406,7 +1429,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   bd.parts_c = L.parts_c;
   bd.parts_e = L.parts_e;
   bd.nplans = grp->nplans;
-  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, P, L.chc, L.che, L.sym_tb, L.sch, grid_c, grid_e,
+  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, Pe, L.chc, L.che, L.sym_tb, L.sch, grid_c, grid_e,
                                     base, grp->flag);
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f, plans, plan_of, x, y, z, q, img, tgt,
@@ -1445,14 +1468,14 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       k_gemm_bf<3><<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->Kp, g->lhat_bf, h32, c2);
     else
       k_gemm_nt<<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->lhat32, h32, c2);
-    k_fit_qd<T2><<<(int)cdiv((int64_t)nsys * P, 256), 256, 0, st>>>(nsys, P, c2, qd);
+    k_fit_qd<T2><<<(int)cdiv((int64_t)nsys * P, 256), 256, 0, st>>>(nsys, P, Pe, plans, plan_of, c2, qd);
   } else if constexpr (MODE == HSMA_PAIR_FP64) {
     k_fit_moments<double><<<dim3((unsigned)cdiv(K, 4), nsys), 256, 0, st>>>(K, M, g->pinv64, uv, ab);
-    k_fit_surface<double, T2><<<dim3((unsigned)cdiv(P, 4), nsys), 256, 0, st>>>(nsys, base, P, K, g->lhat64, plans,
+    k_fit_surface<double, T2><<<dim3((unsigned)cdiv(P, 4), nsys), 256, 0, st>>>(nsys, base, P, Pe, K, g->lhat64, plans,
                                                                                 plan_of, g->nidx, ab, qd);
   } else {
     k_fit_moments<float><<<dim3((unsigned)cdiv(K, 4), nsys), 256, 0, st>>>(K, M, g->pinv32, uv, ab);
-    k_fit_surface<float, T2><<<dim3((unsigned)cdiv(P, 4), nsys), 256, 0, st>>>(nsys, base, P, K, g->lhat32, plans,
+    k_fit_surface<float, T2><<<dim3((unsigned)cdiv(P, 4), nsys), 256, 0, st>>>(nsys, base, P, Pe, K, g->lhat32, plans,
                                                                                plan_of, g->nidx, ab, qd);
   }
   prof_end(pr, st);
@@ -1465,10 +1488,10 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       const float *wk = (const float *)(ws + L.wk);
       const double *rk = (const double *)(ws + L.rk);
       if (L.sym_tb == 256)
-        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
+        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
                                             eval_part);
       else
-        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, P, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
+        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
                                             eval_part);
       done = true;
     }
@@ -1476,21 +1499,21 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   if (L.field) {
     if (L.items_e > 0)
       k_eval_field<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(
-          persistent, nsys, P, L.che, base, sys_e, plan_of, tgt, img, group_nodes<MODE>(grp), qd,
+          persistent, nsys, Pe, L.che, base, sys_e, plan_of, tgt, img, group_nodes<MODE>(grp), qd,
           L.lo ? (const float4 *)(ws + L.tlo) : nullptr, L.lo ? (const float4 *)(ws + L.ilo) : nullptr,
           (double4 *)eval_part);
   } else if (!done && L.items_e > 0) {
-    k_eval<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(persistent, nsys, P, L.che, base, sys_e, plans, plan_of, tgt, img,
+    k_eval<MODE><<<(unsigned)grid_e, TPB, 0, st>>>(persistent, nsys, Pe, L.che, base, sys_e, plans, plan_of, tgt, img,
                                                    group_nodes<MODE>(grp), qd, eval_part);
   }
   prof_end(pr, st);
 
   pr = prof_begin(grp, ST_FINISH, st);
   if (L.fin > 0 && L.field)
-    k_finish_field<<<(int)L.fin, FINB, 0, st>>>(nsys, P, L.che, base, sys_f, (const double4 *)eval_part, self,
+    k_finish_field<<<(int)L.fin, FINB, 0, st>>>(nsys, Pe, L.che, base, sys_f, (const double4 *)eval_part, self,
                                                 (const double4 *)(ws + L.sfield), q, phi, ex, ey, ez, epart);
   else if (L.fin > 0)
-    k_finish<<<(int)L.fin, FINB, 0, st>>>(nsys, P, L.che, L.sym_tb, L.sch, base, sys_f, eval_part, self, q, phi,
+    k_finish<<<(int)L.fin, FINB, 0, st>>>(nsys, Pe, L.che, L.sym_tb, L.sch, base, sys_f, eval_part, self, q, phi,
                                           epart);
   if (E) k_energy<<<nsys, 64, 0, st>>>(nsys, base, epart, E);
   prof_end(pr, st);
@@ -1507,7 +1530,8 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   Layout L;
   L.field = field;
   const Geometry *g = grp->geo;
-  const int64_t M = g->M, P = g->P, K = g->K;
+  const int64_t M = g->M, Pf = g->P, K = g->K;
+  const int64_t P = grp->P_ev;  // surface sources of the evaluation
   const bool fp64 = grp->pair_prec == HSMA_PAIR_FP64;
   L.nsys = nsys;
   L.total_n = total_n;
@@ -1578,7 +1602,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.uv32 = L.mfma ? take(sizeof(float) * 2 * (size_t)M * nsys) : 0;
   L.ab = take(sizeof(double) * 2 * (size_t)K * nsys);
   L.h32 = L.mfma ? take(sizeof(float) * 2 * (size_t)K * nsys) : 0;
-  L.gemm2 = L.mfma ? take(sizeof(float) * 2 * (size_t)P * nsys) : 0;
+  L.gemm2 = L.mfma ? take(sizeof(float) * 2 * (size_t)Pf * nsys) : 0;
   L.qd = take(sizeof(double2) * (size_t)P * nsys);
   L.eval_part = take((field ? sizeof(double4) : sizeof(double)) * (size_t)L.parts_e);
   L.sfield = field ? take(sizeof(double4) * (size_t)total_n) : 0;
@@ -1599,7 +1623,7 @@ hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, con
   if (!grp || nsys < 1 || total_n < 0 || max_n < 0 || max_n > total_n || !ws) return HSMA_EINVAL;
   const bool field = ex || ey || ez;
   if (field && (!ex || !ey || !ez)) return HSMA_EINVAL;
-  if (total_n + grp->geo->P > ((int64_t)1 << 31) - 1) return HSMA_EINVAL;  // 32-bit source indices
+  if (total_n + grp->P_ev > ((int64_t)1 << 31) - 1) return HSMA_EINVAL;  // 32-bit source indices
   if (total_n > 0 && (!x || !y || !z || !q)) return HSMA_EINVAL;
   if (((uintptr_t)ws & 255) != 0) return HSMA_EINVAL;
   if (nsys > 1 && !offsets) return HSMA_EINVAL;
@@ -1792,27 +1816,26 @@ extern "C" hsma_status hsma_debug_intermediates(hsma_plan_t pl, int64_t N, const
   if (u) HSMA_HIP(hipMemcpy(u, w + L.uv, sizeof(double) * M, hipMemcpyDeviceToHost));
   if (v) HSMA_HIP(hipMemcpy(v, w + L.uv + sizeof(double) * M, sizeof(double) * M, hipMemcpyDeviceToHost));
   if (Q || D) {
+    // (Q', D') per node, or from the point-pair layout: Q' at 3s, D' = (outer charge) dy / R_tau
+    const int Pe = pl->self->P_ev, stride = Pe / P;
+    const double dyc = pl->host.dyc;
+    double2 *h = new double2[Pe];
+    hipError_t e;
     if (pl->self->pair_prec == HSMA_PAIR_FP64) {
-      double2 *h = new double2[P];
-      hipError_t e = hipMemcpy(h, w + L.qd, sizeof(double2) * P, hipMemcpyDeviceToHost);
-      if (e == hipSuccess)
-        for (int s = 0; s < P; ++s) {
-          if (Q) Q[s] = h[s].x;
-          if (D) D[s] = h[s].y;
-        }
-      delete[] h;
-      if (e != hipSuccess) return HSMA_EDEVICE;
+      e = hipMemcpy(h, w + L.qd, sizeof(double2) * Pe, hipMemcpyDeviceToHost);
     } else {
-      float2 *h = new float2[P];
-      hipError_t e = hipMemcpy(h, w + L.qd, sizeof(float2) * P, hipMemcpyDeviceToHost);
-      if (e == hipSuccess)
-        for (int s = 0; s < P; ++s) {
-          if (Q) Q[s] = h[s].x;
-          if (D) D[s] = h[s].y;
-        }
-      delete[] h;
-      if (e != hipSuccess) return HSMA_EDEVICE;
+      float2 *f = new float2[Pe];
+      e = hipMemcpy(f, w + L.qd, sizeof(float2) * Pe, hipMemcpyDeviceToHost);
+      for (int s = 0; s < Pe; ++s) h[s] = make_double2(f[s].x, f[s].y);
+      delete[] f;
     }
+    if (e == hipSuccess)
+      for (int s = 0; s < P; ++s) {
+        if (Q) Q[s] = h[stride * s].x;
+        if (D) D[s] = stride == 1 ? h[s].y : h[3 * s + 2].x / dyc;
+      }
+    delete[] h;
+    if (e != hipSuccess) return HSMA_EDEVICE;
   }
   return HSMA_OK;
 }

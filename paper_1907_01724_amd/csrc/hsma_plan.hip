@@ -344,6 +344,18 @@ __global__ void k_chol_solve(int K, int M, const double *L, double *X, double *X
 }
 
 // Per-plan node coordinates: check points at radius rc, surface nodes at R_tau.
+// Point-pair dipoles (eq. "approxG"): node s at 3s (radius R), its inner charge at radius
+// R - dy/2 (3s + 1) and its outer charge at R + dy/2 (3s + 2), along the unit normal.
+__global__ void k_pair_points(int P, const double *unit, double R, double dy, float4 *p32, double4 *p64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * P) return;
+  const int s = i / 3, t = i % 3;
+  const double r = t == 0 ? R : (t == 1 ? R - 0.5 * dy : R + 0.5 * dy);
+  const double x = r * unit[3 * s], y = r * unit[3 * s + 1], z = r * unit[3 * s + 2];
+  p32[i] = make_float4((float)x, (float)y, (float)z, 0.f);
+  p64[i] = make_double4(x, y, z, 0.0);
+}
+
 __global__ void k_scale_points(int n, const double *unit, double r, float4 *p32, double4 *p64) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -537,6 +549,8 @@ extern "C" hsma_plan_opts hsma_plan_opts_default(void) {
   o.F1 = 0;
   o.pair_prec = HSMA_PAIR_FP32_COMP;
   o.check_set = 0;
+  o.dipole = 0;
+  o.dy_over_Rtau = 0.0;
   return o;
 }
 
@@ -556,6 +570,9 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   if (o.rc_over_a <= 0.0) o.rc_over_a = 1.0 + o.tau;
   if (!(isfinite(o.rc_over_a) && o.rc_over_a >= 1.0 && o.rc_over_a < 10.0)) return HSMA_EINVAL;
   if (o.check_set != 0 && o.check_set != 1) return HSMA_EINVAL;
+  if (o.dipole != 0 && o.dipole != 1) return HSMA_EINVAL;
+  if (o.dy_over_Rtau <= 0.0) o.dy_over_Rtau = 1e-5;
+  if (!(isfinite(o.dy_over_Rtau) && o.dy_over_Rtau < 0.1)) return HSMA_EINVAL;
   if (o.p < 0) {
     int s = (int)floor(sqrt((double)P));
     while ((long)(s + 1) * (s + 1) <= P) ++s;
@@ -600,12 +617,16 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   HSMA_TRY(hipMalloc(&consts, sizeof(double) * (3 + o.p + 1)));
   HSMA_TRY(hipMalloc(&pl->chk32, sizeof(float4) * M));
   HSMA_TRY(hipMalloc(&pl->chk64, sizeof(double4) * M));
-  HSMA_TRY(hipMalloc(&pl->nodes32, sizeof(float4) * P));
-  HSMA_TRY(hipMalloc(&pl->nodes64, sizeof(double4) * P));
+  HSMA_TRY(hipMalloc(&pl->nodes32, sizeof(float4) * P * (o.dipole ? 3 : 1)));
+  HSMA_TRY(hipMalloc(&pl->nodes64, sizeof(double4) * P * (o.dipole ? 3 : 1)));
   k_plan_constants<<<1, 1, 0, st>>>(o.p, eps1 / eps2, kappa * a, o.tau, o.rc_over_a, a, consts, pl->fg);
   k_scale_points<<<blocks(M, 256), 256, 0, st>>>(M, g->unit_check, o.rc_over_a * a, pl->chk32, pl->chk64);
-  k_scale_points<<<blocks(P, 256), 256, 0, st>>>(P, g->unit_nodes, (1.0 + o.tau) * a, pl->nodes32,
-                                                 pl->nodes64);
+  if (o.dipole)
+    k_pair_points<<<blocks(3 * P, 256), 256, 0, st>>>(P, g->unit_nodes, (1.0 + o.tau) * a,
+                                                      o.dy_over_Rtau * (1.0 + o.tau) * a, pl->nodes32, pl->nodes64);
+  else
+    k_scale_points<<<blocks(P, 256), 256, 0, st>>>(P, g->unit_nodes, (1.0 + o.tau) * a, pl->nodes32,
+                                                   pl->nodes64);
   HSMA_TRY(hipGetLastError());
   HSMA_TRY(hipMemcpyAsync(hc, consts, sizeof(hc), hipMemcpyDeviceToHost, st));
   HSMA_TRY(hipStreamSynchronize(st));
@@ -624,6 +645,8 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   pl->host.chk64 = pl->chk64;
   pl->host.nodes32 = pl->nodes32;
   pl->host.nodes64 = pl->nodes64;
+  pl->host.dipole = o.dipole;
+  pl->host.dyc = 1.0 / o.dy_over_Rtau;
   (void)hipFree(consts);
   consts = nullptr;
   (void)hipStreamDestroy(st);
@@ -675,6 +698,8 @@ extern "C" hsma_status hsma_plan_get_info(hsma_plan_t pl, hsma_plan_info *info) 
   info->pair_prec = pl->opts.pair_prec;
   info->device = pl->device;
   info->check_set = pl->geo->check_set;
+  info->dipole = pl->opts.dipole;
+  info->dy_over_Rtau = pl->opts.dy_over_Rtau;
   return HSMA_OK;
 }
 
@@ -689,8 +714,10 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
     if (!plans[i]) return HSMA_EINVAL;
   Geometry *g = plans[0]->geo;
   const int prec = plans[0]->opts.pair_prec;
+  const int dipole = plans[0]->opts.dipole;
   for (int i = 1; i < nplans; ++i)
-    if (plans[i]->geo != g || plans[i]->opts.pair_prec != prec) return HSMA_ESTATE;
+    if (plans[i]->geo != g || plans[i]->opts.pair_prec != prec || plans[i]->opts.dipole != dipole)
+      return HSMA_ESTATE;
   int dev = -1;
   HSMA_HIP(hipGetDevice(&dev));
   if (dev != g->device) return HSMA_ESTATE;
@@ -701,6 +728,7 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
   grp->pair_prec = prec;
   grp->device = g->device;
   grp->owned_by_plan = owned_by_plan;
+  grp->P_ev = g->P * (dipole ? 3 : 1);
   grp->tune.persistent = 0;
   grp->tune.target_items = 16384;
   grp->tune.symmetric = 1;
@@ -712,7 +740,7 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
   PlanDev *h = new PlanDev[nplans];
   for (int i = 0; i < nplans; ++i) h[i] = plans[i]->host;
   hsma_status rc = HSMA_OK;
-  const size_t P = (size_t)g->P;
+  const size_t P = (size_t)grp->P_ev;
   if (hipMalloc(&grp->dev, sizeof(PlanDev) * nplans) != hipSuccess ||
       hipMalloc(&grp->flag, sizeof(int)) != hipSuccess ||
       hipMalloc(&grp->nodes32, sizeof(float4) * P * nplans) != hipSuccess ||

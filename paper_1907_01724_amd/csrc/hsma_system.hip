@@ -67,6 +67,27 @@ __device__ __forceinline__ double self_g(const PlanDev &c, double x, double y, d
   return c.c0 / c.a * (c.gamma * c.a2 + 0.5 * c.dbar * (c.Rtau * r - c.a2)) / ((c.a - r) * (c.a + r));
 }
 
+// Row S(x) of node s for a unit charge at x: the monopole 1/|x - y_s| and the dipole kernel,
+// (x - y_s).y_s / |x - y_s|^3 for exact dipoles or (R_tau/dy)(1/|x - y+| - 1/|x - y-|) for the
+// paper's point pairs (nodes at 3s, 3s + 1, 3s + 2).
+__device__ __forceinline__ void surface_row(const PlanDev &c, int s, double x, double y, double z, double &m,
+                                            double &t) {
+  if (!c.dipole) {
+    const double4 yv = c.nodes64[s];
+    const double dx = x - yv.x, dy = y - yv.y, dz = z - yv.z;
+    const double ir = rinv64(dx * dx + dy * dy + dz * dz);
+    m = ir;
+    t = (dx * yv.x + dy * yv.y + dz * yv.z) * ir * ir * ir;
+  } else {
+    const double4 y0 = c.nodes64[3 * s], ym = c.nodes64[3 * s + 1], yp = c.nodes64[3 * s + 2];
+    const double ax = x - y0.x, ay = y - y0.y, az = z - y0.z;
+    const double bx = x - ym.x, by = y - ym.y, bz = z - ym.z;
+    const double px = x - yp.x, py = y - yp.y, pz = z - yp.z;
+    m = rinv64(ax * ax + ay * ay + az * az);
+    t = c.dyc * (rinv64(px * px + py * py + pz * pz) - rinv64(bx * bx + by * by + bz * bz));
+  }
+}
+
 __device__ __forceinline__ double block_sum(double v, double *red) {
   red[threadIdx.x] = v;
   __syncthreads();
@@ -128,13 +149,10 @@ __global__ __launch_bounds__(DB) void k_de_pairs(const SysDev *__restrict__ syst
   }
   const int s = (blk - nA - nB) * DB + threadIdx.x;
   if (s < S.P) {
-    const double4 yv = c.nodes64[s];
-    const double dx1 = x1 - yv.x, dy1 = y1 - yv.y, dz1 = z1 - yv.z;
-    const double dx0 = x0 - yv.x, dy0 = y0 - yv.y, dz0 = z0 - yv.z;
-    const double i1 = rinv64(dx1 * dx1 + dy1 * dy1 + dz1 * dz1), i0 = rinv64(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
-    const double t1 = (dx1 * yv.x + dy1 * yv.y + dz1 * yv.z) * i1 * i1 * i1;
-    const double t0 = (dx0 * yv.x + dy0 * yv.y + dz0 * yv.z) * i0 * i0 * i0;
-    S.dw[s] = qk * (i1 - i0);
+    double m1, m0, t1, t0;
+    surface_row(c, s, x1, y1, z1, m1, t1);
+    surface_row(c, s, x0, y0, z0, m0, t0);
+    S.dw[s] = qk * (m1 - m0);
     S.dw[S.P + s] = qk * (t1 - t0);
   }
 }
@@ -231,13 +249,12 @@ __global__ __launch_bounds__(DB) void k_sys_w(SysDev *__restrict__ sd) {
   __shared__ double red[DB];
   const SysDev &S = *sd;
   const int s = blockIdx.x;
-  const double4 yv = S.pl.nodes64[s];
   double a = 0.0, b = 0.0;
   for (int64_t i = threadIdx.x; i < S.n; i += DB) {
-    const double dx = S.x[i] - yv.x, dy = S.y[i] - yv.y, dz = S.z[i] - yv.z;
-    const double ir = rinv64(dx * dx + dy * dy + dz * dz);
-    a += S.q[i] * ir;
-    b += S.q[i] * (dx * yv.x + dy * yv.y + dz * yv.z) * ir * ir * ir;
+    double m, t;
+    surface_row(S.pl, s, S.x[i], S.y[i], S.z[i], m, t);
+    a += S.q[i] * m;
+    b += S.q[i] * t;
   }
   a = block_sum(a, red);
   b = block_sum(b, red);
@@ -247,12 +264,13 @@ __global__ __launch_bounds__(DB) void k_sys_w(SysDev *__restrict__ sd) {
   }
 }
 
-// s from the full evaluation's strengths (double2 per node) into the Q', D' layout.
-__global__ void k_sys_s(int P, const double2 *__restrict__ qd, double *__restrict__ s) {
+// s from the full evaluation's strengths (double2 per surface source) into the Q', D' layout;
+// with point pairs node i's sources are at 3i (Q') and 3i + 2 (D' R_tau / dy).
+__global__ void k_sys_s(int P, int dipole, double dyc, const double2 *__restrict__ qd, double *__restrict__ s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  s[i] = qd[i].x;
-  s[P + i] = qd[i].y;
+  s[i] = dipole ? qd[3 * i].x : qd[i].x;
+  s[P + i] = dipole ? qd[3 * i + 2].x / dyc : qd[i].y;
 }
 
 // Direct Coulomb energy in FP64: partials of sum_{j != i} q_j / |x_i - x_j| per target and
@@ -454,7 +472,7 @@ extern "C" hsma_status hsma_system_create_ex(hsma_plan_t pl, int64_t N, const do
     rc = add_coulomb(h, N, h.E, (char *)sys->ws + L.total, st);
     if (rc != HSMA_OK) goto fail;
   }
-  k_sys_s<<<(P + 255) / 256, 256, 0, st>>>(P, (const double2 *)((char *)sys->ws + L.qd), h.s);
+  k_sys_s<<<(P + 255) / 256, 256, 0, st>>>(P, h.pl.dipole, h.pl.dyc, (const double2 *)((char *)sys->ws + L.qd), h.s);
   k_sys_w<<<P, DB, 0, st>>>(sys->d);
   HSMA_TRY(hipGetLastError());
   HSMA_TRY(hipStreamSynchronize(st));
