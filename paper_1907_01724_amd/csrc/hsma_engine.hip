@@ -35,6 +35,7 @@ constexpr int GRP = 64;          // targets per item
 constexpr int TILE = 32;         // sources per FP32 partial sum before folding into FP64
 constexpr int FINB = 256;        // ions per finish block
 constexpr int SCHED_T = 1024;    // threads of the schedule kernel
+constexpr int SYM_SH = 2;        // surface items per block and chunk (each takes 1/SYM_SH of the block's ions)
 constexpr int64_t SYM_MAX_BYTES = (int64_t)16 << 30;  // partial-slot bound above which the symmetric
                                                        // Kelvin kernel is not used
 
@@ -91,10 +92,12 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 // Schedule.  sched (int64) holds, each with nsys + 1 entries:
 //   [0] ion offsets  [1] check-item prefix  [2] eval-item prefix  [3] finish-block prefix
 //   [4] check partial-slot prefix  [5] eval partial-slot prefix
+//   [6] surface-item prefix of the symmetric kernel (its items are every system's block pairs,
+//       counted by [2], followed by every system's surface items, counted here)
 // followed by 8 words: [0] check item counter, [1] eval item counter.
 // ---------------------------------------------------------------------------------
 struct Sched {
-  int64_t *off, *ic, *ie, *fb, *pc, *pe, *ctr;
+  int64_t *off, *ic, *ie, *fb, *pc, *pe, *is, *ctr;
   __host__ __device__ Sched(int64_t *base, int nsys) {
     const int64_t s = nsys + 1;
     off = base;
@@ -103,7 +106,8 @@ struct Sched {
     fb = base + 3 * s;
     pc = base + 4 * s;
     pe = base + 5 * s;
-    ctr = base + 6 * s;
+    is = base + 6 * s;
+    ctr = base + 7 * s;
   }
 };
 
@@ -113,13 +117,17 @@ struct Bounds {
   int nplans;
 };
 
+// Evaluation items of a system: one-directional (items), or for the symmetric kernel its block
+// pairs I <= J (items) and its surface items (surf: SYM_SH per block and surface chunk).
 __device__ __forceinline__ void eval_counts(int64_t n, int P, int che, int sym_tb, int sch, int64_t &items,
-                                            int64_t &parts) {
+                                            int64_t &surf, int64_t &parts) {
+  surf = 0;
   if (n <= 0) {
     items = parts = 0;
-  } else if (sym_tb > 0) {  // symmetric Kelvin blocks: pair items I <= J, then surface chunks
+  } else if (sym_tb > 0) {
     const int64_t B = cdiv64(n, sym_tb);
-    items = B * (B + 1) / 2 + B * sch;
+    items = B * (B + 1) / 2;
+    surf = B * sch * SYM_SH;
     parts = n * (B + sch);
   } else {
     items = cdiv64(n, GRP) * cdiv64(n + P, che);
@@ -133,7 +141,7 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
                                                       int64_t grid_e, int64_t *__restrict__ base,
                                                       int *__restrict__ flag) {
   Sched S(base, nsys);
-  __shared__ int64_t sc[5][SCHED_T];
+  __shared__ int64_t sc[6][SCHED_T];
   const int t = threadIdx.x, nt = blockDim.x;  // nt <= SCHED_T, a multiple of 64
   const int seg = (nsys + nt - 1) / nt;
   const int b0 = t * seg, b1 = min(nsys, b0 + seg);
@@ -149,48 +157,52 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     if (plan_of && (plan_of[b] < 0 || plan_of[b] >= bd.nplans)) bad = 1;
   }
   bad = __syncthreads_or(bad);
-  int64_t acc[5] = {0, 0, 0, 0, 0};
+  int64_t acc[6] = {0, 0, 0, 0, 0, 0};
   for (int b = b0; b < b1 && !bad; ++b) {
     const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
     const int64_t n = hi - lo;
     const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
-    int64_t items_e, parts_e;
-    eval_counts(n, P, che, sym_tb, sch, items_e, parts_e);
+    int64_t items_e, surf_e, parts_e;
+    eval_counts(n, P, che, sym_tb, sch, items_e, surf_e, parts_e);
     acc[0] += Gc * chunks_c;
     acc[1] += items_e;
     acc[2] += cdiv64(n, FINB);
     acc[3] += Gc * chunks_c * GRP;
     acc[4] += parts_e;
+    acc[5] += surf_e;
   }
-  for (int k = 0; k < 5; ++k) sc[k][t] = acc[k];
+  for (int k = 0; k < 6; ++k) sc[k][t] = acc[k];
   __syncthreads();
   // inclusive Hillis-Steele scan over the thread totals
   for (int o = 1; o < nt; o <<= 1) {
-    int64_t v[5];
-    for (int k = 0; k < 5; ++k) v[k] = t >= o ? sc[k][t - o] : 0;
+    int64_t v[6];
+    for (int k = 0; k < 6; ++k) v[k] = t >= o ? sc[k][t - o] : 0;
     __syncthreads();
-    for (int k = 0; k < 5; ++k) sc[k][t] += v[k];
+    for (int k = 0; k < 6; ++k) sc[k][t] += v[k];
     __syncthreads();
   }
-  int64_t run[5];
-  for (int k = 0; k < 5; ++k) run[k] = sc[k][t] - acc[k];  // exclusive start of this segment
+  int64_t run[6];
+  for (int k = 0; k < 6; ++k) run[k] = sc[k][t] - acc[k];  // exclusive start of this segment
+  run[5] += sc[1][nt - 1];  // surface items follow every system's evaluation items
   for (int b = b0; b < b1 && !bad; ++b) {
     const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
     const int64_t n = hi - lo;
     const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
-    int64_t items_e, parts_e;
-    eval_counts(n, P, che, sym_tb, sch, items_e, parts_e);
+    int64_t items_e, surf_e, parts_e;
+    eval_counts(n, P, che, sym_tb, sch, items_e, surf_e, parts_e);
     S.off[b] = lo;
     S.ic[b] = run[0];
     S.ie[b] = run[1];
     S.fb[b] = run[2];
     S.pc[b] = run[3];
     S.pe[b] = run[4];
+    S.is[b] = run[5];
     run[0] += Gc * chunks_c;
     run[1] += items_e;
     run[2] += cdiv64(n, FINB);
     run[3] += Gc * chunks_c * GRP;
     run[4] += parts_e;
+    run[5] += surf_e;
   }
   if (t == nt - 1) {
     S.off[nsys] = offsets ? offsets[nsys] : n_single;
@@ -199,10 +211,11 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     S.fb[nsys] = sc[2][t];
     S.pc[nsys] = sc[3][t];
     S.pe[nsys] = sc[4][t];
+    S.is[nsys] = sc[1][t] + sc[5][t];
     for (int k = 0; k < 8; ++k) S.ctr[k] = 0;
     S.ctr[0] = grid_c;  // items below the grid size are taken by block index
     S.ctr[1] = grid_e;
-    const bool fits = sc[0][t] <= bd.items_c && sc[1][t] <= bd.items_e && sc[2][t] <= bd.fin &&
+    const bool fits = sc[0][t] <= bd.items_c && sc[1][t] + sc[5][t] <= bd.items_e && sc[2][t] <= bd.fin &&
                       sc[3][t] <= bd.parts_c && sc[4][t] <= bd.parts_e;
     const bool ok = !bad && fits;
     S.ctr[2] = ok ? 1 : 0;  // every later kernel of the call does nothing unless set
@@ -1129,31 +1142,89 @@ __device__ __forceinline__ float wave_total_lane63(float v) {
 
 template <int R>
 __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, const int64_t *__restrict__ base,
-                                                    const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
+                                                    const int32_t *__restrict__ plan_of,
                                                     const float4 *__restrict__ tgt, const float4 *__restrict__ img,
                                                     const float *__restrict__ wk, const double *__restrict__ rk,
                                                     const float4 *__restrict__ nodes,
                                                     const float2 *__restrict__ qd, double *__restrict__ part) {
   constexpr int TB = 64 * R;
+  constexpr int RS = R / SYM_SH;         // target sets per lane of a surface item
   constexpr float FAR_TARGET = 3.0e18f;  // stand-in position of an empty target lane
   Sched S(const_cast<int64_t *>(base), nsys);
   const int lane = threadIdx.x & 63, w = wave_id();
   if (!sched_ok(S)) return;
   const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);  // one item per wave
-  if (item >= S.ie[nsys]) return;
-  const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
+  if (item >= S.is[nsys]) return;
+  // every system's block pairs first, then every system's surface items: the shorter surface
+  // items fill the end of the launch
+  const bool surface = item >= S.ie[nsys];
+  const int b = __builtin_amdgcn_readfirstlane(surface ? system_of(S.is, nsys, item) : system_of(S.ie, nsys, item));
   const int64_t lo = S.off[b];
   const int n = (int)(S.off[b + 1] - lo);
   const int64_t B = cdiv64(n, TB);
-  const int64_t npair = B * (B + 1) / 2;
-  const int64_t loc = item - S.ie[b];
   double *pb = part + S.pe[b];
   const float4 *im = img + lo;
+  if (surface) {
+    // surface item: block I, node chunk c, target sets h RS .. h RS + RS - 1 of each lane
+    const int64_t t = item - S.is[b];
+    const int I = __builtin_amdgcn_readfirstlane((int)(t / (sch * SYM_SH)));
+    const int rem = (int)(t % (sch * SYM_SH));
+    const int c = __builtin_amdgcn_readfirstlane(rem / SYM_SH), h = __builtin_amdgcn_readfirstlane(rem % SYM_SH);
+    const int t0 = I * TB + h * RS * 64;
+    float sx[RS], sy[RS], sz[RS];
+#pragma unroll
+    for (int k = 0; k < RS; ++k) {
+      const int i = t0 + k * 64 + lane;
+      if (i < n) {
+        const float4 tv = tgt[lo + i];
+        sx[k] = tv.x;
+        sy[k] = tv.y;
+        sz[k] = tv.z;
+      } else {
+        sx[k] = FAR_TARGET;
+        sy[k] = 0.0f;
+        sz[k] = 0.0f;
+      }
+    }
+    double acc[RS];
+#pragma unroll
+    for (int k = 0; k < RS; ++k) acc[k] = 0.0;
+    const int per = (P + sch - 1) / sch;
+    const int s0 = c * per, s1 = s0 + per < P ? s0 + per : P;
+    const int pl = plan_of ? plan_of[b] : 0;
+    const float4 *nd = nodes + (size_t)pl * P;
+    const float2 *qb = qd + (size_t)b * P;
+    for (int sb = s0; sb < s1; sb += TILE) {
+      const int se = sb + TILE < s1 ? sb + TILE : s1;
+      float sum[RS];
+#pragma unroll
+      for (int k = 0; k < RS; ++k) sum[k] = 0.0f;
+      for (int m = sb; m < se; ++m) {
+        const float4 yv = nd[m];
+        const float2 wv = qb[m];
+#pragma unroll
+        for (int k = 0; k < RS; ++k) {
+          const float dx = sx[k] - yv.x, dy = sy[k] - yv.y, dz = sz[k] - yv.z;
+          const float ri = rinv(dx * dx + dy * dy + dz * dz);
+          const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
+          sum[k] = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < RS; ++k) acc[k] += (double)sum[k];
+    }
+    const int64_t slot = B + c;
+#pragma unroll
+    for (int k = 0; k < RS; ++k) {
+      const int i = t0 + k * 64 + lane;
+      if (i < n) pb[(size_t)slot * n + i] = acc[k];
+    }
+    return;
+  }
   int I, J;
-  bool surface = false;
-  int c = 0;
-  if (loc < npair) {
+  {
     // rows I = 0..B-1 of the triangle J = I..B-1 start at I B - I (I - 1) / 2
+    const int64_t loc = item - S.ie[b];
     const double bb = 2.0 * (double)B + 1.0;
     int64_t r = (int64_t)((bb - sqrt(bb * bb - 8.0 * (double)loc)) * 0.5);
     r = r < 0 ? 0 : (r > B - 1 ? B - 1 : r);
@@ -1161,12 +1232,6 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
     while (r + 1 < B && (r + 1) * B - (r + 1) * r / 2 <= loc) ++r;
     I = (int)r;
     J = (int)(I + (loc - (r * B - r * (r - 1) / 2)));
-  } else {
-    surface = true;
-    const int64_t t = loc - npair;
-    I = (int)(t / sch);
-    c = (int)(t % sch);
-    J = 0;
   }
   I = __builtin_amdgcn_readfirstlane(I);
   J = __builtin_amdgcn_readfirstlane(J);
@@ -1192,33 +1257,7 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
 #pragma unroll
   for (int k = 0; k < R; ++k) acc[k] = 0.0;
   int slot;
-  if (surface) {
-    const int per = (P + sch - 1) / sch;
-    const int s0 = c * per, s1 = s0 + per < P ? s0 + per : P;
-    const int pl = plan_of ? plan_of[b] : 0;
-    const float4 *nd = nodes + (size_t)pl * P;
-    const float2 *qb = qd + (size_t)b * P;
-    for (int sb = s0; sb < s1; sb += TILE) {
-      const int se = sb + TILE < s1 ? sb + TILE : s1;
-      float sum[R];
-#pragma unroll
-      for (int k = 0; k < R; ++k) sum[k] = 0.0f;
-      for (int m = sb; m < se; ++m) {
-        const float4 yv = nd[m];
-        const float2 wv = qb[m];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          const float dx = tx[k] - yv.x, dy = ty[k] - yv.y, dz = tz[k] - yv.z;
-          const float ri = rinv(dx * dx + dy * dy + dz * dz);
-          const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
-          sum[k] = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum[k]);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < R; ++k) acc[k] += (double)sum[k];
-    }
-    slot = (int)B + c;
-  } else {
+  {
     const int j0 = J * TB, j1 = j0 + TB < n ? j0 + TB : n;
     if (I == J) {
       // diagonal block: one-directional, the ion's own image excluded (it is the analytic term)
@@ -1488,10 +1527,10 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       const float *wk = (const float *)(ws + L.wk);
       const double *rk = (const double *)(ws + L.rk);
       if (L.sym_tb == 256)
-        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
+        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
                                             eval_part);
       else
-        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
+        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
                                             eval_part);
       done = true;
     }
@@ -1566,11 +1605,11 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
       const int64_t sch = cdiv(P, (2 * tb) / 3);     // surface chunks of about 2/3 of a block's cost
       const int64_t parts = total_n * (bmax + sch);  // >= sum_b n_b (B_b + sch)
       const int64_t sb = total_n / tb + nsys;        // >= sum_b B_b
-      const int64_t waves = sb * (bmax + 1) / 2 + sb * sch;
+      const int64_t waves = sb * (bmax + 1) / 2 + sb * sch * SYM_SH;
       if (parts * (int64_t)sizeof(double) > SYM_MAX_BYTES || (mode == 1 && waves < 4 * (int64_t)g->ncu)) continue;
       L.sym_tb = (int)tb;
       L.sch = (int)sch;
-      L.items_e = waves + 1;  // >= sum_b B_b (B_b + 1) / 2 + B_b sch
+      L.items_e = waves + 1;  // >= sum_b B_b (B_b + 1) / 2 + B_b sch SYM_SH
       L.parts_e = parts;
       break;
     }
@@ -1587,7 +1626,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
     o = align256(o + bytes);
     return at;
   };
-  L.sched = take(sizeof(int64_t) * (6 * (size_t)(nsys + 1) + 8));
+  L.sched = take(sizeof(int64_t) * (7 * (size_t)(nsys + 1) + 8));
   L.item_sys_c = take(sizeof(int) * (size_t)L.items_c);
   L.item_sys_e = take(sizeof(int) * (size_t)L.items_e);
   L.fin_sys = take(sizeof(int) * (size_t)L.fin);
