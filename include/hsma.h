@@ -248,6 +248,16 @@ hsma_status hsma_group_set_symmetric(hsma_group_t group, int mode);
  * surface chunk) at least cover every SIMD of the device. */
 int hsma_group_eval_kernel(hsma_group_t group, int nsys, int64_t total_n, int64_t max_n);
 
+/* Order of the symmetric kernel's work items (one wave each: a block pair of one system, or
+ * half of one ion block against one chunk of surface nodes).  mode 1: each system's surface
+ * items right after its own block pairs, so its ion blocks are read again while still in L2;
+ * 2: every system's block pairs first, then every surface item, so that the shorter surface
+ * items fill the end of the launch; 0 (default): 2 when the launch's block pairs number at
+ * most four waves per resident-wave slot of the device (compute units x resident waves of the
+ * kernel), else 1.  Every item computes the same sums in either order: results are
+ * bit-identical.  Errors: HSMA_EINVAL. */
+hsma_status hsma_group_set_sym_order(hsma_group_t group, int mode);
+
 /* Fit apply (Algorithm 1, steps 3-4: alpha' = Y^+ u, beta' = Y^+ v, then the surface
  * strengths Q', D' through the fixed operator of eq. "GreenSecond") in the FP32 pair modes.
  * mode 0 (default): FP32 GEMVs below 8 systems per call, FP32 MFMA GEMMs from 8 systems;

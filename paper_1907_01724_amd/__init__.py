@@ -110,6 +110,7 @@ def load_library(path: str | None = None):
     L.hsma_group_eval_kernel.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
     L.hsma_group_eval_kernel.restype = C.c_int
     L.hsma_group_set_fit.argtypes = [_VP, C.c_int]
+    L.hsma_group_set_sym_order.argtypes = [_VP, C.c_int]
     L.hsma_system_create_ex.argtypes = [_VP, C.c_int64] + [_VP] * 4 + [C.c_int, _VP, C.POINTER(_VP)]
     L.hsma_kirkwood_workspace_bytes.argtypes = [C.c_int, C.c_int64]
     L.hsma_kirkwood_workspace_bytes.restype = C.c_size_t
@@ -146,8 +147,8 @@ def load_library(path: str | None = None):
                  "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
-                 "hsma_group_set_fit", "hsma_field", "hsma_field_batched", "hsma_kirkwood", "hsma_system_create_ex",
-                 "hsma_system_create", "hsma_delta_energy",
+                 "hsma_group_set_fit", "hsma_group_set_sym_order", "hsma_field", "hsma_field_batched",
+                 "hsma_kirkwood", "hsma_system_create_ex", "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
                  "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
@@ -350,6 +351,11 @@ class Plan:
         blocks of 256 / 512."""
         _check(load_library().hsma_group_set_symmetric(self.group, int(mode)), "hsma_group_set_symmetric")
 
+    def set_sym_order(self, mode: int = 0):
+        """Item order of the symmetric kernel: 0 automatic, 1 each system's surface items after
+        its block pairs, 2 all block pairs first (bit-identical results)."""
+        _check(load_library().hsma_group_set_sym_order(self.group, int(mode)), "hsma_group_set_sym_order")
+
     def eval_kernel(self, N: int) -> int:
         return int(load_library().hsma_group_eval_kernel(self.group, 1, int(N), int(N)))
 
@@ -470,6 +476,11 @@ class Group:
         """Symmetric Kelvin kernel: 0 never, 1 for large launches (default), 2 / 3 always with ion
         blocks of 256 / 512."""
         _check(load_library().hsma_group_set_symmetric(self._h, int(mode)), "hsma_group_set_symmetric")
+
+    def set_sym_order(self, mode: int = 0):
+        """Item order of the symmetric kernel: 0 automatic, 1 each system's surface items after
+        its block pairs, 2 all block pairs first (bit-identical results)."""
+        _check(load_library().hsma_group_set_sym_order(self._h, int(mode)), "hsma_group_set_sym_order")
 
     def eval_kernel(self, nsys: int, total_n: int, max_n: int) -> int:
         """Ion-block size of the symmetric Kelvin kernel these sizes would use, or 0."""

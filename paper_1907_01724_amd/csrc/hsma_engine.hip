@@ -36,6 +36,8 @@ constexpr int TILE = 32;         // sources per FP32 partial sum before folding 
 constexpr int FINB = 256;        // ions per finish block
 constexpr int SCHED_T = 1024;    // threads of the schedule kernel
 constexpr int SYM_SH = 2;        // surface items per block and chunk (each takes 1/SYM_SH of the block's ions)
+constexpr int64_t SYM_TAIL_ROUNDS = 4;  // launches of at most this many rounds of resident waves
+                                        // of block pairs put the surface items last
 constexpr int64_t SYM_MAX_BYTES = (int64_t)16 << 30;  // partial-slot bound above which the symmetric
                                                        // Kelvin kernel is not used
 
@@ -92,8 +94,13 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 // Schedule.  sched (int64) holds, each with nsys + 1 entries:
 //   [0] ion offsets  [1] check-item prefix  [2] eval-item prefix  [3] finish-block prefix
 //   [4] check partial-slot prefix  [5] eval partial-slot prefix
-//   [6] surface-item prefix of the symmetric kernel (its items are every system's block pairs,
-//       counted by [2], followed by every system's surface items, counted here)
+//   [6] surface-item prefix of the symmetric kernel.  Its items come in one of two orders: in
+//       a launch of few block pairs (one round of the chip's resident waves or less), every
+//       system's block pairs, then every system's surface items, so that the shorter surface
+//       items fill the end of the launch; otherwise each system's block pairs and then its
+//       surface items, so that a system's targets are read while they are still in L2.
+//       Either way system b's pairs are items [2][b] .. [6][b] - 1 when interleaved, or start
+//       at [2][b] otherwise, and its surface items start at [6][b].
 // followed by 8 words: [0] check item counter, [1] eval item counter.
 // ---------------------------------------------------------------------------------
 struct Sched {
@@ -137,8 +144,8 @@ __device__ __forceinline__ void eval_counts(int64_t n, int P, int che, int sym_t
 
 __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *__restrict__ offsets,
                                                       const int32_t *__restrict__ plan_of, Bounds bd, int M, int P,
-                                                      int chc, int che, int sym_tb, int sch, int64_t grid_c,
-                                                      int64_t grid_e, int64_t *__restrict__ base,
+                                                      int chc, int che, int sym_tb, int sch, int64_t sym_tail,
+                                                      int64_t grid_c, int64_t grid_e, int64_t *__restrict__ base,
                                                       int *__restrict__ flag) {
   Sched S(base, nsys);
   __shared__ int64_t sc[6][SCHED_T];
@@ -183,7 +190,9 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
   }
   int64_t run[6];
   for (int k = 0; k < 6; ++k) run[k] = sc[k][t] - acc[k];  // exclusive start of this segment
-  run[5] += sc[1][nt - 1];  // surface items follow every system's evaluation items
+  // surface items last when the block pairs of the launch are few (sc[1] holds only pairs)
+  const bool surf_last = sc[1][nt - 1] <= sym_tail;
+  if (surf_last) run[5] += sc[1][nt - 1];
   for (int b = b0; b < b1 && !bad; ++b) {
     const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
     const int64_t n = hi - lo;
@@ -192,11 +201,11 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     eval_counts(n, P, che, sym_tb, sch, items_e, surf_e, parts_e);
     S.off[b] = lo;
     S.ic[b] = run[0];
-    S.ie[b] = run[1];
+    S.ie[b] = surf_last ? run[1] : run[1] + run[5];
     S.fb[b] = run[2];
     S.pc[b] = run[3];
     S.pe[b] = run[4];
-    S.is[b] = run[5];
+    S.is[b] = surf_last ? run[5] : S.ie[b] + items_e;
     run[0] += Gc * chunks_c;
     run[1] += items_e;
     run[2] += cdiv64(n, FINB);
@@ -207,7 +216,7 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
   if (t == nt - 1) {
     S.off[nsys] = offsets ? offsets[nsys] : n_single;
     S.ic[nsys] = sc[0][t];
-    S.ie[nsys] = sc[1][t];
+    S.ie[nsys] = surf_last ? sc[1][t] : sc[1][t] + sc[5][t];
     S.fb[nsys] = sc[2][t];
     S.pc[nsys] = sc[3][t];
     S.pe[nsys] = sc[4][t];
@@ -246,6 +255,7 @@ __device__ __forceinline__ void fill_maps(const Sched &S, int nsys, int *__restr
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < S.ic[nsys]; i += stride) sys_c[i] = system_of(S.ic, nsys, i);
   for (int64_t i = t0; i < S.ie[nsys]; i += stride) sys_e[i] = system_of(S.ie, nsys, i);
+  for (int64_t i = S.ie[nsys] + t0; i < S.is[nsys]; i += stride) sys_e[i] = system_of(S.is, nsys, i);
   for (int64_t i = t0; i < S.fb[nsys]; i += stride) sys_f[i] = system_of(S.fb, nsys, i);
 }
 
@@ -1142,7 +1152,7 @@ __device__ __forceinline__ float wave_total_lane63(float v) {
 
 template <int R>
 __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, const int64_t *__restrict__ base,
-                                                    const int32_t *__restrict__ plan_of,
+                                                    const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
                                                     const float4 *__restrict__ tgt, const float4 *__restrict__ img,
                                                     const float *__restrict__ wk, const double *__restrict__ rk,
                                                     const float4 *__restrict__ nodes,
@@ -1155,10 +1165,8 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
   if (!sched_ok(S)) return;
   const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);  // one item per wave
   if (item >= S.is[nsys]) return;
-  // every system's block pairs first, then every system's surface items: the shorter surface
-  // items fill the end of the launch
-  const bool surface = item >= S.ie[nsys];
-  const int b = __builtin_amdgcn_readfirstlane(surface ? system_of(S.is, nsys, item) : system_of(S.ie, nsys, item));
+  const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
+  const bool surface = item >= S.is[b];
   const int64_t lo = S.off[b];
   const int n = (int)(S.off[b + 1] - lo);
   const int64_t B = cdiv64(n, TB);
@@ -1468,8 +1476,14 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   bd.parts_c = L.parts_c;
   bd.parts_e = L.parts_e;
   bd.nplans = grp->nplans;
-  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, Pe, L.chc, L.che, L.sym_tb, L.sch, grid_c, grid_e,
-                                    base, grp->flag);
+  // symmetric kernel: surface items last when the block pairs fill at most SYM_TAIL_ROUNDS
+  // rounds of the device's resident waves
+  const int64_t sym_tail = grp->tune.sym_order == 1 ? -1
+                           : grp->tune.sym_order == 2
+                               ? INT64_MAX
+                               : SYM_TAIL_ROUNDS * g->ncu * WAVES * grp->tune.occ_sym[L.sym_tb == 512];
+  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, Pe, L.chc, L.che, L.sym_tb, L.sch, sym_tail, grid_c,
+                                    grid_e, base, grp->flag);
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f, plans, plan_of, x, y, z, q, img, tgt,
                                              srcw, self,
@@ -1527,11 +1541,11 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       const float *wk = (const float *)(ws + L.wk);
       const double *rk = (const double *)(ws + L.rk);
       if (L.sym_tb == 256)
-        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
-                                            eval_part);
+        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk,
+                                            grp->nodes32, qd, eval_part);
       else
-        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, plan_of, tgt, img, wk, rk, grp->nodes32, qd,
-                                            eval_part);
+        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk,
+                                            grp->nodes32, qd, eval_part);
       done = true;
     }
   }
@@ -1696,6 +1710,16 @@ hsma_status occupancy_of(int *oc, int *oe) {
   return HSMA_OK;
 }
 
+hsma_status sym_occupancy(int *o256, int *o512) {
+  int a = 0, b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_kelvin_sym<4>, TPB, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_kelvin_sym<8>, TPB, 0) != hipSuccess)
+    return HSMA_EDEVICE;
+  *o256 = a > 0 ? a : 1;
+  *o512 = b > 0 ? b : 1;
+  return HSMA_OK;
+}
+
 hsma_status pair_occupancy(int pair_prec, int *occ_check, int *occ_eval) {
   switch (pair_prec) {
     case HSMA_PAIR_FP32:
@@ -1830,6 +1854,12 @@ extern "C" int hsma_group_eval_kernel(hsma_group_t grp, int nsys, int64_t total_
 extern "C" hsma_status hsma_group_set_symmetric(hsma_group_t grp, int on) {
   if (!grp || on < 0 || on > 3) return HSMA_EINVAL;
   grp->tune.symmetric = on;
+  return HSMA_OK;
+}
+
+extern "C" hsma_status hsma_group_set_sym_order(hsma_group_t grp, int mode) {
+  if (!grp || mode < 0 || mode > 2) return HSMA_EINVAL;
+  grp->tune.sym_order = mode;
   return HSMA_OK;
 }
 

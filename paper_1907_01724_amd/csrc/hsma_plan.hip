@@ -733,7 +733,9 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
   grp->tune.target_items = 16384;
   grp->tune.symmetric = 1;
   grp->tune.fit = 0;
-  if (pair_occupancy(prec, &grp->tune.occ_check, &grp->tune.occ_eval) != HSMA_OK) {
+  grp->tune.sym_order = 0;
+  if (pair_occupancy(prec, &grp->tune.occ_check, &grp->tune.occ_eval) != HSMA_OK ||
+      sym_occupancy(&grp->tune.occ_sym[0], &grp->tune.occ_sym[1]) != HSMA_OK) {
     delete grp;
     return HSMA_EDEVICE;
   }

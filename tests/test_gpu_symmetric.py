@@ -118,3 +118,40 @@ def test_uneven_batch(dev, block):
         ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
         assert _rel(out[block][0][lo:hi], ref) <= 1e-6, (b, _rel(out[block][0][lo:hi], ref))
         assert _rel(out[block][0][lo:hi], out[0][0][lo:hi]) <= 1e-6
+
+
+@pytest.mark.parametrize("block", [256, 512])
+def test_item_orders_are_bit_identical(dev, block):
+    """The two item orders of the symmetric kernel (each system's surface items after its own
+    block pairs, or all block pairs first) compute the same sums into the same slots, so the
+    potentials and energies agree bit for bit; the batch has empty, single-block and ragged
+    systems so that the two item -> system maps differ everywhere."""
+    sizes = [1300, 0, 1, 700, 513, 0, 2049, 64]
+    systems = [W.small_uniform(N=n, a=25.0, seed=W.SEED_BASE + 325 + k) if n > 0 else None
+               for k, n in enumerate(sizes)]
+    plan = hs.Plan(25.0, 1.0, 78.5, 0.3, 1024, 1536, pair_prec="fp32c")
+    group = hs.Group([plan])
+    group.set_symmetric({256: 2, 512: 3}[block])
+    parts = [s for s in systems if s is not None]
+    cat = [np.concatenate([getattr(s, k) for s in parts]) for k in "xyzq"]
+    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
+    off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    off = torch.tensor(off_h, dtype=torch.int64, device=dev)
+    total, max_n = int(off_h[-1]), int(max(sizes))
+    assert group.eval_kernel(len(sizes), total, max_n) == block
+    out = {}
+    for order in (1, 2, 0):
+        group.set_sym_order(order)
+        phi = torch.empty(total, dtype=torch.float64, device=dev)
+        E = group.energy(off, xb, yb, zb, qb, total_n=total, max_n=max_n, phi=phi)
+        assert group.stream_check() == 0
+        out[order] = (phi.cpu().numpy(), E.cpu().numpy())
+    assert np.array_equal(out[1][0], out[2][0]) and np.array_equal(out[1][1], out[2][1])
+    assert np.array_equal(out[0][0], out[2][0])  # a launch this small takes order 2
+    prm = _params(plan)
+    for b, s in enumerate(systems):
+        if s is not None:
+            ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
+            assert _rel(out[1][0][off_h[b]:off_h[b + 1]], ref) <= 1e-6
+    with pytest.raises(RuntimeError):
+        group.set_sym_order(3)
