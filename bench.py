@@ -13,7 +13,8 @@ Pairs per system and step = N*M (check) + N*(N-1) (Kelvin images, own image
 analytic) + N*P (surface nodes).  value = pairs / time, in GPairs/s.
 
 Prints one JSON line.  Accuracy against the FP64 CPU oracle is measured outside the
-timed region; the oracle is also timed on the host cores (cpu_baseline).
+timed regions, by the cpu_baseline leg at the end, which also times the oracle on the host
+cores; the other legs hand it their GPU results as plain arrays.
 """
 from __future__ import annotations
 
@@ -54,6 +55,18 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+class OracleChecks:
+    """Accuracy checks of the legs' GPU results.  A leg hands over plain data (plan parameters,
+    inputs, its GPU outputs) and a function that receives the errors; the cpu_baseline leg, the
+    only code in this file that runs the oracle, computes the references and calls it."""
+
+    def __init__(self):
+        self.jobs = []
+
+    def add(self, kind: str, report, **data):
+        self.jobs.append((kind, data, report))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,9 +75,9 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood",
-                    help="extra workloads after the headline one: batched, serving, sweep, field, kirkwood (comma "
-                         "list, or none)")
+    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood,accuracy",
+                    help="extra workloads after the headline one: batched, serving, sweep, field, kirkwood, "
+                         "accuracy (comma list, or none)")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--serving-slots", default="1,2",
                     help="request server: concurrent single-ion-move batches and full energies")
@@ -213,58 +226,45 @@ def main() -> int:
         }
         out["stage_ms_per_step"] = {k: v[0] / args.steps for k, v in stages.items()}
 
-    if not args.no_oracle:
-        import oracle
-        worst_phi, worst_e = 0.0, 0.0
-        phis = [phi[b * N:(b + 1) * N] for b in range(nsys)]
-        Es = [E[b:b + 1] for b in range(nsys)]
+    checks = None if args.no_oracle else OracleChecks()
+    if checks is not None:
+        phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
 
-        def oracle_params(p):
-            i = p.info
-            return oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
-                                 M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"])
+        def report_headline(r):
+            out["rel_err_phi_l2_max"] = max(r["rel_phi"])
+            out["rel_err_energy_max"] = max(r["rel_e"])
+            out["cpu_baseline"] = {
+                "value": pairs_sys * r["calls"] / r["seconds"] / 1e9,
+                "unit": "GPairs/s",
+                "cores": r["cores"],
+                "kind": "oracle",
+                "sample": f"{r['calls']} oracle evaluations (cycling over the four parameter sets) of the full "
+                          f"N={N} configuration: FP64 direct check sums, Householder least squares, Kelvin and "
+                          f"surface sums",
+                "seconds": r["seconds"],
+            }
+            log(f"bench: oracle: phi rel L2 {out['rel_err_phi_l2_max']:.2e}, energy {out['rel_err_energy_max']:.2e}; "
+                f"cpu_baseline {out['cpu_baseline']['value']:.2f} GPairs/s on {r['cores']} threads")
 
-        cpu_s, cpu_calls = 0.0, 0
-        for p, ph, e, s in zip(plans, phis, Es, systems):
-            t2 = time.perf_counter()
-            ref = oracle.hsma_eval(oracle_params(p), s.x, s.y, s.z, s.q)
-            cpu_s += time.perf_counter() - t2
-            cpu_calls += 1
-            got = ph.cpu().numpy()
-            worst_phi = max(worst_phi, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
-            e_ref = oracle.energy(s.q, ref)
-            worst_e = max(worst_e, abs(float(e.cpu().numpy()[0]) - e_ref) / abs(e_ref))
-        # CPU baseline: keep evaluating the same configurations with the oracle until about
-        # ten seconds of host time have been spent.
-        while cpu_s < 10.0:
-            p, s = plans[cpu_calls % nsys], systems[cpu_calls % nsys]
-            t2 = time.perf_counter()
-            oracle.hsma_eval(oracle_params(p), s.x, s.y, s.z, s.q)
-            cpu_s += time.perf_counter() - t2
-            cpu_calls += 1
-        out["cpu_baseline"] = {
-            "value": pairs_sys * cpu_calls / cpu_s / 1e9,
-            "unit": "GPairs/s",
-            "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{cpu_calls} oracle evaluations (cycling over the four parameter sets) of the full "
-                      f"N={N} configuration: FP64 direct check sums, Householder least squares, Kelvin and "
-                      f"surface sums",
-            "seconds": cpu_s,
-        }
-        out["rel_err_phi_l2_max"] = worst_phi
-        out["rel_err_energy_max"] = worst_e
+        checks.add("baseline", report_headline, infos=[p.info for p in plans],
+                   systems=[(s.x, s.y, s.z, s.q) for s in systems],
+                   phis=[phi_h[b * N:(b + 1) * N] for b in range(nsys)], Es=[float(e) for e in E_h],
+                   min_seconds=10.0)
     legs = [l for l in args.legs.split(",") if l and l != "none"]
     if "batched" in legs:
-        out["batched"] = leg_batched(args)
+        out["batched"] = leg_batched(args, checks)
     if "serving" in legs:
         out["serving"] = leg_serving(args)
     if "sweep" in legs:
-        out["precision_sweep"] = leg_sweep(args)
+        out["precision_sweep"] = leg_sweep(args, checks)
     if "field" in legs:
-        out["field"] = leg_field(args)
+        out["field"] = leg_field(args, checks)
     if "kirkwood" in legs:
-        out["kirkwood"] = leg_kirkwood(args)
+        out["kirkwood"] = leg_kirkwood(args, checks)
+    if "accuracy" in legs:
+        out["accuracy"] = leg_accuracy(args, checks)
+    if checks is not None:
+        leg_cpu_baseline(checks)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -292,11 +292,11 @@ def _eval_roofline(pairs_kelvin, pairs_surface, avg_s, sym=0):
             "frac": t_min / avg_s, "avg_launch_ms": avg_s * 1e3, "symmetric_block": sym}
 
 
-def leg_field(args) -> dict:
+def leg_field(args, checks) -> dict:
     """Potential, field and energy at the ions of the headline workload (N = 20000, a = 30,
     30% in the shell, P = 1600, M = 2400, the four parameter sets in one batched call):
-    time per call, the field kernel against its ALU roofline, and the relative L2 error of
-    every ion's potential and field per system against the oracle's."""
+    time per call and the field kernel against its ALU roofline; every ion's potential and field
+    per system go to the oracle checks (relative L2 errors)."""
     import numpy as np
     import torch
 
@@ -349,33 +349,29 @@ def leg_field(args) -> dict:
                         "frac": t_min / ev, "avg_launch_ms": ev * 1e3,
                         "peak_model": "%d / %d non-transcendental VALU instructions per Kelvin / surface pair" % (
                             SLOTS_FIELD_KELVIN, SLOTS_FIELD_SURFACE)}}
-    if not args.no_oracle:
-        import oracle
+    if checks is not None:
         phi_h, f_h = phi.cpu().numpy(), f.cpu().numpy()
-        wp, wf = 0.0, 0.0
-        for b, (p, s) in enumerate(zip(plans, systems)):
-            i = p.info
-            prm = oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
-                                M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"])
-            rp, rf = oracle.hsma_field(prm, s.x, s.y, s.z, s.q)
-            gp, gf = phi_h[b * N:(b + 1) * N], f_h[b * N:(b + 1) * N]
-            wp = max(wp, float(np.linalg.norm(gp - rp) / np.linalg.norm(rp)))
-            wf = max(wf, float(np.linalg.norm(gf - rf) / np.linalg.norm(rf)))
-        res["rel_err_phi_l2_max"] = wp
-        res["rel_err_field_l2_max"] = wf
+
+        def report(r):
+            res["rel_err_phi_l2_max"] = max(r["rel_phi"])
+            res["rel_err_field_l2_max"] = max(r["rel_field"])
+            log(f"bench[field]: oracle: phi rel L2 {res['rel_err_phi_l2_max']:.2e}, "
+                f"field rel L2 {res['rel_err_field_l2_max']:.2e}")
+
+        checks.add("field", report, infos=[p.info for p in plans], systems=[(s.x, s.y, s.z, s.q) for s in systems],
+                   phis=[phi_h[b * N:(b + 1) * N] for b in range(nsys)],
+                   fields=[f_h[b * N:(b + 1) * N] for b in range(nsys)])
     for p in plans:
         p.close()
-    log(f"bench[field]: {ms:.3f} ms/call, eval {ev * 1e3:.3f} ms ({res['roofline']['frac']:.2f} of its ALU peak)" +
-        (f", errors phi {res['rel_err_phi_l2_max']:.2e} field {res['rel_err_field_l2_max']:.2e}"
-         if "rel_err_field_l2_max" in res else ""))
+    log(f"bench[field]: {ms:.3f} ms/call, eval {ev * 1e3:.3f} ms ({res['roofline']['frac']:.2f} of its ALU peak)")
     return res
 
 
-def leg_kirkwood(args) -> dict:
+def leg_kirkwood(args, checks) -> dict:
     """The paper's comparison (Sec. 4.1) on the GPU: the C1 system (N = 200 uniform in a = 10,
     eps1 = 1, eps2 = 80, kappa = 0.1) by HSMA (FP64 pairs; P = 400, p = 10 and P = 1600, p = 20)
-    and by the Kirkwood series truncated at order 40, each against the converged series
-    (the oracle's O2, not timed); then the time of the order-40 series on the N = 20000 shell
+    and by the Kirkwood series truncated at order 40, each handed to the oracle checks against
+    the converged series (the oracle's O2, not timed); then the time of the order-40 series on the N = 20000 shell
     system of the headline workload (first parameter set) beside HSMA's."""
     import numpy as np
     import torch
@@ -400,15 +396,17 @@ def leg_kirkwood(args) -> dict:
             out["kirkwood_order40"] = plan.kirkwood(*t, order=40).cpu().numpy()
             assert plan.stream_check() == 0
         plan.close()
-    if not args.no_oracle:
-        import oracle
-        truth = oracle.kirkwood_eval(ph.a, ph.eps1, ph.eps2, ph.kappa, s.x, s.y, s.z, s.q)
-        res["rel_err_l2_vs_converged_series"] = {k: float(np.linalg.norm(v - truth) / np.linalg.norm(truth))
-                                                 for k, v in out.items()}
+    if checks is not None:
         r = np.sqrt(s.x ** 2 + s.y ** 2 + s.z ** 2)
-        inner = r < 0.9 * ph.a
-        res["rel_err_l2_inner_ions_r_below_0.9a"] = {
-            k: float(np.linalg.norm(v[inner] - truth[inner]) / np.linalg.norm(truth[inner])) for k, v in out.items()}
+
+        def report(errs):
+            res["rel_err_l2_vs_converged_series"] = errs["all"]
+            res["rel_err_l2_inner_ions_r_below_0.9a"] = errs["inner"]
+            log("bench[kirkwood]: rel L2 vs the converged series, all ions / r < 0.9a: " +
+                ", ".join(f"{k} {errs['all'][k]:.2e} / {errs['inner'][k]:.2e}" for k in errs["all"]))
+
+        checks.add("series", report, physics=(ph.a, ph.eps1, ph.eps2, ph.kappa), system=(s.x, s.y, s.z, s.q),
+                   outputs=out, inner=r < 0.9 * ph.a)
     wl2 = W.workload_c2()
     s2 = wl2.systems[0]
     p2 = hs.Plan(s2.phys.a, s2.phys.eps1, s2.phys.eps2, s2.phys.kappa, wl2.disc.P, wl2.disc.M)
@@ -427,12 +425,11 @@ def leg_kirkwood(args) -> dict:
     assert p2.stream_check() == 0
     p2.close()
     res["ms_per_call_n20000"] = times
-    log("bench[kirkwood]: " + (", ".join(f"{k} err {v:.2e}" for k, v in res.get("rel_err_l2_vs_converged_series", {}).items()))
-        + "; N=20000: " + ", ".join(f"{k} {v:.2f} ms" for k, v in times.items()))
+    log("bench[kirkwood]: N=20000: " + ", ".join(f"{k} {v:.2f} ms" for k, v in times.items()))
     return res
 
 
-def leg_batched(args) -> dict:
+def leg_batched(args, checks) -> dict:
     """4096 configurations (a = 25, eps1 = 1, eps2 = 78.5, kappa = 0.3, P = 1024, M = 1536),
     N log-uniform in [100, 20000]: one batched call (shared plan, fit as MFMA GEMMs) per step,
     against the plain per-system path on the same systems."""
@@ -501,26 +498,13 @@ def leg_batched(args) -> dict:
         "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()},
         "roofline": _eval_roofline(pk, ps, st["eval"][0] / steps * 1e-3, group.eval_kernel(nsys, total, max_n)),
     }
-    if not args.no_oracle:
-        import oracle
-        rng = np.random.default_rng(0)
-        pick = rng.choice(np.nonzero(sizes <= 3000)[0], 6, replace=False)
-        phi_h = phi.cpu().numpy()
-        E_h = E.cpu().numpy()
-        prm = oracle.Params(a=info["a"], eps1=info["eps1"], eps2=info["eps2"], kappa=info["kappa"], p=info["p"],
-                            P=info["P"], M=info["M"], tau=info["tau"], rc_over_a=info["rc"] / info["a"], F1=info["F1"])
-        wphi, we = 0.0, 0.0
-        refs = {}
-        for b in pick:
-            s = wl.systems[b]
-            ref = refs[b] = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
-            got = phi_h[off_h[b]:off_h[b + 1]]
-            wphi = max(wphi, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
-            e_ref = oracle.energy(s.q, ref)
-            we = max(we, abs(E_h[b] - e_ref) / abs(e_ref))
-        res["rel_err_phi_l2_max_sampled"] = wphi
-        res["rel_err_energy_max_sampled"] = we
-        res["sampled_systems"] = [int(b) for b in pick]
+    # sampled systems for the oracle checks: the default route's potentials and energies here,
+    # each fit route's potentials below
+    rng = np.random.default_rng(0)
+    pick = rng.choice(np.nonzero(sizes <= 3000)[0], 6, replace=False)
+    phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
+    sampled = {"default": [phi_h[off_h[b]:off_h[b + 1]] for b in pick]}
+    res["sampled_systems"] = [int(b) for b in pick]
     # The fit apply by each route on the same call: stage time, rate against the MFMA peak of its
     # type (the split-BF16 routes count their term products), and the sampled errors.
     K, P, M = info["K"], info["P"], info["M"]
@@ -541,27 +525,37 @@ def leg_batched(args) -> dict:
         if peak is not None:
             tf = fit_flop * mult / (fit_ms * 1e-3) / 1e12
             r.update({"tflops": tf, "peak_tflops": peak, "frac": tf / peak})
-        if not args.no_oracle:
-            phi_h = phi.cpu().numpy()
-            r["rel_err_phi_l2_max_sampled"] = max(
-                float(np.linalg.norm(phi_h[off_h[b]:off_h[b + 1]] - refs[b]) / np.linalg.norm(refs[b])) for b in pick)
+        phi_h = phi.cpu().numpy()
+        sampled[name] = [phi_h[off_h[b]:off_h[b + 1]] for b in pick]
         routes[name] = r
-        log(f"bench[batched]: fit {name}: {fit_ms:.3f} ms" +
-            (f", max sampled rel L2 {r['rel_err_phi_l2_max_sampled']:.2e}" if "rel_err_phi_l2_max_sampled" in r else ""))
+        log(f"bench[batched]: fit {name}: {fit_ms:.3f} ms")
     group.set_fit(0)
     res["fit_routes"] = {"flop_per_call": fit_flop, **routes}
+    if checks is not None:
+        def report(r):
+            res["rel_err_phi_l2_max_sampled"] = max(r["rel_phi"]["default"])
+            res["rel_err_energy_max_sampled"] = max(r["rel_e"])
+            for name in routes:
+                routes[name]["rel_err_phi_l2_max_sampled"] = max(r["rel_phi"][name])
+            log("bench[batched]: oracle on the sampled systems: max rel L2 " +
+                ", ".join(f"{k} {max(v):.2e}" for k, v in r["rel_phi"].items()) +
+                f"; energy {res['rel_err_energy_max_sampled']:.2e}")
+
+        checks.add("potentials", report, info=info,
+                   systems=[(wl.systems[b].x, wl.systems[b].y, wl.systems[b].z, wl.systems[b].q) for b in pick],
+                   phis=sampled, Es=[float(E_h[b]) for b in pick])
     log(f"bench[batched]: {ms:.2f} ms/call, {res['systems_per_s']:.0f} systems/s "
         f"(per-system path {res['per_system_path_systems_per_s']:.0f})")
     return res
 
 
-def leg_sweep(args) -> dict:
+def leg_sweep(args, checks) -> dict:
     """Precision sweep on N = 1e6 ions uniform in a = 200 (charges +-1 and +-2, 2:1), eps1 = 1,
     eps2 = 80, kappa = 0.1, P = 6400, M = 9600 (p = 40): the whole path with FP32, compensated
     FP32 and FP64 pair sums (fit applied with FP32 GEMVs for the FP32 modes, FP64 GEMVs for FP64
     pairs), and the compensated FP32 path again with the fit applied as FP32 MFMA GEMMs and as
-    split-BF16x3 and split-BF16x6 MFMA GEMMs.  The potentials of 256 sampled ions are compared with the oracle's,
-    the energies with the FP64 run's; each run also reports its fit-stage time."""
+    split-BF16x3 and split-BF16x6 MFMA GEMMs.  The potentials of 256 sampled ions go to the oracle
+    checks, the energies are compared with the FP64 run's; each run also reports its fit-stage time."""
     import numpy as np
     import torch
 
@@ -617,24 +611,174 @@ def leg_sweep(args) -> dict:
         del ws, phi
     for label, _, _ in runs[:-1]:
         res[label]["rel_err_energy_vs_fp64"] = abs(Es[label] - Es["fp64"]) / abs(Es["fp64"])
-    if not args.no_oracle:
-        import oracle
-        i = plans["fp64"].info
-        prm = oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
-                            M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"])
-        t0 = time.perf_counter()
-        ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q,
-                               targets=np.stack([s.x[idx], s.y[idx], s.z[idx]], axis=1))
-        res["oracle_s"] = time.perf_counter() - t0
-        for label, _, _ in runs:
-            err = phis[label] - ref
-            res[label]["rel_err_phi_l2_sampled"] = float(np.linalg.norm(err) / np.linalg.norm(ref))
-            res[label]["max_err_over_max_phi_sampled"] = float(np.max(np.abs(err)) / np.max(np.abs(ref)))
-        log(f"bench[sweep]: oracle on 256 sampled ions in {res['oracle_s']:.1f} s; rel L2 " +
-            ", ".join(f"{lb} {res[lb]['rel_err_phi_l2_sampled']:.2e}" for lb, _, _ in runs))
+    if checks is not None:
+        def report(r):
+            res["oracle_s"] = r["seconds"]
+            for label, _, _ in runs:
+                res[label]["rel_err_phi_l2_sampled"] = r["rel_phi"][label]
+                res[label]["max_err_over_max_phi_sampled"] = r["max_over_max"][label]
+            log(f"bench[sweep]: oracle on 256 sampled ions in {r['seconds']:.1f} s; rel L2 " +
+                ", ".join(f"{lb} {res[lb]['rel_err_phi_l2_sampled']:.2e}" for lb, _, _ in runs))
+
+        checks.add("sampled", report, info=plans["fp64"].info, system=(s.x, s.y, s.z, s.q), idx=idx, phis=phis)
     for plan in plans.values():
         plan.close()
     return res
+
+
+def leg_accuracy(args, checks) -> dict:
+    """The accuracy study of Sec. 4.1 (one unit charge, a = 1, eps1 = 2, eps2 = 80, kappa = 5) run
+    by the library in FP64 pairs with the paper's own discretisation: the Gauss-Legendre check grid
+    of 2p x (2p + 1) points on the interface and +-dy/2 point dipoles (dy = 1e-5 R_tau), up to
+    p = 60 and F2 = 6765.  The GPU self energies go to the oracle checks against the converged
+    Kirkwood series:
+      fig2a: p = 30, F2 = 1597, tau in {0.05, 0.1, 0.15}, r_s from 0.1 to 0.98;
+      fig2b: r_s = 0.9, tau = 0.1, F2 = 6765, p from 10 to 60;
+      fig3:  r_s = 0.95, tau = 0.1, p in {15, 35, 55}, F2 in {610, 1597, 6765};
+      fig4:  p = 20, F2 = 1597, r_s from 0.9 to 0.98, beside the Kirkwood series (on the GPU) at
+             orders 20, 40 and 60.
+    Plan set-up times (geometry build on the GPU) are reported too."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    a, eps1, eps2, kappa = 1.0, 2.0, 80.0, 5.0
+    fib = {610: 377, 1597: 987, 6765: 4181}
+
+    def plan(p, tau, F2):
+        return hs.Plan(a, eps1, eps2, kappa, 2 * (F2 + 1), 2 * p * (2 * p + 1), p=p, tau=tau, rc_over_a=1.0,
+                       F1=fib[F2], pair_prec="fp64", check_set=1, dipole=1, dy_over_Rtau=1e-5)
+
+    def self_energy(pl, r_s, order=None):
+        t = [torch.tensor(v, dtype=torch.float64, device=dev) for v in W.single_charge(r_s, a)]
+        if order is None:
+            e = float(pl.energy(*t).cpu().numpy()[0])
+        else:
+            e = 0.5 * float(pl.kirkwood(*t, order=order).cpu().numpy()[0])
+        assert pl.stream_check() == 0
+        return e
+
+    rows = []  # (figure, label, r_s, E_self by the GPU)
+    build_s = {}
+    t_all = time.perf_counter()
+    cases = [("fig2a", 30, tau, 1597, [0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 0.92, 0.94, 0.95, 0.96, 0.97, 0.98])
+             for tau in (0.05, 0.1, 0.15)]
+    cases += [("fig2b", p, 0.1, 6765, [0.9]) for p in (10, 20, 30, 40, 50, 60)]
+    cases += [("fig3", p, 0.1, F2, [0.95]) for p in (15, 35, 55) for F2 in (610, 1597, 6765)]
+    cases += [("fig4", 20, 0.1, 1597, [0.9, 0.92, 0.94, 0.96, 0.98])]
+    for fig, p, tau, F2, rs in cases:
+        t0 = time.perf_counter()
+        pl = plan(p, tau, F2)
+        build_s[f"p{p}_F2_{F2}_tau{tau}"] = time.perf_counter() - t0
+        label = f"hsma_p{p}_F2_{F2}_tau{tau}"
+        for r_s in rs:
+            rows.append((fig, label, r_s, self_energy(pl, r_s)))
+            if fig == "fig4":
+                for order in (20, 40, 60):
+                    rows.append((fig, f"kirkwood_order{order}", r_s, self_energy(pl, r_s, order)))
+        pl.close()
+    res = {"workload": "one unit charge, a=1, eps1=2, eps2=80, kappa=5; Gauss-Legendre check grid on the "
+                       "interface, point-pair dipoles dy=1e-5 R_tau, FP64 pairs",
+           "plan_build_s": build_s, "seconds": time.perf_counter() - t_all}
+    log(f"bench[accuracy]: {len(rows)} self energies from {len(cases)} plans in {res['seconds']:.1f} s "
+        f"(largest plan build {max(build_s.values()):.2f} s)")
+    if checks is not None:
+        def report(refs):
+            table = {}
+            for fig, label, r_s, e in rows:
+                table.setdefault(fig, {}).setdefault(label, {})[str(r_s)] = abs(e - refs[r_s])
+            res["abs_err_self_energy"] = table
+            res["ref_self_energy"] = {str(k): v for k, v in sorted(refs.items())}
+            f2b = table["fig2b"]
+            f3 = table["fig3"]
+            f4 = table["fig4"]
+            log("bench[accuracy]: fig2b r_s=0.9 error vs p: " +
+                ", ".join(f"p{k.split('_')[1][1:]} {v['0.9']:.1e}" for k, v in f2b.items()))
+            log("bench[accuracy]: fig3 r_s=0.95 relative error (p, F2): " +
+                ", ".join(f"({k.split('_')[1][1:]}, {k.split('_')[3]}) {v['0.95'] / abs(refs[0.95]):.1e}"
+                          for k, v in f3.items()))
+            log("bench[accuracy]: fig4 max error over r_s in [0.9, 0.98]: " +
+                ", ".join(f"{k} {max(v.values()):.1e}" for k, v in f4.items()))
+
+        checks.add("self_energy", report, physics=(a, eps1, eps2, kappa), r_s=sorted({r[2] for r in rows}))
+    return res
+
+
+def leg_cpu_baseline(checks: OracleChecks) -> None:
+    """The cpu_baseline leg: the only code in this file that runs the oracle.  It times the oracle
+    on the headline workload (the cpu_baseline object, about ten seconds of host time) and computes
+    the reference values of every accuracy check the other legs registered, handing each leg its
+    errors.  Nothing here is timed as GPU work."""
+    import numpy as np
+
+    import oracle
+
+    def params(i):
+        return oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
+                             M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"], dipole=i["dipole"],
+                             dy_over_Rtau=i["dy_over_Rtau"], check_set=i["check_set"])
+
+    def rel(x, ref):
+        return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+    for kind, d, report in checks.jobs:
+        if kind == "baseline":
+            rel_phi, rel_e, secs, calls = [], [], 0.0, 0
+            for i, (x, y, z, q), ph, e in zip(d["infos"], d["systems"], d["phis"], d["Es"]):
+                t0 = time.perf_counter()
+                ref = oracle.hsma_eval(params(i), x, y, z, q)
+                secs += time.perf_counter() - t0
+                calls += 1
+                rel_phi.append(rel(ph, ref))
+                e_ref = oracle.energy(q, ref)
+                rel_e.append(abs(e - e_ref) / abs(e_ref))
+            n = len(d["infos"])
+            while secs < d["min_seconds"]:
+                t0 = time.perf_counter()
+                oracle.hsma_eval(params(d["infos"][calls % n]), *d["systems"][calls % n])
+                secs += time.perf_counter() - t0
+                calls += 1
+            report({"rel_phi": rel_phi, "rel_e": rel_e, "calls": calls, "seconds": secs,
+                    "cores": oracle.num_threads()})
+        elif kind == "field":
+            rp, rf = [], []
+            for i, sysd, ph, f in zip(d["infos"], d["systems"], d["phis"], d["fields"]):
+                ref_phi, ref_f = oracle.hsma_field(params(i), *sysd)
+                rp.append(rel(ph, ref_phi))
+                rf.append(rel(f, ref_f))
+            report({"rel_phi": rp, "rel_field": rf})
+        elif kind == "series":
+            truth = oracle.kirkwood_eval(*d["physics"], *d["system"])
+            inner = d["inner"]
+            report({"all": {k: rel(v, truth) for k, v in d["outputs"].items()},
+                    "inner": {k: rel(v[inner], truth[inner]) for k, v in d["outputs"].items()}})
+        elif kind == "potentials":
+            refs = [oracle.hsma_eval(params(d["info"]), *sysd) for sysd in d["systems"]]
+            rel_phi = {k: [rel(g, r) for g, r in zip(v, refs)] for k, v in d["phis"].items()}
+            rel_e = []
+            for sysd, r, e in zip(d["systems"], refs, d["Es"]):
+                e_ref = oracle.energy(sysd[3], r)
+                rel_e.append(abs(e - e_ref) / abs(e_ref))
+            report({"rel_phi": rel_phi, "rel_e": rel_e})
+        elif kind == "sampled":
+            x, y, z, q = d["system"]
+            idx = d["idx"]
+            t0 = time.perf_counter()
+            ref = oracle.hsma_eval(params(d["info"]), x, y, z, q, targets=np.stack([x[idx], y[idx], z[idx]], axis=1))
+            secs = time.perf_counter() - t0
+            report({"seconds": secs, "rel_phi": {k: rel(v, ref) for k, v in d["phis"].items()},
+                    "max_over_max": {k: float(np.max(np.abs(v - ref)) / np.max(np.abs(ref)))
+                                     for k, v in d["phis"].items()}})
+        elif kind == "self_energy":
+            import workloads as W
+            a = d["physics"][0]
+            report({r_s: 0.5 * float(oracle.kirkwood_eval(*d["physics"], *W.single_charge(r_s, a))[0])
+                    for r_s in d["r_s"]})
+        else:
+            raise ValueError(kind)
 
 
 def leg_serving(args) -> dict:
