@@ -93,7 +93,11 @@ typedef struct {
   int dipole;       /* surface dipoles (eq. "GreenSecond"): 0 exact normal dipoles (default);
                        1 the paper's pair of point charges -+D/dy at R_tau -+ dy/2 along the
                        normal (eq. "approxG"); the pair cancels about log10(R_tau/dy) digits, so
-                       it is meant for FP64 pairs or a large dy */
+                       it is meant for FP64 pairs or a large dy; 2 no dipole layer: a single
+                       layer of monopoles alone (the first integral of eq. "threeintegrals"),
+                       with the density that has the same harmonic potential inside the
+                       sphere, Q'_s = w_s sum (2n+1)/R_tau (R_tau/a)^n Ahat_nm Y_nm(y_s), D' = 0.
+                       Plans of one group must share this choice. */
   double dy_over_Rtau; /* dy / R_tau for dipole = 1, in (0, 0.1); <= 0: 1e-5 */
 } hsma_plan_opts;
 

@@ -114,7 +114,7 @@ class Params:
     tau: float = 0.1
     rc_over_a: float = 1.1
     F1: int | None = None
-    dipole: int = 0
+    dipole: int = 0  # 0 exact normal dipoles, 1 the +-dy/2 point pairs, 2 a single layer (monopoles only)
     dy_over_Rtau: float = 1e-5
     check_set: int = 0  # 0 golden-angle lattice, 1 the Gauss-Legendre grid, 2p x (2p + 1) (M = 2p (2p + 1))
 

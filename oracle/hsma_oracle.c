@@ -25,6 +25,11 @@
  *   - the normal derivative of G in Green's second identity (eq. "GreenSecond") is
  *     used exactly (a surface dipole) by default; the paper's central difference
  *     with step dy (eq. "approxG") is selectable;
+ *   - a single-layer variant (dipole = 2) keeps only the monopole integral of
+ *     eq. "threeintegrals": the density on the auxiliary sphere whose single-layer
+ *     potential is the same interior harmonic, sigma_nm = (2n+1)/R_tau (R_tau/a)^n
+ *     Ahat_nm for Phi_corr = sum Ahat_nm (r/a)^n Y_nm (the classical single-layer
+ *     expansion of a harmonic function inside a sphere), and no dipoles;
  *   - the Fibonacci rule (Sec. 2.4) is used as printed, with F2 = P/2 - 1 and any
  *     F1 coprime to F2 when F2 is not a Fibonacci number.
  *
@@ -289,7 +294,8 @@ typedef struct {
   int P;                       /* surface nodes = 2 (F2 + 1) */
   int M;                       /* check points */
   int F1;                      /* Fibonacci F1 (F2 = P/2 - 1) */
-  int dipole;                  /* 0 exact normal dipole, 1 central-difference point pair */
+  int dipole;                  /* 0 exact normal dipole, 1 central-difference point pair,
+                                  2 no dipole layer (single layer of monopoles only) */
   double dy_over_Rtau;         /* central-difference step / R_tau (dipole = 1) */
   int check_set;               /* 0 golden-angle lattice of M points, 1 the Gauss-Legendre grid (M = 2p (2p+1)) */
 } orc_params;
@@ -310,6 +316,7 @@ static int orc_params_ok(const orc_params *pp) {
   if (!(pp->tau > 0.0 && pp->rc_over_a >= 1.0)) return 0;
   if (pp->p < 0 || pp->P < 4 || (pp->P & 1) || pp->M < (pp->p + 1) * (pp->p + 1)) return 0;
   if (pp->check_set != 0 && (pp->check_set != 1 || pp->M != 2 * pp->p * (2 * pp->p + 1))) return 0;
+  if (pp->dipole < 0 || pp->dipole > 2) return 0;
   return 1;
 }
 
@@ -400,7 +407,11 @@ void orc_correction_coeffs(const orc_params *pp, const double *alpha, const doub
 /* Surface strengths from Green's second identity (eq. "GreenSecond") discretised by
  * the Fibonacci rule: at node y_s with weight w_s,
  *   Q_s = w_s dPhi_corr/dr (y_s),  D_s = -w_s Phi_corr(y_s),
- * so that Phi_corr(x) ~ sum_s [Q_s / |x - y_s| + D_s (x - y_s).y^_s / |x - y_s|^3] / (4 pi). */
+ * so that Phi_corr(x) ~ sum_s [Q_s / |x - y_s| + D_s (x - y_s).y^_s / |x - y_s|^3] / (4 pi).
+ * Single layer (dipole = 2): 1/|x - y| = sum_n 4 pi r^n / ((2n+1) R^(n+1)) sum_m Y_nm(x^) Y_nm(y^)
+ * for r < R gives, for a density sigma = sum sigma_nm Y_nm on the sphere of radius R,
+ *   (1/4 pi) int sigma(y) / |x - y| dS = sum R / (2n+1) (r/R)^n sigma_nm Y_nm(x^),
+ * so Phi_corr is reproduced by sigma_nm = (2n+1)/R (R/a)^n Ahat_nm: Q_s = w_s sigma(y_s), D_s = 0. */
 void orc_surface_strengths(const orc_params *pp, const double *Ahat, const double *nodes, const double *w,
                            double *Q, double *D) {
   int p = pp->p, K = (p + 1) * (p + 1);
@@ -417,11 +428,11 @@ void orc_surface_strengths(const orc_params *pp, const double *Ahat, const doubl
         for (int m = -n; m <= n; m++) {
           double t = Ahat[n * n + n + m] * rn * Y[n * n + n + m];
           phi += t;
-          dphi += t * n / Rt;
+          dphi += t * (pp->dipole == 2 ? 2.0 * n + 1.0 : (double)n) / Rt;
         }
       }
       Q[s] = w[s] * dphi;
-      D[s] = -w[s] * phi;
+      D[s] = pp->dipole == 2 ? 0.0 : -w[s] * phi;
     }
     free(Y);
   }
@@ -444,7 +455,7 @@ void orc_surface_potential(const orc_params *pp, const double *nodes, const doub
       s += Q[k] / (4.0 * ORC_PI * r);
       if (pp->dipole == 0) {
         s += D[k] * (dx * ux + dyy * uy + dz * uz) / (4.0 * ORC_PI * r * r * r);
-      } else {
+      } else if (pp->dipole == 1) {
         double rm = Rt - 0.5 * dy, rp = Rt + 0.5 * dy;
         double mx = tx[t] - rm * ux, my = ty[t] - rm * uy, mz = tz[t] - rm * uz;
         double px = tx[t] - rp * ux, py = ty[t] - rp * uy, pz = tz[t] - rp * uz;
@@ -607,7 +618,7 @@ void orc_surface_field(const orc_params *pp, const double *nodes, const double *
         fx += cd * dx - cu * ux;
         fy += cd * dyy - cu * uy;
         fz += cd * dz - cu * uz;
-      } else {
+      } else if (pp->dipole == 1) {
         double rm = Rt - 0.5 * dy, rp = Rt + 0.5 * dy;
         double mx = tx[t] - rm * ux, my = ty[t] - rm * uy, mz = tz[t] - rm * uz;
         double px = tx[t] - rp * ux, py = ty[t] - rp * uy, pz = tz[t] - rp * uz;

@@ -212,7 +212,10 @@ def _ensure(cache: dict, key, nbytes: int, device) -> Workspace:
 
 
 class Plan:
-    """One cavity (a, eps1, eps2, kappa) discretised with P surface nodes and M check points."""
+    """One cavity (a, eps1, eps2, kappa) discretised with P surface nodes and M check points.
+
+    check_set: 0 golden-angle lattice, 1 the Gauss-Legendre grid (M = 2p (2p + 1));
+    dipole: 0 exact surface dipoles, 1 the +-dy/2 point pairs, 2 a single layer (monopoles only)."""
 
     def __init__(self, a: float, eps1: float, eps2: float, kappa: float, P: int, M: int, p: int | None = None,
                  tau: float = 0.1, rc_over_a: float | None = None, F1: int | None = None,

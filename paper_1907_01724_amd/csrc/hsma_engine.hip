@@ -596,7 +596,8 @@ __global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__
   const int b = blockIdx.y;
   const int lane = threadIdx.x & 63;
   if (s >= P) return;
-  const double *fg = plans[plan_of ? plan_of[b] : 0].fg;
+  const PlanDev &c = plans[plan_of ? plan_of[b] : 0];
+  const double *fg = c.fg;
   const TM *lr = lhat + (size_t)s * K;
   const double *al = ab + (size_t)(2 * b) * K;
   const double *be = al + K;
@@ -605,12 +606,12 @@ __global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__
   for (int k = lane; k < K; k += 64) {
     const double h = fg[k] * al[k] + fg[K + k] * be[k];
     const double l = (double)lr[k];
-    sq = fma(l * (double)nidx[k], h, sq);
+    sq = fma(l * (double)degree_weight(nidx[k], c.dipole), h, sq);
     sd = fma(l, h, sd);
   }
   sq = wave_sum(sq);
   sd = wave_sum(sd);
-  if (lane == 0) store_strengths(qd, b, s, P, Pe, sq, -sd, plans[plan_of ? plan_of[b] : 0].dyc);
+  if (lane == 0) store_strengths(qd, b, s, P, Pe, sq, c.dipole == 2 ? 0.0 : -sd, c.dyc);
 }
 
 // ---------------------------------------------------------------------------------
@@ -792,9 +793,10 @@ __global__ __launch_bounds__(256) void k_fit_h(int nsys, const int64_t *__restri
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)nsys * K) return;
   const int b = (int)(t / K), k = (int)(t % K);
-  const double *fg = plans[plan_of ? plan_of[b] : 0].fg;
-  const double h = fg[k] * (double)ab32[(size_t)(2 * b) * K + k] + fg[K + k] * (double)ab32[(size_t)(2 * b + 1) * K + k];
-  h32[(size_t)(2 * b) * K + k] = (float)(h * (double)nidx[k]);
+  const PlanDev &c = plans[plan_of ? plan_of[b] : 0];
+  const double h = c.fg[k] * (double)ab32[(size_t)(2 * b) * K + k] +
+                   c.fg[K + k] * (double)ab32[(size_t)(2 * b + 1) * K + k];
+  h32[(size_t)(2 * b) * K + k] = (float)(h * (double)degree_weight(nidx[k], c.dipole));
   h32[(size_t)(2 * b + 1) * K + k] = (float)h;
 }
 
@@ -806,8 +808,9 @@ __global__ __launch_bounds__(256) void k_fit_qd(int nsys, int P, int Pe, const P
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)nsys * P) return;
   const int b = (int)(t / P), s = (int)(t % P);
-  store_strengths(qd, b, s, P, Pe, (double)Cq[(size_t)(2 * b) * P + s], -(double)Cq[(size_t)(2 * b + 1) * P + s],
-                  plans[plan_of ? plan_of[b] : 0].dyc);
+  const PlanDev &c = plans[plan_of ? plan_of[b] : 0];
+  store_strengths(qd, b, s, P, Pe, (double)Cq[(size_t)(2 * b) * P + s],
+                  c.dipole == 2 ? 0.0 : -(double)Cq[(size_t)(2 * b + 1) * P + s], c.dyc);
 }
 
 // ---------------------------------------------------------------------------------

@@ -570,7 +570,7 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   if (o.rc_over_a <= 0.0) o.rc_over_a = 1.0 + o.tau;
   if (!(isfinite(o.rc_over_a) && o.rc_over_a >= 1.0 && o.rc_over_a < 10.0)) return HSMA_EINVAL;
   if (o.check_set != 0 && o.check_set != 1) return HSMA_EINVAL;
-  if (o.dipole != 0 && o.dipole != 1) return HSMA_EINVAL;
+  if (o.dipole < 0 || o.dipole > 2) return HSMA_EINVAL;
   if (o.dy_over_Rtau <= 0.0) o.dy_over_Rtau = 1e-5;
   if (!(isfinite(o.dy_over_Rtau) && o.dy_over_Rtau < 0.1)) return HSMA_EINVAL;
   if (o.p < 0) {
@@ -617,11 +617,11 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   HSMA_TRY(hipMalloc(&consts, sizeof(double) * (3 + o.p + 1)));
   HSMA_TRY(hipMalloc(&pl->chk32, sizeof(float4) * M));
   HSMA_TRY(hipMalloc(&pl->chk64, sizeof(double4) * M));
-  HSMA_TRY(hipMalloc(&pl->nodes32, sizeof(float4) * P * (o.dipole ? 3 : 1)));
-  HSMA_TRY(hipMalloc(&pl->nodes64, sizeof(double4) * P * (o.dipole ? 3 : 1)));
+  HSMA_TRY(hipMalloc(&pl->nodes32, sizeof(float4) * P * (o.dipole == 1 ? 3 : 1)));
+  HSMA_TRY(hipMalloc(&pl->nodes64, sizeof(double4) * P * (o.dipole == 1 ? 3 : 1)));
   k_plan_constants<<<1, 1, 0, st>>>(o.p, eps1 / eps2, kappa * a, o.tau, o.rc_over_a, a, consts, pl->fg);
   k_scale_points<<<blocks(M, 256), 256, 0, st>>>(M, g->unit_check, o.rc_over_a * a, pl->chk32, pl->chk64);
-  if (o.dipole)
+  if (o.dipole == 1)
     k_pair_points<<<blocks(3 * P, 256), 256, 0, st>>>(P, g->unit_nodes, (1.0 + o.tau) * a,
                                                       o.dy_over_Rtau * (1.0 + o.tau) * a, pl->nodes32, pl->nodes64);
   else
@@ -728,7 +728,7 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
   grp->pair_prec = prec;
   grp->device = g->device;
   grp->owned_by_plan = owned_by_plan;
-  grp->P_ev = g->P * (dipole ? 3 : 1);
+  grp->P_ev = g->P * (dipole == 1 ? 3 : 1);
   grp->tune.persistent = 0;
   grp->tune.target_items = 16384;
   grp->tune.symmetric = 1;

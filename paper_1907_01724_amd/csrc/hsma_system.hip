@@ -72,7 +72,7 @@ __device__ __forceinline__ double self_g(const PlanDev &c, double x, double y, d
 // paper's point pairs (nodes at 3s, 3s + 1, 3s + 2).
 __device__ __forceinline__ void surface_row(const PlanDev &c, int s, double x, double y, double z, double &m,
                                             double &t) {
-  if (!c.dipole) {
+  if (c.dipole != 1) {
     const double4 yv = c.nodes64[s];
     const double dx = x - yv.x, dy = y - yv.y, dz = z - yv.z;
     const double ir = rinv64(dx * dx + dy * dy + dz * dz);
@@ -197,13 +197,13 @@ __global__ __launch_bounds__(256) void k_de_fit2(const SysDev *__restrict__ syst
   double sq = 0.0, sd = 0.0;
   for (int k = lane; k < S.K; k += 64) {
     const double h = fg[k] * S.ab[k] + fg[S.K + k] * S.ab[S.K + k];
-    sq = fma(lr[k] * (double)S.nidx[k], h, sq);
+    sq = fma(lr[k] * (double)degree_weight(S.nidx[k], S.pl.dipole), h, sq);
     sd = fma(lr[k], h, sd);
   }
   sq = wave_sum64(sq);
   sd = wave_sum64(sd);
   if (lane == 0) {
-    const double dq = sq, dd = -sd;
+    const double dq = sq, dd = S.pl.dipole == 2 ? 0.0 : -sd;
     S.ds[s] = dq;
     S.ds[S.P + s] = dd;
     const double dwq = S.dw[s], dwd = S.dw[S.P + s];
@@ -269,8 +269,8 @@ __global__ __launch_bounds__(DB) void k_sys_w(SysDev *__restrict__ sd) {
 __global__ void k_sys_s(int P, int dipole, double dyc, const double2 *__restrict__ qd, double *__restrict__ s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  s[i] = dipole ? qd[3 * i].x : qd[i].x;
-  s[P + i] = dipole ? qd[3 * i + 2].x / dyc : qd[i].y;
+  s[i] = dipole == 1 ? qd[3 * i].x : qd[i].x;
+  s[P + i] = dipole == 1 ? qd[3 * i + 2].x / dyc : qd[i].y;
 }
 
 // Direct Coulomb energy in FP64: partials of sum_{j != i} q_j / |x_i - x_j| per target and

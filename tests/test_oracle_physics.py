@@ -194,19 +194,22 @@ def test_paper_claim_hsma_beats_kirkwood():
     assert max(r[f"kirk{c['p_kirkwood_fails']}"] for r in rows) > c["kirkwood_fails_above"]
 
 
+@pytest.mark.parametrize("dipole", [0, 2])
 @pytest.mark.parametrize("eps1,eps2,kappa", [(1.0, 80.0, 0.1), (80.0, 80.0, 0.5), (2.0, 80.0, 5.0),
                                              (1.0, 78.5, 40.0)])
-def test_hsma_matches_kirkwood_well_inside(eps1, eps2, kappa):
+def test_hsma_matches_kirkwood_well_inside(eps1, eps2, kappa, dipole):
     """Sources and targets inside r < 0.55 a: the truncation error at p = 24 is ~0.3^25,
     so the HSMA and the series must agree to near rounding (a dropped term, wrong sign
-    or wrong factor anywhere in the image construction would show as O(1) here)."""
+    or wrong factor anywhere in the image construction would show as O(1) here).  The
+    single-layer variant (dipole = 2) represents the same harmonic by another density and
+    must agree just as closely."""
     a = 4.0
     rng = np.random.default_rng(3)
     n = 10
     pos = rng.standard_normal((n, 3))
     pos *= (0.55 * a * rng.random(n) ** (1 / 3) / np.linalg.norm(pos, axis=1))[:, None]
     q = rng.choice([-1.0, 1.0, 2.0], n)
-    prm = oracle.Params(a=a, eps1=eps1, eps2=eps2, kappa=kappa, p=24, P=2 * 1598, M=1000, F1=987)
+    prm = oracle.Params(a=a, eps1=eps1, eps2=eps2, kappa=kappa, p=24, P=2 * 1598, M=1000, F1=987, dipole=dipole)
     h = oracle.hsma_eval(prm, pos[:, 0], pos[:, 1], pos[:, 2], q)
     k = oracle.kirkwood_eval(a, eps1, eps2, kappa, pos[:, 0], pos[:, 1], pos[:, 2], q)
     assert np.max(np.abs(h - k)) <= 1e-10 * np.max(np.abs(k))
@@ -215,14 +218,18 @@ def test_hsma_matches_kirkwood_well_inside(eps1, eps2, kappa):
 def test_surface_images_reproduce_harmonics():
     """Green's second identity on the auxiliary sphere (eq. "GreenSecond"): for
     Phi = sum Ahat (r/a)^n Y_nm, the Fibonacci-discretised monopole + dipole layer
-    reproduces Phi inside; the +-dy/2 pair of eq. "approxG" agrees to O(dy^2)."""
+    reproduces Phi inside; the +-dy/2 pair of eq. "approxG" agrees to O(dy^2); the single
+    layer alone (dipole = 2, the monopole integral of eq. "threeintegrals" with the density
+    of the same interior harmonic) reproduces it too."""
     a = 2.0
     rng = np.random.default_rng(9)
-    for dip, tol in ((0, 1e-11), (1, 1e-8)):
+    for dip, tol in ((0, 1e-11), (1, 1e-8), (2, 1e-11)):
         prm = oracle.Params(a=a, eps1=1.0, eps2=80.0, kappa=0.3, p=8, P=2 * 1598, M=200, F1=987, dipole=dip)
         Ah = rng.standard_normal(prm.K)
         nodes, w = oracle.fibonacci_nodes(987, 1597, (1 + prm.tau) * a)
         Q, D = oracle.surface_strengths(prm, Ah, nodes, w)
+        if dip == 2:
+            assert not np.any(D)
         tg = rng.standard_normal((30, 3))
         # well inside R_tau the Fibonacci rule is at rounding; near it, at its O(1e-5) level
         tg *= (0.6 * a * rng.random(30) / np.linalg.norm(tg, axis=1))[:, None]
