@@ -75,9 +75,12 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood,accuracy",
+    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood,accuracy,single_layer",
                     help="extra workloads after the headline one: batched, serving, sweep, field, kirkwood, "
-                         "accuracy (comma list, or none)")
+                         "accuracy, single_layer (comma list, or none)")
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="seconds of untimed steps before the warm-up steps, so that the device has left its idle "
+                         "clock state when timing starts (the first steps after idle run about 8%% slower)")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--serving-slots", default="1,2",
                     help="request server: concurrent single-ion-move batches and full energies")
@@ -135,6 +138,11 @@ def main() -> int:
                      stream=stream, ws=ws)
 
     log(f"bench: workload {wl.name}, N={N}, P={P}, M={M}, p={inf['p']}, prec={args.prec}, {nsys} systems/step")
+    t_settle, settle_steps = time.perf_counter(), 0
+    while time.perf_counter() - t_settle < args.settle_s:
+        step()
+        torch.cuda.synchronize()
+        settle_steps += 1
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -195,6 +203,7 @@ def main() -> int:
                    "N": N, "P": P, "M": M, "p": inf["p"], "systems_per_step": len(plans),
                    "pair_precision": args.prec},
         "systems_per_s": nsys / (ms * 1e-3),
+        "settle": {"seconds": args.settle_s, "steps": settle_steps},
         "per_system_path_ms_per_step": ms_single,
     }
     if stages:
@@ -263,6 +272,8 @@ def main() -> int:
         out["kirkwood"] = leg_kirkwood(args, checks)
     if "accuracy" in legs:
         out["accuracy"] = leg_accuracy(args, checks)
+    if "single_layer" in legs:
+        out["single_layer"] = leg_single_layer(args, checks)
     if checks is not None:
         leg_cpu_baseline(checks)
     print(json.dumps(out), flush=True)
@@ -364,6 +375,72 @@ def leg_field(args, checks) -> dict:
     for p in plans:
         p.close()
     log(f"bench[field]: {ms:.3f} ms/call, eval {ev * 1e3:.3f} ms ({res['roofline']['frac']:.2f} of its ALU peak)")
+    return res
+
+
+def leg_single_layer(args, checks) -> dict:
+    """The headline workload (four parameter sets of N = 20000, one batched call per step) with
+    the single-layer surface form (monopoles only, option dipole = 2) beside the default
+    Green's-identity form: time per step, the evaluation launch, and the potentials and energies
+    handed to the oracle checks (the oracle built with the same form)."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.workload_c2()
+    d, systems = wl.disc, wl.systems
+    N, nsys = systems[0].n, len(systems)
+    cat = [np.concatenate([getattr(s, k) for s in systems]) for k in "xyzq"]
+    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
+    off = torch.tensor(np.arange(nsys + 1) * N, dtype=torch.int64, device=dev)
+    plan_of = torch.arange(nsys, dtype=torch.int32, device=dev)
+    phi = torch.empty(nsys * N, dtype=torch.float64, device=dev)
+    E = torch.empty(nsys, dtype=torch.float64, device=dev)
+    res = {"workload": "N=20000, a=30, 30% in the shell [a-1/2,a), P=1600, M=2400, p=20, 4 (eps1,eps2,kappa) sets"}
+    steps = 20
+    for form, dip in (("green_identity", 0), ("single_layer", 2)):
+        plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=args.prec, dipole=dip)
+                 for s in systems]
+        group = hs.Group(plans)
+
+        def step():
+            group.energy(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of, phi=phi, E=E)
+
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        assert group.stream_check() == 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        group.profile(True)
+        group.profile_read()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        st = group.profile_read()
+        group.profile(False)
+        res[form] = {"ms_per_step": ms, "eval_ms": st["eval"][0] / steps}
+        log(f"bench[single_layer]: {form}: {ms:.4f} ms/step, evaluation {st['eval'][0] / steps:.4f} ms")
+        if checks is not None:
+            phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
+
+            def report(r, form=form):
+                res[form]["rel_err_phi_l2_max"] = max(r["rel_phi"]["phi"])
+                res[form]["rel_err_energy_max"] = max(r["rel_e"])
+                log(f"bench[single_layer]: {form}: oracle phi rel L2 {res[form]['rel_err_phi_l2_max']:.2e}, "
+                    f"energy {res[form]['rel_err_energy_max']:.2e}")
+
+            checks.add("potentials", report, infos=[p.info for p in plans],
+                       systems=[(s.x, s.y, s.z, s.q) for s in systems],
+                       phis={"phi": [phi_h[b * N:(b + 1) * N] for b in range(nsys)]}, Es=[float(e) for e in E_h])
+        for p in plans:
+            p.close()
     return res
 
 
@@ -541,7 +618,7 @@ def leg_batched(args, checks) -> dict:
                 ", ".join(f"{k} {max(v):.2e}" for k, v in r["rel_phi"].items()) +
                 f"; energy {res['rel_err_energy_max_sampled']:.2e}")
 
-        checks.add("potentials", report, info=info,
+        checks.add("potentials", report, infos=[info] * len(pick),
                    systems=[(wl.systems[b].x, wl.systems[b].y, wl.systems[b].z, wl.systems[b].q) for b in pick],
                    phis=sampled, Es=[float(E_h[b]) for b in pick])
     log(f"bench[batched]: {ms:.2f} ms/call, {res['systems_per_s']:.0f} systems/s "
@@ -756,7 +833,7 @@ def leg_cpu_baseline(checks: OracleChecks) -> None:
             report({"all": {k: rel(v, truth) for k, v in d["outputs"].items()},
                     "inner": {k: rel(v[inner], truth[inner]) for k, v in d["outputs"].items()}})
         elif kind == "potentials":
-            refs = [oracle.hsma_eval(params(d["info"]), *sysd) for sysd in d["systems"]]
+            refs = [oracle.hsma_eval(params(i), *sysd) for i, sysd in zip(d["infos"], d["systems"])]
             rel_phi = {k: [rel(g, r) for g, r in zip(v, refs)] for k, v in d["phis"].items()}
             rel_e = []
             for sysd, r, e in zip(d["systems"], refs, d["Es"]):

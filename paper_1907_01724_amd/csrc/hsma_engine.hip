@@ -859,7 +859,7 @@ __device__ __forceinline__ double kelvin_range(const typename PT<MODE>::T4 &t, i
   }
 }
 
-template <int MODE>
+template <int MODE, bool MONO>
 __device__ __forceinline__ double surface_range(const typename PT<MODE>::T4 &t,
                                                 const typename PT<MODE>::T4 *__restrict__ nodes,
                                                 const typename PT<MODE>::T2 *__restrict__ qd, int s0, int s1) {
@@ -876,8 +876,12 @@ __device__ __forceinline__ double surface_range(const typename PT<MODE>::T4 &t,
       const T2 wv = qd[k];
       const T dx = t.x - yv.x, dy = t.y - yv.y, dz = t.z - yv.z;
       const T ri = rinv(dx * dx + dy * dy + dz * dz);
-      const T dot = dx * yv.x + dy * yv.y + dz * yv.z;  // (x - y_s) . y_s = R_tau (x - y_s) . y^_s
-      s = fma(ri, fma(wv.y * dot, ri * ri, wv.x), s);
+      if constexpr (MONO) {  // single layer: monopoles only
+        s = fma(wv.x, ri, s);
+      } else {
+        const T dot = dx * yv.x + dy * yv.y + dz * yv.z;  // (x - y_s) . y_s = R_tau (x - y_s) . y^_s
+        s = fma(ri, fma(wv.y * dot, ri * ri, wv.x), s);
+      }
     }
     if constexpr (MODE == HSMA_PAIR_FP32) {
       acc = (double)((T)acc + s);
@@ -927,7 +931,10 @@ __global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, i
     const int64_t s0 = (j0 > n ? j0 : n) - n, s1 = j1 - n;
     if (s0 < s1) {
       const int pl = plan_of ? plan_of[b] : 0;
-      acc += surface_range<MODE>(t, nodes + (size_t)pl * P, qd + (size_t)b * P, (int)s0, (int)s1);
+      const T4 *nd = nodes + (size_t)pl * P;
+      const typename PT<MODE>::T2 *qb = qd + (size_t)b * P;
+      acc += plans[pl].dipole == 2 ? surface_range<MODE, true>(t, nd, qb, (int)s0, (int)s1)
+                                   : surface_range<MODE, false>(t, nd, qb, (int)s0, (int)s1);
     }
     red[w][lane] = acc;
     __syncthreads();
@@ -1153,8 +1160,40 @@ __device__ __forceinline__ float wave_total_lane63(float v) {
   return v;
 }
 
+// Surface nodes s0..s1-1 onto RS target sets per lane, FP32 tiles of TILE nodes folded into
+// FP64.  MONO: the single-layer form, monopoles only (the dipole strengths are zero).
+template <int RS, bool MONO>
+__device__ __forceinline__ void sym_surface(const float (&sx)[RS], const float (&sy)[RS], const float (&sz)[RS],
+                                            const float4 *__restrict__ nd, const float2 *__restrict__ qb, int s0,
+                                            int s1, double (&acc)[RS]) {
+  for (int sb = s0; sb < s1; sb += TILE) {
+    const int se = sb + TILE < s1 ? sb + TILE : s1;
+    float sum[RS];
+#pragma unroll
+    for (int k = 0; k < RS; ++k) sum[k] = 0.0f;
+    for (int m = sb; m < se; ++m) {
+      const float4 yv = nd[m];
+      const float2 wv = qb[m];
+#pragma unroll
+      for (int k = 0; k < RS; ++k) {
+        const float dx = sx[k] - yv.x, dy = sy[k] - yv.y, dz = sz[k] - yv.z;
+        const float ri = rinv(dx * dx + dy * dy + dz * dz);
+        if constexpr (MONO) {
+          sum[k] = fmaf(wv.x, ri, sum[k]);
+        } else {
+          const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
+          sum[k] = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RS; ++k) acc[k] += (double)sum[k];
+  }
+}
+
 template <int R>
-__global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, const int64_t *__restrict__ base,
+__global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, int mono,
+                                                    const int64_t *__restrict__ base,
                                                     const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
                                                     const float4 *__restrict__ tgt, const float4 *__restrict__ img,
                                                     const float *__restrict__ wk, const double *__restrict__ rk,
@@ -1205,25 +1244,10 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, co
     const int pl = plan_of ? plan_of[b] : 0;
     const float4 *nd = nodes + (size_t)pl * P;
     const float2 *qb = qd + (size_t)b * P;
-    for (int sb = s0; sb < s1; sb += TILE) {
-      const int se = sb + TILE < s1 ? sb + TILE : s1;
-      float sum[RS];
-#pragma unroll
-      for (int k = 0; k < RS; ++k) sum[k] = 0.0f;
-      for (int m = sb; m < se; ++m) {
-        const float4 yv = nd[m];
-        const float2 wv = qb[m];
-#pragma unroll
-        for (int k = 0; k < RS; ++k) {
-          const float dx = sx[k] - yv.x, dy = sy[k] - yv.y, dz = sz[k] - yv.z;
-          const float ri = rinv(dx * dx + dy * dy + dz * dz);
-          const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
-          sum[k] = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum[k]);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < RS; ++k) acc[k] += (double)sum[k];
-    }
+    if (mono)
+      sym_surface<RS, true>(sx, sy, sz, nd, qb, s0, s1, acc);
+    else
+      sym_surface<RS, false>(sx, sy, sz, nd, qb, s0, s1, acc);
     const int64_t slot = B + c;
 #pragma unroll
     for (int k = 0; k < RS; ++k) {
@@ -1544,11 +1568,11 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       const float *wk = (const float *)(ws + L.wk);
       const double *rk = (const double *)(ws + L.rk);
       if (L.sym_tb == 256)
-        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk,
-                                            grp->nodes32, qd, eval_part);
+        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img,
+                                            wk, rk, grp->nodes32, qd, eval_part);
       else
-        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, base, sys_e, plan_of, tgt, img, wk, rk,
-                                            grp->nodes32, qd, eval_part);
+        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img,
+                                            wk, rk, grp->nodes32, qd, eval_part);
       done = true;
     }
   }

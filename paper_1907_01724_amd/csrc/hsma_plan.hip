@@ -729,6 +729,7 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
   grp->device = g->device;
   grp->owned_by_plan = owned_by_plan;
   grp->P_ev = g->P * (dipole == 1 ? 3 : 1);
+  grp->dipole = dipole;
   grp->tune.persistent = 0;
   grp->tune.target_items = 16384;
   grp->tune.symmetric = 1;
