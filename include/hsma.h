@@ -201,7 +201,7 @@ hsma_group_t hsma_plan_group(hsma_plan_t plan);
 /* Batched reaction potentials and energies of nsys independent ion configurations in
  * one set of launches (the persistent pair kernels take (system, 64 ions, source chunk)
  * items from a device work counter; the fit is applied to all systems at once, as FP32
- * MFMA GEMMs when nsys >= 8 in the FP32 pair modes).
+ * MFMA GEMMs when nsys >= 192 in the FP32 pair modes).
  *   offsets: [device] nsys + 1 int64, offsets[0] = 0, non-decreasing; system b owns ions
  *            [offsets[b], offsets[b+1]) of x, y, z, q, phi;
  *   plan_of: [device] nsys int32 plan indices into the group, or NULL (all use plan 0);
@@ -264,7 +264,8 @@ hsma_status hsma_group_set_sym_order(hsma_group_t group, int mode);
 
 /* Fit apply (Algorithm 1, steps 3-4: alpha' = Y^+ u, beta' = Y^+ v, then the surface
  * strengths Q', D' through the fixed operator of eq. "GreenSecond") in the FP32 pair modes.
- * mode 0 (default): FP32 GEMVs below 8 systems per call, FP32 MFMA GEMMs from 8 systems;
+ * mode 0 (default): FP32 GEMVs below 192 systems per call, FP32 MFMA GEMMs from 192 systems
+ * (the GEMMs have few row tiles, K / 64, and stay near 0.25-0.4 ms at any smaller batch);
  * 1: always the GEMVs; 2: always the FP32 MFMA GEMMs; 3: always BF16 MFMA GEMMs with
  * split-BF16x3 products (each factor split into two BF16 terms, three term products: about
  * 2^-16 relative per product); 4: the same with split-BF16x6 products (three BF16 terms, six

@@ -36,6 +36,11 @@ constexpr int TILE = 32;         // sources per FP32 partial sum before folding 
 constexpr int FINB = 256;        // ions per finish block
 constexpr int SCHED_T = 1024;    // threads of the schedule kernel
 constexpr int SYM_SH = 2;        // surface items per block and chunk (each takes 1/SYM_SH of the block's ions)
+// Automatic fit route: the FP32 MFMA GEMMs from this many systems per call, the GEMVs below.
+// The GEMMs have K / 64 row tiles (7 at p = 20) and take 0.25-0.4 ms at any batch up to
+// about 1000 systems, while the GEMVs grow by 1.2-2.5 us per system (P = 1024-1600): the
+// measured crossover lies between 128 and 256 systems.
+constexpr int FIT_MFMA_MIN_SYS = 192;
 constexpr int64_t SYM_TAIL_ROUNDS = 4;  // launches of at most this many rounds of resident waves
                                         // of block pairs put the surface items last
 constexpr int64_t SYM_MAX_BYTES = (int64_t)16 << 30;  // partial-slot bound above which the symmetric
@@ -1657,7 +1662,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   }
   L.fin = total_n > 0 ? total_n / FINB + nsys : 0;
   const int fit = grp->tune.fit;
-  L.mfma = !fp64 && (fit >= 2 || (fit == 0 && nsys >= 8));
+  L.mfma = !fp64 && (fit >= 2 || (fit == 0 && nsys >= FIT_MFMA_MIN_SYS));
   L.bf_terms = fp64 ? 0 : fit == 3 ? 2 : fit == 4 ? 3 : 0;
   const size_t t4 = fp64 ? sizeof(double4) : sizeof(float4);
   const size_t t1 = fp64 ? sizeof(double) : sizeof(float);

@@ -132,6 +132,15 @@ def test_fp64_pairs_keep_the_fp64_fit(dev):
     plan.close()
 
 
+def test_automatic_route_switches_at_192_systems(dev):
+    """Mode 0 takes the GEMVs below 192 systems per call and the FP32 MFMA GEMMs from 192 (the
+    measured crossover: the GEMMs have K / 64 row tiles and are latency-bound below it)."""
+    plan = hs.Plan(25.0, 1.0, 78.5, 0.3, 1024, 1536, pair_prec="fp32c")
+    group = hs.Group([plan])
+    assert [group.fit_route(n) for n in (1, 8, 191, 192, 4096)] == [1, 1, 1, 2, 2]
+    plan.close()
+
+
 def test_invalid_fit_mode_is_refused(dev):
     plan = hs.Plan(10.0, 1.0, 80.0, 0.1, 400, 600)
     for bad in (-1, 5):
