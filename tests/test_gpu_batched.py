@@ -135,8 +135,8 @@ def test_plans_with_different_cavities(dev):
 
 @pytest.mark.parametrize("mode", [0, 2])
 def test_graph_replay_matches_eager(dev, mode):
-    """Mode 2 forces the symmetric Kelvin kernel, whose block pairs run on the group's second
-    stream: the captured graph then holds the fork and join between the two streams."""
+    """Mode 0 captures the one-directional evaluation kernel and mode 2 the symmetric Kelvin
+    kernel; every replay must reproduce the eager call."""
     a = 25.0
     plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536)
     group = hs.Group([plan])
