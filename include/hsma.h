@@ -240,8 +240,8 @@ hsma_status hsma_group_tune(hsma_group_t group, int persistent, int target_items
 /* Kelvin sums by the symmetric kernel.  The image distance of an ion pair satisfies
  * |x_j - r_K,i| = (r_j / r_i) |x_i - r_K,j| (Sec. 2.4 images), so one reciprocal root serves
  * both ions of a pair.  The kernel works on blocks of 256 or 512 ions and applies to the
- * compensated FP32 pair precision when its partial sums (8 bytes per ion and block) fit in
- * 16 GiB.  mode 0: never; 1 (default): blocks of 256, else 512, when it applies and the launch
+ * compensated FP32 and the FP64 pair precisions (not to the plain FP32 sweep mode, nor to the
+ * field) when its partial sums (8 bytes per ion and block) fit in 16 GiB.  mode 0: never; 1 (default): blocks of 256, else 512, when it applies and the launch
  * is large enough (see hsma_group_eval_kernel); 2 / 3: blocks of 256 / 512 whenever they
  * apply.  Results differ only in rounding.  Errors: HSMA_EINVAL. */
 hsma_status hsma_group_set_symmetric(hsma_group_t group, int mode);

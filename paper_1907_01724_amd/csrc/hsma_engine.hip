@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
                                               typename PT<MODE>::T4 *__restrict__ img,
                                               typename PT<MODE>::T4 *__restrict__ tgt,
                                               typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
-                                              float *__restrict__ wk, double *__restrict__ rk,
+                                              typename PT<MODE>::T *__restrict__ wk, double *__restrict__ rk,
                                               double4 *__restrict__ sfield, float4 *__restrict__ tlo,
                                               float4 *__restrict__ ilo, int *__restrict__ flag) {
   using T4 = typename PT<MODE>::T4;
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
     srcw[i] = (T)0;
     self[i] = 0.0;
     if (wk) {
-      wk[i] = 0.0f;
+      wk[i] = (T)0;
       rk[i] = 0.0;
     }
     if (sfield) sfield[i] = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   }
   srcw[i] = (T)(qp * r / c.a);
   if (wk) {
-    wk[i] = (float)(qk * reff);  // c0 q_K r: the ion's image strength times its radius
+    wk[i] = (T)(qk * reff);  // c0 q_K r: the ion's image strength times its radius
     rk[i] = 1.0 / reff;
   }
 }
@@ -1363,6 +1363,163 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, in
   }
 }
 
+// The symmetric Kelvin sums in FP64 pairs: the same items, slots and identity as
+// k_kelvin_sym, with FP64 positions, strengths and sums throughout.  A pair's reciprocal root
+// (an FP32 seed and one FP64 Newton step) is the most expensive part of an FP64 pair, so the
+// shared root nearly halves the work.  FP64 values cross lanes as two 32-bit DPP moves.
+template <int CTRL, bool BOUND_ZERO>
+__device__ __forceinline__ double dpp_move64(double old, double v) {
+  const long long ov = __double_as_longlong(old), vv = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)ov, (int)vv, CTRL, 0xf, 0xf, BOUND_ZERO);
+  const int hi = __builtin_amdgcn_update_dpp((int)(ov >> 32), (int)(vv >> 32), CTRL, 0xf, 0xf, BOUND_ZERO);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes, complete in lane 63 (the steps of wave_total_lane63).
+__device__ __forceinline__ double wave_total_lane63_f64(double v) {
+  v += dpp_move64<0x111, true>(0.0, v);  // row_shr:1
+  v += dpp_move64<0x112, true>(0.0, v);  // row_shr:2
+  v += dpp_move64<0x114, true>(0.0, v);  // row_shr:4
+  v += dpp_move64<0x118, true>(0.0, v);  // row_shr:8
+  v += dpp_move64<0x142, true>(0.0, v);  // row_bcast:15
+  v += dpp_move64<0x143, true>(0.0, v);  // row_bcast:31
+  return v;
+}
+
+template <int R>
+__global__ __launch_bounds__(TPB) void k_kelvin_sym64(int nsys, int P, int sch, int mono,
+                                                      const int64_t *__restrict__ base, const int *__restrict__ sys_e,
+                                                      const int32_t *__restrict__ plan_of,
+                                                      const double4 *__restrict__ tgt, const double4 *__restrict__ img,
+                                                      const double *__restrict__ wk, const double *__restrict__ rk,
+                                                      const double4 *__restrict__ nodes,
+                                                      const double2 *__restrict__ qd, double *__restrict__ part) {
+  constexpr int TB = 64 * R;
+  constexpr int RS = R / SYM_SH;
+  constexpr double FAR_TARGET = 3.0e18;
+  Sched S(const_cast<int64_t *>(base), nsys);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (!sched_ok(S)) return;
+  const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);
+  if (item >= S.is[nsys]) return;
+  const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
+  const bool surface = item >= S.is[b];
+  const int64_t lo = S.off[b];
+  const int n = (int)(S.off[b + 1] - lo);
+  const int64_t B = cdiv64(n, TB);
+  double *pb = part + S.pe[b];
+  const double4 *im = img + lo;
+  if (surface) {
+    const int64_t t = item - S.is[b];
+    const int I = __builtin_amdgcn_readfirstlane((int)(t / (sch * SYM_SH)));
+    const int rem = (int)(t % (sch * SYM_SH));
+    const int c = __builtin_amdgcn_readfirstlane(rem / SYM_SH), h = __builtin_amdgcn_readfirstlane(rem % SYM_SH);
+    const int t0 = I * TB + h * RS * 64;
+    double sx[RS], sy[RS], sz[RS], acc[RS];
+#pragma unroll
+    for (int k = 0; k < RS; ++k) {
+      const int i = t0 + k * 64 + lane;
+      const double4 tv = i < n ? tgt[lo + i] : make_double4(FAR_TARGET, 0.0, 0.0, 0.0);
+      sx[k] = tv.x;
+      sy[k] = tv.y;
+      sz[k] = tv.z;
+      acc[k] = 0.0;
+    }
+    const int per = (P + sch - 1) / sch;
+    const int s0 = c * per, s1 = s0 + per < P ? s0 + per : P;
+    const int pl = plan_of ? plan_of[b] : 0;
+    const double4 *nd = nodes + (size_t)pl * P;
+    const double2 *qb = qd + (size_t)b * P;
+    for (int m = s0; m < s1; ++m) {
+      const double4 yv = nd[m];
+      const double2 wv = qb[m];
+#pragma unroll
+      for (int k = 0; k < RS; ++k) {
+        const double dx = sx[k] - yv.x, dy = sy[k] - yv.y, dz = sz[k] - yv.z;
+        const double ri = rinv(dx * dx + dy * dy + dz * dz);
+        if (mono) {
+          acc[k] = fma(wv.x, ri, acc[k]);
+        } else {
+          const double dot = dx * yv.x + dy * yv.y + dz * yv.z;
+          acc[k] = fma(ri, fma(wv.y * dot, ri * ri, wv.x), acc[k]);
+        }
+      }
+    }
+    const int64_t slot = B + c;
+#pragma unroll
+    for (int k = 0; k < RS; ++k) {
+      const int i = t0 + k * 64 + lane;
+      if (i < n) pb[(size_t)slot * n + i] = acc[k];
+    }
+    return;
+  }
+  int I, J;
+  {
+    const int64_t loc = item - S.ie[b];
+    const double bb = 2.0 * (double)B + 1.0;
+    int64_t r = (int64_t)((bb - sqrt(bb * bb - 8.0 * (double)loc)) * 0.5);
+    r = r < 0 ? 0 : (r > B - 1 ? B - 1 : r);
+    while (r > 0 && r * B - r * (r - 1) / 2 > loc) --r;
+    while (r + 1 < B && (r + 1) * B - (r + 1) * r / 2 <= loc) ++r;
+    I = (int)r;
+    J = (int)(I + (loc - (r * B - r * (r - 1) / 2)));
+  }
+  I = __builtin_amdgcn_readfirstlane(I);
+  J = __builtin_amdgcn_readfirstlane(J);
+  const int t0 = I * TB;
+  double tx[R], ty[R], tz[R], tw[R], acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int i = t0 + k * 64 + lane;
+    const bool in = i < n;
+    const double4 t = in ? tgt[lo + i] : make_double4(FAR_TARGET, 0.0, 0.0, 0.0);
+    tx[k] = t.x;
+    ty[k] = t.y;
+    tz[k] = t.z;
+    tw[k] = in ? wk[lo + i] : 0.0;
+    acc[k] = 0.0;
+  }
+  const int j0 = J * TB, j1 = j0 + TB < n ? j0 + TB : n;
+  if (I == J) {
+    // diagonal block: one-directional, the ion's own image excluded (it is the analytic term)
+    for (int j = j0; j < j1; ++j) {
+      const double4 v = im[j];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const double dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
+        double ri = rinv(dx * dx + dy * dy + dz * dz);
+        ri = (j == t0 + k * 64 + lane) ? 0.0 : ri;
+        acc[k] = fma(v.w, ri, acc[k]);
+      }
+    }
+  } else {
+    for (int jg = j0; jg < j1; jg += 64) {
+      const int ge = jg + 64 < j1 ? jg + 64 : j1;
+      double rb = 0.0;  // reverse totals, moved down one lane per source as in k_kelvin_sym
+      for (int j = jg; j < ge; ++j) {
+        const double4 v = im[j];
+        double rev = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const double dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
+          const double ri = rinv(dx * dx + dy * dy + dz * dz);
+          acc[k] = fma(v.w, ri, acc[k]);
+          rev = fma(tw[k], ri, rev);
+        }
+        rev = wave_total_lane63_f64(rev);
+        rb = dpp_move64<0x130, false>(rev, rb);  // wave_shl:1; lane 63 keeps the new total
+      }
+      const int js = jg + lane - (64 - (ge - jg));
+      if (js >= jg) pb[(size_t)I * n + js] = rb * rk[lo + js];  // slot I of ion js
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int i = t0 + k * 64 + lane;
+    if (i < n) pb[(size_t)J * n + i] = acc[k];
+  }
+}
+
 // Phi_i = own-image term + fixed-order sum of the chunk partials; block partial of 1/2 sum q Phi.
 __global__ __launch_bounds__(FINB) void k_finish(int nsys, int P, int che, int sym_tb, int sch,
                                                  const int64_t *__restrict__ base,
@@ -1519,7 +1676,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f, plans, plan_of, x, y, z, q, img, tgt,
                                              srcw, self,
-                                             (float *)(ws + L.wk), (double *)(ws + L.rk),
+                                             (T *)(ws + L.wk), (double *)(ws + L.rk),
                                              L.field ? (double4 *)(ws + L.sfield) : nullptr,
                                              L.lo ? (float4 *)(ws + L.tlo) : nullptr,
                                              L.lo ? (float4 *)(ws + L.ilo) : nullptr, grp->flag);
@@ -1578,6 +1735,19 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       else
         k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img,
                                             wk, rk, grp->nodes32, qd, eval_part);
+      done = true;
+    }
+  } else if constexpr (MODE == HSMA_PAIR_FP64) {
+    if (L.sym_tb > 0 && L.items_e > 0) {
+      const unsigned gs = (unsigned)cdiv(L.items_e, WAVES);
+      const double *wk = (const double *)(ws + L.wk);
+      const double *rk = (const double *)(ws + L.rk);
+      if (L.sym_tb == 256)
+        k_kelvin_sym64<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, wk,
+                                              rk, grp->nodes64, qd, eval_part);
+      else
+        k_kelvin_sym64<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, wk,
+                                              rk, grp->nodes64, qd, eval_part);
       done = true;
     }
   }
@@ -1643,7 +1813,8 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.sym_tb = 0;
   L.sch = 0;
   const int mode = grp->tune.symmetric;
-  if (grp->pair_prec == HSMA_PAIR_FP32_COMP && mode != 0 && total_n > 0 && !field) {
+  if ((grp->pair_prec == HSMA_PAIR_FP32_COMP || grp->pair_prec == HSMA_PAIR_FP64) && mode != 0 && total_n > 0 &&
+      !field) {
     for (int r = 4; r <= 8; r *= 2) {
       if ((mode == 2 && r != 4) || (mode == 3 && r != 8)) continue;
       const int64_t tb = 64 * r;
@@ -1680,7 +1851,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.tgt = take(t4 * (size_t)total_n);
   L.srcw = take(t1 * (size_t)total_n);
   L.self = take(sizeof(double) * (size_t)total_n);
-  L.wk = take(sizeof(float) * (size_t)total_n);
+  L.wk = take(t1 * (size_t)total_n);
   L.rk = take(sizeof(double) * (size_t)total_n);
   L.chk_part = take(sizeof(double) * 2 * (size_t)L.parts_c);
   L.uv = take(sizeof(double) * 2 * (size_t)M * nsys);

@@ -1,12 +1,13 @@
-"""GPU parity of the symmetric Kelvin kernel (compensated FP32 pairs) through the C ABI.
+"""GPU parity of the symmetric Kelvin kernels (compensated FP32 and FP64 pairs) through the C ABI.
 
 The kernel computes each ion pair's reciprocal image distance once and uses it for both ions,
 through the identity |x_j - r_K,i| = (r_j / r_i) |x_i - r_K,j| of the modified Kelvin images
 (Sec. 2.4).  It runs on blocks of 256 or 512 ions with one-directional diagonal blocks and
 surface chunks, so the cases are chosen around those edges: systems of 1, 2, 63-65, 255-257,
 511-513 and 1300 ions, an ion at the exact centre (image at infinity), ions within 1e-9 a of
-the interface and an uneven batch, with either block size forced on.  Each is compared with the FP64 oracle
-(1e-6 relative L2, the FP32 tolerance) and with the one-directional kernel of the library.
+the interface and an uneven batch, with either block size forced on, in compensated FP32 and in
+FP64 pairs (k_kelvin_sym64).  Each is compared with the FP64 oracle (1e-6 relative L2 for FP32
+pairs, 1e-10 for FP64) and with the one-directional kernel of the library (1e-6 / 1e-12).
 """
 import math
 
@@ -20,6 +21,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1907_01724_amd as hs  # noqa: E402
+
+TOL = {"fp32c": 1e-6, "fp64": 1e-10}       # against the oracle
+TOL_ONE = {"fp32c": 1e-6, "fp64": 1e-12}   # against the one-directional kernel
 
 
 @pytest.fixture(scope="module")
@@ -50,23 +54,27 @@ def _run(plan, s, dev, block):
     return phi.cpu().numpy(), float(E.cpu().numpy()[0])
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 @pytest.mark.parametrize("block", [256, 512])
 @pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 255, 256, 257, 511, 512, 513, 1300])
-def test_block_edges(dev, N, block):
+def test_block_edges(dev, N, block, prec):
     s = W.small_uniform(N=N, a=10.0, seed=W.SEED_BASE + 300 + N)
-    plan = hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, 400, 600, pair_prec="fp32c")
+    plan = hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, 400, 600, pair_prec=prec)
     phi_s, e_s = _run(plan, s, dev, block)
     phi_o, e_o = _run(plan, s, dev, 0)
     ref = oracle.hsma_eval(_params(plan), s.x, s.y, s.z, s.q)
     e_ref = oracle.energy(s.q, ref)
-    assert _rel(phi_s, ref) <= 1e-6, (N, _rel(phi_s, ref))
-    assert _rel(phi_s, phi_o) <= 1e-6
-    scale = 0.5 * float(np.sum(np.abs(s.q * ref)))
-    assert abs(e_s - e_ref) <= 2.0 ** -24 * scale
+    assert _rel(phi_s, ref) <= TOL[prec], (N, _rel(phi_s, ref))
+    assert _rel(phi_s, phi_o) <= TOL_ONE[prec]
+    if prec == "fp64":
+        assert abs(e_s - e_ref) <= 1e-11 * abs(e_ref)
+    else:
+        assert abs(e_s - e_ref) <= 2.0 ** -24 * 0.5 * float(np.sum(np.abs(s.q * ref)))
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 @pytest.mark.parametrize("block", [256, 512])
-def test_centre_and_interface_ions(dev, block):
+def test_centre_and_interface_ions(dev, block, prec):
     rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 310))
     a = 30.0
     N = 1200
@@ -77,23 +85,24 @@ def test_centre_and_interface_ions(dev, block):
         pos[k] = d / np.linalg.norm(d) * a * (1.0 - 1e-9 * k)
     q = W.balanced_charges(rng, N)
     s = W.System(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, W.Physics(a, 1.0, 80.0, 0.5))
-    plan = hs.Plan(a, 1.0, 80.0, 0.5, 1600, 2400, pair_prec="fp32c")
+    plan = hs.Plan(a, 1.0, 80.0, 0.5, 1600, 2400, pair_prec=prec)
     phi_s, _ = _run(plan, s, dev, block)
     phi_o, _ = _run(plan, s, dev, 0)
     ref = oracle.hsma_eval(_params(plan), s.x, s.y, s.z, s.q)
     delta = a - float(np.max(np.sqrt(s.x ** 2 + s.y ** 2 + s.z ** 2)))
-    tol = max(1e-6, 1e-15 * a / delta)
+    tol = max(TOL[prec], 1e-15 * a / delta)
     assert _rel(phi_s, ref) <= tol
-    assert _rel(phi_s, phi_o) <= tol
+    assert _rel(phi_s, phi_o) <= max(TOL_ONE[prec], 1e-15 * a / delta)
     assert math.isfinite(phi_s[0])
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 @pytest.mark.parametrize("block", [256, 512])
-def test_uneven_batch(dev, block):
+def test_uneven_batch(dev, block, prec):
     sizes = [700, 1, 1537, 64, 0, 2049, 513]
     systems = [W.small_uniform(N=n, a=25.0, seed=W.SEED_BASE + 320 + k) if n > 0 else None
                for k, n in enumerate(sizes)]
-    plan = hs.Plan(25.0, 1.0, 78.5, 0.3, 1024, 1536, pair_prec="fp32c")
+    plan = hs.Plan(25.0, 1.0, 78.5, 0.3, 1024, 1536, pair_prec=prec)
     group = hs.Group([plan])
     parts = [s for s in systems if s is not None]
     cat = [np.concatenate([getattr(s, k) for s in parts]) for k in "xyzq"]
@@ -116,12 +125,13 @@ def test_uneven_batch(dev, block):
             continue
         lo, hi = off_h[b], off_h[b + 1]
         ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
-        assert _rel(out[block][0][lo:hi], ref) <= 1e-6, (b, _rel(out[block][0][lo:hi], ref))
-        assert _rel(out[block][0][lo:hi], out[0][0][lo:hi]) <= 1e-6
+        assert _rel(out[block][0][lo:hi], ref) <= TOL[prec], (b, _rel(out[block][0][lo:hi], ref))
+        assert _rel(out[block][0][lo:hi], out[0][0][lo:hi]) <= TOL_ONE[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 @pytest.mark.parametrize("block", [256, 512])
-def test_item_orders_are_bit_identical(dev, block):
+def test_item_orders_are_bit_identical(dev, block, prec):
     """The two item orders of the symmetric kernel (each system's surface items after its own
     block pairs, or all block pairs first) compute the same sums into the same slots, so the
     potentials and energies agree bit for bit; the batch has empty, single-block and ragged
@@ -129,7 +139,7 @@ def test_item_orders_are_bit_identical(dev, block):
     sizes = [1300, 0, 1, 700, 513, 0, 2049, 64]
     systems = [W.small_uniform(N=n, a=25.0, seed=W.SEED_BASE + 325 + k) if n > 0 else None
                for k, n in enumerate(sizes)]
-    plan = hs.Plan(25.0, 1.0, 78.5, 0.3, 1024, 1536, pair_prec="fp32c")
+    plan = hs.Plan(25.0, 1.0, 78.5, 0.3, 1024, 1536, pair_prec=prec)
     group = hs.Group([plan])
     group.set_symmetric({256: 2, 512: 3}[block])
     parts = [s for s in systems if s is not None]
@@ -152,6 +162,6 @@ def test_item_orders_are_bit_identical(dev, block):
     for b, s in enumerate(systems):
         if s is not None:
             ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
-            assert _rel(out[1][0][off_h[b]:off_h[b + 1]], ref) <= 1e-6
+            assert _rel(out[1][0][off_h[b]:off_h[b + 1]], ref) <= TOL[prec]
     with pytest.raises(RuntimeError):
         group.set_sym_order(3)
