@@ -8,7 +8,7 @@ and no dipoles (the oracle's pins: it reproduces harmonic polynomials and agrees
 Kirkwood series to near rounding well inside).  Tolerances as for the default form: 1e-6
 relative L2 for the compensated FP32 pairs, 1e-10 for FP64.  Cases: C1 with the fit routes of
 FP32 accuracy (GEMV, FP32 MFMA, split-BF16x6), the shell system, a ragged batch through the
-symmetric and the one-directional kernels, the field, single-ion moves on a resident system,
+symmetric and the one-directional kernels in both pair precisions, the field, single-ion moves on a resident system,
 and the library's dipole strengths being zero.
 """
 import numpy as np
@@ -84,10 +84,11 @@ def test_shell_system(dev, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 @pytest.mark.parametrize("sym", [0, 2, 3])
-def test_ragged_batch(dev, sym):
+def test_ragged_batch(dev, sym, prec):
     a = 25.0
-    plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536, pair_prec="fp32c", dipole=2)
+    plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536, pair_prec=prec, dipole=2)
     group = hs.Group([plan])
     group.set_symmetric(sym)
     sizes = [700, 0, 1, 1537, 64, 513]
@@ -109,7 +110,7 @@ def test_ragged_batch(dev, sym):
             assert E[b] == 0.0
             continue
         ref = oracle.hsma_eval(prm, s.x, s.y, s.z, s.q)
-        assert _rel(phi[off_h[b]:off_h[b + 1]], ref) <= 1e-6, (b, _rel(phi[off_h[b]:off_h[b + 1]], ref))
+        assert _rel(phi[off_h[b]:off_h[b + 1]], ref) <= TOL[prec], (b, _rel(phi[off_h[b]:off_h[b + 1]], ref))
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
