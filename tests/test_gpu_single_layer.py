@@ -8,8 +8,8 @@ and no dipoles (the oracle's pins: it reproduces harmonic polynomials and agrees
 Kirkwood series to near rounding well inside).  Tolerances as for the default form: 1e-6
 relative L2 for the compensated FP32 pairs, 1e-10 for FP64.  Cases: C1 with the fit routes of
 FP32 accuracy (GEMV, FP32 MFMA, split-BF16x6), the shell system, a ragged batch through the
-symmetric and the one-directional kernels in both pair precisions, the field, single-ion moves on a resident system,
-and the library's dipole strengths being zero.
+symmetric and the one-directional kernels in both pair precisions, the field, single-ion moves
+on a resident system, and the library's dipole strengths being zero.
 """
 import numpy as np
 import pytest
