@@ -3,7 +3,8 @@ R_tau -+ dy/2 along each node's normal, option dipole = 1) against the oracle bu
 way.  The pair's two potentials cancel about log10(R_tau/dy) digits, so the FP32 pair modes
 are compared at dy = 1e-2 R_tau (1e-6 relative L2) and the FP64 mode at the paper's
 dy = 1e-5 R_tau (1e-10).  Cases: C1 potentials and strengths, a batch of two cavities, the
-field, and single-ion moves on a resident system.
+field, a ragged batch through both symmetric Kelvin kernels, and single-ion moves on a resident
+system.
 """
 import math
 
@@ -92,6 +93,39 @@ def test_batch_of_two_cavities_and_field(dev, prec, dy, tol):
         lo, hi = off_h[b], off_h[b + 1]
         assert _rel(phi[lo:hi], rp) <= tol, (b, _rel(phi[lo:hi], rp))
         assert _rel(f[lo:hi], rf) <= tol, (b, _rel(f[lo:hi], rf))
+
+
+@pytest.mark.parametrize("prec,dy,tol", [("fp32c", 1e-2, 1e-6), ("fp64", 1e-5, 1e-10)])
+@pytest.mark.parametrize("sym", [2, 3])
+def test_symmetric_kernels_with_point_pairs(dev, prec, dy, tol, sym):
+    """The symmetric Kelvin kernels (forced on, blocks of 256 or 512) take the 3P point charges
+    of each node as their surface sources: a ragged batch over two cavities against the oracle,
+    and against the one-directional kernel of the library."""
+    cav = [(15.0, 0.05), (27.0, 0.4)]
+    plans = [hs.Plan(a, 1.0, 78.5, k, 1024, 1536, pair_prec=prec, dipole=1, dy_over_Rtau=dy) for a, k in cav]
+    group = hs.Group(plans)
+    which = [0, 1, 1, 0, 1]
+    sizes = [700, 1, 1300, 513, 64]
+    systems = [W.small_uniform(n, cav[w][0], seed=W.SEED_BASE + 405 + b) for b, (w, n) in enumerate(zip(which, sizes))]
+    cat = [np.concatenate([getattr(s, k) for s in systems]) for k in "xyzq"]
+    off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    off = torch.tensor(off_h, dtype=torch.int64, device=dev)
+    plan_of = torch.tensor(which, dtype=torch.int32, device=dev)
+    t = [_t(v, dev) for v in cat]
+    total, max_n = int(off_h[-1]), max(sizes)
+    out = {}
+    for mode in (sym, 0):
+        group.set_symmetric(mode)
+        assert group.eval_kernel(len(sizes), total, max_n) == {0: 0, 2: 256, 3: 512}[mode]
+        phi = torch.empty(total, dtype=torch.float64, device=dev)
+        group.energy(off, *t, total_n=total, max_n=max_n, plan_of=plan_of, phi=phi)
+        assert group.stream_check() == 0
+        out[mode] = phi.cpu().numpy()
+    for b, s in enumerate(systems):
+        ref = oracle.hsma_eval(_params(plans[which[b]]), s.x, s.y, s.z, s.q)
+        lo, hi = off_h[b], off_h[b + 1]
+        assert _rel(out[sym][lo:hi], ref) <= tol, (b, _rel(out[sym][lo:hi], ref))
+        assert _rel(out[sym][lo:hi], out[0][lo:hi]) <= (1e-6 if prec == "fp32c" else 1e-12)
 
 
 def test_groups_do_not_mix_dipole_forms(dev):
