@@ -88,7 +88,7 @@ def main() -> int:
                     help="first run two device copies of 256 MiB (a known-traffic kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
         return 2
 
