@@ -289,6 +289,34 @@ int hsma_group_fit_route(hsma_group_t group, int nsys);
 hsma_status hsma_profile_enable(hsma_group_t group, int on);
 hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int64_t *count /* [host] 5 */);
 
+/* Treecode far field for the Kelvin-image sum of one system (the role of the FMM the paper
+ * uses for N up to 10^6, Sec. 3 and Sec. 4.2), as a Barnes-Hut treecode in the FP32 pair modes.
+ * The check sums, the fit and the surface sums are those of hsma_energy; only the sum over the
+ * other ions' Kelvin images is approximated.  The images are sorted into an octree over the
+ * cube of half-width 8a (depth levels below the root; images farther out, of ions within a/8 of
+ * the centre, are summed directly).  A cell of radius r_c at distance d from a group of 64
+ * targets of radius r_g is evaluated from its Cartesian multipole moments of the given order
+ * when r_c + r_g < theta d, else opened; leaves that are not accepted are summed directly.
+ *   theta: in [0, 1); 0 accepts no cell (every image is then summed directly, the check of the
+ *          traversal); order: 2, 4 or 6; depth: 2..9, or 0 for a depth from N (about 8 at
+ *          N = 10^6).
+ * The error is the treecode's: relative L2 errors of the Kelvin sum of about 2e-3 (order 4,
+ * theta 0.5) to 2e-6 (order 12) on uniformly filled cavities with balanced charges; the
+ * method's own 1e-6 target needs high orders, at which the direct symmetric sums of
+ * hsma_energy are faster below about 10^7 ions on one device.
+ *   phi: [device] N doubles (required); E: [device] one double or NULL;
+ *   ws: [device] ws_bytes >= hsma_tree_workspace_bytes(plan, N, opts) (0 for invalid arguments).
+ * Errors: HSMA_EINVAL (also for the FP64 pair mode), HSMA_ESTATE, HSMA_EDEVICE. */
+typedef struct {
+  double theta;
+  int order;
+  int depth;
+} hsma_tree_opts;
+size_t hsma_tree_workspace_bytes(hsma_plan_t plan, int64_t N, const hsma_tree_opts *opts);
+hsma_status hsma_energy_tree(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
+                             const double *q, double *phi, double *E, const hsma_tree_opts *opts, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
+
 /* Resident system (a Monte Carlo state): copies x, y, z, q ([device], N >= 1 ions) and keeps
  * on the device what a single-ion move needs: the positions, the surface strengths s and
  * surface rows w = sum_i q_i S(x_i) of the HSMA energy, and the energy itself, all from a

@@ -28,6 +28,10 @@ class HsmaError(RuntimeError):
         super().__init__(f"{where}: {STATUS.get(code, code)}")
 
 
+class TreeOpts(C.Structure):
+    _fields_ = [("theta", C.c_double), ("order", C.c_int), ("depth", C.c_int)]
+
+
 class PlanOpts(C.Structure):
     _fields_ = [("p", C.c_int), ("tau", C.c_double), ("rc_over_a", C.c_double), ("F1", C.c_int),
                 ("pair_prec", C.c_int), ("check_set", C.c_int), ("dipole", C.c_int), ("dy_over_Rtau", C.c_double)]
@@ -115,6 +119,9 @@ def load_library(path: str | None = None):
     L.hsma_kirkwood_workspace_bytes.argtypes = [C.c_int, C.c_int64]
     L.hsma_kirkwood_workspace_bytes.restype = C.c_size_t
     L.hsma_kirkwood.argtypes = [_VP, C.c_int, C.c_int64] + [_VP] * 6 + [_VP, C.c_size_t, _VP]
+    L.hsma_tree_workspace_bytes.argtypes = [_VP, C.c_int64, C.POINTER(TreeOpts)]
+    L.hsma_tree_workspace_bytes.restype = C.c_size_t
+    L.hsma_energy_tree.argtypes = [_VP, C.c_int64] + [_VP] * 6 + [C.POINTER(TreeOpts), _VP, C.c_size_t, _VP]
     L.hsma_field_workspace_bytes.argtypes = [_VP, C.c_int64]
     L.hsma_field_workspace_bytes.restype = C.c_size_t
     L.hsma_field.argtypes = [_VP, C.c_int64] + [_VP] * 9 + [_VP, C.c_size_t, _VP]
@@ -148,7 +155,7 @@ def load_library(path: str | None = None):
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
                  "hsma_group_set_fit", "hsma_group_set_sym_order", "hsma_field", "hsma_field_batched",
-                 "hsma_kirkwood", "hsma_system_create_ex", "hsma_system_create", "hsma_delta_energy",
+                 "hsma_kirkwood", "hsma_energy_tree", "hsma_system_create_ex", "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
                  "hsma_server_remove_system", "hsma_server_submit", "hsma_server_stats", "hsma_server_run_load"):
@@ -324,6 +331,31 @@ class Plan:
                                  _dev_ptr(q, "q", N), _dev_ptr(phi, "phi", N),
                                  _dev_ptr(E, "E", 1) if E is not None else None, w.ptr, w.nbytes,
                                  _stream_ptr(stream)), "hsma_kirkwood")
+        return phi
+
+    def tree_workspace_bytes(self, N: int, theta: float = 0.5, order: int = 4, depth: int = 0) -> int:
+        o = TreeOpts(float(theta), int(order), int(depth))
+        return int(load_library().hsma_tree_workspace_bytes(self._h, int(N), C.byref(o)))
+
+    def energy_tree(self, x, y, z, q, theta: float = 0.5, order: int = 4, depth: int = 0, phi=None, E=None,
+                    stream=None, ws: Workspace | None = None):
+        """Potentials (and the energy when E is given) with the Kelvin-image sum by the treecode
+        (opening angle theta, multipole order 2, 4 or 6; depth 0 = from N).  Returns phi."""
+        torch = _torch()
+        N = x.numel()
+        if phi is None:
+            phi = torch.empty(N, dtype=torch.float64, device=x.device)
+        lib = load_library()
+        o = TreeOpts(float(theta), int(order), int(depth))
+        nb = int(lib.hsma_tree_workspace_bytes(self._h, N, C.byref(o)))
+        if nb == 0:
+            raise RuntimeError("hsma_tree_workspace_bytes: invalid arguments")
+        w = ws if ws is not None else _ensure(self._ws, ("tree", N, float(theta), int(order), int(depth),
+                                                         str(x.device)), nb, x.device)
+        _check(lib.hsma_energy_tree(self._h, N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N), _dev_ptr(z, "z", N),
+                                    _dev_ptr(q, "q", N), _dev_ptr(phi, "phi", N),
+                                    _dev_ptr(E, "E", 1) if E is not None else None, C.byref(o), w.ptr, w.nbytes,
+                                    _stream_ptr(stream)), "hsma_energy_tree")
         return phi
 
     def intermediates(self, N: int, device, stream=None):

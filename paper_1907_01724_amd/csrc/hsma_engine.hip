@@ -1721,6 +1721,10 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
                                                                                plan_of, g->nidx, ab, qd);
   }
   prof_end(pr, st);
+  if (L.upto_fit) {
+    HSMA_HIP(hipGetLastError());
+    return HSMA_OK;
+  }
 
   pr = prof_begin(grp, ST_EVAL, st);
   bool done = false;
@@ -1781,7 +1785,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
 // Item sizes are chosen from upper bounds known on the host (system count, total and
 // largest system size): the check chunk aims at about 8192 items, the evaluation chunk at
 // about 8192 items of the largest possible pair count; both multiples of 4 waves x 32.
-Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n, bool field) {
+Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n, bool field, bool no_sym) {
   Layout L;
   L.field = field;
   const Geometry *g = grp->geo;
@@ -1814,7 +1818,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.sch = 0;
   const int mode = grp->tune.symmetric;
   if ((grp->pair_prec == HSMA_PAIR_FP32_COMP || grp->pair_prec == HSMA_PAIR_FP64) && mode != 0 && total_n > 0 &&
-      !field) {
+      !field && !no_sym) {
     for (int r = 4; r <= 8; r *= 2) {
       if ((mode == 2 && r != 4) || (mode == 3 && r != 8)) continue;
       const int64_t tb = 64 * r;
@@ -1897,6 +1901,21 @@ hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, con
       return launch<HSMA_PAIR_FP32_COMP>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
     case HSMA_PAIR_FP64:
       return launch<HSMA_PAIR_FP64>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
+    default:
+      return HSMA_EINVAL;
+  }
+}
+
+hsma_status run_front(hsma_group_s *grp, const Layout &L, int64_t n, const double *x, const double *y,
+                      const double *z, const double *q, char *ws, hipStream_t st) {
+  if (!L.upto_fit || L.nsys != 1) return HSMA_EINVAL;
+  switch (grp->pair_prec) {
+    case HSMA_PAIR_FP32:
+      return launch<HSMA_PAIR_FP32>(grp, L, nullptr, nullptr, n, x, y, z, q, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr, ws, st);
+    case HSMA_PAIR_FP32_COMP:
+      return launch<HSMA_PAIR_FP32_COMP>(grp, L, nullptr, nullptr, n, x, y, z, q, nullptr, nullptr, nullptr,
+                                         nullptr, nullptr, ws, st);
     default:
       return HSMA_EINVAL;
   }

@@ -1,0 +1,577 @@
+// Treecode far field for the Kelvin-image sum (the role of the paper's FMM in Sec. 3 and
+// Sec. 4.2, as a Barnes-Hut treecode): one system, FP32 pair modes.
+//
+// Every Kelvin image lies outside the cavity and every target inside it.  The images are
+// sorted by the Morton code of their position in the cube [-L, L]^3, L = 8a, at depth D; the
+// few images outside the cube (ions within a/8 of the centre, whose images are more than 8a
+// away) sort last and form the far set, summed directly.  Each level l = 0..D of the octree is
+// the run-length encoding of the codes shifted by 3 (D - l) bits.  Per cell, Cartesian
+// multipole moments about the cell centre
+//   M_k = sum_j q_K,j (y_j - c)^k,  |k| <= p,
+// and the potential at x of an accepted cell is sum_k a_k(x - c) M_k with the Taylor
+// coefficients a_k(R) = (1/k!) d^k/dy^k 1/|x - y| at y = c, from the recurrence
+//   |R|^2 a_k = ((2n - 1)/n) sum_i R_i a_{k - e_i} - ((n - 1)/n) sum_i a_{k - 2e_i},  n = |k|,
+// a_0 = 1/|R| (the recurrence for the Taylor coefficients of 1/|x - y| used by Cartesian
+// treecodes, e.g. Lindsay and Krasny; it follows from 1/|x - y| satisfying Laplace's equation).
+// A cell is accepted for a group of 64 targets when (r_cell + r_group) < theta |c_cell - c_group|;
+// leaves that are not accepted are summed directly, the ion's own image excluded (it is the
+// analytic FP64 term of the packing kernel).  If an ion's own image lies in an accepted cell,
+// its exact FP32 term is subtracted again.  theta = 0 accepts nothing: the traversal then sums
+// every image directly.  The targets are the ions in the images' sorted order, so a group of
+// 64 consecutive targets is compact wherever the Kelvin map is (everywhere but the centre).
+//
+// The check sums, the fit and the surface strengths are those of the direct path
+// (run_front); the surface nodes are summed directly per target after the traversal.
+#include <cmath>
+
+#include "hsma_internal.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+namespace hsma {
+namespace {
+
+constexpr int TR_WAVES = 4;             // waves per block, one target group each
+constexpr int TR_STACK = 96;            // traversal stack entries per wave (>= 7 (D + 1) + 8)
+constexpr int TR_MAX_DEPTH = 10;        // codes of 3 D bits plus the far flag fit in 31 bits
+constexpr unsigned TR_FAR = 1u << 30;   // code of an image outside the cube
+constexpr double TR_CUBE = 8.0;         // cube half-width in units of a
+
+// Graded multi-index order: degree n, then kx descending, then ky descending.
+constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int kidx(int kx, int ky, int kz) {
+  const int n = kx + ky + kz;
+  return n * (n + 1) * (n + 2) / 6 + (n - kx) * (n - kx + 1) / 2 + (n - kx - ky);
+}
+struct K3 {
+  int x, y, z;
+};
+__host__ __device__ constexpr K3 kof(int k) {  // the k-th multi-index of the graded order
+  int i = 0;
+  for (int n = 0; n <= 16; ++n)
+    for (int x = n; x >= 0; --x)
+      for (int y = n - x; y >= 0; --y) {
+        if (i == k) return K3{x, y, n - x - y};
+        ++i;
+      }
+  return K3{0, 0, 0};
+}
+
+// a_k(R) for |k| <= P into a[ncoef(P)], one coefficient per instantiation (constant indices).
+template <int P, int K>
+__device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float ir2, float (&a)[ncoef(P)]) {
+  if constexpr (K < ncoef(P)) {
+    constexpr K3 t = kof(K);
+    constexpr int n = t.x + t.y + t.z;
+    constexpr float c1 = (float)(2 * n - 1) / (float)n, c2 = (float)(n - 1) / (float)n;
+    float s1 = 0.0f, s2 = 0.0f;
+    if constexpr (t.x >= 1) s1 = fmaf(rx, a[kidx(t.x - 1, t.y, t.z)], s1);
+    if constexpr (t.y >= 1) s1 = fmaf(ry, a[kidx(t.x, t.y - 1, t.z)], s1);
+    if constexpr (t.z >= 1) s1 = fmaf(rz, a[kidx(t.x, t.y, t.z - 1)], s1);
+    if constexpr (t.x >= 2) s2 += a[kidx(t.x - 2, t.y, t.z)];
+    if constexpr (t.y >= 2) s2 += a[kidx(t.x, t.y - 2, t.z)];
+    if constexpr (t.z >= 2) s2 += a[kidx(t.x, t.y, t.z - 2)];
+    a[K] = (c1 * s1 - c2 * s2) * ir2;
+    taylor_rec<P, K + 1>(rx, ry, rz, ir2, a);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void taylor(float rx, float ry, float rz, float (&a)[ncoef(P)]) {
+  const float ir = __builtin_amdgcn_rsqf(rx * rx + ry * ry + rz * rz);
+  a[0] = ir;
+  taylor_rec<P, 1>(rx, ry, rz, ir * ir, a);
+}
+
+// m[k] += q d^k for every |k| <= P (px, py, pz: powers of the offset's components).
+template <int P, int K>
+__device__ __forceinline__ void moment_rec(float q, const float (&px)[P + 1], const float (&py)[P + 1],
+                                           const float (&pz)[P + 1], float (&m)[ncoef(P)]) {
+  if constexpr (K < ncoef(P)) {
+    constexpr K3 t = kof(K);
+    m[K] = fmaf(q, px[t.x] * py[t.y] * pz[t.z], m[K]);
+    moment_rec<P, K + 1>(q, px, py, pz, m);
+  }
+}
+
+__device__ __forceinline__ unsigned spread3(unsigned v) {  // 10 bits -> every third bit
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__device__ __forceinline__ unsigned compact3(unsigned v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030c30c3u;
+  v = (v | (v >> 4)) & 0x0300f00fu;
+  v = (v | (v >> 8)) & 0x030000ffu;
+  v = (v | (v >> 16)) & 0x3ffu;
+  return v;
+}
+
+// codes[i], ids[i] = i for every ion's image.
+__global__ void k_tree_keys(int n, int D, float L, const float4 *__restrict__ img, unsigned *__restrict__ codes,
+                            int *__restrict__ ids) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 v = img[i];
+  unsigned code = TR_FAR;
+  if (fabsf(v.x) < L && fabsf(v.y) < L && fabsf(v.z) < L) {
+    const float sc = (float)(1 << D) / (2.0f * L);
+    const int m = (1 << D) - 1;
+    const int ix = min(m, max(0, (int)((v.x + L) * sc)));
+    const int iy = min(m, max(0, (int)((v.y + L) * sc)));
+    const int iz = min(m, max(0, (int)((v.z + L) * sc)));
+    code = spread3((unsigned)ix) | (spread3((unsigned)iy) << 1) | (spread3((unsigned)iz) << 2);
+  }
+  codes[i] = code;
+  ids[i] = i;
+}
+
+// Sorted images and targets; inv[i] = sorted position of ion i.
+__global__ void k_tree_gather(int n, const int *__restrict__ perm, const float4 *__restrict__ img,
+                              const float4 *__restrict__ tgt, float4 *__restrict__ simg, float4 *__restrict__ stgt,
+                              int *__restrict__ inv) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = perm[s];
+  simg[s] = img[i];
+  stgt[s] = tgt[i];
+  inv[i] = s;
+}
+
+// Run-length flags of the level-l keys: from the sorted codes (leaf level, src_key = codes,
+// shift 0) or from the level-(l+1) cell keys (shift 3).  m = number of valid source entries
+// (*m_dev, on the device); entries from m up to cap get flag 0.
+__global__ void k_tree_flags(int cap, const int *__restrict__ m_dev, int m_host, const unsigned *__restrict__ src_key,
+                             int shift, int *__restrict__ flags) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cap) return;
+  const int m = m_dev ? *m_dev : m_host;
+  int f = 0;
+  if (j < m) f = (j == 0 || (src_key[j] >> shift) != (src_key[j - 1] >> shift)) ? 1 : 0;
+  flags[j] = f;
+}
+
+// Cells of a level from the flags and their exclusive scan: key, first source entry (child),
+// and first image (start).  The last thread also stores the count and the end sentinel.
+__global__ void k_tree_cells(int cap, const int *__restrict__ m_dev, int m_host, int n_img,
+                             const unsigned *__restrict__ src_key, int shift, const int *__restrict__ src_start,
+                             const int *__restrict__ flags, const int *__restrict__ scan, unsigned *__restrict__ key,
+                             int *__restrict__ child, int *__restrict__ start, int *__restrict__ count_out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = m_dev ? *m_dev : m_host;
+  if (j < m && flags[j]) {
+    const int c = scan[j];
+    key[c] = src_key[j] >> shift;
+    child[c] = j;
+    start[c] = src_start ? src_start[j] : j;
+  }
+  if (j == 0) {
+    const int nc = m > 0 ? scan[m - 1] + flags[m - 1] : 0;
+    *count_out = nc;
+    start[nc] = n_img;  // end sentinel of the last cell's images
+    child[nc] = m;      // ... and of its children
+  }
+}
+
+// Moments, centre and radius of every cell of one level: one wave per cell.  The centre is the
+// geometric centre of the octree cell; the far cell (outside the cube) gets radius +inf.
+template <int P>
+__global__ __launch_bounds__(256) void k_tree_moments(int cap, const int *__restrict__ ncell, int level, float L,
+                                                     const unsigned *__restrict__ key, const int *__restrict__ start,
+                                                     const float4 *__restrict__ simg, float4 *__restrict__ cen,
+                                                     float *__restrict__ mom) {
+  constexpr int NC = ncoef(P);
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= cap || c >= *ncell) return;
+  const unsigned k = key[c];
+  const int s0 = start[c], s1 = start[c + 1];
+  const bool far = (k >> (3 * level)) != 0;  // cube cells of level l have keys below 8^l
+  float cx = 0.f, cy = 0.f, cz = 0.f;
+  if (!far) {
+    const float h = 2.0f * L / (float)(1 << level);
+    cx = -L + ((float)compact3(k) + 0.5f) * h;
+    cy = -L + ((float)compact3(k >> 1) + 0.5f) * h;
+    cz = -L + ((float)compact3(k >> 2) + 0.5f) * h;
+  }
+  float m[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) m[t] = 0.0f;
+  float rmax = 0.0f;
+  for (int s = s0 + lane; s < s1; s += 64) {
+    const float4 v = simg[s];
+    const float dx = v.x - cx, dy = v.y - cy, dz = v.z - cz;
+    rmax = fmaxf(rmax, sqrtf(dx * dx + dy * dy + dz * dz));
+    // powers dx^i dy^j dz^l by degree
+    float px[P + 1], py[P + 1], pz[P + 1];
+    px[0] = py[0] = pz[0] = 1.0f;
+#pragma unroll
+    for (int e = 1; e <= P; ++e) {
+      px[e] = px[e - 1] * dx;
+      py[e] = py[e - 1] * dy;
+      pz[e] = pz[e - 1] * dz;
+    }
+    moment_rec<P, 0>(v.w, px, py, pz, m);
+  }
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    float v = m[t];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    m[t] = v;
+  }
+  for (int o = 32; o > 0; o >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, o));
+  if (lane == 0) {
+    cen[c] = make_float4(cx, cy, cz, far ? INFINITY : rmax);
+#pragma unroll
+    for (int t = 0; t < NC; ++t) mom[(size_t)c * NC + t] = m[t];
+  }
+}
+
+// Bounding sphere of each group of 64 consecutive sorted targets.
+__global__ __launch_bounds__(64) void k_tree_groups(int n, const float4 *__restrict__ stgt, float4 *__restrict__ grp) {
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const int s = g * 64 + lane;
+  const bool in = s < n;
+  const float4 t = in ? stgt[s] : stgt[g * 64];
+  float lo[3] = {t.x, t.y, t.z}, hi[3] = {t.x, t.y, t.z};
+  for (int o = 32; o > 0; o >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fminf(lo[d], __shfl_xor(lo[d], o));
+      hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], o));
+    }
+  const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+  float r = in ? sqrtf((t.x - cx) * (t.x - cx) + (t.y - cy) * (t.y - cy) + (t.z - cz) * (t.z - cz)) : 0.0f;
+  for (int o = 32; o > 0; o >>= 1) r = fmaxf(r, __shfl_xor(r, o));
+  if (lane == 0) grp[g] = make_float4(cx, cy, cz, r);
+}
+
+struct TreeLevels {
+  const unsigned *key[TR_MAX_DEPTH + 1];
+  const int *start[TR_MAX_DEPTH + 1], *child[TR_MAX_DEPTH + 1];
+  const float4 *cen[TR_MAX_DEPTH + 1];
+  const float *mom[TR_MAX_DEPTH + 1];
+  const int *ncell;  // D + 1 counts
+};
+
+__device__ __forceinline__ void direct_range(float tx, float ty, float tz, int own, const float4 *__restrict__ simg,
+                                             int s0, int s1, double &acc) {
+  for (int sb = s0; sb < s1; sb += 32) {
+    const int se = sb + 32 < s1 ? sb + 32 : s1;
+    float sum = 0.0f;
+    for (int j = sb; j < se; ++j) {
+      const float4 v = simg[j];
+      const float dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
+      float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+      ri = (j == own) ? 0.0f : ri;
+      sum = fmaf(v.w, ri, sum);
+    }
+    acc += (double)sum;
+  }
+}
+
+// One wave per group of 64 sorted targets: traversal, far set, surface nodes; writes phi in the
+// ions' original order (own-image term included).
+template <int P>
+__global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, int D, float theta, TreeLevels T,
+                                                            const float4 *__restrict__ simg,
+                                                            const float4 *__restrict__ stgt,
+                                                            const int *__restrict__ perm,
+                                                            const float4 *__restrict__ grp,
+                                                            const double *__restrict__ self, int Pn, int mono,
+                                                            const float4 *__restrict__ nodes,
+                                                            const float2 *__restrict__ qd, double *__restrict__ phi) {
+  constexpr int NC = ncoef(P);
+  __shared__ int stack[TR_WAVES][TR_STACK];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = blockIdx.x * TR_WAVES + w;
+  if (g * 64 >= n) return;
+  const int s = g * 64 + lane;
+  const bool in = s < n;
+  const float4 t = stgt[in ? s : g * 64];
+  const int own = in ? s : -1;
+  const float4 G = grp[g];
+  // the far set: the leaf level's last cell when its key lies beyond the cube's 8^D cells
+  const int nl = T.ncell[D];
+  const int far_start = (nl > 0 && (T.key[D][nl - 1] >> (3 * D)) != 0u) ? T.start[D][nl - 1] : n;
+  double acc = 0.0;
+  int sp = 0;
+  // the level-0 cells: the cube (key 0) and possibly the far cell, which is summed below
+  const int n0 = T.ncell[0];
+  for (int c = 0; c < n0; ++c)
+    if (T.key[0][c] == 0u) stack[w][sp++] = c;  // level 0 in the top bits
+  while (sp > 0) {
+    const int e = __builtin_amdgcn_readfirstlane(stack[w][--sp]);
+    const int l = e >> 27, c = e & ((1 << 27) - 1);
+    const float4 cc = T.cen[l][c];
+    const int c0 = T.start[l][c], c1 = T.start[l][c + 1];
+    const float dx = cc.x - G.x, dy = cc.y - G.y, dz = cc.z - G.z;
+    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+    if (cc.w + G.w < theta * d) {
+      float a[NC];
+      taylor<P>(t.x - cc.x, t.y - cc.y, t.z - cc.z, a);
+      const float *m = T.mom[l] + (size_t)c * NC;
+      float v = 0.0f;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) v = fmaf(a[k], m[k], v);
+      if (own >= c0 && own < c1) {  // the ion's own image is in the cell: take its term out again
+        const float4 o = simg[own];
+        const float ox = t.x - o.x, oy = t.y - o.y, oz = t.z - o.z;
+        v -= o.w * __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+      }
+      acc += (double)v;
+    } else if (l == D) {
+      direct_range(t.x, t.y, t.z, own, simg, c0, c1, acc);
+    } else {
+      const int k0 = T.child[l][c], k1 = T.child[l][c + 1];
+      for (int k = k1 - 1; k >= k0 && sp < TR_STACK; --k) stack[w][sp++] = ((l + 1) << 27) | k;
+    }
+  }
+  if (far_start < n) direct_range(t.x, t.y, t.z, own, simg, far_start, n, acc);
+  // surface nodes, as the direct path
+  for (int sb = 0; sb < Pn; sb += 32) {
+    const int se = sb + 32 < Pn ? sb + 32 : Pn;
+    float sum = 0.0f;
+    for (int m = sb; m < se; ++m) {
+      const float4 yv = nodes[m];
+      const float2 wv = qd[m];
+      const float dx = t.x - yv.x, dy = t.y - yv.y, dz = t.z - yv.z;
+      const float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+      if (mono) {
+        sum = fmaf(wv.x, ri, sum);
+      } else {
+        const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
+        sum = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum);
+      }
+    }
+    acc += (double)sum;
+  }
+  if (in) {
+    const int i = perm[s];
+    phi[i] = self[i] + acc;
+  }
+}
+
+// Block partials of (1/2) sum q phi in the original ion order, then one block adds them.
+__global__ __launch_bounds__(256) void k_tree_epart(int n, const double *__restrict__ q,
+                                                    const double *__restrict__ phi, double *__restrict__ ep) {
+  __shared__ double red[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  red[threadIdx.x] = i < n ? 0.5 * q[i] * phi[i] : 0.0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ep[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_tree_esum(int nb, const double *__restrict__ ep, double *__restrict__ E) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) s += ep[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *E = red[0];
+}
+
+inline int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int auto_depth(int64_t n) {
+  // about 30-120 images per occupied leaf near the interface for uniformly filled cavities
+  const double d = 8.0 + (std::log2((double)(n > 1 ? n : 1)) - std::log2(1e6)) / 3.0;
+  int D = (int)std::lround(d);
+  return D < 2 ? 2 : (D > TR_MAX_DEPTH - 1 ? TR_MAX_DEPTH - 1 : D);
+}
+
+struct TreeLayout {
+  int D, P, nc, ngroups;
+  int64_t cap[TR_MAX_DEPTH + 1];
+  size_t codes_a, codes_b, ids_a, ids_b, simg, stgt, inv, flags, scan, grp, ncell, ep, temp, temp_bytes;
+  size_t key[TR_MAX_DEPTH + 1], start[TR_MAX_DEPTH + 1], child[TR_MAX_DEPTH + 1], cen[TR_MAX_DEPTH + 1],
+      mom[TR_MAX_DEPTH + 1];
+  size_t total;
+};
+
+hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
+  T.D = D;
+  T.P = P;
+  T.nc = ncoef(P);
+  T.ngroups = (int)cdivl(n, 64);
+  size_t o = al256(base);
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o = al256(o + (b > 0 ? b : 1));
+    return at;
+  };
+  const size_t N = (size_t)(n > 0 ? n : 1);
+  T.codes_a = take(4 * N);
+  T.codes_b = take(4 * N);
+  T.ids_a = take(4 * N);
+  T.ids_b = take(4 * N);
+  T.simg = take(16 * N);
+  T.stgt = take(16 * N);
+  T.inv = take(4 * N);
+  T.flags = take(4 * N);
+  T.scan = take(4 * N);
+  T.grp = take(16 * (size_t)T.ngroups);
+  T.ncell = take(4 * (TR_MAX_DEPTH + 1));
+  T.ep = take(8 * (size_t)cdivl(n, 256));
+  for (int l = 0; l <= D; ++l) {
+    int64_t c = (int64_t)1 << (3 * l);
+    c = (c + 1 < (int64_t)N ? c + 1 : (int64_t)N);  // level l holds at most 8^l cube cells and the far cell
+    T.cap[l] = c;
+    T.key[l] = take(4 * (size_t)c);
+    T.start[l] = take(4 * ((size_t)c + 1));
+    T.child[l] = take(4 * ((size_t)c + 1));
+    T.cen[l] = take(16 * (size_t)c);
+    T.mom[l] = take(4 * (size_t)c * T.nc);
+  }
+  size_t sort_b = 0, scan_b = 0;
+  if (rocprim::radix_sort_pairs(nullptr, sort_b, (const unsigned *)nullptr, (unsigned *)nullptr, (const int *)nullptr,
+                                (int *)nullptr, (unsigned)N, 0, 31) != hipSuccess)
+    return HSMA_EDEVICE;
+  if (rocprim::exclusive_scan(nullptr, scan_b, (const int *)nullptr, (int *)nullptr, 0, N, rocprim::plus<int>()) !=
+      hipSuccess)
+    return HSMA_EDEVICE;
+  T.temp_bytes = sort_b > scan_b ? sort_b : scan_b;
+  T.temp = take(T.temp_bytes);
+  T.total = o;
+  return HSMA_OK;
+}
+
+}  // namespace
+}  // namespace hsma
+
+using namespace hsma;
+
+static hsma_status tree_args(hsma_plan_t pl, int64_t N, const hsma_tree_opts *opts, int &D, int &P, float &theta) {
+  if (!pl || N < 0 || !opts) return HSMA_EINVAL;
+  if (pl->opts.pair_prec != HSMA_PAIR_FP32 && pl->opts.pair_prec != HSMA_PAIR_FP32_COMP) return HSMA_EINVAL;
+  if (!(opts->theta >= 0.0 && opts->theta < 1.0)) return HSMA_EINVAL;
+  if (opts->order != 2 && opts->order != 4 && opts->order != 6) return HSMA_EINVAL;
+  if (opts->depth != 0 && (opts->depth < 2 || opts->depth > TR_MAX_DEPTH - 1)) return HSMA_EINVAL;
+  if (N > ((int64_t)1 << 27) - 1) return HSMA_EINVAL;  // cell indices in 27 bits
+  D = opts->depth ? opts->depth : auto_depth(N);
+  P = opts->order;
+  theta = (float)opts->theta;
+  return HSMA_OK;
+}
+
+extern "C" size_t hsma_tree_workspace_bytes(hsma_plan_t pl, int64_t N, const hsma_tree_opts *opts) {
+  int D, P;
+  float th;
+  if (tree_args(pl, N, opts, D, P, th) != HSMA_OK) return 0;
+  Layout L = layout(pl->self, 1, N, N, false, true);
+  TreeLayout T;
+  if (tree_layout(N, D, P, L.total, T) != HSMA_OK) return 0;
+  return T.total;
+}
+
+extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
+                                        const double *q, double *phi, double *E, const hsma_tree_opts *opts, void *ws,
+                                        size_t ws_bytes, hipStream_t st) {
+  int D, P;
+  float theta;
+  hsma_status rc = tree_args(pl, N, opts, D, P, theta);
+  if (rc != HSMA_OK) return rc;
+  if (!ws || ((uintptr_t)ws & 255) != 0 || (N > 0 && (!x || !y || !z || !q || !phi))) return HSMA_EINVAL;
+  int dev = -1;
+  HSMA_HIP(hipGetDevice(&dev));
+  if (dev != pl->device) return HSMA_ESTATE;
+  Layout L = layout(pl->self, 1, N, N, false, true);
+  L.upto_fit = true;
+  TreeLayout T;
+  rc = tree_layout(N, D, P, L.total, T);
+  if (rc != HSMA_OK) return rc;
+  if (ws_bytes < T.total) return HSMA_EINVAL;
+  char *w = (char *)ws;
+  if (N == 0) {
+    if (E) k_tree_esum<<<1, 256, 0, st>>>(0, nullptr, E);
+    HSMA_HIP(hipGetLastError());
+    return HSMA_OK;
+  }
+  rc = run_front(pl->self, L, N, x, y, z, q, w, st);
+  if (rc != HSMA_OK) return rc;
+  const int n = (int)N;
+  const float4 *img = (const float4 *)(w + L.img);
+  const float4 *tgt = (const float4 *)(w + L.tgt);
+  const double *self = (const double *)(w + L.self);
+  const float2 *qd = (const float2 *)(w + L.qd);
+  unsigned *codes_a = (unsigned *)(w + T.codes_a), *codes_b = (unsigned *)(w + T.codes_b);
+  int *ids_a = (int *)(w + T.ids_a), *ids_b = (int *)(w + T.ids_b);
+  float4 *simg = (float4 *)(w + T.simg), *stgt = (float4 *)(w + T.stgt);
+  int *inv = (int *)(w + T.inv), *flags = (int *)(w + T.flags), *scan = (int *)(w + T.scan);
+  int *ncell = (int *)(w + T.ncell);
+  const float Lc = (float)(TR_CUBE * pl->a);
+  const int nb = (int)cdivl(n, 256);
+  k_tree_keys<<<nb, 256, 0, st>>>(n, D, Lc, img, codes_a, ids_a);
+  size_t tb = T.temp_bytes;
+  HSMA_HIP(rocprim::radix_sort_pairs(w + T.temp, tb, codes_a, codes_b, ids_a, ids_b, (unsigned)n, 0, 31, st));
+  k_tree_gather<<<nb, 256, 0, st>>>(n, ids_b, img, tgt, simg, stgt, inv);
+  // levels from the leaves up
+  for (int l = D; l >= 0; --l) {
+    const int64_t cap_src = l == D ? N : T.cap[l + 1];
+    const unsigned *src_key = l == D ? codes_b : (const unsigned *)(w + T.key[l + 1]);
+    const int *src_start = l == D ? nullptr : (const int *)(w + T.start[l + 1]);
+    const int *m_dev = l == D ? nullptr : ncell + (l + 1);
+    const int shift = l == D ? 0 : 3;
+    const int gsrc = (int)cdivl(cap_src, 256);
+    k_tree_flags<<<gsrc, 256, 0, st>>>((int)cap_src, m_dev, n, src_key, shift, flags);
+    size_t sb = T.temp_bytes;
+    HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, flags, scan, 0, (size_t)cap_src, rocprim::plus<int>(), st));
+    k_tree_cells<<<gsrc, 256, 0, st>>>((int)cap_src, m_dev, n, n, src_key, shift, src_start, flags, scan,
+                                       (unsigned *)(w + T.key[l]), (int *)(w + T.child[l]), (int *)(w + T.start[l]),
+                                       ncell + l);
+  }
+  TreeLevels TL;
+  for (int l = 0; l <= D; ++l) {
+    const int gm = (int)cdivl(T.cap[l], 4);
+    if (P == 2)
+      k_tree_moments<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, (const unsigned *)(w + T.key[l]),
+                                             (const int *)(w + T.start[l]), simg, (float4 *)(w + T.cen[l]),
+                                             (float *)(w + T.mom[l]));
+    else if (P == 4)
+      k_tree_moments<4><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, (const unsigned *)(w + T.key[l]),
+                                             (const int *)(w + T.start[l]), simg, (float4 *)(w + T.cen[l]),
+                                             (float *)(w + T.mom[l]));
+    else
+      k_tree_moments<6><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, (const unsigned *)(w + T.key[l]),
+                                             (const int *)(w + T.start[l]), simg, (float4 *)(w + T.cen[l]),
+                                             (float *)(w + T.mom[l]));
+    TL.key[l] = (const unsigned *)(w + T.key[l]);
+    TL.start[l] = (const int *)(w + T.start[l]);
+    TL.child[l] = (const int *)(w + T.child[l]);
+    TL.cen[l] = (const float4 *)(w + T.cen[l]);
+    TL.mom[l] = (const float *)(w + T.mom[l]);
+  }
+  TL.ncell = ncell;
+  k_tree_groups<<<T.ngroups, 64, 0, st>>>(n, stgt, (float4 *)(w + T.grp));
+  const hsma_group_s *grp = pl->self;
+  const int ge = (int)cdivl(T.ngroups, TR_WAVES);
+  const float4 *gp = (const float4 *)(w + T.grp);
+  if (P == 2)
+    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, gp, self, grp->P_ev,
+                                                 grp->dipole == 2, grp->nodes32, qd, phi);
+  else if (P == 4)
+    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, gp, self, grp->P_ev,
+                                                 grp->dipole == 2, grp->nodes32, qd, phi);
+  else
+    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, gp, self, grp->P_ev,
+                                                 grp->dipole == 2, grp->nodes32, qd, phi);
+  if (E) {
+    double *ep = (double *)(w + T.ep);
+    k_tree_epart<<<nb, 256, 0, st>>>(n, q, phi, ep);
+    k_tree_esum<<<1, 256, 0, st>>>(nb, ep, E);
+  }
+  HSMA_HIP(hipGetLastError());
+  return HSMA_OK;
+}
