@@ -75,9 +75,9 @@ def main() -> int:
     ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood,accuracy,single_layer",
+    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood,accuracy,single_layer,tree",
                     help="extra workloads after the headline one: batched, serving, sweep, field, kirkwood, "
-                         "accuracy, single_layer (comma list, or none)")
+                         "accuracy, single_layer, tree (comma list, or none)")
     ap.add_argument("--settle-s", type=float, default=1.0,
                     help="seconds of untimed steps before the warm-up steps, so that the device has left its idle "
                          "clock state when timing starts (the first steps after idle run about 8%% slower)")
@@ -274,6 +274,8 @@ def main() -> int:
         out["accuracy"] = leg_accuracy(args, checks)
     if "single_layer" in legs:
         out["single_layer"] = leg_single_layer(args, checks)
+    if "tree" in legs:
+        out["tree"] = leg_tree(args, checks)
     if checks is not None:
         leg_cpu_baseline(checks)
     print(json.dumps(out), flush=True)
@@ -857,6 +859,67 @@ def leg_cpu_baseline(checks: OracleChecks) -> None:
                     for r_s in d["r_s"]})
         else:
             raise ValueError(kind)
+
+
+def leg_tree(args, checks) -> dict:
+    """The treecode far field on N = 1e6 ions uniform in a = 200 (the precision-sweep system:
+    charges +-1/+-2, eps1 = 1, eps2 = 80, kappa = 0.1, P = 6400, M = 9600, compensated FP32
+    pairs): time per call for several (order, theta) beside the direct path, and the potentials
+    of 256 sampled ions handed to the oracle checks."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.workload_c3()
+    s = wl.systems[0]
+    d = wl.disc
+    N = s.n
+    x, y, z, q = (torch.tensor(v, dtype=torch.float64, device=dev) for v in (s.x, s.y, s.z, s.q))
+    rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 20))
+    idx = np.sort(rng.choice(N, 256, replace=False))
+    idx_d = torch.tensor(idx, dtype=torch.int64, device=dev)
+    plan = hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec="fp32c")
+    phi = torch.empty(N, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    res = {"workload": "N=1e6 uniform in a=200, charges +-1/+-2 (2:1), eps1=1, eps2=80, kappa=0.1, P=6400, M=9600, "
+                       "p=40, compensated FP32 pairs"}
+    sampled = {}
+    runs = [("direct", None), ("tree_order4_theta0.5", (4, 0.5)), ("tree_order6_theta0.4", (6, 0.4)),
+            ("tree_order6_theta0.3", (6, 0.3))]
+    for label, cfg in runs:
+        if cfg is None:
+            def call():
+                plan.energy(x, y, z, q, phi=phi, E=E)
+        else:
+            def call(cfg=cfg):
+                plan.energy_tree(x, y, z, q, order=cfg[0], theta=cfg[1], phi=phi, E=E)
+        call()
+        torch.cuda.synchronize()
+        assert plan.stream_check() == 0
+        t0 = time.perf_counter()
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / 3
+        sampled[label] = phi[idx_d].cpu().numpy()
+        res[label] = {"ms_per_call": ms, "E": float(E.cpu().numpy()[0])}
+        log(f"bench[tree]: {label}: {ms:.1f} ms/call")
+    for label, _ in runs[1:]:
+        res[label]["speedup_vs_direct"] = res["direct"]["ms_per_call"] / res[label]["ms_per_call"]
+        res[label]["rel_err_energy_vs_direct"] = abs(res[label]["E"] - res["direct"]["E"]) / abs(res["direct"]["E"])
+    if checks is not None:
+        def report(r):
+            for label, _ in runs:
+                res[label]["rel_err_phi_l2_sampled"] = r["rel_phi"][label]
+            log("bench[tree]: oracle on 256 sampled ions: rel L2 " +
+                ", ".join(f"{lb} {r['rel_phi'][lb]:.2e}" for lb, _ in runs))
+
+        checks.add("sampled", report, info=plan.info, system=(s.x, s.y, s.z, s.q), idx=idx, phis=sampled)
+    plan.close()
+    return res
 
 
 def leg_serving(args) -> dict:

@@ -191,13 +191,14 @@ __global__ __launch_bounds__(256) void k_tree_moments(int cap, const int *__rest
   const unsigned k = key[c];
   const int s0 = start[c], s1 = start[c + 1];
   const bool far = (k >> (3 * level)) != 0;  // cube cells of level l have keys below 8^l
-  float cx = 0.f, cy = 0.f, cz = 0.f;
-  if (!far) {
-    const float h = 2.0f * L / (float)(1 << level);
-    cx = -L + ((float)compact3(k) + 0.5f) * h;
-    cy = -L + ((float)compact3(k >> 1) + 0.5f) * h;
-    cz = -L + ((float)compact3(k >> 2) + 0.5f) * h;
+  if (far) {  // never accepted: no moments
+    if (lane == 0) cen[c] = make_float4(0.f, 0.f, 0.f, INFINITY);
+    return;
   }
+  const float h = 2.0f * L / (float)(1 << level);
+  const float cx = -L + ((float)compact3(k) + 0.5f) * h;
+  const float cy = -L + ((float)compact3(k >> 1) + 0.5f) * h;
+  const float cz = -L + ((float)compact3(k >> 2) + 0.5f) * h;
   float m[NC];
 #pragma unroll
   for (int t = 0; t < NC; ++t) m[t] = 0.0f;
@@ -225,18 +226,102 @@ __global__ __launch_bounds__(256) void k_tree_moments(int cap, const int *__rest
   }
   for (int o = 32; o > 0; o >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, o));
   if (lane == 0) {
-    cen[c] = make_float4(cx, cy, cz, far ? INFINITY : rmax);
+    cen[c] = make_float4(cx, cy, cz, rmax);
 #pragma unroll
     for (int t = 0; t < NC; ++t) mom[(size_t)c * NC + t] = m[t];
   }
 }
 
-// Bounding sphere of each group of 64 consecutive sorted targets.
-__global__ __launch_bounds__(64) void k_tree_groups(int n, const float4 *__restrict__ stgt, float4 *__restrict__ grp) {
+// Moments of the cells of level l < D from their children (level l + 1), about the parent's
+// centre: M_k(parent) = sum over children and j <= k of C(k, j) (c_child - c_parent)^(k - j)
+// M_j(child), with C the product of the three binomial coefficients.  One wave per parent, lanes
+// over k; the radius bound is max over children of |c_child - c_parent| + r_child.
+__device__ __forceinline__ float binom(int n, int k) {
+  float r = 1.0f;
+  for (int i = 1; i <= k; ++i) r = r * (float)(n - k + i) / (float)i;
+  return r;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_tree_m2m(int cap, const int *__restrict__ ncell, int level, float L,
+                                                 const unsigned *__restrict__ key, const int *__restrict__ child,
+                                                 const float4 *__restrict__ ccen, const float *__restrict__ cmom,
+                                                 float4 *__restrict__ cen, float *__restrict__ mom) {
+  constexpr int NC = ncoef(P);
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= cap || c >= *ncell) return;
+  const unsigned kk = key[c];
+  if ((kk >> (3 * level)) != 0) {  // the far cell: never accepted
+    if (lane == 0) cen[c] = make_float4(0.f, 0.f, 0.f, INFINITY);
+    return;
+  }
+  const float h = 2.0f * L / (float)(1 << level);
+  const float cx = -L + ((float)compact3(kk) + 0.5f) * h;
+  const float cy = -L + ((float)compact3(kk >> 1) + 0.5f) * h;
+  const float cz = -L + ((float)compact3(kk >> 2) + 0.5f) * h;
+  const int k0 = child[c], k1 = child[c + 1];
+  float acc[2] = {0.0f, 0.0f};  // coefficients lane and lane + 64
+  float rad = 0.0f;
+  for (int ch = k0; ch < k1; ++ch) {
+    const float4 cc = ccen[ch];
+    const float dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
+    rad = fmaxf(rad, sqrtf(dx * dx + dy * dy + dz * dz) + cc.w);
+    float px[P + 1], py[P + 1], pz[P + 1];
+    px[0] = py[0] = pz[0] = 1.0f;
+    for (int e = 1; e <= P; ++e) {
+      px[e] = px[e - 1] * dx;
+      py[e] = py[e - 1] * dy;
+      pz[e] = pz[e - 1] * dz;
+    }
+    const float *cm = cmom + (size_t)ch * NC;
+    for (int r = 0; r < 2; ++r) {
+      const int k = lane + 64 * r;
+      if (k >= NC) break;
+      const K3 t = kof(k);
+      float v = 0.0f;
+      for (int jx = 0; jx <= t.x; ++jx)
+        for (int jy = 0; jy <= t.y; ++jy)
+          for (int jz = 0; jz <= t.z; ++jz)
+            v = fmaf(binom(t.x, jx) * binom(t.y, jy) * binom(t.z, jz) * px[t.x - jx] * py[t.y - jy] * pz[t.z - jz],
+                     cm[kidx(jx, jy, jz)], v);
+      acc[r] += v;
+    }
+  }
+  for (int r = 0; r < 2; ++r) {
+    const int k = lane + 64 * r;
+    if (k < NC) mom[(size_t)c * NC + k] = acc[r];
+  }
+  if (lane == 0) cen[c] = make_float4(cx, cy, cz, rad);
+}
+
+// Target groups: the sorted targets of each cell of the grouping level in runs of up to 64,
+// so that no group straddles a jump of the space-filling order.  ng[c] = groups of cell c.
+__global__ void k_tree_gcount(int cap, const int *__restrict__ ncell, const int *__restrict__ start,
+                              int *__restrict__ ng) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cap) return;
+  ng[c] = c < *ncell ? (start[c + 1] - start[c] + 63) / 64 : 0;
+}
+
+__global__ void k_tree_gfill(int cap, const int *__restrict__ ncell, const int *__restrict__ start,
+                             const int *__restrict__ ng, const int *__restrict__ gofs, int2 *__restrict__ gr,
+                             int *__restrict__ ngroups) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nc = *ncell;
+  if (c == 0) *ngroups = nc > 0 ? gofs[nc - 1] + ng[nc - 1] : 0;
+  if (c >= cap || c >= nc) return;
+  const int s0 = start[c], cnt = start[c + 1] - s0;
+  for (int k = 0; k < ng[c]; ++k) gr[gofs[c] + k] = make_int2(s0 + 64 * k, min(64, cnt - 64 * k));
+}
+
+// Bounding sphere of each target group.
+__global__ __launch_bounds__(64) void k_tree_groups(const int *__restrict__ ngroups, const int2 *__restrict__ gr,
+                                                    const float4 *__restrict__ stgt, float4 *__restrict__ grp) {
   const int g = blockIdx.x, lane = threadIdx.x;
-  const int s = g * 64 + lane;
-  const bool in = s < n;
-  const float4 t = in ? stgt[s] : stgt[g * 64];
+  if (g >= *ngroups) return;
+  const int2 rg = gr[g];
+  const bool in = lane < rg.y;
+  const float4 t = stgt[rg.x + (in ? lane : 0)];
   float lo[3] = {t.x, t.y, t.z}, hi[3] = {t.x, t.y, t.z};
   for (int o = 32; o > 0; o >>= 1)
     for (int d = 0; d < 3; ++d) {
@@ -280,6 +365,8 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, int D, float
                                                             const float4 *__restrict__ simg,
                                                             const float4 *__restrict__ stgt,
                                                             const int *__restrict__ perm,
+                                                            const int *__restrict__ ngroups,
+                                                            const int2 *__restrict__ gr,
                                                             const float4 *__restrict__ grp,
                                                             const double *__restrict__ self, int Pn, int mono,
                                                             const float4 *__restrict__ nodes,
@@ -288,10 +375,11 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, int D, float
   __shared__ int stack[TR_WAVES][TR_STACK];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = blockIdx.x * TR_WAVES + w;
-  if (g * 64 >= n) return;
-  const int s = g * 64 + lane;
-  const bool in = s < n;
-  const float4 t = stgt[in ? s : g * 64];
+  if (g >= *ngroups) return;
+  const int2 gg = gr[g];
+  const bool in = lane < gg.y;
+  const int s = gg.x + (in ? lane : 0);
+  const float4 t = stgt[s];
   const int own = in ? s : -1;
   const float4 G = grp[g];
   // the far set: the leaf level's last cell when its key lies beyond the cube's 8^D cells
@@ -386,8 +474,8 @@ inline int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int auto_depth(int64_t n) {
-  // about 30-120 images per occupied leaf near the interface for uniformly filled cavities
-  const double d = 8.0 + (std::log2((double)(n > 1 ? n : 1)) - std::log2(1e6)) / 3.0;
+  // the fastest depth measured on uniformly filled cavities: 7 at N = 10^6, 6 at 2 10^5
+  const double d = 7.0 + (std::log2((double)(n > 1 ? n : 1)) - std::log2(1e6)) / 3.0;
   int D = (int)std::lround(d);
   return D < 2 ? 2 : (D > TR_MAX_DEPTH - 1 ? TR_MAX_DEPTH - 1 : D);
 }
@@ -395,7 +483,8 @@ int auto_depth(int64_t n) {
 struct TreeLayout {
   int D, P, nc, ngroups;
   int64_t cap[TR_MAX_DEPTH + 1];
-  size_t codes_a, codes_b, ids_a, ids_b, simg, stgt, inv, flags, scan, grp, ncell, ep, temp, temp_bytes;
+  size_t codes_a, codes_b, ids_a, ids_b, simg, stgt, inv, flags, scan, grp, gr, gng, gofs, ncell, ep, temp,
+      temp_bytes;
   size_t key[TR_MAX_DEPTH + 1], start[TR_MAX_DEPTH + 1], child[TR_MAX_DEPTH + 1], cen[TR_MAX_DEPTH + 1],
       mom[TR_MAX_DEPTH + 1];
   size_t total;
@@ -405,7 +494,6 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
   T.D = D;
   T.P = P;
   T.nc = ncoef(P);
-  T.ngroups = (int)cdivl(n, 64);
   size_t o = al256(base);
   auto take = [&](size_t b) {
     const size_t at = o;
@@ -422,13 +510,22 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
   T.inv = take(4 * N);
   T.flags = take(4 * N);
   T.scan = take(4 * N);
-  T.grp = take(16 * (size_t)T.ngroups);
-  T.ncell = take(4 * (TR_MAX_DEPTH + 1));
+
+  T.ncell = take(4 * (TR_MAX_DEPTH + 2));  // cells per level, then the number of target groups
   T.ep = take(8 * (size_t)cdivl(n, 256));
   for (int l = 0; l <= D; ++l) {
     int64_t c = (int64_t)1 << (3 * l);
     c = (c + 1 < (int64_t)N ? c + 1 : (int64_t)N);  // level l holds at most 8^l cube cells and the far cell
     T.cap[l] = c;
+  }
+  // target groups: at most one partial group per cell of the grouping level D - 1
+  T.ngroups = (int)(cdivl(n, 64) + T.cap[D - 1]);
+  T.grp = take(16 * (size_t)T.ngroups);
+  T.gr = take(8 * (size_t)T.ngroups);
+  T.gng = take(4 * (size_t)T.cap[D - 1]);
+  T.gofs = take(4 * (size_t)T.cap[D - 1]);
+  for (int l = 0; l <= D; ++l) {
+    const int64_t c = T.cap[l];
     T.key[l] = take(4 * (size_t)c);
     T.start[l] = take(4 * ((size_t)c + 1));
     T.child[l] = take(4 * ((size_t)c + 1));
@@ -533,39 +630,65 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
                                        ncell + l);
   }
   TreeLevels TL;
-  for (int l = 0; l <= D; ++l) {
+  for (int l = D; l >= 0; --l) {
     const int gm = (int)cdivl(T.cap[l], 4);
-    if (P == 2)
-      k_tree_moments<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, (const unsigned *)(w + T.key[l]),
-                                             (const int *)(w + T.start[l]), simg, (float4 *)(w + T.cen[l]),
-                                             (float *)(w + T.mom[l]));
-    else if (P == 4)
-      k_tree_moments<4><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, (const unsigned *)(w + T.key[l]),
-                                             (const int *)(w + T.start[l]), simg, (float4 *)(w + T.cen[l]),
-                                             (float *)(w + T.mom[l]));
-    else
-      k_tree_moments<6><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, (const unsigned *)(w + T.key[l]),
-                                             (const int *)(w + T.start[l]), simg, (float4 *)(w + T.cen[l]),
-                                             (float *)(w + T.mom[l]));
-    TL.key[l] = (const unsigned *)(w + T.key[l]);
+    const unsigned *kl = (const unsigned *)(w + T.key[l]);
+    float4 *cl = (float4 *)(w + T.cen[l]);
+    float *ml = (float *)(w + T.mom[l]);
+    if (l == D) {  // leaves: moments from their images
+      if (P == 2)
+        k_tree_moments<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
+                                               simg, cl, ml);
+      else if (P == 4)
+        k_tree_moments<4><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
+                                               simg, cl, ml);
+      else
+        k_tree_moments<6><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
+                                               simg, cl, ml);
+    } else {  // upper levels: translated from the children
+      const int *chl = (const int *)(w + T.child[l]);
+      const float4 *cc = (const float4 *)(w + T.cen[l + 1]);
+      const float *cm = (const float *)(w + T.mom[l + 1]);
+      if (P == 2)
+        k_tree_m2m<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+      else if (P == 4)
+        k_tree_m2m<4><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+      else
+        k_tree_m2m<6><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+    }
+    TL.key[l] = kl;
     TL.start[l] = (const int *)(w + T.start[l]);
     TL.child[l] = (const int *)(w + T.child[l]);
-    TL.cen[l] = (const float4 *)(w + T.cen[l]);
-    TL.mom[l] = (const float *)(w + T.mom[l]);
+    TL.cen[l] = cl;
+    TL.mom[l] = ml;
   }
   TL.ncell = ncell;
-  k_tree_groups<<<T.ngroups, 64, 0, st>>>(n, stgt, (float4 *)(w + T.grp));
+  {
+    const int lg = D - 1;  // grouping level
+    const int gc = (int)cdivl(T.cap[lg], 256);
+    int *gng = (int *)(w + T.gng), *gofs = (int *)(w + T.gofs);
+    k_tree_gcount<<<gc, 256, 0, st>>>((int)T.cap[lg], ncell + lg, (const int *)(w + T.start[lg]), gng);
+    size_t sb = T.temp_bytes;
+    HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, gng, gofs, 0, (size_t)T.cap[lg], rocprim::plus<int>(), st));
+    k_tree_gfill<<<gc, 256, 0, st>>>((int)T.cap[lg], ncell + lg, (const int *)(w + T.start[lg]), gng, gofs,
+                                     (int2 *)(w + T.gr), ncell + TR_MAX_DEPTH + 1);
+    k_tree_groups<<<T.ngroups, 64, 0, st>>>(ncell + TR_MAX_DEPTH + 1, (const int2 *)(w + T.gr), stgt,
+                                            (float4 *)(w + T.grp));
+  }
   const hsma_group_s *grp = pl->self;
   const int ge = (int)cdivl(T.ngroups, TR_WAVES);
   const float4 *gp = (const float4 *)(w + T.grp);
   if (P == 2)
-    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, gp, self, grp->P_ev,
+    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, ncell + TR_MAX_DEPTH + 1,
+                                                 (const int2 *)(w + T.gr), gp, self, grp->P_ev,
                                                  grp->dipole == 2, grp->nodes32, qd, phi);
   else if (P == 4)
-    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, gp, self, grp->P_ev,
+    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, ncell + TR_MAX_DEPTH + 1,
+                                                 (const int2 *)(w + T.gr), gp, self, grp->P_ev,
                                                  grp->dipole == 2, grp->nodes32, qd, phi);
   else
-    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, gp, self, grp->P_ev,
+    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, ncell + TR_MAX_DEPTH + 1,
+                                                 (const int2 *)(w + T.gr), gp, self, grp->P_ev,
                                                  grp->dipole == 2, grp->nodes32, qd, phi);
   if (E) {
     double *ep = (double *)(w + T.ep);
