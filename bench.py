@@ -887,8 +887,8 @@ def leg_tree(args, checks) -> dict:
     res = {"workload": "N=1e6 uniform in a=200, charges +-1/+-2 (2:1), eps1=1, eps2=80, kappa=0.1, P=6400, M=9600, "
                        "p=40, compensated FP32 pairs"}
     sampled = {}
-    runs = [("direct", None), ("tree_order4_theta0.5", (4, 0.5)), ("tree_order6_theta0.4", (6, 0.4)),
-            ("tree_order6_theta0.3", (6, 0.3))]
+    runs = [("direct", None), ("tree_order4_theta0.5", (4, 0.5)), ("tree_order6_theta0.5", (6, 0.5)),
+            ("tree_order6_theta0.4", (6, 0.4)), ("tree_order6_theta0.3", (6, 0.3))]
     for label, cfg in runs:
         if cfg is None:
             def call():

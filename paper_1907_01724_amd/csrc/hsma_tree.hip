@@ -236,12 +236,6 @@ __global__ __launch_bounds__(256) void k_tree_moments(int cap, const int *__rest
 // centre: M_k(parent) = sum over children and j <= k of C(k, j) (c_child - c_parent)^(k - j)
 // M_j(child), with C the product of the three binomial coefficients.  One wave per parent, lanes
 // over k; the radius bound is max over children of |c_child - c_parent| + r_child.
-__device__ __forceinline__ float binom(int n, int k) {
-  float r = 1.0f;
-  for (int i = 1; i <= k; ++i) r = r * (float)(n - k + i) / (float)i;
-  return r;
-}
-
 template <int P>
 __global__ __launch_bounds__(256) void k_tree_m2m(int cap, const int *__restrict__ ncell, int level, float L,
                                                  const unsigned *__restrict__ key, const int *__restrict__ child,
@@ -266,24 +260,29 @@ __global__ __launch_bounds__(256) void k_tree_m2m(int cap, const int *__restrict
     const float4 cc = ccen[ch];
     const float dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
     rad = fmaxf(rad, sqrtf(dx * dx + dy * dy + dz * dz) + cc.w);
-    float px[P + 1], py[P + 1], pz[P + 1];
-    px[0] = py[0] = pz[0] = 1.0f;
-    for (int e = 1; e <= P; ++e) {
-      px[e] = px[e - 1] * dx;
-      py[e] = py[e - 1] * dy;
-      pz[e] = pz[e - 1] * dz;
-    }
     const float *cm = cmom + (size_t)ch * NC;
     for (int r = 0; r < 2; ++r) {
       const int k = lane + 64 * r;
       if (k >= NC) break;
       const K3 t = kof(k);
-      float v = 0.0f;
-      for (int jx = 0; jx <= t.x; ++jx)
-        for (int jy = 0; jy <= t.y; ++jy)
-          for (int jz = 0; jz <= t.z; ++jz)
-            v = fmaf(binom(t.x, jx) * binom(t.y, jy) * binom(t.z, jz) * px[t.x - jx] * py[t.y - jy] * pz[t.z - jz],
-                     cm[kidx(jx, jy, jz)], v);
+      // j from k down to 0 in each component: binomial C(k_i, j_i) and power d_i^(k_i - j_i)
+      // carried along, so that nothing is indexed at run time
+      float v = 0.0f, bx = 1.0f, wx = 1.0f;
+      for (int jx = t.x; jx >= 0; --jx) {
+        float by = 1.0f, wy = 1.0f;
+        for (int jy = t.y; jy >= 0; --jy) {
+          float bz = 1.0f, wz = 1.0f;
+          for (int jz = t.z; jz >= 0; --jz) {
+            v = fmaf(bx * by * bz * (wx * wy * wz), cm[kidx(jx, jy, jz)], v);
+            bz = bz * (float)jz / (float)(t.z - jz + 1);
+            wz *= dz;
+          }
+          by = by * (float)jy / (float)(t.y - jy + 1);
+          wy *= dy;
+        }
+        bx = bx * (float)jx / (float)(t.x - jx + 1);
+        wx *= dx;
+      }
       acc[r] += v;
     }
   }
