@@ -300,10 +300,11 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  *   theta: in [0, 1); 0 accepts no cell (every image is then summed directly, the check of the
  *          traversal); order: 2, 4 or 6; depth: 2..9, or 0 for a depth from N (about 8 at
  *          N = 10^6).
- * The error is the treecode's: relative L2 errors of the Kelvin sum of about 2e-3 (order 4,
- * theta 0.5) to 2e-6 (order 12) on uniformly filled cavities with balanced charges; the
- * method's own 1e-6 target needs high orders, at which the direct symmetric sums of
- * hsma_energy are faster below about 10^7 ions on one device.
+ * The error is the treecode's. On 10^6 ions uniform in a cavity with balanced charges, the
+ * relative L2 errors of the potentials are 1e-3 (order 4, theta 0.5), 1e-4 (order 6, theta 0.5),
+ * 1.5e-5 (order 6, theta 0.4) and 1.6e-6 (order 6, theta 0.3).  Against the direct symmetric sums
+ * of hsma_energy these run 5.6, 3.1, 2.1 and 1.05 times faster; below a few 10^5 ions the direct
+ * path is faster at any setting.
  *   phi: [device] N doubles (required); E: [device] one double or NULL;
  *   ws: [device] ws_bytes >= hsma_tree_workspace_bytes(plan, N, opts) (0 for invalid arguments).
  * Errors: HSMA_EINVAL (also for the FP64 pair mode), HSMA_ESTATE, HSMA_EDEVICE. */
