@@ -307,6 +307,9 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  * path is faster at any setting.
  *   phi: [device] N doubles (required); E: [device] one double or NULL;
  *   ws: [device] ws_bytes >= hsma_tree_workspace_bytes(plan, N, opts) (0 for invalid arguments).
+ * Like the other compute calls it allocates nothing and does not synchronise; unlike them it
+ * is not meant for graph capture, since its radix sort and scans (rocPRIM, with their
+ * temporary storage in ws) may enqueue memory fills.
  * Errors: HSMA_EINVAL (also for the FP64 pair mode), HSMA_ESTATE, HSMA_EDEVICE. */
 typedef struct {
   double theta;
