@@ -17,8 +17,11 @@
 // leaves that are not accepted are summed directly, the ion's own image excluded (it is the
 // analytic FP64 term of the packing kernel).  If an ion's own image lies in an accepted cell,
 // its exact FP32 term is subtracted again.  theta = 0 accepts nothing: the traversal then sums
-// every image directly.  The targets are the ions in the images' sorted order, so a group of
-// 64 consecutive targets is compact wherever the Kelvin map is (everywhere but the centre).
+// every image directly.  The targets are grouped by their own positions, not by their images:
+// sorted by Morton code in [-a, a]^3 and cut into runs of up to 64 within the cells of a coarse
+// level, so that groups are compact and nearly full everywhere in the cavity.  (Grouped by their
+// images' cells, the ions near the centre, whose images are spread thinly far out, formed groups
+// of one or two targets, each with a whole traversal.)
 //
 // The check sums, the fit and the surface strengths are those of the direct path
 // (run_front); the surface nodes are summed directly per target after the traversal.
@@ -37,6 +40,7 @@ constexpr int TR_STACK = 96;            // traversal stack entries per wave (>= 
 constexpr int TR_MAX_DEPTH = 10;        // codes of 3 D bits plus the far flag fit in 31 bits
 constexpr unsigned TR_FAR = 1u << 30;   // code of an image outside the cube
 constexpr double TR_CUBE = 8.0;         // cube half-width in units of a
+constexpr int TR_TBITS = 10;            // bits per axis of the targets' codes in [-a, a]^3
 
 // Graded multi-index order: degree n, then kx descending, then ky descending.
 constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
@@ -131,16 +135,39 @@ __global__ void k_tree_keys(int n, int D, float L, const float4 *__restrict__ im
   ids[i] = i;
 }
 
-// Sorted images and targets; inv[i] = sorted position of ion i.
+// Sorted images; inv[i] = sorted position of ion i's image.
 __global__ void k_tree_gather(int n, const int *__restrict__ perm, const float4 *__restrict__ img,
-                              const float4 *__restrict__ tgt, float4 *__restrict__ simg, float4 *__restrict__ stgt,
-                              int *__restrict__ inv) {
+                              float4 *__restrict__ simg, int *__restrict__ inv) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = perm[s];
   simg[s] = img[i];
-  stgt[s] = tgt[i];
   inv[i] = s;
+}
+
+// Codes of the targets (the ions) in the cube [-a, a]^3 at TR_TBITS bits per axis.
+__global__ void k_tree_tkeys(int n, float a, const float4 *__restrict__ tgt, unsigned *__restrict__ codes,
+                             int *__restrict__ ids) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 v = tgt[i];
+  const float sc = (float)(1 << TR_TBITS) / (2.0f * a);
+  const int m = (1 << TR_TBITS) - 1;
+  const int ix = min(m, max(0, (int)((v.x + a) * sc)));
+  const int iy = min(m, max(0, (int)((v.y + a) * sc)));
+  const int iz = min(m, max(0, (int)((v.z + a) * sc)));
+  codes[i] = spread3((unsigned)ix) | (spread3((unsigned)iy) << 1) | (spread3((unsigned)iz) << 2);
+  ids[i] = i;
+}
+
+// Targets in their own sorted order, with the sorted position of each one's image.
+__global__ void k_tree_tgather(int n, const int *__restrict__ tperm, const float4 *__restrict__ tgt,
+                               const int *__restrict__ inv, float4 *__restrict__ stgt, int *__restrict__ town) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int i = tperm[s];
+  stgt[s] = tgt[i];
+  town[s] = inv[i];
 }
 
 // Run-length flags of the level-l keys: from the sorted codes (leaf level, src_key = codes,
@@ -293,8 +320,8 @@ __global__ __launch_bounds__(256) void k_tree_m2m(int cap, const int *__restrict
   if (lane == 0) cen[c] = make_float4(cx, cy, cz, rad);
 }
 
-// Target groups: the sorted targets of each cell of the grouping level in runs of up to 64,
-// so that no group straddles a jump of the space-filling order.  ng[c] = groups of cell c.
+// Target groups: the sorted targets of each cell of the targets' grouping level in runs of up
+// to 64, so that no group straddles a jump of the space-filling order.  ng[c] = groups of cell c.
 __global__ void k_tree_gcount(int cap, const int *__restrict__ ncell, const int *__restrict__ start,
                               int *__restrict__ ng) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -333,36 +360,98 @@ __global__ __launch_bounds__(64) void k_tree_groups(const int *__restrict__ ngro
   if (lane == 0) grp[g] = make_float4(cx, cy, cz, r);
 }
 
-struct TreeLevels {
-  const unsigned *key[TR_MAX_DEPTH + 1];
-  const int *start[TR_MAX_DEPTH + 1], *child[TR_MAX_DEPTH + 1];
-  const float4 *cen[TR_MAX_DEPTH + 1];
-  const float *mom[TR_MAX_DEPTH + 1];
-  const int *ncell;  // D + 1 counts
+// One cell of any level, as the traversal reads it: one 32-byte scalar load per visit.  Cells
+// are numbered globally, level by level (level l from off[l]); a leaf has k0 == k1.
+struct __align__(32) CellRec {
+  float cx, cy, cz, r;  // geometric centre and radius bound (+inf for the far cell)
+  int s0, s1;           // sorted images [s0, s1)
+  int k0, k1;           // children [k0, k1), global numbers
 };
 
+// Records of the cells of level l (children of level l + 1 numbered from off_next).
+__global__ void k_tree_pack(int cap, const int *__restrict__ ncell, int leaf, int off_l, int off_next,
+                            const float4 *__restrict__ cen, const int *__restrict__ start,
+                            const int *__restrict__ child, CellRec *__restrict__ rec) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cap || c >= *ncell) return;
+  const float4 cc = cen[c];
+  CellRec r;
+  r.cx = cc.x;
+  r.cy = cc.y;
+  r.cz = cc.z;
+  r.r = cc.w;
+  r.s0 = start[c];
+  r.s1 = start[c + 1];
+  r.k0 = leaf ? 0 : off_next + child[c];
+  r.k1 = leaf ? 0 : off_next + child[c + 1];
+  rec[off_l + c] = r;
+}
+
+template <int U>
+__device__ __forceinline__ void direct_terms(float tx, float ty, float tz, int own, const float4 *__restrict__ simg,
+                                             int j, float &sum) {
+  float4 v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = simg[j + u];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const float dx = tx - v[u].x, dy = ty - v[u].y, dz = tz - v[u].z;
+    float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+    ri = (j + u == own) ? 0.0f : ri;
+    sum = fmaf(v[u].w, ri, sum);
+  }
+}
+
+// sum over the images [s0, s1) but the ion's own, in FP32 blocks of 32 terms added into FP64;
+// the loads are issued four at a time
 __device__ __forceinline__ void direct_range(float tx, float ty, float tz, int own, const float4 *__restrict__ simg,
                                              int s0, int s1, double &acc) {
   for (int sb = s0; sb < s1; sb += 32) {
     const int se = sb + 32 < s1 ? sb + 32 : s1;
     float sum = 0.0f;
-    for (int j = sb; j < se; ++j) {
-      const float4 v = simg[j];
-      const float dx = tx - v.x, dy = ty - v.y, dz = tz - v.z;
-      float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
-      ri = (j == own) ? 0.0f : ri;
-      sum = fmaf(v.w, ri, sum);
-    }
+    int j = sb;
+    for (; j + 4 <= se; j += 4) direct_terms<4>(tx, ty, tz, own, simg, j, sum);
+    for (; j < se; ++j) direct_terms<1>(tx, ty, tz, own, simg, j, sum);
     acc += (double)sum;
   }
 }
 
-// One wave per group of 64 sorted targets: traversal, far set, surface nodes; writes phi in the
-// ions' original order (own-image term included).
+template <int U>
+__device__ __forceinline__ void surface_terms(float tx, float ty, float tz, int mono, const float4 *__restrict__ nodes,
+                                              const float2 *__restrict__ qd, int m, float &sum) {
+  float4 yv[U];
+  float2 wv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    yv[u] = nodes[m + u];
+    wv[u] = qd[m + u];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const float dx = tx - yv[u].x, dy = ty - yv[u].y, dz = tz - yv[u].z;
+    const float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+    if (mono) {
+      sum = fmaf(wv[u].x, ri, sum);
+    } else {
+      const float dot = dx * yv[u].x + dy * yv[u].y + dz * yv[u].z;
+      sum = fmaf(ri, fmaf(wv[u].y * dot, ri * ri, wv[u].x), sum);
+    }
+  }
+}
+
+// One wave per group of up to 64 sorted targets: traversal, far set, surface nodes; writes phi
+// in the ions' original order (own-image term included).  Every decision of the traversal is
+// taken from cell and group data alone, so it is uniform over the wave and runs on the scalar
+// unit; the acceptance test is compared in squares, (r_c + r_g)^2 < theta^2 d^2.
 template <int P>
-__global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, int D, float theta, TreeLevels T,
+__global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2, const CellRec *__restrict__ rec,
+                                                            const float *__restrict__ mom,
+                                                            const unsigned *__restrict__ key0,
+                                                            const int *__restrict__ start0,
+                                                            const int *__restrict__ ncell,
                                                             const float4 *__restrict__ simg,
                                                             const float4 *__restrict__ stgt,
+                                                            const int *__restrict__ town,
                                                             const int *__restrict__ perm,
                                                             const int *__restrict__ ngroups,
                                                             const int2 *__restrict__ gr,
@@ -379,42 +468,43 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, int D, float
   const bool in = lane < gg.y;
   const int s = gg.x + (in ? lane : 0);
   const float4 t = stgt[s];
-  const int own = in ? s : -1;
+  const int own = in ? town[s] : -1;  // sorted position of the target's own image
   const float4 G = grp[g];
-  // the far set: the leaf level's last cell when its key lies beyond the cube's 8^D cells
-  const int nl = T.ncell[D];
-  const int far_start = (nl > 0 && (T.key[D][nl - 1] >> (3 * D)) != 0u) ? T.start[D][nl - 1] : n;
   double acc = 0.0;
   int sp = 0;
-  // the level-0 cells: the cube (key 0) and possibly the far cell, which is summed below
-  const int n0 = T.ncell[0];
-  for (int c = 0; c < n0; ++c)
-    if (T.key[0][c] == 0u) stack[w][sp++] = c;  // level 0 in the top bits
+  // level 0 (cells 0 and 1): the cube, key 0, pushed as the root, and the cell of the images
+  // outside the cube, the far set, summed directly below
+  int far_start = n;
+  const int n0 = ncell[0];
+  for (int c = 0; c < n0; ++c) {
+    if (key0[c] == 0u)
+      stack[w][sp++] = c;
+    else
+      far_start = start0[c];
+  }
   while (sp > 0) {
-    const int e = __builtin_amdgcn_readfirstlane(stack[w][--sp]);
-    const int l = e >> 27, c = e & ((1 << 27) - 1);
-    const float4 cc = T.cen[l][c];
-    const int c0 = T.start[l][c], c1 = T.start[l][c + 1];
-    const float dx = cc.x - G.x, dy = cc.y - G.y, dz = cc.z - G.z;
-    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
-    if (cc.w + G.w < theta * d) {
+    const int c = __builtin_amdgcn_readfirstlane(stack[w][--sp]);
+    const CellRec rc = rec[c];
+    const float dx = rc.cx - G.x, dy = rc.cy - G.y, dz = rc.cz - G.z;
+    const float rs = rc.r + G.w;
+    const int accept = __builtin_amdgcn_readfirstlane((int)(rs * rs < theta2 * (dx * dx + dy * dy + dz * dz)));
+    if (accept) {
       float a[NC];
-      taylor<P>(t.x - cc.x, t.y - cc.y, t.z - cc.z, a);
-      const float *m = T.mom[l] + (size_t)c * NC;
+      taylor<P>(t.x - rc.cx, t.y - rc.cy, t.z - rc.cz, a);
+      const float *m = mom + (size_t)c * NC;
       float v = 0.0f;
 #pragma unroll
       for (int k = 0; k < NC; ++k) v = fmaf(a[k], m[k], v);
-      if (own >= c0 && own < c1) {  // the ion's own image is in the cell: take its term out again
+      if (own >= rc.s0 && own < rc.s1) {  // the ion's own image is in the cell: take its term out again
         const float4 o = simg[own];
         const float ox = t.x - o.x, oy = t.y - o.y, oz = t.z - o.z;
         v -= o.w * __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
       }
       acc += (double)v;
-    } else if (l == D) {
-      direct_range(t.x, t.y, t.z, own, simg, c0, c1, acc);
+    } else if (rc.k0 == rc.k1) {  // a leaf
+      direct_range(t.x, t.y, t.z, own, simg, rc.s0, rc.s1, acc);
     } else {
-      const int k0 = T.child[l][c], k1 = T.child[l][c + 1];
-      for (int k = k1 - 1; k >= k0 && sp < TR_STACK; --k) stack[w][sp++] = ((l + 1) << 27) | k;
+      for (int k = rc.k1 - 1; k >= rc.k0 && sp < TR_STACK; --k) stack[w][sp++] = k;
     }
   }
   if (far_start < n) direct_range(t.x, t.y, t.z, own, simg, far_start, n, acc);
@@ -422,18 +512,9 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, int D, float
   for (int sb = 0; sb < Pn; sb += 32) {
     const int se = sb + 32 < Pn ? sb + 32 : Pn;
     float sum = 0.0f;
-    for (int m = sb; m < se; ++m) {
-      const float4 yv = nodes[m];
-      const float2 wv = qd[m];
-      const float dx = t.x - yv.x, dy = t.y - yv.y, dz = t.z - yv.z;
-      const float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
-      if (mono) {
-        sum = fmaf(wv.x, ri, sum);
-      } else {
-        const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
-        sum = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum);
-      }
-    }
+    int m = sb;
+    for (; m + 4 <= se; m += 4) surface_terms<4>(t.x, t.y, t.z, mono, nodes, qd, m, sum);
+    for (; m < se; ++m) surface_terms<1>(t.x, t.y, t.z, mono, nodes, qd, m, sum);
     acc += (double)sum;
   }
   if (in) {
@@ -471,10 +552,12 @@ __global__ __launch_bounds__(256) void k_tree_esum(int nb, const double *__restr
 
 inline int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Level whose cells the target groups may not cross: one above the leaves.  Groups there are
-// only about 25 targets full on average at the depth rule below, yet grouping two levels up
-// was slower (the larger group radii open more cells: C3, order 4, theta 0.5, 21.7 -> 27 ms).
-inline int group_level(int D) { return D - 1; }
+// Level of the targets' cells in [-a, a]^3 that no group crosses: about 8 groups of 64 per cell
+// of a uniformly filled cavity (the ball fills pi/6 of the cube), so that groups are nearly full.
+int target_level(int64_t n) {
+  const int l = (int)std::lround(std::log2((double)(n > 1 ? n : 1) / 200.0) / 3.0);
+  return l < 0 ? 0 : (l > TR_TBITS ? TR_TBITS : l);
+}
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int auto_depth(int64_t n) {
@@ -485,12 +568,13 @@ int auto_depth(int64_t n) {
 }
 
 struct TreeLayout {
-  int D, P, nc, ngroups;
-  int64_t cap[TR_MAX_DEPTH + 1];
-  size_t codes_a, codes_b, ids_a, ids_b, simg, stgt, inv, flags, scan, grp, gr, gng, gofs, ncell, ep, temp,
-      temp_bytes;
-  size_t key[TR_MAX_DEPTH + 1], start[TR_MAX_DEPTH + 1], child[TR_MAX_DEPTH + 1], cen[TR_MAX_DEPTH + 1],
-      mom[TR_MAX_DEPTH + 1];
+  int D, P, nc, ngroups, lt;
+  int64_t cap[TR_MAX_DEPTH + 1], tcap;
+  size_t codes_a, codes_b, ids_a, ids_b, codes_t, ids_t, town, simg, stgt, inv, flags, scan, grp, gr, gng, gofs,
+      tkey, tstart, tchild, ncell, ep, temp, temp_bytes;
+  size_t key[TR_MAX_DEPTH + 1], start[TR_MAX_DEPTH + 1], child[TR_MAX_DEPTH + 1], cen[TR_MAX_DEPTH + 1];
+  int64_t off[TR_MAX_DEPTH + 2];  // global number of each level's first cell; off[D + 1] = all cells
+  size_t rec, mom;                // records and moments of every cell, by global number
   size_t total;
 };
 
@@ -509,37 +593,54 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
   T.codes_b = take(4 * N);
   T.ids_a = take(4 * N);
   T.ids_b = take(4 * N);
+  T.codes_t = take(4 * N);
+  T.ids_t = take(4 * N);
+  T.town = take(4 * N);
   T.simg = take(16 * N);
   T.stgt = take(16 * N);
   T.inv = take(4 * N);
   T.flags = take(4 * N);
   T.scan = take(4 * N);
 
-  T.ncell = take(4 * (TR_MAX_DEPTH + 2));  // cells per level, then the number of target groups
+  // cells per level; at TR_MAX_DEPTH + 1 the number of target groups, at + 2 of target cells
+  T.ncell = take(4 * (TR_MAX_DEPTH + 3));
   T.ep = take(8 * (size_t)cdivl(n, 256));
   for (int l = 0; l <= D; ++l) {
     int64_t c = (int64_t)1 << (3 * l);
     c = (c + 1 < (int64_t)N ? c + 1 : (int64_t)N);  // level l holds at most 8^l cube cells and the far cell
     T.cap[l] = c;
   }
-  // target groups: at most one partial group per cell of the grouping level D - 1
-  T.ngroups = (int)(cdivl(n, 64) + T.cap[group_level(D)]);
+  // target cells: at most 8^lt, and at most one per target
+  T.lt = target_level(n);
+  T.tcap = std::min<int64_t>((int64_t)1 << (3 * T.lt), (int64_t)N);
+  T.tkey = take(4 * (size_t)T.tcap);
+  T.tstart = take(4 * ((size_t)T.tcap + 1));
+  T.tchild = take(4 * ((size_t)T.tcap + 1));
+  // target groups: at most one partial group per target cell
+  T.ngroups = (int)(cdivl(n, 64) + T.tcap);
   T.grp = take(16 * (size_t)T.ngroups);
   T.gr = take(8 * (size_t)T.ngroups);
-  T.gng = take(4 * (size_t)T.cap[group_level(D)]);
-  T.gofs = take(4 * (size_t)T.cap[group_level(D)]);
+  T.gng = take(4 * (size_t)T.tcap);
+  T.gofs = take(4 * (size_t)T.tcap);
+  T.off[0] = 0;
   for (int l = 0; l <= D; ++l) {
     const int64_t c = T.cap[l];
     T.key[l] = take(4 * (size_t)c);
     T.start[l] = take(4 * ((size_t)c + 1));
     T.child[l] = take(4 * ((size_t)c + 1));
     T.cen[l] = take(16 * (size_t)c);
-    T.mom[l] = take(4 * (size_t)c * T.nc);
+    T.off[l + 1] = T.off[l] + c;
   }
+  T.rec = take(sizeof(CellRec) * (size_t)T.off[D + 1]);
+  T.mom = take(4 * (size_t)T.off[D + 1] * T.nc);
   size_t sort_b = 0, scan_b = 0;
-  if (rocprim::radix_sort_pairs(nullptr, sort_b, (const unsigned *)nullptr, (unsigned *)nullptr, (const int *)nullptr,
-                                (int *)nullptr, (unsigned)N, 0, 31) != hipSuccess)
-    return HSMA_EDEVICE;
+  for (int bits : {31, 3 * TR_TBITS}) {  // the images' sort, then the targets'
+    size_t b = 0;
+    if (rocprim::radix_sort_pairs(nullptr, b, (const unsigned *)nullptr, (unsigned *)nullptr, (const int *)nullptr,
+                                  (int *)nullptr, (unsigned)N, 0, bits) != hipSuccess)
+      return HSMA_EDEVICE;
+    sort_b = b > sort_b ? b : sort_b;
+  }
   if (rocprim::exclusive_scan(nullptr, scan_b, (const int *)nullptr, (int *)nullptr, 0, N, rocprim::plus<int>()) !=
       hipSuccess)
     return HSMA_EDEVICE;
@@ -560,7 +661,7 @@ static hsma_status tree_args(hsma_plan_t pl, int64_t N, const hsma_tree_opts *op
   if (!(opts->theta >= 0.0 && opts->theta < 1.0)) return HSMA_EINVAL;
   if (opts->order != 2 && opts->order != 4 && opts->order != 6) return HSMA_EINVAL;
   if (opts->depth != 0 && (opts->depth < 2 || opts->depth > TR_MAX_DEPTH - 1)) return HSMA_EINVAL;
-  if (N > ((int64_t)1 << 27) - 1) return HSMA_EINVAL;  // cell indices in 27 bits
+  if (N > ((int64_t)1 << 27) - 1) return HSMA_EINVAL;  // global cell numbers, at most (D + 1) N, in an int
   D = opts->depth ? opts->depth : auto_depth(N);
   P = opts->order;
   theta = (float)opts->theta;
@@ -617,7 +718,7 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
   k_tree_keys<<<nb, 256, 0, st>>>(n, D, Lc, img, codes_a, ids_a);
   size_t tb = T.temp_bytes;
   HSMA_HIP(rocprim::radix_sort_pairs(w + T.temp, tb, codes_a, codes_b, ids_a, ids_b, (unsigned)n, 0, 31, st));
-  k_tree_gather<<<nb, 256, 0, st>>>(n, ids_b, img, tgt, simg, stgt, inv);
+  k_tree_gather<<<nb, 256, 0, st>>>(n, ids_b, img, simg, inv);
   // levels from the leaves up
   for (int l = D; l >= 0; --l) {
     const int64_t cap_src = l == D ? N : T.cap[l + 1];
@@ -633,12 +734,13 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
                                        (unsigned *)(w + T.key[l]), (int *)(w + T.child[l]), (int *)(w + T.start[l]),
                                        ncell + l);
   }
-  TreeLevels TL;
+  float *mom = (float *)(w + T.mom);
+  CellRec *rec = (CellRec *)(w + T.rec);
   for (int l = D; l >= 0; --l) {
     const int gm = (int)cdivl(T.cap[l], 4);
     const unsigned *kl = (const unsigned *)(w + T.key[l]);
     float4 *cl = (float4 *)(w + T.cen[l]);
-    float *ml = (float *)(w + T.mom[l]);
+    float *ml = mom + (size_t)T.off[l] * T.nc;
     if (l == D) {  // leaves: moments from their images
       if (P == 2)
         k_tree_moments<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
@@ -652,7 +754,7 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
     } else {  // upper levels: translated from the children
       const int *chl = (const int *)(w + T.child[l]);
       const float4 *cc = (const float4 *)(w + T.cen[l + 1]);
-      const float *cm = (const float *)(w + T.mom[l + 1]);
+      const float *cm = mom + (size_t)T.off[l + 1] * T.nc;
       if (P == 2)
         k_tree_m2m<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
       else if (P == 4)
@@ -660,40 +762,56 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
       else
         k_tree_m2m<6><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
     }
-    TL.key[l] = kl;
-    TL.start[l] = (const int *)(w + T.start[l]);
-    TL.child[l] = (const int *)(w + T.child[l]);
-    TL.cen[l] = cl;
-    TL.mom[l] = ml;
+    k_tree_pack<<<(int)cdivl(T.cap[l], 256), 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l],
+                                                           (int)T.off[l + 1], cl, (const int *)(w + T.start[l]),
+                                                           (const int *)(w + T.child[l]), rec);
   }
-  TL.ncell = ncell;
   {
-    const int lg = group_level(D);
-    const int gc = (int)cdivl(T.cap[lg], 256);
-    int *gng = (int *)(w + T.gng), *gofs = (int *)(w + T.gofs);
-    k_tree_gcount<<<gc, 256, 0, st>>>((int)T.cap[lg], ncell + lg, (const int *)(w + T.start[lg]), gng);
+    // targets: sorted by their own codes (codes_a and ids_a are free again), cells of level lt,
+    // then groups of up to 64 within each cell
+    unsigned *codes_t = (unsigned *)(w + T.codes_t);
+    int *ids_t = (int *)(w + T.ids_t);
+    k_tree_tkeys<<<nb, 256, 0, st>>>(n, (float)pl->a, tgt, codes_a, ids_a);
+    size_t tb2 = T.temp_bytes;
+    HSMA_HIP(rocprim::radix_sort_pairs(w + T.temp, tb2, codes_a, codes_t, ids_a, ids_t, (unsigned)n, 0,
+                                       3 * TR_TBITS, st));
+    k_tree_tgather<<<nb, 256, 0, st>>>(n, ids_t, tgt, inv, stgt, (int *)(w + T.town));
+    const int tshift = 3 * (TR_TBITS - T.lt);
+    int *tcount = ncell + TR_MAX_DEPTH + 2;
+    k_tree_flags<<<nb, 256, 0, st>>>(n, nullptr, n, codes_t, tshift, flags);
     size_t sb = T.temp_bytes;
-    HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, gng, gofs, 0, (size_t)T.cap[lg], rocprim::plus<int>(), st));
-    k_tree_gfill<<<gc, 256, 0, st>>>((int)T.cap[lg], ncell + lg, (const int *)(w + T.start[lg]), gng, gofs,
-                                     (int2 *)(w + T.gr), ncell + TR_MAX_DEPTH + 1);
+    HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, flags, scan, 0, (size_t)n, rocprim::plus<int>(), st));
+    k_tree_cells<<<nb, 256, 0, st>>>(n, nullptr, n, n, codes_t, tshift, nullptr, flags, scan, (unsigned *)(w + T.tkey),
+                                     (int *)(w + T.tchild), (int *)(w + T.tstart), tcount);
+    const int gc = (int)cdivl(T.tcap, 256);
+    int *gng = (int *)(w + T.gng), *gofs = (int *)(w + T.gofs);
+    const int *tstart = (const int *)(w + T.tstart);
+    k_tree_gcount<<<gc, 256, 0, st>>>((int)T.tcap, tcount, tstart, gng);
+    sb = T.temp_bytes;
+    HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, gng, gofs, 0, (size_t)T.tcap, rocprim::plus<int>(), st));
+    k_tree_gfill<<<gc, 256, 0, st>>>((int)T.tcap, tcount, tstart, gng, gofs, (int2 *)(w + T.gr),
+                                     ncell + TR_MAX_DEPTH + 1);
     k_tree_groups<<<T.ngroups, 64, 0, st>>>(ncell + TR_MAX_DEPTH + 1, (const int2 *)(w + T.gr), stgt,
                                             (float4 *)(w + T.grp));
   }
   const hsma_group_s *grp = pl->self;
   const int ge = (int)cdivl(T.ngroups, TR_WAVES);
   const float4 *gp = (const float4 *)(w + T.grp);
+  const float th2 = theta * theta;
+  const unsigned *key0 = (const unsigned *)(w + T.key[0]);
+  const int *start0 = (const int *)(w + T.start[0]);
+  const int *ngp = ncell + TR_MAX_DEPTH + 1;
+  const int *town = (const int *)(w + T.town), *ids_t = (const int *)(w + T.ids_t);
+  const int2 *grr = (const int2 *)(w + T.gr);
   if (P == 2)
-    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, ncell + TR_MAX_DEPTH + 1,
-                                                 (const int2 *)(w + T.gr), gp, self, grp->P_ev,
-                                                 grp->dipole == 2, grp->nodes32, qd, phi);
+    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, mom, key0, start0, ncell, simg, stgt, town, ids_t, ngp, grr,
+                                                 gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
   else if (P == 4)
-    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, ncell + TR_MAX_DEPTH + 1,
-                                                 (const int2 *)(w + T.gr), gp, self, grp->P_ev,
-                                                 grp->dipole == 2, grp->nodes32, qd, phi);
+    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, mom, key0, start0, ncell, simg, stgt, town, ids_t, ngp, grr,
+                                                 gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
   else
-    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, D, theta, TL, simg, stgt, ids_b, ncell + TR_MAX_DEPTH + 1,
-                                                 (const int2 *)(w + T.gr), gp, self, grp->P_ev,
-                                                 grp->dipole == 2, grp->nodes32, qd, phi);
+    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, mom, key0, start0, ncell, simg, stgt, town, ids_t, ngp, grr,
+                                                 gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
   if (E) {
     double *ep = (double *)(w + T.ep);
     k_tree_epart<<<nb, 256, 0, st>>>(n, q, phi, ep);
