@@ -62,30 +62,72 @@ __host__ __device__ constexpr K3 kof(int k) {  // the k-th multi-index of the gr
   return K3{0, 0, 0};
 }
 
-// a_k(R) for |k| <= P into a[ncoef(P)], one coefficient per instantiation (constant indices).
+// The Taylor coefficients of 1/|x - y| are harmonic in y: for k = m + 2 e_z,
+//   k! a_k = -(m + 2 e_x)! a_{m + 2 e_x} - (m + 2 e_y)! a_{m + 2 e_y},
+// so a sum over all |k| <= p of a_k M_k equals one over the k with k_z <= 1 only (2n + 1 per
+// degree n, (p + 1)^2 in all) against folded moments, and the recurrence above, restricted to
+// k_z <= 1, only ever refers to such k.  Reduced order: degree n from index n^2, first k_z = 0
+// (k_x = n .. 0), then k_z = 1 (k_x = n - 1 .. 0).
+constexpr int nred(int p) { return (p + 1) * (p + 1); }
+__host__ __device__ constexpr int ridx(int kx, int ky, int kz) {
+  const int n = kx + ky + kz;
+  return n * n + (kz == 0 ? n - kx : n + 1 + (n - 1 - kx));
+}
+__host__ __device__ constexpr K3 rof(int k) {  // the k-th multi-index of the reduced order
+  int n = 0;
+  while ((n + 1) * (n + 1) <= k) ++n;
+  const int j = k - n * n;
+  return j <= n ? K3{n - j, j, 0} : K3{n - 1 - (j - n - 1), j - n - 1, 1};
+}
+
+// a_k(R) for |k| <= P, k_z <= 1, into a[nred(P)], one coefficient per instantiation.
 template <int P, int K>
-__device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float ir2, float (&a)[ncoef(P)]) {
-  if constexpr (K < ncoef(P)) {
-    constexpr K3 t = kof(K);
+__device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float ir2, float (&a)[nred(P)]) {
+  if constexpr (K < nred(P)) {
+    constexpr K3 t = rof(K);
     constexpr int n = t.x + t.y + t.z;
     constexpr float c1 = (float)(2 * n - 1) / (float)n, c2 = (float)(n - 1) / (float)n;
     float s1 = 0.0f, s2 = 0.0f;
-    if constexpr (t.x >= 1) s1 = fmaf(rx, a[kidx(t.x - 1, t.y, t.z)], s1);
-    if constexpr (t.y >= 1) s1 = fmaf(ry, a[kidx(t.x, t.y - 1, t.z)], s1);
-    if constexpr (t.z >= 1) s1 = fmaf(rz, a[kidx(t.x, t.y, t.z - 1)], s1);
-    if constexpr (t.x >= 2) s2 += a[kidx(t.x - 2, t.y, t.z)];
-    if constexpr (t.y >= 2) s2 += a[kidx(t.x, t.y - 2, t.z)];
-    if constexpr (t.z >= 2) s2 += a[kidx(t.x, t.y, t.z - 2)];
+    if constexpr (t.x >= 1) s1 = fmaf(rx, a[ridx(t.x - 1, t.y, t.z)], s1);
+    if constexpr (t.y >= 1) s1 = fmaf(ry, a[ridx(t.x, t.y - 1, t.z)], s1);
+    if constexpr (t.z >= 1) s1 = fmaf(rz, a[ridx(t.x, t.y, t.z - 1)], s1);
+    if constexpr (t.x >= 2) s2 += a[ridx(t.x - 2, t.y, t.z)];
+    if constexpr (t.y >= 2) s2 += a[ridx(t.x, t.y - 2, t.z)];
     a[K] = (c1 * s1 - c2 * s2) * ir2;
     taylor_rec<P, K + 1>(rx, ry, rz, ir2, a);
   }
 }
 
 template <int P>
-__device__ __forceinline__ void taylor(float rx, float ry, float rz, float (&a)[ncoef(P)]) {
+__device__ __forceinline__ void taylor(float rx, float ry, float rz, float (&a)[nred(P)]) {
   const float ir = __builtin_amdgcn_rsqf(rx * rx + ry * ry + rz * rz);
   a[0] = ir;
   taylor_rec<P, 1>(rx, ry, rz, ir * ir, a);
+}
+
+// Folds the moments with k_z >= 2 into those of two lower k_z (the identity above), from the
+// highest index down: both targets of a k have the same degree and a lower index.
+template <int P, int K>
+__device__ __forceinline__ void fold_rec(float (&f)[ncoef(P)]) {
+  if constexpr (K >= 0) {
+    constexpr K3 t = kof(K);
+    if constexpr (t.z >= 2) {
+      constexpr float d = (float)(t.z * (t.z - 1));
+      constexpr float cx = (float)((t.x + 2) * (t.x + 1)) / d, cy = (float)((t.y + 2) * (t.y + 1)) / d;
+      f[kidx(t.x + 2, t.y, t.z - 2)] = fmaf(-cx, f[K], f[kidx(t.x + 2, t.y, t.z - 2)]);
+      f[kidx(t.x, t.y + 2, t.z - 2)] = fmaf(-cy, f[K], f[kidx(t.x, t.y + 2, t.z - 2)]);
+    }
+    fold_rec<P, K - 1>(f);
+  }
+}
+
+template <int P, int K>
+__device__ __forceinline__ void reduce_rec(const float (&f)[ncoef(P)], float *__restrict__ out) {
+  if constexpr (K < nred(P)) {
+    constexpr K3 t = rof(K);
+    out[K] = f[kidx(t.x, t.y, t.z)];
+    reduce_rec<P, K + 1>(f, out);
+  }
 }
 
 // m[k] += q d^k for every |k| <= P (px, py, pz: powers of the offset's components).
@@ -261,15 +303,19 @@ __global__ __launch_bounds__(256) void k_tree_moments(int cap, const int *__rest
 
 // Moments of the cells of level l < D from their children (level l + 1), about the parent's
 // centre: M_k(parent) = sum over children and j <= k of C(k, j) (c_child - c_parent)^(k - j)
-// M_j(child), with C the product of the three binomial coefficients.  One wave per parent, lanes
-// over k; the radius bound is max over children of |c_child - c_parent| + r_child.
+// M_j(child), with C the product of the three binomial coefficients.  One wave per parent (a
+// cell of the cube has at most 8 children, stored consecutively): the children's moments and
+// centres are first copied to LDS in one coalesced pass, then the lanes take the k; the radius
+// bound is max over children of |c_child - c_parent| + r_child.
 template <int P>
-__global__ __launch_bounds__(256) void k_tree_m2m(int cap, const int *__restrict__ ncell, int level, float L,
-                                                 const unsigned *__restrict__ key, const int *__restrict__ child,
-                                                 const float4 *__restrict__ ccen, const float *__restrict__ cmom,
-                                                 float4 *__restrict__ cen, float *__restrict__ mom) {
+__global__ __launch_bounds__(64) void k_tree_m2m(int cap, const int *__restrict__ ncell, int level, float L,
+                                                const unsigned *__restrict__ key, const int *__restrict__ child,
+                                                const float4 *__restrict__ ccen, const float *__restrict__ cmom,
+                                                float4 *__restrict__ cen, float *__restrict__ mom) {
   constexpr int NC = ncoef(P);
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  __shared__ float sm[8 * NC];
+  __shared__ float4 sc[8];
+  const int c = blockIdx.x, lane = threadIdx.x;
   if (c >= cap || c >= *ncell) return;
   const unsigned kk = key[c];
   if ((kk >> (3 * level)) != 0) {  // the far cell: never accepted
@@ -280,14 +326,18 @@ __global__ __launch_bounds__(256) void k_tree_m2m(int cap, const int *__restrict
   const float cx = -L + ((float)compact3(kk) + 0.5f) * h;
   const float cy = -L + ((float)compact3(kk >> 1) + 0.5f) * h;
   const float cz = -L + ((float)compact3(kk >> 2) + 0.5f) * h;
-  const int k0 = child[c], k1 = child[c + 1];
+  const int k0 = child[c];
+  const int nch = min(child[c + 1] - k0, 8);
+  for (int e = lane; e < nch * NC; e += 64) sm[e] = cmom[(size_t)k0 * NC + e];
+  if (lane < nch) sc[lane] = ccen[k0 + lane];
+  __syncthreads();
   float acc[2] = {0.0f, 0.0f};  // coefficients lane and lane + 64
   float rad = 0.0f;
-  for (int ch = k0; ch < k1; ++ch) {
-    const float4 cc = ccen[ch];
+  for (int ch = 0; ch < nch; ++ch) {
+    const float4 cc = sc[ch];
     const float dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
     rad = fmaxf(rad, sqrtf(dx * dx + dy * dy + dz * dz) + cc.w);
-    const float *cm = cmom + (size_t)ch * NC;
+    const float *cm = sm + ch * NC;
     for (int r = 0; r < 2; ++r) {
       const int k = lane + 64 * r;
       if (k >= NC) break;
@@ -340,11 +390,21 @@ __global__ void k_tree_gfill(int cap, const int *__restrict__ ncell, const int *
   for (int k = 0; k < ng[c]; ++k) gr[gofs[c] + k] = make_int2(s0 + 64 * k, min(64, cnt - 64 * k));
 }
 
-// Bounding sphere of each target group.
+// Bounding sphere of each target group, and a sort key that orders the groups by decreasing
+// distance of their centre from the cavity's: groups near the interface, close to the dense
+// shell of images just outside it, open the most cells, and are launched first so that the
+// light ones fill the end of the launch.  Slots beyond the group count get the largest key.
 __global__ __launch_bounds__(64) void k_tree_groups(const int *__restrict__ ngroups, const int2 *__restrict__ gr,
-                                                    const float4 *__restrict__ stgt, float4 *__restrict__ grp) {
+                                                    const float4 *__restrict__ stgt, float4 *__restrict__ grp,
+                                                    unsigned *__restrict__ gkey, int *__restrict__ gid) {
   const int g = blockIdx.x, lane = threadIdx.x;
-  if (g >= *ngroups) return;
+  if (g >= *ngroups) {
+    if (lane == 0) {
+      gkey[g] = 0xffffffffu;
+      gid[g] = g;
+    }
+    return;
+  }
   const int2 rg = gr[g];
   const bool in = lane < rg.y;
   const float4 t = stgt[rg.x + (in ? lane : 0)];
@@ -357,7 +417,12 @@ __global__ __launch_bounds__(64) void k_tree_groups(const int *__restrict__ ngro
   const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
   float r = in ? sqrtf((t.x - cx) * (t.x - cx) + (t.y - cy) * (t.y - cy) + (t.z - cz) * (t.z - cz)) : 0.0f;
   for (int o = 32; o > 0; o >>= 1) r = fmaxf(r, __shfl_xor(r, o));
-  if (lane == 0) grp[g] = make_float4(cx, cy, cz, r);
+  if (lane == 0) {
+    grp[g] = make_float4(cx, cy, cz, r);
+    // non-negative floats order as their bit patterns; the complement reverses the order
+    gkey[g] = ~__float_as_uint(sqrtf(cx * cx + cy * cy + cz * cz)) & 0x7fffffffu;
+    gid[g] = g;
+  }
 }
 
 // One cell of any level, as the traversal reads it: one 32-byte scalar load per visit.  Cells
@@ -368,13 +433,27 @@ struct __align__(32) CellRec {
   int k0, k1;           // children [k0, k1), global numbers
 };
 
-// Records of the cells of level l (children of level l + 1 numbered from off_next).
+// Records of the cells of level l (children of level l + 1 numbered from off_next), and their
+// moments folded to the reduced set (zero for the far cell, which is never accepted).
+template <int P>
 __global__ void k_tree_pack(int cap, const int *__restrict__ ncell, int leaf, int off_l, int off_next,
                             const float4 *__restrict__ cen, const int *__restrict__ start,
-                            const int *__restrict__ child, CellRec *__restrict__ rec) {
+                            const int *__restrict__ child, const float *__restrict__ mom, CellRec *__restrict__ rec,
+                            float *__restrict__ red) {
+  constexpr int NC = ncoef(P), NR = nred(P);
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cap || c >= *ncell) return;
   const float4 cc = cen[c];
+  float *out = red + (size_t)(off_l + c) * NR;
+  if (cc.w == INFINITY) {
+    for (int k = 0; k < NR; ++k) out[k] = 0.0f;
+  } else {
+    float f[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) f[k] = mom[(size_t)c * NC + k];
+    fold_rec<P, NC - 1>(f);
+    reduce_rec<P, 0>(f, out);
+  }
   CellRec r;
   r.cx = cc.x;
   r.cy = cc.y;
@@ -387,7 +466,7 @@ __global__ void k_tree_pack(int cap, const int *__restrict__ ncell, int leaf, in
   rec[off_l + c] = r;
 }
 
-template <int U>
+template <int U, bool MASK>
 __device__ __forceinline__ void direct_terms(float tx, float ty, float tz, int own, const float4 *__restrict__ simg,
                                              int j, float &sum) {
   float4 v[U];
@@ -397,23 +476,33 @@ __device__ __forceinline__ void direct_terms(float tx, float ty, float tz, int o
   for (int u = 0; u < U; ++u) {
     const float dx = tx - v[u].x, dy = ty - v[u].y, dz = tz - v[u].z;
     float ri = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
-    ri = (j + u == own) ? 0.0f : ri;
+    if constexpr (MASK) ri = (j + u == own) ? 0.0f : ri;
     sum = fmaf(v[u].w, ri, sum);
   }
 }
 
-// sum over the images [s0, s1) but the ion's own, in FP32 blocks of 32 terms added into FP64;
-// the loads are issued four at a time
-__device__ __forceinline__ void direct_range(float tx, float ty, float tz, int own, const float4 *__restrict__ simg,
-                                             int s0, int s1, double &acc) {
+template <bool MASK>
+__device__ __forceinline__ void direct_blocks(float tx, float ty, float tz, int own, const float4 *__restrict__ simg,
+                                              int s0, int s1, double &acc) {
   for (int sb = s0; sb < s1; sb += 32) {
     const int se = sb + 32 < s1 ? sb + 32 : s1;
     float sum = 0.0f;
     int j = sb;
-    for (; j + 4 <= se; j += 4) direct_terms<4>(tx, ty, tz, own, simg, j, sum);
-    for (; j < se; ++j) direct_terms<1>(tx, ty, tz, own, simg, j, sum);
+    for (; j + 4 <= se; j += 4) direct_terms<4, MASK>(tx, ty, tz, own, simg, j, sum);
+    for (; j < se; ++j) direct_terms<1, MASK>(tx, ty, tz, own, simg, j, sum);
     acc += (double)sum;
   }
+}
+
+// sum over the images [s0, s1) but the ion's own, in FP32 blocks of 32 terms added into FP64;
+// the loads are issued four at a time.  The own image is masked only where some lane's own
+// image lies in the range (the same sums either way).
+__device__ __forceinline__ void direct_range(float tx, float ty, float tz, int own, const float4 *__restrict__ simg,
+                                             int s0, int s1, double &acc) {
+  if (__ballot(own >= s0 && own < s1) != 0)
+    direct_blocks<true>(tx, ty, tz, own, simg, s0, s1, acc);
+  else
+    direct_blocks<false>(tx, ty, tz, own, simg, s0, s1, acc);
 }
 
 template <int U>
@@ -445,7 +534,7 @@ __device__ __forceinline__ void surface_terms(float tx, float ty, float tz, int 
 // unit; the acceptance test is compared in squares, (r_c + r_g)^2 < theta^2 d^2.
 template <int P>
 __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2, const CellRec *__restrict__ rec,
-                                                            const float *__restrict__ mom,
+                                                            const float *__restrict__ red,
                                                             const unsigned *__restrict__ key0,
                                                             const int *__restrict__ start0,
                                                             const int *__restrict__ ncell,
@@ -454,16 +543,18 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2
                                                             const int *__restrict__ town,
                                                             const int *__restrict__ perm,
                                                             const int *__restrict__ ngroups,
+                                                            const int *__restrict__ gorder,
                                                             const int2 *__restrict__ gr,
                                                             const float4 *__restrict__ grp,
                                                             const double *__restrict__ self, int Pn, int mono,
                                                             const float4 *__restrict__ nodes,
                                                             const float2 *__restrict__ qd, double *__restrict__ phi) {
-  constexpr int NC = ncoef(P);
+  constexpr int NR = nred(P);
   __shared__ int stack[TR_WAVES][TR_STACK];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = blockIdx.x * TR_WAVES + w;
-  if (g >= *ngroups) return;
+  const int slot = blockIdx.x * TR_WAVES + w;
+  if (slot >= *ngroups) return;
+  const int g = gorder[slot];  // the valid groups sort first
   const int2 gg = gr[g];
   const bool in = lane < gg.y;
   const int s = gg.x + (in ? lane : 0);
@@ -489,12 +580,12 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2
     const float rs = rc.r + G.w;
     const int accept = __builtin_amdgcn_readfirstlane((int)(rs * rs < theta2 * (dx * dx + dy * dy + dz * dz)));
     if (accept) {
-      float a[NC];
+      float a[NR];
       taylor<P>(t.x - rc.cx, t.y - rc.cy, t.z - rc.cz, a);
-      const float *m = mom + (size_t)c * NC;
+      const float *m = red + (size_t)c * NR;
       float v = 0.0f;
 #pragma unroll
-      for (int k = 0; k < NC; ++k) v = fmaf(a[k], m[k], v);
+      for (int k = 0; k < NR; ++k) v = fmaf(a[k], m[k], v);
       if (own >= rc.s0 && own < rc.s1) {  // the ion's own image is in the cell: take its term out again
         const float4 o = simg[own];
         const float ox = t.x - o.x, oy = t.y - o.y, oz = t.z - o.z;
@@ -571,10 +662,10 @@ struct TreeLayout {
   int D, P, nc, ngroups, lt;
   int64_t cap[TR_MAX_DEPTH + 1], tcap;
   size_t codes_a, codes_b, ids_a, ids_b, codes_t, ids_t, town, simg, stgt, inv, flags, scan, grp, gr, gng, gofs,
-      tkey, tstart, tchild, ncell, ep, temp, temp_bytes;
+      tkey, tstart, tchild, gkey_a, gkey_b, gid_a, gid_b, ncell, ep, temp, temp_bytes;
   size_t key[TR_MAX_DEPTH + 1], start[TR_MAX_DEPTH + 1], child[TR_MAX_DEPTH + 1], cen[TR_MAX_DEPTH + 1];
   int64_t off[TR_MAX_DEPTH + 2];  // global number of each level's first cell; off[D + 1] = all cells
-  size_t rec, mom;                // records and moments of every cell, by global number
+  size_t rec, mom, red;           // records, moments and folded moments of every cell, by global number
   size_t total;
 };
 
@@ -622,6 +713,10 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
   T.gr = take(8 * (size_t)T.ngroups);
   T.gng = take(4 * (size_t)T.tcap);
   T.gofs = take(4 * (size_t)T.tcap);
+  T.gkey_a = take(4 * (size_t)T.ngroups);  // launch order of the groups, sorted by key
+  T.gkey_b = take(4 * (size_t)T.ngroups);
+  T.gid_a = take(4 * (size_t)T.ngroups);
+  T.gid_b = take(4 * (size_t)T.ngroups);
   T.off[0] = 0;
   for (int l = 0; l <= D; ++l) {
     const int64_t c = T.cap[l];
@@ -633,11 +728,14 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
   }
   T.rec = take(sizeof(CellRec) * (size_t)T.off[D + 1]);
   T.mom = take(4 * (size_t)T.off[D + 1] * T.nc);
+  T.red = take(4 * (size_t)T.off[D + 1] * nred(P));
   size_t sort_b = 0, scan_b = 0;
-  for (int bits : {31, 3 * TR_TBITS}) {  // the images' sort, then the targets'
+  // the images' sort, the targets', and the groups' launch order (up to 2 N groups)
+  const unsigned ns = (unsigned)std::max<int64_t>((int64_t)N, T.ngroups);
+  for (int bits : {31, 3 * TR_TBITS, 32}) {
     size_t b = 0;
     if (rocprim::radix_sort_pairs(nullptr, b, (const unsigned *)nullptr, (unsigned *)nullptr, (const int *)nullptr,
-                                  (int *)nullptr, (unsigned)N, 0, bits) != hipSuccess)
+                                  (int *)nullptr, ns, 0, bits) != hipSuccess)
       return HSMA_EDEVICE;
     sort_b = b > sort_b ? b : sort_b;
   }
@@ -734,7 +832,7 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
                                        (unsigned *)(w + T.key[l]), (int *)(w + T.child[l]), (int *)(w + T.start[l]),
                                        ncell + l);
   }
-  float *mom = (float *)(w + T.mom);
+  float *mom = (float *)(w + T.mom), *red = (float *)(w + T.red);
   CellRec *rec = (CellRec *)(w + T.rec);
   for (int l = D; l >= 0; --l) {
     const int gm = (int)cdivl(T.cap[l], 4);
@@ -756,15 +854,23 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
       const float4 *cc = (const float4 *)(w + T.cen[l + 1]);
       const float *cm = mom + (size_t)T.off[l + 1] * T.nc;
       if (P == 2)
-        k_tree_m2m<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+        k_tree_m2m<2><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
       else if (P == 4)
-        k_tree_m2m<4><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+        k_tree_m2m<4><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
       else
-        k_tree_m2m<6><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+        k_tree_m2m<6><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
     }
-    k_tree_pack<<<(int)cdivl(T.cap[l], 256), 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l],
-                                                           (int)T.off[l + 1], cl, (const int *)(w + T.start[l]),
-                                                           (const int *)(w + T.child[l]), rec);
+    const int gpk = (int)cdivl(T.cap[l], 256);
+    const int *sl = (const int *)(w + T.start[l]), *chp = (const int *)(w + T.child[l]);
+    if (P == 2)
+      k_tree_pack<2><<<gpk, 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l], (int)T.off[l + 1], cl, sl,
+                                          chp, ml, rec, red);
+    else if (P == 4)
+      k_tree_pack<4><<<gpk, 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l], (int)T.off[l + 1], cl, sl,
+                                          chp, ml, rec, red);
+    else
+      k_tree_pack<6><<<gpk, 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l], (int)T.off[l + 1], cl, sl,
+                                          chp, ml, rec, red);
   }
   {
     // targets: sorted by their own codes (codes_a and ids_a are free again), cells of level lt,
@@ -791,8 +897,12 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
     HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, gng, gofs, 0, (size_t)T.tcap, rocprim::plus<int>(), st));
     k_tree_gfill<<<gc, 256, 0, st>>>((int)T.tcap, tcount, tstart, gng, gofs, (int2 *)(w + T.gr),
                                      ncell + TR_MAX_DEPTH + 1);
+    unsigned *gka = (unsigned *)(w + T.gkey_a), *gkb = (unsigned *)(w + T.gkey_b);
+    int *gia = (int *)(w + T.gid_a), *gib = (int *)(w + T.gid_b);
     k_tree_groups<<<T.ngroups, 64, 0, st>>>(ncell + TR_MAX_DEPTH + 1, (const int2 *)(w + T.gr), stgt,
-                                            (float4 *)(w + T.grp));
+                                            (float4 *)(w + T.grp), gka, gia);
+    size_t tb3 = T.temp_bytes;
+    HSMA_HIP(rocprim::radix_sort_pairs(w + T.temp, tb3, gka, gkb, gia, gib, (unsigned)T.ngroups, 0, 32, st));
   }
   const hsma_group_s *grp = pl->self;
   const int ge = (int)cdivl(T.ngroups, TR_WAVES);
@@ -802,15 +912,16 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
   const int *start0 = (const int *)(w + T.start[0]);
   const int *ngp = ncell + TR_MAX_DEPTH + 1;
   const int *town = (const int *)(w + T.town), *ids_t = (const int *)(w + T.ids_t);
+  const int *gord = (const int *)(w + T.gid_b);
   const int2 *grr = (const int2 *)(w + T.gr);
   if (P == 2)
-    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, mom, key0, start0, ncell, simg, stgt, town, ids_t, ngp, grr,
+    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr,
                                                  gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
   else if (P == 4)
-    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, mom, key0, start0, ncell, simg, stgt, town, ids_t, ngp, grr,
+    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr,
                                                  gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
   else
-    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, mom, key0, start0, ncell, simg, stgt, town, ids_t, ngp, grr,
+    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr,
                                                  gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
   if (E) {
     double *ep = (double *)(w + T.ep);
