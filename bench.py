@@ -888,7 +888,8 @@ def leg_tree(args, checks) -> dict:
                        "p=40, compensated FP32 pairs"}
     sampled = {}
     runs = [("direct", None), ("tree_order4_theta0.5", (4, 0.5)), ("tree_order6_theta0.5", (6, 0.5)),
-            ("tree_order6_theta0.4", (6, 0.4)), ("tree_order6_theta0.3", (6, 0.3))]
+            ("tree_order6_theta0.4", (6, 0.4)), ("tree_order8_theta0.5", (8, 0.5)), ("tree_order6_theta0.3", (6, 0.3)),
+            ("tree_order8_theta0.4", (8, 0.4))]
     for label, cfg in runs:
         if cfg is None:
             def call():

@@ -26,6 +26,7 @@
 // The check sums, the fit and the surface strengths are those of the direct path
 // (run_front); the surface nodes are summed directly per target after the traversal.
 #include <cmath>
+#include <type_traits>
 
 #include "hsma_internal.h"
 
@@ -80,9 +81,12 @@ __host__ __device__ constexpr K3 rof(int k) {  // the k-th multi-index of the re
   return j <= n ? K3{n - j, j, 0} : K3{n - 1 - (j - n - 1), j - n - 1, 1};
 }
 
-// a_k(R) for |k| <= P, k_z <= 1, into a[nred(P)], one coefficient per instantiation.
+// a_k(R) for |k| <= P, k_z <= 1, into a[nred(P)], one coefficient per instantiation, each
+// added into v = sum_k a_k m_k as soon as it is formed (so that a coefficient is dead two
+// degrees later, which keeps the registers of high orders down).
 template <int P, int K>
-__device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float ir2, float (&a)[nred(P)]) {
+__device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float ir2, float (&a)[nred(P)],
+                                           const float *__restrict__ m, float &v) {
   if constexpr (K < nred(P)) {
     constexpr K3 t = rof(K);
     constexpr int n = t.x + t.y + t.z;
@@ -94,15 +98,20 @@ __device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float i
     if constexpr (t.x >= 2) s2 += a[ridx(t.x - 2, t.y, t.z)];
     if constexpr (t.y >= 2) s2 += a[ridx(t.x, t.y - 2, t.z)];
     a[K] = (c1 * s1 - c2 * s2) * ir2;
-    taylor_rec<P, K + 1>(rx, ry, rz, ir2, a);
+    v = fmaf(a[K], m[K], v);
+    taylor_rec<P, K + 1>(rx, ry, rz, ir2, a, m, v);
   }
 }
 
+// sum over |k| <= P, k_z <= 1 of a_k(R) m_k, in the order of k
 template <int P>
-__device__ __forceinline__ void taylor(float rx, float ry, float rz, float (&a)[nred(P)]) {
+__device__ __forceinline__ float taylor_dot(float rx, float ry, float rz, const float *__restrict__ m) {
+  float a[nred(P)];
   const float ir = __builtin_amdgcn_rsqf(rx * rx + ry * ry + rz * rz);
   a[0] = ir;
-  taylor_rec<P, 1>(rx, ry, rz, ir * ir, a);
+  float v = fmaf(ir, m[0], 0.0f);
+  taylor_rec<P, 1>(rx, ry, rz, ir * ir, a, m, v);
+  return v;
 }
 
 // Folds the moments with k_z >= 2 into those of two lower k_z (the identity above), from the
@@ -331,14 +340,16 @@ __global__ __launch_bounds__(64) void k_tree_m2m(int cap, const int *__restrict_
   for (int e = lane; e < nch * NC; e += 64) sm[e] = cmom[(size_t)k0 * NC + e];
   if (lane < nch) sc[lane] = ccen[k0 + lane];
   __syncthreads();
-  float acc[2] = {0.0f, 0.0f};  // coefficients lane and lane + 64
+  constexpr int NRND = (NC + 63) / 64;
+  float acc[NRND];  // coefficients lane + 64 r
+  for (int r = 0; r < NRND; ++r) acc[r] = 0.0f;
   float rad = 0.0f;
   for (int ch = 0; ch < nch; ++ch) {
     const float4 cc = sc[ch];
     const float dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
     rad = fmaxf(rad, sqrtf(dx * dx + dy * dy + dz * dz) + cc.w);
     const float *cm = sm + ch * NC;
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < NRND; ++r) {
       const int k = lane + 64 * r;
       if (k >= NC) break;
       const K3 t = kof(k);
@@ -363,7 +374,7 @@ __global__ __launch_bounds__(64) void k_tree_m2m(int cap, const int *__restrict_
       acc[r] += v;
     }
   }
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < NRND; ++r) {
     const int k = lane + 64 * r;
     if (k < NC) mom[(size_t)c * NC + k] = acc[r];
   }
@@ -580,12 +591,7 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2
     const float rs = rc.r + G.w;
     const int accept = __builtin_amdgcn_readfirstlane((int)(rs * rs < theta2 * (dx * dx + dy * dy + dz * dz)));
     if (accept) {
-      float a[NR];
-      taylor<P>(t.x - rc.cx, t.y - rc.cy, t.z - rc.cz, a);
-      const float *m = red + (size_t)c * NR;
-      float v = 0.0f;
-#pragma unroll
-      for (int k = 0; k < NR; ++k) v = fmaf(a[k], m[k], v);
+      float v = taylor_dot<P>(t.x - rc.cx, t.y - rc.cy, t.z - rc.cz, red + (size_t)c * NR);
       if (own >= rc.s0 && own < rc.s1) {  // the ion's own image is in the cell: take its term out again
         const float4 o = simg[own];
         const float ox = t.x - o.x, oy = t.y - o.y, oz = t.z - o.z;
@@ -642,6 +648,17 @@ __global__ __launch_bounds__(256) void k_tree_esum(int nb, const double *__restr
 }
 
 inline int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Calls f with the multipole order as a compile-time constant (decltype(o)::value): 2, 4, 6 or 8.
+template <typename F>
+void with_order(int P, F &&f) {
+  switch (P) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+  }
+}
 
 // Level of the targets' cells in [-a, a]^3 that no group crosses: about 8 groups of 64 per cell
 // of a uniformly filled cavity (the ball fills pi/6 of the cube), so that groups are nearly full.
@@ -757,7 +774,7 @@ static hsma_status tree_args(hsma_plan_t pl, int64_t N, const hsma_tree_opts *op
   if (!pl || N < 0 || !opts) return HSMA_EINVAL;
   if (pl->opts.pair_prec != HSMA_PAIR_FP32 && pl->opts.pair_prec != HSMA_PAIR_FP32_COMP) return HSMA_EINVAL;
   if (!(opts->theta >= 0.0 && opts->theta < 1.0)) return HSMA_EINVAL;
-  if (opts->order != 2 && opts->order != 4 && opts->order != 6) return HSMA_EINVAL;
+  if (opts->order != 2 && opts->order != 4 && opts->order != 6 && opts->order != 8) return HSMA_EINVAL;
   if (opts->depth != 0 && (opts->depth < 2 || opts->depth > TR_MAX_DEPTH - 1)) return HSMA_EINVAL;
   if (N > ((int64_t)1 << 27) - 1) return HSMA_EINVAL;  // global cell numbers, at most (D + 1) N, in an int
   D = opts->depth ? opts->depth : auto_depth(N);
@@ -840,37 +857,24 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
     float4 *cl = (float4 *)(w + T.cen[l]);
     float *ml = mom + (size_t)T.off[l] * T.nc;
     if (l == D) {  // leaves: moments from their images
-      if (P == 2)
-        k_tree_moments<2><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
-                                               simg, cl, ml);
-      else if (P == 4)
-        k_tree_moments<4><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
-                                               simg, cl, ml);
-      else
-        k_tree_moments<6><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
-                                               simg, cl, ml);
+      with_order(P, [&](auto o) {
+        k_tree_moments<decltype(o)::value><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl,
+                                                     (const int *)(w + T.start[l]), simg, cl, ml);
+      });
     } else {  // upper levels: translated from the children
       const int *chl = (const int *)(w + T.child[l]);
       const float4 *cc = (const float4 *)(w + T.cen[l + 1]);
       const float *cm = mom + (size_t)T.off[l + 1] * T.nc;
-      if (P == 2)
-        k_tree_m2m<2><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
-      else if (P == 4)
-        k_tree_m2m<4><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
-      else
-        k_tree_m2m<6><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+      with_order(P, [&](auto o) {
+        k_tree_m2m<decltype(o)::value><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+      });
     }
     const int gpk = (int)cdivl(T.cap[l], 256);
     const int *sl = (const int *)(w + T.start[l]), *chp = (const int *)(w + T.child[l]);
-    if (P == 2)
-      k_tree_pack<2><<<gpk, 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l], (int)T.off[l + 1], cl, sl,
-                                          chp, ml, rec, red);
-    else if (P == 4)
-      k_tree_pack<4><<<gpk, 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l], (int)T.off[l + 1], cl, sl,
-                                          chp, ml, rec, red);
-    else
-      k_tree_pack<6><<<gpk, 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l], (int)T.off[l + 1], cl, sl,
-                                          chp, ml, rec, red);
+    with_order(P, [&](auto o) {
+      k_tree_pack<decltype(o)::value><<<gpk, 256, 0, st>>>((int)T.cap[l], ncell + l, l == D, (int)T.off[l], (int)T.off[l + 1],
+                                                cl, sl, chp, ml, rec, red);
+    });
   }
   {
     // targets: sorted by their own codes (codes_a and ids_a are free again), cells of level lt,
@@ -914,15 +918,11 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
   const int *town = (const int *)(w + T.town), *ids_t = (const int *)(w + T.ids_t);
   const int *gord = (const int *)(w + T.gid_b);
   const int2 *grr = (const int2 *)(w + T.gr);
-  if (P == 2)
-    k_tree_eval<2><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr,
-                                                 gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
-  else if (P == 4)
-    k_tree_eval<4><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr,
-                                                 gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
-  else
-    k_tree_eval<6><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr,
-                                                 gp, self, grp->P_ev, grp->dipole == 2, grp->nodes32, qd, phi);
+  with_order(P, [&](auto o) {
+    k_tree_eval<decltype(o)::value><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t,
+                                                       ngp, gord, grr, gp, self, grp->P_ev, grp->dipole == 2,
+                                                       grp->nodes32, qd, phi);
+  });
   if (E) {
     double *ep = (double *)(w + T.ep);
     k_tree_epart<<<nb, 256, 0, st>>>(n, q, phi, ep);
