@@ -294,21 +294,23 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  * The check sums, the fit and the surface sums are those of hsma_energy; only the sum over the
  * other ions' Kelvin images is approximated.  The images are sorted into an octree over the
  * cube of half-width 8a (depth levels below the root; images farther out, of ions within a/8 of
- * the centre, are summed directly).  A cell of radius r_c at distance d from a group of 64
- * targets of radius r_g is evaluated from its Cartesian multipole moments of the given order
- * when r_c + r_g < theta d, else opened; leaves that are not accepted are summed directly.
+ * the centre, are summed directly).  The targets are grouped by their own positions, in groups
+ * of up to 64.  A cell of radius r_c at distance d from a group of radius r_g is evaluated from
+ * its Cartesian multipole moments of the given order when r_c + r_g < theta d, else opened;
+ * leaves that are not accepted are summed directly.
  *   theta: in [0, 1); 0 accepts no cell (every image is then summed directly, the check of the
- *          traversal); order: 2, 4 or 6; depth: 2..9, or 0 for a depth from N (about 8 at
+ *          traversal); order: 2, 4, 6 or 8; depth: 2..9, or 0 for a depth from N (7 at
  *          N = 10^6).
  * The error is the treecode's. On 10^6 ions uniform in a cavity with balanced charges, the
- * relative L2 errors of the potentials are 1e-3 (order 4, theta 0.5), 1e-4 (order 6, theta 0.5),
- * 1.5e-5 (order 6, theta 0.4) and 1.6e-6 (order 6, theta 0.3).  Against the direct symmetric sums
- * of hsma_energy these run 5.6, 3.1, 2.1 and 1.05 times faster; below a few 10^5 ions the direct
- * path is faster at any setting.
+ * relative L2 errors of the potentials are 9.5e-4 (order 4, theta 0.5), 9.3e-5 (order 6,
+ * theta 0.5), 1.4e-5 (order 6, theta 0.4), 1.5e-6 (order 6, theta 0.3) and 1.2e-6 (order 8,
+ * theta 0.4).  Against the direct symmetric sums of hsma_energy these run 10.5, 6.8, 5.0, 2.9
+ * and 3.2 times faster; near 2 10^5 ions the two paths are about even, and below that the
+ * direct path is faster at any setting.
  *   phi: [device] N doubles (required); E: [device] one double or NULL;
  *   ws: [device] ws_bytes >= hsma_tree_workspace_bytes(plan, N, opts) (0 for invalid arguments).
  * Like the other compute calls it allocates nothing and does not synchronise; unlike them it
- * is not meant for graph capture, since its radix sort and scans (rocPRIM, with their
+ * is not meant for graph capture, since its radix sorts and scans (rocPRIM, with their
  * temporary storage in ws) may enqueue memory fills.
  * Errors: HSMA_EINVAL (also for the FP64 pair mode), HSMA_ESTATE, HSMA_EDEVICE. */
 typedef struct {
