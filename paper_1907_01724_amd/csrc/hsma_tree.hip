@@ -42,6 +42,7 @@ constexpr int TR_MAX_DEPTH = 10;        // codes of 3 D bits plus the far flag f
 constexpr unsigned TR_FAR = 1u << 30;   // code of an image outside the cube
 constexpr double TR_CUBE = 8.0;         // cube half-width in units of a
 constexpr int TR_TBITS = 10;            // bits per axis of the targets' codes in [-a, a]^3
+constexpr int TR_LEAF = 64;             // cells of at most this many images are leaves at any level
 
 // Graded multi-index order: degree n, then kx descending, then ky descending.
 constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
@@ -472,8 +473,9 @@ __global__ void k_tree_pack(int cap, const int *__restrict__ ncell, int leaf, in
   r.r = cc.w;
   r.s0 = start[c];
   r.s1 = start[c + 1];
-  r.k0 = leaf ? 0 : off_next + child[c];
-  r.k1 = leaf ? 0 : off_next + child[c + 1];
+  const bool lf = leaf || r.s1 - r.s0 <= TR_LEAF;
+  r.k0 = lf ? 0 : off_next + child[c];
+  r.k1 = lf ? 0 : off_next + child[c + 1];
   rec[off_l + c] = r;
 }
 
