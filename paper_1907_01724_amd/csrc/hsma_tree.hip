@@ -43,6 +43,7 @@ constexpr unsigned TR_FAR = 1u << 30;   // code of an image outside the cube
 constexpr double TR_CUBE = 8.0;         // cube half-width in units of a
 constexpr int TR_TBITS = 10;            // bits per axis of the targets' codes in [-a, a]^3
 constexpr int TR_LEAF = 64;             // cells of at most this many images are leaves at any level
+constexpr int TR_CELL_BLOCKS = 8192;    // blocks of the moment kernels (one wave each, grid-stride)
 
 // Graded multi-index order: degree n, then kx descending, then ky descending.
 constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
@@ -257,129 +258,147 @@ __global__ void k_tree_cells(int cap, const int *__restrict__ m_dev, int m_host,
   }
 }
 
-// Moments, centre and radius of every cell of one level: one wave per cell.  The centre is the
+// Centre of the level-l octree cell of key k.
+__device__ __forceinline__ float3 cell_centre(unsigned k, int level, float L) {
+  const float h = 2.0f * L / (float)(1 << level);
+  return make_float3(-L + ((float)compact3(k) + 0.5f) * h, -L + ((float)compact3(k >> 1) + 0.5f) * h,
+                     -L + ((float)compact3(k >> 2) + 0.5f) * h);
+}
+
+// Moments, centre and radius of the leaf cells: one wave per cell (a grid-stride loop over the
+// cells), the lanes over the coefficients k.  The images are taken 64 at a time: each lane
+// stages the powers of one image's offset from the centre in LDS, then every lane adds
+// q d_x^kx d_y^ky d_z^kz for its own k over the chunk, in image order.  The centre is the
 // geometric centre of the octree cell; the far cell (outside the cube) gets radius +inf.
 template <int P>
-__global__ __launch_bounds__(256) void k_tree_moments(int cap, const int *__restrict__ ncell, int level, float L,
-                                                     const unsigned *__restrict__ key, const int *__restrict__ start,
-                                                     const float4 *__restrict__ simg, float4 *__restrict__ cen,
-                                                     float *__restrict__ mom) {
-  constexpr int NC = ncoef(P);
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (c >= cap || c >= *ncell) return;
-  const unsigned k = key[c];
-  const int s0 = start[c], s1 = start[c + 1];
-  const bool far = (k >> (3 * level)) != 0;  // cube cells of level l have keys below 8^l
-  if (far) {  // never accepted: no moments
-    if (lane == 0) cen[c] = make_float4(0.f, 0.f, 0.f, INFINITY);
-    return;
-  }
-  const float h = 2.0f * L / (float)(1 << level);
-  const float cx = -L + ((float)compact3(k) + 0.5f) * h;
-  const float cy = -L + ((float)compact3(k >> 1) + 0.5f) * h;
-  const float cz = -L + ((float)compact3(k >> 2) + 0.5f) * h;
-  float m[NC];
-#pragma unroll
-  for (int t = 0; t < NC; ++t) m[t] = 0.0f;
-  float rmax = 0.0f;
-  for (int s = s0 + lane; s < s1; s += 64) {
-    const float4 v = simg[s];
-    const float dx = v.x - cx, dy = v.y - cy, dz = v.z - cz;
-    rmax = fmaxf(rmax, sqrtf(dx * dx + dy * dy + dz * dz));
-    // powers dx^i dy^j dz^l by degree
-    float px[P + 1], py[P + 1], pz[P + 1];
-    px[0] = py[0] = pz[0] = 1.0f;
-#pragma unroll
-    for (int e = 1; e <= P; ++e) {
-      px[e] = px[e - 1] * dx;
-      py[e] = py[e - 1] * dy;
-      pz[e] = pz[e - 1] * dz;
+__global__ __launch_bounds__(64) void k_tree_moments(const int *__restrict__ ncell, int level, float L,
+                                                    const unsigned *__restrict__ key, const int *__restrict__ start,
+                                                    const float4 *__restrict__ simg, float4 *__restrict__ cen,
+                                                    float *__restrict__ mom) {
+  constexpr int NC = ncoef(P), NRND = (NC + 63) / 64;
+  __shared__ float pw[64][3][P + 1];
+  __shared__ float sq[64];
+  const int lane = threadIdx.x;
+  K3 kk[NRND];
+  for (int r = 0; r < NRND; ++r) kk[r] = kof(lane + 64 * r < NC ? lane + 64 * r : 0);
+  const int nc = *ncell;
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    const unsigned k = key[c];
+    if ((k >> (3 * level)) != 0) {  // cube cells of level l have keys below 8^l; the far cell has no moments
+      if (lane == 0) cen[c] = make_float4(0.f, 0.f, 0.f, INFINITY);
+      continue;
     }
-    moment_rec<P, 0>(v.w, px, py, pz, m);
-  }
-#pragma unroll
-  for (int t = 0; t < NC; ++t) {
-    float v = m[t];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    m[t] = v;
-  }
-  for (int o = 32; o > 0; o >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, o));
-  if (lane == 0) {
-    cen[c] = make_float4(cx, cy, cz, rmax);
-#pragma unroll
-    for (int t = 0; t < NC; ++t) mom[(size_t)c * NC + t] = m[t];
+    const float3 ce = cell_centre(k, level, L);
+    const int s0 = start[c], s1 = start[c + 1];
+    float acc[NRND];
+    for (int r = 0; r < NRND; ++r) acc[r] = 0.0f;
+    float rmax = 0.0f;
+    for (int sb = s0; sb < s1; sb += 64) {
+      const int cnt = s1 - sb < 64 ? s1 - sb : 64;
+      __syncthreads();  // the previous chunk's powers are no longer read
+      if (lane < cnt) {
+        const float4 v = simg[sb + lane];
+        const float d[3] = {v.x - ce.x, v.y - ce.y, v.z - ce.z};
+        rmax = fmaxf(rmax, sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+        for (int a = 0; a < 3; ++a) {
+          float p = 1.0f;
+          for (int e = 0; e <= P; ++e) {
+            pw[lane][a][e] = p;
+            p *= d[a];
+          }
+        }
+        sq[lane] = v.w;
+      }
+      __syncthreads();
+      for (int r = 0; r < NRND; ++r) {
+        if (lane + 64 * r >= NC) break;
+        const K3 t = kk[r];
+        float m = acc[r];
+        for (int i = 0; i < cnt; ++i) m = fmaf(sq[i], pw[i][0][t.x] * pw[i][1][t.y] * pw[i][2][t.z], m);
+        acc[r] = m;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, o));
+    for (int r = 0; r < NRND; ++r)
+      if (lane + 64 * r < NC) mom[(size_t)c * NC + lane + 64 * r] = acc[r];
+    if (lane == 0) cen[c] = make_float4(ce.x, ce.y, ce.z, rmax);
   }
 }
 
 // Moments of the cells of level l < D from their children (level l + 1), about the parent's
 // centre: M_k(parent) = sum over children and j <= k of C(k, j) (c_child - c_parent)^(k - j)
 // M_j(child), with C the product of the three binomial coefficients.  One wave per parent (a
-// cell of the cube has at most 8 children, stored consecutively): the children's moments and
-// centres are first copied to LDS in one coalesced pass, then the lanes take the k; the radius
-// bound is max over children of |c_child - c_parent| + r_child.
+// grid-stride loop; a cell of the cube has at most 8 children, stored consecutively): the
+// children's moments and the powers of their offsets are staged in LDS with a table of binomial
+// coefficients, then the lanes take the k.  The radius bound is max over children of
+// |c_child - c_parent| + r_child.
 template <int P>
-__global__ __launch_bounds__(64) void k_tree_m2m(int cap, const int *__restrict__ ncell, int level, float L,
+__global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, int level, float L,
                                                 const unsigned *__restrict__ key, const int *__restrict__ child,
                                                 const float4 *__restrict__ ccen, const float *__restrict__ cmom,
                                                 float4 *__restrict__ cen, float *__restrict__ mom) {
-  constexpr int NC = ncoef(P);
+  constexpr int NC = ncoef(P), NRND = (NC + 63) / 64;
   __shared__ float sm[8 * NC];
-  __shared__ float4 sc[8];
-  const int c = blockIdx.x, lane = threadIdx.x;
-  if (c >= cap || c >= *ncell) return;
-  const unsigned kk = key[c];
-  if ((kk >> (3 * level)) != 0) {  // the far cell: never accepted
-    if (lane == 0) cen[c] = make_float4(0.f, 0.f, 0.f, INFINITY);
-    return;
+  __shared__ float pw[8][3][P + 1];
+  __shared__ float bin[P + 1][P + 1];
+  __shared__ float rad8[8];
+  const int lane = threadIdx.x;
+  for (int e = lane; e < (P + 1) * (P + 1); e += 64) {  // C(i, j), exact in FP32 for i <= 8
+    const int i = e / (P + 1), j = e % (P + 1);
+    float b = 1.0f;
+    for (int u = 1; u <= j; ++u) b = b * (float)(i - j + u) / (float)u;
+    bin[i][j] = j <= i ? b : 0.0f;
   }
-  const float h = 2.0f * L / (float)(1 << level);
-  const float cx = -L + ((float)compact3(kk) + 0.5f) * h;
-  const float cy = -L + ((float)compact3(kk >> 1) + 0.5f) * h;
-  const float cz = -L + ((float)compact3(kk >> 2) + 0.5f) * h;
-  const int k0 = child[c];
-  const int nch = min(child[c + 1] - k0, 8);
-  for (int e = lane; e < nch * NC; e += 64) sm[e] = cmom[(size_t)k0 * NC + e];
-  if (lane < nch) sc[lane] = ccen[k0 + lane];
-  __syncthreads();
-  constexpr int NRND = (NC + 63) / 64;
-  float acc[NRND];  // coefficients lane + 64 r
-  for (int r = 0; r < NRND; ++r) acc[r] = 0.0f;
-  float rad = 0.0f;
-  for (int ch = 0; ch < nch; ++ch) {
-    const float4 cc = sc[ch];
-    const float dx = cc.x - cx, dy = cc.y - cy, dz = cc.z - cz;
-    rad = fmaxf(rad, sqrtf(dx * dx + dy * dy + dz * dz) + cc.w);
-    const float *cm = sm + ch * NC;
-    for (int r = 0; r < NRND; ++r) {
-      const int k = lane + 64 * r;
-      if (k >= NC) break;
-      const K3 t = kof(k);
-      // j from k down to 0 in each component: binomial C(k_i, j_i) and power d_i^(k_i - j_i)
-      // carried along, so that nothing is indexed at run time
-      float v = 0.0f, bx = 1.0f, wx = 1.0f;
-      for (int jx = t.x; jx >= 0; --jx) {
-        float by = 1.0f, wy = 1.0f;
-        for (int jy = t.y; jy >= 0; --jy) {
-          float bz = 1.0f, wz = 1.0f;
-          for (int jz = t.z; jz >= 0; --jz) {
-            v = fmaf(bx * by * bz * (wx * wy * wz), cm[kidx(jx, jy, jz)], v);
-            bz = bz * (float)jz / (float)(t.z - jz + 1);
-            wz *= dz;
-          }
-          by = by * (float)jy / (float)(t.y - jy + 1);
-          wy *= dy;
+  K3 kk[NRND];
+  for (int r = 0; r < NRND; ++r) kk[r] = kof(lane + 64 * r < NC ? lane + 64 * r : 0);
+  const int nc = *ncell;
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    const unsigned k = key[c];
+    if ((k >> (3 * level)) != 0) {  // the far cell: never accepted
+      if (lane == 0) cen[c] = make_float4(0.f, 0.f, 0.f, INFINITY);
+      continue;
+    }
+    const float3 ce = cell_centre(k, level, L);
+    const int k0 = child[c];
+    const int nch = min(child[c + 1] - k0, 8);
+    __syncthreads();  // the previous parent's tables are no longer read
+    for (int e = lane; e < nch * NC; e += 64) sm[e] = cmom[(size_t)k0 * NC + e];
+    if (lane < nch) {
+      const float4 cc = ccen[k0 + lane];
+      const float d[3] = {cc.x - ce.x, cc.y - ce.y, cc.z - ce.z};
+      rad8[lane] = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) + cc.w;
+      for (int a = 0; a < 3; ++a) {
+        float p = 1.0f;
+        for (int e = 0; e <= P; ++e) {
+          pw[lane][a][e] = p;
+          p *= d[a];
         }
-        bx = bx * (float)jx / (float)(t.x - jx + 1);
-        wx *= dx;
       }
-      acc[r] += v;
+    }
+    __syncthreads();
+    for (int r = 0; r < NRND; ++r) {
+      if (lane + 64 * r >= NC) break;
+      const K3 t = kk[r];
+      float v = 0.0f;
+      for (int ch = 0; ch < nch; ++ch) {
+        const float *cm = sm + ch * NC;
+        for (int jx = 0; jx <= t.x; ++jx) {
+          const float fx = bin[t.x][jx] * pw[ch][0][t.x - jx];
+          for (int jy = 0; jy <= t.y; ++jy) {
+            const float fxy = fx * bin[t.y][jy] * pw[ch][1][t.y - jy];
+            for (int jz = 0; jz <= t.z; ++jz)
+              v = fmaf(fxy * (bin[t.z][jz] * pw[ch][2][t.z - jz]), cm[kidx(jx, jy, jz)], v);
+          }
+        }
+      }
+      mom[(size_t)c * NC + lane + 64 * r] = v;
+    }
+    if (lane == 0) {
+      float rad = 0.0f;
+      for (int ch = 0; ch < nch; ++ch) rad = fmaxf(rad, rad8[ch]);
+      cen[c] = make_float4(ce.x, ce.y, ce.z, rad);
     }
   }
-  for (int r = 0; r < NRND; ++r) {
-    const int k = lane + 64 * r;
-    if (k < NC) mom[(size_t)c * NC + k] = acc[r];
-  }
-  if (lane == 0) cen[c] = make_float4(cx, cy, cz, rad);
 }
 
 // Target groups: the sorted targets of each cell of the targets' grouping level in runs of up
@@ -854,21 +873,21 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
   float *mom = (float *)(w + T.mom), *red = (float *)(w + T.red);
   CellRec *rec = (CellRec *)(w + T.rec);
   for (int l = D; l >= 0; --l) {
-    const int gm = (int)cdivl(T.cap[l], 4);
+    const int gm = (int)std::min<int64_t>(T.cap[l], TR_CELL_BLOCKS);  // grid-stride over the cells
     const unsigned *kl = (const unsigned *)(w + T.key[l]);
     float4 *cl = (float4 *)(w + T.cen[l]);
     float *ml = mom + (size_t)T.off[l] * T.nc;
     if (l == D) {  // leaves: moments from their images
       with_order(P, [&](auto o) {
-        k_tree_moments<decltype(o)::value><<<gm, 256, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl,
-                                                     (const int *)(w + T.start[l]), simg, cl, ml);
+        k_tree_moments<decltype(o)::value><<<gm, 64, 0, st>>>(ncell + l, l, Lc, kl, (const int *)(w + T.start[l]),
+                                                              simg, cl, ml);
       });
     } else {  // upper levels: translated from the children
       const int *chl = (const int *)(w + T.child[l]);
       const float4 *cc = (const float4 *)(w + T.cen[l + 1]);
       const float *cm = mom + (size_t)T.off[l + 1] * T.nc;
       with_order(P, [&](auto o) {
-        k_tree_m2m<decltype(o)::value><<<(int)T.cap[l], 64, 0, st>>>((int)T.cap[l], ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+        k_tree_m2m<decltype(o)::value><<<gm, 64, 0, st>>>(ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
       });
     }
     const int gpk = (int)cdivl(T.cap[l], 256);
