@@ -401,6 +401,86 @@ __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, 
   }
 }
 
+// Surface nodes and their strengths (Q, D) in their sorted order.
+__global__ void k_tree_ngather(int pn, const int *__restrict__ perm, const float4 *__restrict__ nodes,
+                               const float2 *__restrict__ qd, float4 *__restrict__ snodes, float2 *__restrict__ sqd) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= pn) return;
+  const int i = perm[s];
+  snodes[s] = nodes[i];
+  sqd[s] = qd[i];
+}
+
+// Moments of the patches of surface nodes (runs of up to 64 sorted nodes within cells): one
+// wave per patch, a grid-stride loop.  A node y of strengths (Q, D) is a charge Q and the
+// radial dipole p = D y (its potential at x is Q / |x - y| + D (x - y).y / |x - y|^3, the form
+// of the direct sum), so with d = y - c
+//   M_k += Q d^k + sum_i p_i k_i d^(k - e_i),
+// the dipole's moments being p . grad_y of the charge's.  The centre is the centre of the
+// patch's bounding box; pstart gets each patch's first node and the end sentinel.
+template <int P>
+__global__ __launch_bounds__(64) void k_tree_patch(const int *__restrict__ npatch, const int2 *__restrict__ pr,
+                                                  const float4 *__restrict__ snodes, const float2 *__restrict__ sqd,
+                                                  int mono, float4 *__restrict__ pcen, int *__restrict__ pstart,
+                                                  float *__restrict__ pm) {
+  constexpr int NC = ncoef(P), NRND = (NC + 63) / 64;
+  __shared__ float pw[64][3][P + 1];
+  __shared__ float4 sw[64];  // Q, p
+  const int lane = threadIdx.x;
+  K3 kk[NRND];
+  for (int r = 0; r < NRND; ++r) kk[r] = kof(lane + 64 * r < NC ? lane + 64 * r : 0);
+  const int np = *npatch;
+  for (int g = blockIdx.x; g < np; g += gridDim.x) {
+    const int2 rg = pr[g];
+    const bool in = lane < rg.y;
+    const float4 y = snodes[rg.x + (in ? lane : 0)];
+    const float2 w = sqd[rg.x + (in ? lane : 0)];
+    float lo[3] = {y.x, y.y, y.z}, hi[3] = {y.x, y.y, y.z};
+    for (int o = 32; o > 0; o >>= 1)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], __shfl_xor(lo[a], o));
+        hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o));
+      }
+    const float c[3] = {0.5f * (lo[0] + hi[0]), 0.5f * (lo[1] + hi[1]), 0.5f * (lo[2] + hi[2])};
+    const float d[3] = {y.x - c[0], y.y - c[1], y.z - c[2]};
+    float rad = in ? sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) : 0.0f;
+    for (int o = 32; o > 0; o >>= 1) rad = fmaxf(rad, __shfl_xor(rad, o));
+    __syncthreads();  // the previous patch's tables are no longer read
+    if (in) {
+      for (int a = 0; a < 3; ++a) {
+        float pv = 1.0f;
+        for (int e = 0; e <= P; ++e) {
+          pw[lane][a][e] = pv;
+          pv *= d[a];
+        }
+      }
+      const float D = mono ? 0.0f : w.y;
+      sw[lane] = make_float4(w.x, D * y.x, D * y.y, D * y.z);
+    }
+    __syncthreads();
+    for (int r = 0; r < NRND; ++r) {
+      if (lane + 64 * r >= NC) break;
+      const K3 t = kk[r];
+      float m = 0.0f;
+      for (int i = 0; i < rg.y; ++i) {
+        const float px = pw[i][0][t.x], py = pw[i][1][t.y], pz = pw[i][2][t.z];
+        const float4 q = sw[i];
+        float v = q.x * px * py * pz;
+        if (t.x > 0) v = fmaf(q.y * (float)t.x, pw[i][0][t.x - 1] * py * pz, v);
+        if (t.y > 0) v = fmaf(q.z * (float)t.y, px * pw[i][1][t.y - 1] * pz, v);
+        if (t.z > 0) v = fmaf(q.w * (float)t.z, px * py * pw[i][2][t.z - 1], v);
+        m += v;
+      }
+      pm[(size_t)g * NC + lane + 64 * r] = m;
+    }
+    if (lane == 0) {
+      pcen[g] = make_float4(c[0], c[1], c[2], rad);
+      pstart[g] = rg.x;
+      if (g == np - 1) pstart[np] = rg.x + rg.y;
+    }
+  }
+}
+
 // Target groups: the sorted targets of each cell of the targets' grouping level in runs of up
 // to 64, so that no group straddles a jump of the space-filling order.  ng[c] = groups of cell c.
 __global__ void k_tree_gcount(int cap, const int *__restrict__ ncell, const int *__restrict__ start,
@@ -578,9 +658,12 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2
                                                             const int *__restrict__ gorder,
                                                             const int2 *__restrict__ gr,
                                                             const float4 *__restrict__ grp,
-                                                            const double *__restrict__ self, int Pn, int mono,
-                                                            const float4 *__restrict__ nodes,
-                                                            const float2 *__restrict__ qd, double *__restrict__ phi) {
+                                                            const double *__restrict__ self, int mono,
+                                                            const CellRec *__restrict__ prec,
+                                                            const float *__restrict__ pred,
+                                                            const int *__restrict__ npatch,
+                                                            const float4 *__restrict__ snodes,
+                                                            const float2 *__restrict__ sqd, double *__restrict__ phi) {
   constexpr int NR = nred(P);
   __shared__ int stack[TR_WAVES][TR_STACK];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -626,14 +709,22 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2
     }
   }
   if (far_start < n) direct_range(t.x, t.y, t.z, own, simg, far_start, n, acc);
-  // surface nodes, as the direct path
-  for (int sb = 0; sb < Pn; sb += 32) {
-    const int se = sb + 32 < Pn ? sb + 32 : Pn;
-    float sum = 0.0f;
-    int m = sb;
-    for (; m + 4 <= se; m += 4) surface_terms<4>(t.x, t.y, t.z, mono, nodes, qd, m, sum);
-    for (; m < se; ++m) surface_terms<1>(t.x, t.y, t.z, mono, nodes, qd, m, sum);
-    acc += (double)sum;
+  // surface nodes: each patch from its multipoles when the same test accepts it, else directly
+  const int np = *npatch;
+  for (int pc = 0; pc < np; ++pc) {
+    const CellRec rc = prec[pc];
+    const float dx = rc.cx - G.x, dy = rc.cy - G.y, dz = rc.cz - G.z;
+    const float rs = rc.r + G.w;
+    const int accept = __builtin_amdgcn_readfirstlane((int)(rs * rs < theta2 * (dx * dx + dy * dy + dz * dz)));
+    if (accept) {
+      acc += (double)taylor_dot<P>(t.x - rc.cx, t.y - rc.cy, t.z - rc.cz, pred + (size_t)pc * NR);
+    } else {
+      float sum = 0.0f;
+      int m = rc.s0;
+      for (; m + 4 <= rc.s1; m += 4) surface_terms<4>(t.x, t.y, t.z, mono, snodes, sqd, m, sum);
+      for (; m < rc.s1; ++m) surface_terms<1>(t.x, t.y, t.z, mono, snodes, sqd, m, sum);
+      acc += (double)sum;
+    }
   }
   if (in) {
     const int i = perm[s];
@@ -689,6 +780,13 @@ int target_level(int64_t n) {
 }
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Level of the nodes' cells in the cube of half-width 1.125 R_tau: the sphere crosses about
+// pi 4^l cells of level l, so that about 32 nodes fall in each.
+int patch_level(int pn) {
+  const int l = (int)std::lround(std::log2((double)(pn > 1 ? pn : 1) / 100.0) / 2.0);
+  return l < 0 ? 0 : (l > TR_TBITS ? TR_TBITS : l);
+}
+
 int auto_depth(int64_t n) {
   // the fastest depth measured on uniformly filled cavities: 7 at N = 10^6, 6 at 2 10^5
   const double d = 7.0 + (std::log2((double)(n > 1 ? n : 1)) - std::log2(1e6)) / 3.0;
@@ -697,17 +795,20 @@ int auto_depth(int64_t n) {
 }
 
 struct TreeLayout {
-  int D, P, nc, ngroups, lt;
-  int64_t cap[TR_MAX_DEPTH + 1], tcap;
+  int D, P, nc, ngroups, lt, pn, lp, npcap;
+  int64_t cap[TR_MAX_DEPTH + 1], tcap, ncap;
   size_t codes_a, codes_b, ids_a, ids_b, codes_t, ids_t, town, simg, stgt, inv, flags, scan, grp, gr, gng, gofs,
       tkey, tstart, tchild, gkey_a, gkey_b, gid_a, gid_b, ncell, ep, temp, temp_bytes;
   size_t key[TR_MAX_DEPTH + 1], start[TR_MAX_DEPTH + 1], child[TR_MAX_DEPTH + 1], cen[TR_MAX_DEPTH + 1];
   int64_t off[TR_MAX_DEPTH + 2];  // global number of each level's first cell; off[D + 1] = all cells
   size_t rec, mom, red;           // records, moments and folded moments of every cell, by global number
+  // surface nodes: sort, cells of level lp, patches and their records and moments
+  size_t ncodes_a, ncodes_b, nids_a, nids_b, nflags, nscan, snodes, sqd, nkey, nstart, nchild, nng, ngofs, pr, pcen,
+      pstart, pm, prec, pred;
   size_t total;
 };
 
-hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
+hsma_status tree_layout(int64_t n, int D, int P, int pn, size_t base, TreeLayout &T) {
   T.D = D;
   T.P = P;
   T.nc = ncoef(P);
@@ -731,8 +832,9 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
   T.flags = take(4 * N);
   T.scan = take(4 * N);
 
-  // cells per level; at TR_MAX_DEPTH + 1 the number of target groups, at + 2 of target cells
-  T.ncell = take(4 * (TR_MAX_DEPTH + 3));
+  // cells per level; at TR_MAX_DEPTH + 1 the number of target groups, at + 2 of target cells,
+  // at + 3 of node cells, at + 4 of node patches
+  T.ncell = take(4 * (TR_MAX_DEPTH + 5));
   T.ep = take(8 * (size_t)cdivl(n, 256));
   for (int l = 0; l <= D; ++l) {
     int64_t c = (int64_t)1 << (3 * l);
@@ -765,11 +867,35 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
     T.off[l + 1] = T.off[l] + c;
   }
   T.rec = take(sizeof(CellRec) * (size_t)T.off[D + 1]);
+  T.pn = pn;
+  const size_t PN = (size_t)(pn > 0 ? pn : 1);
+  T.lp = patch_level(pn);
+  T.ncap = std::min<int64_t>((int64_t)1 << (3 * T.lp), (int64_t)PN);
+  T.npcap = (int)(cdivl((int64_t)PN, 64) + T.ncap);
+  T.ncodes_a = take(4 * PN);
+  T.ncodes_b = take(4 * PN);
+  T.nids_a = take(4 * PN);
+  T.nids_b = take(4 * PN);
+  T.nflags = take(4 * PN);
+  T.nscan = take(4 * PN);
+  T.snodes = take(16 * PN);
+  T.sqd = take(8 * PN);
+  T.nkey = take(4 * (size_t)T.ncap);
+  T.nstart = take(4 * ((size_t)T.ncap + 1));
+  T.nchild = take(4 * ((size_t)T.ncap + 1));
+  T.nng = take(4 * (size_t)T.ncap);
+  T.ngofs = take(4 * (size_t)T.ncap);
+  T.pr = take(8 * (size_t)T.npcap);
+  T.pcen = take(16 * (size_t)T.npcap);
+  T.pstart = take(4 * ((size_t)T.npcap + 1));
+  T.pm = take(4 * (size_t)T.npcap * T.nc);
+  T.prec = take(sizeof(CellRec) * (size_t)T.npcap);
+  T.pred = take(4 * (size_t)T.npcap * nred(P));
   T.mom = take(4 * (size_t)T.off[D + 1] * T.nc);
   T.red = take(4 * (size_t)T.off[D + 1] * nred(P));
   size_t sort_b = 0, scan_b = 0;
   // the images' sort, the targets', and the groups' launch order (up to 2 N groups)
-  const unsigned ns = (unsigned)std::max<int64_t>((int64_t)N, T.ngroups);
+  const unsigned ns = (unsigned)std::max<int64_t>(std::max<int64_t>((int64_t)N, T.ngroups), (int64_t)PN);
   for (int bits : {31, 3 * TR_TBITS, 32}) {
     size_t b = 0;
     if (rocprim::radix_sort_pairs(nullptr, b, (const unsigned *)nullptr, (unsigned *)nullptr, (const int *)nullptr,
@@ -777,7 +903,8 @@ hsma_status tree_layout(int64_t n, int D, int P, size_t base, TreeLayout &T) {
       return HSMA_EDEVICE;
     sort_b = b > sort_b ? b : sort_b;
   }
-  if (rocprim::exclusive_scan(nullptr, scan_b, (const int *)nullptr, (int *)nullptr, 0, N, rocprim::plus<int>()) !=
+  if (rocprim::exclusive_scan(nullptr, scan_b, (const int *)nullptr, (int *)nullptr, 0, std::max(N, PN),
+                              rocprim::plus<int>()) !=
       hipSuccess)
     return HSMA_EDEVICE;
   T.temp_bytes = sort_b > scan_b ? sort_b : scan_b;
@@ -810,7 +937,7 @@ extern "C" size_t hsma_tree_workspace_bytes(hsma_plan_t pl, int64_t N, const hsm
   if (tree_args(pl, N, opts, D, P, th) != HSMA_OK) return 0;
   Layout L = layout(pl->self, 1, N, N, false, true);
   TreeLayout T;
-  if (tree_layout(N, D, P, L.total, T) != HSMA_OK) return 0;
+  if (tree_layout(N, D, P, pl->self->P_ev, L.total, T) != HSMA_OK) return 0;
   return T.total;
 }
 
@@ -828,7 +955,7 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
   Layout L = layout(pl->self, 1, N, N, false, true);
   L.upto_fit = true;
   TreeLayout T;
-  rc = tree_layout(N, D, P, L.total, T);
+  rc = tree_layout(N, D, P, pl->self->P_ev, L.total, T);
   if (rc != HSMA_OK) return rc;
   if (ws_bytes < T.total) return HSMA_EINVAL;
   char *w = (char *)ws;
@@ -929,6 +1056,46 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
     size_t tb3 = T.temp_bytes;
     HSMA_HIP(rocprim::radix_sort_pairs(w + T.temp, tb3, gka, gkb, gia, gib, (unsigned)T.ngroups, 0, 32, st));
   }
+  {
+    // surface nodes: sorted by their codes in the cube of half-width 1.125 R_tau (the nodes of
+    // point pairs lie within R_tau (1 + dy/2R_tau)), cells of level lp, patches of up to 64
+    // nodes within each cell, their moments and records
+    const int pn = T.pn;
+    const int nbp = (int)cdivl(pn, 256);
+    unsigned *nca = (unsigned *)(w + T.ncodes_a), *ncb = (unsigned *)(w + T.ncodes_b);
+    int *nia = (int *)(w + T.nids_a), *nib = (int *)(w + T.nids_b);
+    int *nfl = (int *)(w + T.nflags), *nsc = (int *)(w + T.nscan);
+    float4 *snodes = (float4 *)(w + T.snodes);
+    float2 *sqd = (float2 *)(w + T.sqd);
+    const float Rn = (float)(1.125 * (1.0 + pl->opts.tau) * pl->a);
+    k_tree_tkeys<<<nbp, 256, 0, st>>>(pn, Rn, pl->self->nodes32, nca, nia);
+    size_t tb4 = T.temp_bytes;
+    HSMA_HIP(rocprim::radix_sort_pairs(w + T.temp, tb4, nca, ncb, nia, nib, (unsigned)pn, 0, 3 * TR_TBITS, st));
+    k_tree_ngather<<<nbp, 256, 0, st>>>(pn, nib, pl->self->nodes32, qd, snodes, sqd);
+    const int nshift = 3 * (TR_TBITS - T.lp);
+    int *nccount = ncell + TR_MAX_DEPTH + 3, *npatch = ncell + TR_MAX_DEPTH + 4;
+    k_tree_flags<<<nbp, 256, 0, st>>>(pn, nullptr, pn, ncb, nshift, nfl);
+    size_t sb = T.temp_bytes;
+    HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, nfl, nsc, 0, (size_t)pn, rocprim::plus<int>(), st));
+    k_tree_cells<<<nbp, 256, 0, st>>>(pn, nullptr, pn, pn, ncb, nshift, nullptr, nfl, nsc, (unsigned *)(w + T.nkey),
+                                      (int *)(w + T.nchild), (int *)(w + T.nstart), nccount);
+    const int gcn = (int)cdivl(T.ncap, 256);
+    int *nng = (int *)(w + T.nng), *ngofs = (int *)(w + T.ngofs);
+    const int *nstart = (const int *)(w + T.nstart);
+    k_tree_gcount<<<gcn, 256, 0, st>>>((int)T.ncap, nccount, nstart, nng);
+    sb = T.temp_bytes;
+    HSMA_HIP(rocprim::exclusive_scan(w + T.temp, sb, nng, ngofs, 0, (size_t)T.ncap, rocprim::plus<int>(), st));
+    k_tree_gfill<<<gcn, 256, 0, st>>>((int)T.ncap, nccount, nstart, nng, ngofs, (int2 *)(w + T.pr), npatch);
+    float4 *pcen = (float4 *)(w + T.pcen);
+    int *pstart = (int *)(w + T.pstart);
+    float *pm = (float *)(w + T.pm);
+    with_order(P, [&](auto o) {
+      k_tree_patch<decltype(o)::value><<<std::min(T.npcap, 1024), 64, 0, st>>>(
+          npatch, (const int2 *)(w + T.pr), snodes, sqd, pl->self->dipole == 2, pcen, pstart, pm);
+      k_tree_pack<decltype(o)::value><<<(int)cdivl(T.npcap, 256), 256, 0, st>>>(
+          T.npcap, npatch, 1, 0, 0, pcen, pstart, pstart, pm, (CellRec *)(w + T.prec), (float *)(w + T.pred));
+    });
+  }
   const hsma_group_s *grp = pl->self;
   const int ge = (int)cdivl(T.ngroups, TR_WAVES);
   const float4 *gp = (const float4 *)(w + T.grp);
@@ -940,9 +1107,10 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
   const int *gord = (const int *)(w + T.gid_b);
   const int2 *grr = (const int2 *)(w + T.gr);
   with_order(P, [&](auto o) {
-    k_tree_eval<decltype(o)::value><<<ge, 64 * TR_WAVES, 0, st>>>(n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t,
-                                                       ngp, gord, grr, gp, self, grp->P_ev, grp->dipole == 2,
-                                                       grp->nodes32, qd, phi);
+    k_tree_eval<decltype(o)::value><<<ge, 64 * TR_WAVES, 0, st>>>(
+        n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr, gp, self, grp->dipole == 2,
+        (const CellRec *)(w + T.prec), (const float *)(w + T.pred), ncell + TR_MAX_DEPTH + 4,
+        (const float4 *)(w + T.snodes), (const float2 *)(w + T.sqd), phi);
   });
   if (E) {
     double *ep = (double *)(w + T.ep);
