@@ -15,6 +15,9 @@ C ABI, against the oracle's direct HSMA sum (O1).
   theta = 0.4 meet the method's 1e-6.  The moments are folded onto the k_z <= 1 set by the
   harmonic identity of the Taylor coefficients, an exact rewriting: a mistake in it would show
   here as errors of the order of the moments themselves.
+* The surface nodes are summed in patches, by multipoles where the same test accepts them: the
+  single-layer form (charges only) and the point-pair dipoles (3P nodes) at theta = 0 and 0.5,
+  and plain FP32 pairs.
 """
 import numpy as np
 import pytest
@@ -111,15 +114,26 @@ def test_error_falls_with_order_and_theta(dev):
     plan.close()
 
 
-def test_single_layer_and_plain_fp32_plans(dev):
+# (plan options, theta, order) -> bound on the relative L2 error against O1: theta = 0 is the
+# direct sum; at theta = 0.5, order 6 (measured 6.8e-8 and 8.6e-8 on this small system, whose
+# far node patches are taken by multipoles) the bound covers the patches' moments of the
+# single-layer form (charges only) and of the point-pair dipoles (3P nodes at R_tau -+ dy/2,
+# whose pairs nearly cancel); a wrong dipole term would show at the size of the surface sum
+PLAN_CASES = [({"pair_prec": "fp32c", "dipole": 2}, 0.0, 2, 2e-6), ({"pair_prec": "fp32"}, 0.0, 2, 2e-6),
+              ({"pair_prec": "fp32c", "dipole": 2}, 0.5, 6, 1e-6), ({"pair_prec": "fp32c", "dipole": 1}, 0.0, 4, 2e-6),
+              ({"pair_prec": "fp32c", "dipole": 1}, 0.5, 6, 1e-6)]
+
+
+@pytest.mark.parametrize("kw,theta,order,bound", PLAN_CASES)
+def test_plan_variants(dev, kw, theta, order, bound):
     a = 20.0
     s = _system(3000, a, W.SEED_BASE + 530)
-    for kw in ({"pair_prec": "fp32c", "dipole": 2}, {"pair_prec": "fp32"}):
-        plan = hs.Plan(a, 1.0, 80.0, 0.3, 1024, 1536, **kw)
-        phi, _ = _run(plan, s, dev, theta=0.0, order=2)
-        ref = oracle.hsma_eval(_params(plan), s.x, s.y, s.z, s.q)
-        assert _rel(phi, ref) <= 2e-6, (kw, _rel(phi, ref))
-        plan.close()
+    plan = hs.Plan(a, 1.0, 80.0, 0.3, 1024, 1536, **kw)
+    phi, _ = _run(plan, s, dev, theta=theta, order=order)
+    ref = oracle.hsma_eval(_params(plan), s.x, s.y, s.z, s.q)
+    print(f"{kw} theta {theta} order {order}: rel L2 {_rel(phi, ref):.2e}", flush=True)
+    assert _rel(phi, ref) <= bound, (kw, _rel(phi, ref))
+    plan.close()
 
 
 def test_invalid_arguments(dev):
