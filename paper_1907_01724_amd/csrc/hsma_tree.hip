@@ -331,9 +331,13 @@ __global__ __launch_bounds__(64) void k_tree_moments(const int *__restrict__ nce
 // grid-stride loop; a cell of the cube has at most 8 children, stored consecutively): the
 // children's moments and the powers of their offsets are staged in LDS with a table of binomial
 // coefficients, then the lanes take the k.  The radius bound is max over children of
-// |c_child - c_parent| + r_child.
+// |c_child - c_parent| + r_child.  Every group centre lies in the cavity, |g| <= a, so a cell with
+// r_c >= theta (|c| + a) fails the acceptance test for every group: its moments are never read
+// and are written as zeros instead (the upper levels, whose cells span much of the cube, and
+// every cell at theta = 0).
 template <int P>
-__global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, int level, float L,
+__global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, int level, float L, float theta,
+                                                float a,
                                                 const unsigned *__restrict__ key, const int *__restrict__ child,
                                                 const float4 *__restrict__ ccen, const float *__restrict__ cmom,
                                                 float4 *__restrict__ cen, float *__restrict__ mom) {
@@ -362,7 +366,6 @@ __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, 
     const int k0 = child[c];
     const int nch = min(child[c + 1] - k0, 8);
     __syncthreads();  // the previous parent's tables are no longer read
-    for (int e = lane; e < nch * NC; e += 64) sm[e] = cmom[(size_t)k0 * NC + e];
     if (lane < nch) {
       const float4 cc = ccen[k0 + lane];
       const float d[3] = {cc.x - ce.x, cc.y - ce.y, cc.z - ce.z};
@@ -375,6 +378,16 @@ __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, 
         }
       }
     }
+    __syncthreads();
+    float rad = 0.0f;
+    for (int ch = 0; ch < nch; ++ch) rad = fmaxf(rad, rad8[ch]);
+    if (lane == 0) cen[c] = make_float4(ce.x, ce.y, ce.z, rad);
+    // never accepted (a margin of 1e-4 over the rounding of the traversal's test)
+    if (rad >= 1.0001f * theta * (sqrtf(ce.x * ce.x + ce.y * ce.y + ce.z * ce.z) + a)) {
+      for (int e = lane; e < NC; e += 64) mom[(size_t)c * NC + e] = 0.0f;
+      continue;
+    }
+    for (int e = lane; e < nch * NC; e += 64) sm[e] = cmom[(size_t)k0 * NC + e];
     __syncthreads();
     for (int r = 0; r < NRND; ++r) {
       if (lane + 64 * r >= NC) break;
@@ -392,11 +405,6 @@ __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, 
         }
       }
       mom[(size_t)c * NC + lane + 64 * r] = v;
-    }
-    if (lane == 0) {
-      float rad = 0.0f;
-      for (int ch = 0; ch < nch; ++ch) rad = fmaxf(rad, rad8[ch]);
-      cen[c] = make_float4(ce.x, ce.y, ce.z, rad);
     }
   }
 }
@@ -1014,7 +1022,8 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
       const float4 *cc = (const float4 *)(w + T.cen[l + 1]);
       const float *cm = mom + (size_t)T.off[l + 1] * T.nc;
       with_order(P, [&](auto o) {
-        k_tree_m2m<decltype(o)::value><<<gm, 64, 0, st>>>(ncell + l, l, Lc, kl, chl, cc, cm, cl, ml);
+        k_tree_m2m<decltype(o)::value><<<gm, 64, 0, st>>>(ncell + l, l, Lc, theta, (float)pl->a, kl, chl, cc, cm,
+                                                          cl, ml);
       });
     }
     const int gpk = (int)cdivl(T.cap[l], 256);
