@@ -289,23 +289,24 @@ int hsma_group_fit_route(hsma_group_t group, int nsys);
 hsma_status hsma_profile_enable(hsma_group_t group, int on);
 hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int64_t *count /* [host] 5 */);
 
-/* Treecode far field for the Kelvin-image sum of one system (the role of the FMM the paper
- * uses for N up to 10^6, Sec. 3 and Sec. 4.2), as a Barnes-Hut treecode in the FP32 pair modes.
- * The check sums, the fit and the surface sums are those of hsma_energy; only the sum over the
- * other ions' Kelvin images is approximated.  The images are sorted into an octree over the
- * cube of half-width 8a (depth levels below the root; images farther out, of ions within a/8 of
- * the centre, are summed directly).  The targets are grouped by their own positions, in groups
- * of up to 64.  A cell of radius r_c at distance d from a group of radius r_g is evaluated from
- * its Cartesian multipole moments of the given order when r_c + r_g < theta d, else opened;
- * leaves that are not accepted are summed directly.
- *   theta: in [0, 1); 0 accepts no cell (every image is then summed directly, the check of the
- *          traversal); order: 2, 4, 6 or 8; depth: 2..9, or 0 for a depth from N (7 at
+/* Treecode far field for the Kelvin-image and surface sums of one system (the role of the FMM
+ * the paper uses for N up to 10^6, Sec. 3 and Sec. 4.2), as a Barnes-Hut treecode in the FP32
+ * pair modes.  The check sums and the fit are those of hsma_energy; the sums over the other
+ * ions' Kelvin images and over the surface nodes are approximated.  The images are sorted into
+ * an octree over the cube of half-width 8a (depth levels below the root; images farther out, of
+ * ions within a/8 of the centre, are summed directly), the surface nodes into patches of up to
+ * 64.  The targets are grouped by their own positions, in groups of up to 64.  A cell or patch
+ * of radius r_c at distance d from a group of radius r_g is evaluated from its Cartesian
+ * multipole moments of the given order when r_c + r_g < theta d, else opened; leaves and
+ * patches that are not accepted are summed directly.
+ *   theta: in [0, 1); 0 accepts no cell (every image and node is then summed directly, the
+ *          check of the traversal); order: 2, 4, 6 or 8; depth: 2..9, or 0 for a depth from N (7 at
  *          N = 10^6).
  * The error is the treecode's. On 10^6 ions uniform in a cavity with balanced charges, the
- * relative L2 errors of the potentials are 9.5e-4 (order 4, theta 0.5), 9.3e-5 (order 6,
- * theta 0.5), 1.4e-5 (order 6, theta 0.4), 1.5e-6 (order 6, theta 0.3) and 1.2e-6 (order 8,
- * theta 0.4).  Against the direct symmetric sums of hsma_energy these run 10.5, 6.8, 5.0, 2.9
- * and 3.2 times faster; near 2 10^5 ions the two paths are about even, and below that the
+ * relative L2 errors of sampled potentials are 9.5e-4 (order 4, theta 0.5), 9.4e-5 (order 6,
+ * theta 0.5), 1.4e-5 (order 6, theta 0.4) and 1.3e-6 (order 8, theta 0.4).  Against the direct
+ * symmetric sums of hsma_energy these run 13, 8.2, 5.9 and 3.8 times faster; at 2 10^5 ions
+ * 2.1 times at order 4, theta 0.5, and even at order 6, theta 0.4; below about 10^5 ions the
  * direct path is faster at any setting.
  *   phi: [device] N doubles (required); E: [device] one double or NULL;
  *   ws: [device] ws_bytes >= hsma_tree_workspace_bytes(plan, N, opts) (0 for invalid arguments).
