@@ -1,4 +1,4 @@
-// Treecode far field for the Kelvin-image sum (the role of the paper's FMM in Sec. 3 and
+// Treecode far field for the Kelvin-image and surface sums (the role of the paper's FMM in Sec. 3 and
 // Sec. 4.2, as a Barnes-Hut treecode): one system, FP32 pair modes.
 //
 // Every Kelvin image lies outside the cavity and every target inside it.  The images are
@@ -24,7 +24,11 @@
 // of one or two targets, each with a whole traversal.)
 //
 // The check sums, the fit and the surface strengths are those of the direct path
-// (run_front); the surface nodes are summed directly per target after the traversal.
+// (run_front).  The surface nodes are sorted the same way into patches of up to 64, with
+// moments that include their radial dipoles, and each group takes them by the same rule after
+// the traversal.  The moments of cells and patches are folded onto the multi-indices with
+// k_z <= 1 by the harmonic identity of the Taylor coefficients (see fold_rec), so that an
+// accepted cell costs (p + 1)^2 terms.
 #include <cmath>
 #include <type_traits>
 
