@@ -331,25 +331,27 @@ __global__ __launch_bounds__(64) void k_tree_moments(const int *__restrict__ nce
 
 // Moments of the cells of level l < D from their children (level l + 1), about the parent's
 // centre: M_k(parent) = sum over children and j <= k of C(k, j) (c_child - c_parent)^(k - j)
-// M_j(child), with C the product of the three binomial coefficients.  One wave per parent (a
-// grid-stride loop; a cell of the cube has at most 8 children, stored consecutively): the
-// children's moments and the powers of their offsets are staged in LDS with a table of binomial
-// coefficients, then the lanes take the k.  The radius bound is max over children of
+// M_j(child), with C the product of the three binomial coefficients.  The shift factorises into
+// three one-dimensional shifts, taken as three passes over (child, k) in LDS (z, then y, then x,
+// the last one also summing over the children in order), so that no lane sums more than p + 1
+// terms per item.  One wave per parent (a grid-stride loop; a cell of the cube has at most 8
+// children, stored consecutively).  The radius bound is max over children of
 // |c_child - c_parent| + r_child.  Every group centre lies in the cavity, |g| <= a, so a cell with
 // r_c >= theta (|c| + a) fails the acceptance test for every group: its moments are never read
 // and are written as zeros instead (the upper levels, whose cells span much of the cube, and
 // every cell at theta = 0).
 template <int P>
 __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, int level, float L, float theta,
-                                                float a,
-                                                const unsigned *__restrict__ key, const int *__restrict__ child,
-                                                const float4 *__restrict__ ccen, const float *__restrict__ cmom,
-                                                float4 *__restrict__ cen, float *__restrict__ mom) {
-  constexpr int NC = ncoef(P), NRND = (NC + 63) / 64;
-  __shared__ float sm[8 * NC];
+                                                float a, const unsigned *__restrict__ key,
+                                                const int *__restrict__ child, const float4 *__restrict__ ccen,
+                                                const float *__restrict__ cmom, float4 *__restrict__ cen,
+                                                float *__restrict__ mom) {
+  constexpr int NC = ncoef(P);
+  __shared__ float sa[8 * NC], sb[8 * NC];
   __shared__ float pw[8][3][P + 1];
   __shared__ float bin[P + 1][P + 1];
   __shared__ float rad8[8];
+  __shared__ int kt[NC];  // k_x | k_y << 8 | k_z << 16 of each index
   const int lane = threadIdx.x;
   for (int e = lane; e < (P + 1) * (P + 1); e += 64) {  // C(i, j), exact in FP32 for i <= 8
     const int i = e / (P + 1), j = e % (P + 1);
@@ -357,8 +359,10 @@ __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, 
     for (int u = 1; u <= j; ++u) b = b * (float)(i - j + u) / (float)u;
     bin[i][j] = j <= i ? b : 0.0f;
   }
-  K3 kk[NRND];
-  for (int r = 0; r < NRND; ++r) kk[r] = kof(lane + 64 * r < NC ? lane + 64 * r : 0);
+  for (int k = lane; k < NC; k += 64) {
+    const K3 t = kof(k);
+    kt[k] = t.x | (t.y << 8) | (t.z << 16);
+  }
   const int nc = *ncell;
   for (int c = blockIdx.x; c < nc; c += gridDim.x) {
     const unsigned k = key[c];
@@ -374,11 +378,11 @@ __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, 
       const float4 cc = ccen[k0 + lane];
       const float d[3] = {cc.x - ce.x, cc.y - ce.y, cc.z - ce.z};
       rad8[lane] = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) + cc.w;
-      for (int a = 0; a < 3; ++a) {
-        float p = 1.0f;
+      for (int ax = 0; ax < 3; ++ax) {
+        float pv = 1.0f;
         for (int e = 0; e <= P; ++e) {
-          pw[lane][a][e] = p;
-          p *= d[a];
+          pw[lane][ax][e] = pv;
+          pv *= d[ax];
         }
       }
     }
@@ -391,24 +395,38 @@ __global__ __launch_bounds__(64) void k_tree_m2m(const int *__restrict__ ncell, 
       for (int e = lane; e < NC; e += 64) mom[(size_t)c * NC + e] = 0.0f;
       continue;
     }
-    for (int e = lane; e < nch * NC; e += 64) sm[e] = cmom[(size_t)k0 * NC + e];
+    for (int e = lane; e < nch * NC; e += 64) sa[e] = cmom[(size_t)k0 * NC + e];
     __syncthreads();
-    for (int r = 0; r < NRND; ++r) {
-      if (lane + 64 * r >= NC) break;
-      const K3 t = kk[r];
+    // z: sb(x, y, z) = sum_{j <= z} C(z, j) d_z^(z - j) sa(x, y, j)
+    for (int e = lane; e < nch * NC; e += 64) {
+      const int ch = e / NC, t = kt[e - ch * NC];
+      const int x = t & 255, y = (t >> 8) & 255, z = t >> 16;
+      const float *src = sa + ch * NC;
+      float v = 0.0f;
+      for (int j = 0; j <= z; ++j) v = fmaf(bin[z][j] * pw[ch][2][z - j], src[kidx(x, y, j)], v);
+      sb[e] = v;
+    }
+    __syncthreads();
+    // y: sa(x, y, z) = sum_{j <= y} C(y, j) d_y^(y - j) sb(x, j, z)
+    for (int e = lane; e < nch * NC; e += 64) {
+      const int ch = e / NC, t = kt[e - ch * NC];
+      const int x = t & 255, y = (t >> 8) & 255, z = t >> 16;
+      const float *src = sb + ch * NC;
+      float v = 0.0f;
+      for (int j = 0; j <= y; ++j) v = fmaf(bin[y][j] * pw[ch][1][y - j], src[kidx(x, j, z)], v);
+      sa[e] = v;
+    }
+    __syncthreads();
+    // x, summed over the children in order: M(x, y, z) = sum_ch sum_{j <= x} C(x, j) d_x^(x - j) sa(j, y, z)
+    for (int e = lane; e < NC; e += 64) {
+      const int t = kt[e];
+      const int x = t & 255, y = (t >> 8) & 255, z = t >> 16;
       float v = 0.0f;
       for (int ch = 0; ch < nch; ++ch) {
-        const float *cm = sm + ch * NC;
-        for (int jx = 0; jx <= t.x; ++jx) {
-          const float fx = bin[t.x][jx] * pw[ch][0][t.x - jx];
-          for (int jy = 0; jy <= t.y; ++jy) {
-            const float fxy = fx * bin[t.y][jy] * pw[ch][1][t.y - jy];
-            for (int jz = 0; jz <= t.z; ++jz)
-              v = fmaf(fxy * (bin[t.z][jz] * pw[ch][2][t.z - jz]), cm[kidx(jx, jy, jz)], v);
-          }
-        }
+        const float *src = sa + ch * NC;
+        for (int j = 0; j <= x; ++j) v = fmaf(bin[x][j] * pw[ch][0][x - j], src[kidx(j, y, z)], v);
       }
-      mom[(size_t)c * NC + lane + 64 * r] = v;
+      mom[(size_t)c * NC + e] = v;
     }
   }
 }
