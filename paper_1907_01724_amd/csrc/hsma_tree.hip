@@ -90,7 +90,7 @@ __host__ __device__ constexpr K3 rof(int k) {  // the k-th multi-index of the re
 // a_k(R) for |k| <= P, k_z <= 1, into a[nred(P)], one coefficient per instantiation, each
 // added into v = sum_k a_k m_k as soon as it is formed (so that a coefficient is dead two
 // degrees later, which keeps the registers of high orders down).
-template <int P, int K>
+template <int P, int K, bool DOT = true>
 __device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float ir2, float (&a)[nred(P)],
                                            const float *__restrict__ m, float &v) {
   if constexpr (K < nred(P)) {
@@ -104,8 +104,8 @@ __device__ __forceinline__ void taylor_rec(float rx, float ry, float rz, float i
     if constexpr (t.x >= 2) s2 += a[ridx(t.x - 2, t.y, t.z)];
     if constexpr (t.y >= 2) s2 += a[ridx(t.x, t.y - 2, t.z)];
     a[K] = (c1 * s1 - c2 * s2) * ir2;
-    v = fmaf(a[K], m[K], v);
-    taylor_rec<P, K + 1>(rx, ry, rz, ir2, a, m, v);
+    if constexpr (DOT) v = fmaf(a[K], m[K], v);
+    taylor_rec<P, K + 1, DOT>(rx, ry, rz, ir2, a, m, v);
   }
 }
 
@@ -118,6 +118,47 @@ __device__ __forceinline__ float taylor_dot(float rx, float ry, float rz, const 
   float v = fmaf(ir, m[0], 0.0f);
   taylor_rec<P, 1>(rx, ry, rz, ir * ir, a, m, v);
   return v;
+}
+
+// the reduced coefficients a_k(R) alone
+template <int P>
+__device__ __forceinline__ void taylor_coef(float rx, float ry, float rz, float (&a)[nred(P)]) {
+  const float ir = __builtin_amdgcn_rsqf(rx * rx + ry * ry + rz * rz);
+  a[0] = ir;
+  float unused = 0.0f;
+  taylor_rec<P, 1, false>(rx, ry, rz, ir * ir, a, nullptr, unused);
+}
+
+// The coefficients with k_z >= 2 of a harmonic expansion from those with k_z <= 1, by the
+// identity above, in increasing index order (both terms of a k have a lower index).
+template <int P, int K>
+__device__ __forceinline__ void unfold_rec(float (&f)[ncoef(P)]) {
+  if constexpr (K < ncoef(P)) {
+    constexpr K3 t = kof(K);
+    if constexpr (t.z >= 2) {
+      constexpr float d = (float)(t.z * (t.z - 1));
+      constexpr float cx = (float)((t.x + 2) * (t.x + 1)) / d, cy = (float)((t.y + 2) * (t.y + 1)) / d;
+      f[K] = -fmaf(cx, f[kidx(t.x + 2, t.y, t.z - 2)], cy * f[kidx(t.x, t.y + 2, t.z - 2)]);
+    }
+    unfold_rec<P, K + 1>(f);
+  }
+}
+
+// sum_k L_k x^k over |k| <= P, the monomials built along the graded order
+template <int P, int K>
+__device__ __forceinline__ void local_rec(float x, float y, float z, float (&xk)[ncoef(P)],
+                                          const float *__restrict__ L, float &v) {
+  if constexpr (K < ncoef(P)) {
+    constexpr K3 t = kof(K);
+    if constexpr (t.x >= 1)
+      xk[K] = xk[kidx(t.x - 1, t.y, t.z)] * x;
+    else if constexpr (t.y >= 1)
+      xk[K] = xk[kidx(t.x, t.y - 1, t.z)] * y;
+    else
+      xk[K] = xk[kidx(t.x, t.y, t.z - 1)] * z;
+    v = fmaf(L[K], xk[K], v);
+    local_rec<P, K + 1>(x, y, z, xk, L, v);
+  }
 }
 
 // Folds the moments with k_z >= 2 into those of two lower k_z (the identity above), from the
@@ -133,6 +174,15 @@ __device__ __forceinline__ void fold_rec(float (&f)[ncoef(P)]) {
       f[kidx(t.x, t.y + 2, t.z - 2)] = fmaf(-cy, f[K], f[kidx(t.x, t.y + 2, t.z - 2)]);
     }
     fold_rec<P, K - 1>(f);
+  }
+}
+
+template <int P, int K>
+__device__ __forceinline__ void scatter_red(const float (&r)[nred(P)], float (&f)[ncoef(P)]) {
+  if constexpr (K < nred(P)) {
+    constexpr K3 t = rof(K);
+    f[kidx(t.x, t.y, t.z)] = r[K];
+    scatter_red<P, K + 1>(r, f);
   }
 }
 
@@ -647,6 +697,44 @@ __device__ __forceinline__ void direct_range(float tx, float ty, float tz, int o
     direct_blocks<false>(tx, ty, tz, own, simg, s0, s1, acc);
 }
 
+// Local expansion about the centre of the far set (the images outside the cube, beyond 8a,
+// of ions within a/8 of the centre), for theta > 0: every target lies within a of the centre,
+// so 1/|y - x| = sum_k a_k(y) x^k converges like (1/8)^(p+1), far below the treecode's own
+// truncation.  L_k = sum_far q_K a_k(y_K) over the reduced k (one lane per image, then a fixed
+// butterfly over the lanes), the others from the harmonic identity.  One wave.
+template <int P>
+__global__ __launch_bounds__(64) void k_tree_local(int n, const unsigned *__restrict__ key0,
+                                                  const int *__restrict__ start0, const int *__restrict__ ncell,
+                                                  const float4 *__restrict__ simg, float *__restrict__ Lout) {
+  constexpr int NR = nred(P), NC = ncoef(P);
+  const int lane = threadIdx.x;
+  int far_start = n;
+  for (int c = 0; c < ncell[0]; ++c)
+    if (key0[c] != 0u) far_start = start0[c];
+  float acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0.0f;
+  for (int j = far_start + lane; j < n; j += 64) {
+    const float4 v = simg[j];
+    float a[NR];
+    taylor_coef<P>(v.x, v.y, v.z, a);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = fmaf(v.w, a[k], acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+    for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+  if (lane == 0) {
+    float f[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) f[k] = 0.0f;
+    scatter_red<P, 0>(acc, f);
+    unfold_rec<P, 0>(f);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Lout[k] = f[k];
+  }
+}
+
 template <int U>
 __device__ __forceinline__ void surface_terms(float tx, float ty, float tz, int mono, const float4 *__restrict__ nodes,
                                               const float2 *__restrict__ qd, int m, float &sum) {
@@ -689,6 +777,7 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2
                                                             const int2 *__restrict__ gr,
                                                             const float4 *__restrict__ grp,
                                                             const double *__restrict__ self, int mono,
+                                                            const float *__restrict__ Lfar,
                                                             const CellRec *__restrict__ prec,
                                                             const float *__restrict__ pred,
                                                             const int *__restrict__ npatch,
@@ -738,7 +827,22 @@ __global__ __launch_bounds__(64 * TR_WAVES) void k_tree_eval(int n, float theta2
       for (int k = rc.k1 - 1; k >= rc.k0 && sp < TR_STACK; --k) stack[w][sp++] = k;
     }
   }
-  if (far_start < n) direct_range(t.x, t.y, t.z, own, simg, far_start, n, acc);
+  if (far_start < n) {
+    if (theta2 > 0.0f) {  // the local expansion of the far set; an own image there is taken out
+      float xk[ncoef(P)];  // monomials t^k
+      xk[0] = 1.0f;
+      float v = Lfar[0];
+      local_rec<P, 1>(t.x, t.y, t.z, xk, Lfar, v);
+      if (own >= far_start) {
+        const float4 o = simg[own];
+        const float ox = t.x - o.x, oy = t.y - o.y, oz = t.z - o.z;
+        v -= o.w * __builtin_amdgcn_rsqf(ox * ox + oy * oy + oz * oz);
+      }
+      acc += (double)v;
+    } else {
+      direct_range(t.x, t.y, t.z, own, simg, far_start, n, acc);
+    }
+  }
   // surface nodes: each patch from its multipoles when the same test accepts it, else directly
   const int np = *npatch;
   for (int pc = 0; pc < np; ++pc) {
@@ -832,6 +936,7 @@ struct TreeLayout {
   size_t key[TR_MAX_DEPTH + 1], start[TR_MAX_DEPTH + 1], child[TR_MAX_DEPTH + 1], cen[TR_MAX_DEPTH + 1];
   int64_t off[TR_MAX_DEPTH + 2];  // global number of each level's first cell; off[D + 1] = all cells
   size_t rec, mom, red;           // records, moments and folded moments of every cell, by global number
+  size_t lfar;                    // local expansion of the far set, ncoef(P) floats
   // surface nodes: sort, cells of level lp, patches and their records and moments
   size_t ncodes_a, ncodes_b, nids_a, nids_b, nflags, nscan, snodes, sqd, nkey, nstart, nchild, nng, ngofs, pr, pcen,
       pstart, pm, prec, pred;
@@ -923,6 +1028,7 @@ hsma_status tree_layout(int64_t n, int D, int P, int pn, size_t base, TreeLayout
   T.pred = take(4 * (size_t)T.npcap * nred(P));
   T.mom = take(4 * (size_t)T.off[D + 1] * T.nc);
   T.red = take(4 * (size_t)T.off[D + 1] * nred(P));
+  T.lfar = take(4 * (size_t)T.nc);
   size_t sort_b = 0, scan_b = 0;
   // the images' sort, the targets', and the groups' launch order (up to 2 N groups)
   const unsigned ns = (unsigned)std::max<int64_t>(std::max<int64_t>((int64_t)N, T.ngroups), (int64_t)PN);
@@ -1138,9 +1244,10 @@ extern "C" hsma_status hsma_energy_tree(hsma_plan_t pl, int64_t N, const double 
   const int *gord = (const int *)(w + T.gid_b);
   const int2 *grr = (const int2 *)(w + T.gr);
   with_order(P, [&](auto o) {
+    k_tree_local<decltype(o)::value><<<1, 64, 0, st>>>(n, key0, start0, ncell, simg, (float *)(w + T.lfar));
     k_tree_eval<decltype(o)::value><<<ge, 64 * TR_WAVES, 0, st>>>(
         n, th2, rec, red, key0, start0, ncell, simg, stgt, town, ids_t, ngp, gord, grr, gp, self, grp->dipole == 2,
-        (const CellRec *)(w + T.prec), (const float *)(w + T.pred), ncell + TR_MAX_DEPTH + 4,
+        (const float *)(w + T.lfar), (const CellRec *)(w + T.prec), (const float *)(w + T.pred), ncell + TR_MAX_DEPTH + 4,
         (const float4 *)(w + T.snodes), (const float2 *)(w + T.sqd), phi);
   });
   if (E) {
