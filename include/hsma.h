@@ -294,8 +294,8 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  * pair modes.  The check sums and the fit are those of hsma_energy; the sums over the other
  * ions' Kelvin images and over the surface nodes are approximated.  The images are sorted into
  * an octree over the cube of half-width 8a (depth levels below the root; images farther out, of
- * ions within a/8 of the centre, are summed directly), the surface nodes into patches of up to
- * 64.  The targets are grouped by their own positions, in groups of up to 64.  A cell or patch
+ * ions within a/8 of the centre, are summed directly at theta = 0 and as one local expansion about
+ * the centre otherwise), the surface nodes into patches of up to 64.  The targets are grouped by their own positions, in groups of up to 64.  A cell or patch
  * of radius r_c at distance d from a group of radius r_g is evaluated from its Cartesian
  * multipole moments of the given order when r_c + r_g < theta d, else opened; leaves and
  * patches that are not accepted are summed directly.
@@ -305,7 +305,7 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  * The error is the treecode's. On 10^6 ions uniform in a cavity with balanced charges, the
  * relative L2 errors of sampled potentials are 9.5e-4 (order 4, theta 0.5), 9.4e-5 (order 6,
  * theta 0.5), 1.4e-5 (order 6, theta 0.4) and 1.3e-6 (order 8, theta 0.4).  Against the direct
- * symmetric sums of hsma_energy these run 13, 8.2, 5.9 and 3.8 times faster; at 2 10^5 ions
+ * symmetric sums of hsma_energy these run 14, 9.7, 6.7 and 4.4 times faster; at 2 10^5 ions
  * 2.1 times at order 4, theta 0.5, and even at order 6, theta 0.4; below about 10^5 ions the
  * direct path is faster at any setting.
  *   phi: [device] N doubles (required); E: [device] one double or NULL;
