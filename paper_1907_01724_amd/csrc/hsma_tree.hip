@@ -195,17 +195,6 @@ __device__ __forceinline__ void reduce_rec(const float (&f)[ncoef(P)], float *__
   }
 }
 
-// m[k] += q d^k for every |k| <= P (px, py, pz: powers of the offset's components).
-template <int P, int K>
-__device__ __forceinline__ void moment_rec(float q, const float (&px)[P + 1], const float (&py)[P + 1],
-                                           const float (&pz)[P + 1], float (&m)[ncoef(P)]) {
-  if constexpr (K < ncoef(P)) {
-    constexpr K3 t = kof(K);
-    m[K] = fmaf(q, px[t.x] * py[t.y] * pz[t.z], m[K]);
-    moment_rec<P, K + 1>(q, px, py, pz, m);
-  }
-}
-
 __device__ __forceinline__ unsigned spread3(unsigned v) {  // 10 bits -> every third bit
   v &= 0x3ffu;
   v = (v | (v << 16)) & 0x030000ffu;
