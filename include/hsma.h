@@ -65,7 +65,9 @@ typedef enum {
   HSMA_ESTATE = 6   /* object in the wrong state (e.g. plan built for another device) */
 } hsma_status;
 
-/* Arithmetic of the pair sums (the two Coulomb sums of Algorithm 1, steps 2 and 5). */
+/* Arithmetic of the pair sums of the potentials (the two Coulomb sums of Algorithm 1, steps 2
+ * and 5).  Energies do not depend on it: every entry point that returns E sums them from FP64
+ * pairs (see hsma_energy). */
 typedef enum {
   HSMA_PAIR_FP32 = 0,      /* FP32 pairs, FP32 running sum per target (precision sweep only) */
   HSMA_PAIR_FP32_COMP = 1, /* FP32 pairs, FP32 sums over 32-source tiles folded into FP64 (default) */
@@ -130,8 +132,8 @@ hsma_status hsma_plan_ex(double a, double eps1, double eps2, double kappa, int P
 hsma_status hsma_plan_destroy(hsma_plan_t plan);
 hsma_status hsma_plan_get_info(hsma_plan_t plan, hsma_plan_info *info /* [host] */);
 
-/* Bytes of device workspace hsma_potential / hsma_energy need for N ions
- * (256-byte aligned pointer required). */
+/* Bytes of device workspace hsma_potential / hsma_energy need for N ions, covering both
+ * launches of hsma_energy (256-byte aligned pointer required). */
 size_t hsma_workspace_bytes(hsma_plan_t plan, int64_t N);
 
 /* Reaction potential Phi_RF at every ion (eq. "phirffinall"), N >= 0.
@@ -143,20 +145,27 @@ hsma_status hsma_potential(hsma_plan_t plan, int64_t N, const double *x, const d
                            const double *q, double *phi, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Reaction energy E = (1/2) sum_i q_i Phi_RF(x_i) (the self energy of Sec. 4.1
- * generalised to N ions), reduced in FP64 in a fixed order.  E: [device] one double.
- * phi: [device] N doubles receiving the potentials, or NULL to keep them in ws. */
+ * generalised to N ions), from FP64 pair sums whatever the plan's pair precision, reduced in
+ * a fixed order: relative error about 1e-15 against an FP64 evaluation (target 1e-9).  E is a
+ * bilinear form in the charges, so it is summed without forming the potentials: per ion pair
+ * one reciprocal root serves both ordered image terms (the symmetric image distance of Sec. 2.4),
+ * and every ion block pair and surface-node chunk adds one FP64 value; check sums and fit are
+ * FP64 as well.  E: [device] one double.  phi: [device] N doubles, or NULL for the energy alone;
+ * when given, a second launch on the same workspace writes the potentials in the plan's pair
+ * precision (E is the same bit for bit either way). */
 hsma_status hsma_energy(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
                         const double *q, double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Potential and field at every ion (Algorithm 1, step 5: "potential/field at the source
- * charge locations"): E_i = -grad Phi_RF(x) at x = x_i with every image, the ion's own
+/* Potential and field at every ion (Algorithm 1, step 5, which evaluates both at the ions):
+ * E_i = -grad Phi_RF(x) at x = x_i with every image, the ion's own
  * included, and every surface charge held fixed; the force on ion i is q_i E_i up to the
  * method's error (the fixed-image field of eq. "phirffinall").  Same units as the
  * potential (divide by the length unit).  The evaluation runs the one-directional pair
  * kernel with four sums (Phi, Ex, Ey, Ez) per target; the own image's field is added in
  * FP64 as -x_i Phi_own,i / (a^2 - r_i^2).
  *   ex, ey, ez: [device] N doubles each (output; required when N > 0);
- *   phi: [device] N doubles or NULL; E: [device] one double or NULL;
+ *   phi: [device] N doubles or NULL; E: [device] one double or NULL (when given, computed by
+ *   the FP64 energy launch of hsma_energy before the field launch);
  *   ws: [device] ws_bytes >= hsma_field_workspace_bytes(plan, N).
  * Errors as hsma_potential. */
 size_t hsma_field_workspace_bytes(hsma_plan_t plan, int64_t N);
@@ -181,7 +190,9 @@ size_t hsma_kirkwood_workspace_bytes(int order, int64_t N);
 hsma_status hsma_kirkwood(hsma_plan_t plan, int order, int64_t N, const double *x, const double *y, const double *z,
                           const double *q, double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Intermediate results of the last hsma_potential/hsma_energy call that used ws,
+/* Intermediate results of the last launch that used ws (the potential launch of hsma_potential,
+ * or of hsma_energy with phi, in the plan's pair precision; the FP64 energy launch of hsma_energy
+ * without phi),
  * copied to host arrays (for tests and diagnostics; synchronises the stream).
  * Any output pointer may be NULL.  u, v: M check fields; Q, D: P surface strengths
  * (Q_s and D_s of the header comment, divided by 4 pi and 4 pi R_tau). */
@@ -209,6 +220,9 @@ hsma_group_t hsma_plan_group(hsma_plan_t plan);
  *            the work and the workspace (hsma_batched_workspace_bytes);
  *   phi: [device] total_n doubles or NULL; E: [device] nsys energies or NULL;
  *   ws: [device] ws_bytes >= hsma_batched_workspace_bytes(group, nsys, total_n, max_n).
+ * Energies come from the FP64 energy launch and potentials from the pair-precision launch, as in
+ * hsma_energy; a system's energy does not depend on the batch it is in beyond the rounding of
+ * its check sums, whose chunk lengths follow the call's sizes.
  * A system of 0 ions has energy 0.  The device checks offsets and plan_of against
  * total_n, max_n and the group size before any work: on a mismatch the call does nothing
  * and hsma_group_stream_check reports HSMA_EINVAL.  Errors: HSMA_EINVAL, HSMA_ESTATE,
@@ -308,7 +322,8 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  * symmetric sums of hsma_energy these run 14, 9.7, 6.7 and 4.4 times faster; at 2 10^5 ions
  * 2.1 times at order 4, theta 0.5, and even at order 6, theta 0.4; below about 10^5 ions the
  * direct path is faster at any setting.
- *   phi: [device] N doubles (required); E: [device] one double or NULL;
+ *   phi: [device] N doubles (required); E: [device] one double or NULL (1/2 sum q_i phi_i of the
+ *   treecode's potentials, so of the treecode's accuracy);
  *   ws: [device] ws_bytes >= hsma_tree_workspace_bytes(plan, N, opts) (0 for invalid arguments).
  * Like the other compute calls it allocates nothing and does not synchronise; unlike them it
  * is not meant for graph capture, since its radix sorts and scans (rocPRIM, with their

@@ -554,7 +554,7 @@ done:
 }
 
 /* ------------------------------------------------------------------------- */
-/* Field at the targets (Algorithm 1, step 5: "potential/field").                */
+/* Field at the targets (Algorithm 1, step 5 evaluates the field with the potential). */
 /* ------------------------------------------------------------------------- */
 
 /* E = -grad Phi at the target with every source held fixed: for an image charge c at

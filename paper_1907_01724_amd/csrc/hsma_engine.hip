@@ -61,13 +61,20 @@ struct PT<HSMA_PAIR_FP64> {
 
 __device__ __forceinline__ float rinv(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
-// 1/sqrt(r2) in FP64: the FP32 hardware estimate (relative error ~1e-7) refined by one
-// Newton step y <- y + y (1 - r2 y^2) / 2 (relative error ~2e-14).
+// 1/sqrt(r2) in FP64: the hardware FP64 estimate (v_rsq_f64, relative error below 6e-8,
+// measured) refined by one Newton step y <- y + y (1 - r2 y^2) / 2 (relative error ~4e-15).
 __device__ __forceinline__ double rinv(double r2) {
-  const double y = (double)__builtin_amdgcn_rsqf((float)r2);
+  const double y = __builtin_amdgcn_rsq(r2);
   const double t = r2 * y;
   const double e = fma(-t, y, 1.0);
   return fma(y * 0.5, e, y);
+}
+
+// Twice 1/sqrt(r2) in FP64: y (3 - r2 y^2) from the hardware estimate y, the same Newton step
+// as rinv with its factor 1/2 left to the caller (one instruction fewer per pair).
+__device__ __forceinline__ double rinv2(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  return y * fma(-(r2 * y), y, 3.0);
 }
 
 template <typename T4>
@@ -106,10 +113,15 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 //       surface items, so that a system's targets are read while they are still in L2.
 //       Either way system b's pairs are items [2][b] .. [6][b] - 1 when interleaved, or start
 //       at [2][b] otherwise, and its surface items start at [6][b].
-// followed by 8 words: [0] check item counter, [1] eval item counter.
+//   [7] prefix of the energy-sum chunks (energy-only launches: EC consecutive item energies of
+//       one system, its block pairs first, then its surface items).
+// followed by 8 words: [0] check item counter, [1] eval item counter, [2] schedule valid,
+// [3] launch kind: 1 for the energy-only launch, else 0, plus 16 x the pair precision (read back by
+// hsma_debug_intermediates).
 // ---------------------------------------------------------------------------------
+constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
 struct Sched {
-  int64_t *off, *ic, *ie, *fb, *pc, *pe, *is, *ctr;
+  int64_t *off, *ic, *ie, *fb, *pc, *pe, *is, *ec, *ctr;
   __host__ __device__ Sched(int64_t *base, int nsys) {
     const int64_t s = nsys + 1;
     off = base;
@@ -119,13 +131,14 @@ struct Sched {
     pc = base + 4 * s;
     pe = base + 5 * s;
     is = base + 6 * s;
-    ctr = base + 7 * s;
+    ec = base + 7 * s;
+    ctr = base + 8 * s;
   }
 };
 
 // Bounds the host sized the workspace with; the schedule refuses work beyond them.
 struct Bounds {
-  int64_t total_n, max_n, items_c, items_e, fin, parts_c, parts_e;
+  int64_t total_n, max_n, items_c, items_e, fin, parts_c, parts_e, echunks;
   int nplans;
 };
 
@@ -150,10 +163,10 @@ __device__ __forceinline__ void eval_counts(int64_t n, int P, int che, int sym_t
 __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *__restrict__ offsets,
                                                       const int32_t *__restrict__ plan_of, Bounds bd, int M, int P,
                                                       int chc, int che, int sym_tb, int sch, int64_t sym_tail,
-                                                      int64_t grid_c, int64_t grid_e, int64_t *__restrict__ base,
-                                                      int *__restrict__ flag) {
+                                                      int64_t grid_c, int64_t grid_e, int kind,
+                                                      int64_t *__restrict__ base, int *__restrict__ flag) {
   Sched S(base, nsys);
-  __shared__ int64_t sc[6][SCHED_T];
+  __shared__ int64_t sc[7][SCHED_T];
   const int t = threadIdx.x, nt = blockDim.x;  // nt <= SCHED_T, a multiple of 64
   const int seg = (nsys + nt - 1) / nt;
   const int b0 = t * seg, b1 = min(nsys, b0 + seg);
@@ -169,7 +182,7 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     if (plan_of && (plan_of[b] < 0 || plan_of[b] >= bd.nplans)) bad = 1;
   }
   bad = __syncthreads_or(bad);
-  int64_t acc[6] = {0, 0, 0, 0, 0, 0};
+  int64_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int b = b0; b < b1 && !bad; ++b) {
     const int64_t lo = offsets ? offsets[b] : 0, hi = offsets ? offsets[b + 1] : n_single;
     const int64_t n = hi - lo;
@@ -182,19 +195,20 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     acc[3] += Gc * chunks_c * GRP;
     acc[4] += parts_e;
     acc[5] += surf_e;
+    acc[6] += sym_tb > 0 ? cdiv64(items_e, EC) + cdiv64(surf_e, EC) : 0;
   }
-  for (int k = 0; k < 6; ++k) sc[k][t] = acc[k];
+  for (int k = 0; k < 7; ++k) sc[k][t] = acc[k];
   __syncthreads();
   // inclusive Hillis-Steele scan over the thread totals
   for (int o = 1; o < nt; o <<= 1) {
-    int64_t v[6];
-    for (int k = 0; k < 6; ++k) v[k] = t >= o ? sc[k][t - o] : 0;
+    int64_t v[7];
+    for (int k = 0; k < 7; ++k) v[k] = t >= o ? sc[k][t - o] : 0;
     __syncthreads();
-    for (int k = 0; k < 6; ++k) sc[k][t] += v[k];
+    for (int k = 0; k < 7; ++k) sc[k][t] += v[k];
     __syncthreads();
   }
-  int64_t run[6];
-  for (int k = 0; k < 6; ++k) run[k] = sc[k][t] - acc[k];  // exclusive start of this segment
+  int64_t run[7];
+  for (int k = 0; k < 7; ++k) run[k] = sc[k][t] - acc[k];  // exclusive start of this segment
   // surface items last when the block pairs of the launch are few (sc[1] holds only pairs)
   const bool surf_last = sc[1][nt - 1] <= sym_tail;
   if (surf_last) run[5] += sc[1][nt - 1];
@@ -211,12 +225,14 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     S.pc[b] = run[3];
     S.pe[b] = run[4];
     S.is[b] = surf_last ? run[5] : S.ie[b] + items_e;
+    S.ec[b] = run[6];
     run[0] += Gc * chunks_c;
     run[1] += items_e;
     run[2] += cdiv64(n, FINB);
     run[3] += Gc * chunks_c * GRP;
     run[4] += parts_e;
     run[5] += surf_e;
+    run[6] += sym_tb > 0 ? cdiv64(items_e, EC) + cdiv64(surf_e, EC) : 0;
   }
   if (t == nt - 1) {
     S.off[nsys] = offsets ? offsets[nsys] : n_single;
@@ -226,11 +242,13 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     S.pc[nsys] = sc[3][t];
     S.pe[nsys] = sc[4][t];
     S.is[nsys] = sc[1][t] + sc[5][t];
+    S.ec[nsys] = sc[6][t];
     for (int k = 0; k < 8; ++k) S.ctr[k] = 0;
     S.ctr[0] = grid_c;  // items below the grid size are taken by block index
     S.ctr[1] = grid_e;
+    S.ctr[3] = kind;
     const bool fits = sc[0][t] <= bd.items_c && sc[1][t] + sc[5][t] <= bd.items_e && sc[2][t] <= bd.fin &&
-                      sc[3][t] <= bd.parts_c && sc[4][t] <= bd.parts_e;
+                      sc[3][t] <= bd.parts_c && sc[4][t] <= bd.parts_e && sc[6][t] <= bd.echunks;
     const bool ok = !bad && fits;
     S.ctr[2] = ok ? 1 : 0;  // every later kernel of the call does nothing unless set
     if (!ok) atomicOr(flag, 2);
@@ -278,7 +296,8 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
                                               typename PT<MODE>::T4 *__restrict__ tgt,
                                               typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
                                               typename PT<MODE>::T *__restrict__ wk, double *__restrict__ rk,
-                                              double4 *__restrict__ sfield, float4 *__restrict__ tlo,
+                                              double *__restrict__ qr, double4 *__restrict__ sfield,
+                                              float4 *__restrict__ tlo,
                                               float4 *__restrict__ ilo, int *__restrict__ flag) {
   using T4 = typename PT<MODE>::T4;
   using T = typename PT<MODE>::T;
@@ -307,6 +326,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
       wk[i] = (T)0;
       rk[i] = 0.0;
     }
+    if (qr) qr[i] = 0.0;
     if (sfield) sfield[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     if (tlo) {
       tlo[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -357,6 +377,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
     wk[i] = (T)(qk * reff);  // c0 q_K r: the ion's image strength times its radius
     rk[i] = 1.0 / reff;
   }
+  if (qr) qr[i] = qi / reff;  // the charge over the radius (energy sums)
 }
 
 // ---------------------------------------------------------------------------------
@@ -1520,6 +1541,211 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym64(int nsys, int P, int sch, 
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Energy sums in FP64 pairs, without potentials.  E = 1/2 sum_i q_i Phi_i is a bilinear form
+// in the charges, so a block pair needs no per-ion output: with the image identity above,
+// the two ordered terms of an ion pair share one reciprocal root y = 1/|x_i - r_K,j|,
+//   q_i q'_j / |x_i - r_K,j| + q_j q'_i / |x_j - r_K,i| = y (q_i q'_j + (q'_i r_i)(q_j / r_j)),
+// so a lane keeps two sums per target, S1 = sum_j q'_j y and S2 = sum_j (q_j / r_j) y, and the
+// item's energy is sum_i (q_i S1_i + q'_i r_i S2_i), reduced over the wave in a fixed order
+// and written to the item's own slot.  Diagonal blocks sum every ordered pair j != i; surface
+// items sum q_i times the node potentials.  Every value is FP64; the reciprocal root is the
+// hardware FP64 estimate refined by one Newton step.
+// ---------------------------------------------------------------------------------
+// Block pair (I, J), I <= J, of item number loc within a system's triangle of B blocks:
+// rows I = 0..B-1 of the triangle J = I..B-1 start at I B - I (I - 1) / 2.
+__device__ __forceinline__ void block_pair(int64_t loc, int64_t B, int &I, int &J) {
+  const double bb = 2.0 * (double)B + 1.0;
+  int64_t r = (int64_t)((bb - sqrt(bb * bb - 8.0 * (double)loc)) * 0.5);
+  r = r < 0 ? 0 : (r > B - 1 ? B - 1 : r);
+  while (r > 0 && r * B - r * (r - 1) / 2 > loc) --r;
+  while (r + 1 < B && (r + 1) * B - (r + 1) * r / 2 <= loc) ++r;
+  I = __builtin_amdgcn_readfirstlane((int)r);
+  J = __builtin_amdgcn_readfirstlane((int)(r + (loc - (r * B - r * (r - 1) / 2))));
+}
+
+template <int R>
+__global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int mono, const int64_t *__restrict__ base,
+                                                  const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
+                                                  const double4 *__restrict__ tgt, const double4 *__restrict__ img,
+                                                  const double *__restrict__ q, const double *__restrict__ wk,
+                                                  const double *__restrict__ qr, const double4 *__restrict__ nodes,
+                                                  const double2 *__restrict__ qd, double *__restrict__ epair) {
+  constexpr int TB = 64 * R;
+  constexpr int RS = R / SYM_SH;
+  constexpr double FAR_TARGET = 3.0e18;  // stand-in position of an empty target lane (zero charge)
+  Sched S(const_cast<int64_t *>(base), nsys);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (!sched_ok(S)) return;
+  const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);  // one item per wave
+  if (item >= S.is[nsys]) return;
+  const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
+  const bool surface = item >= S.is[b];
+  const int64_t lo = S.off[b];
+  const int n = (int)(S.off[b + 1] - lo);
+  double e = 0.0;
+  if (surface) {
+    // half of block I's ions (target sets h RS .. h RS + RS - 1 of each lane) against node chunk c
+    const int64_t t = item - S.is[b];
+    const int I = __builtin_amdgcn_readfirstlane((int)(t / (sch * SYM_SH)));
+    const int rem = (int)(t % (sch * SYM_SH));
+    const int c = __builtin_amdgcn_readfirstlane(rem / SYM_SH), h = __builtin_amdgcn_readfirstlane(rem % SYM_SH);
+    const int t0 = I * TB + h * RS * 64;
+    double sx[RS], sy[RS], sz[RS], sq[RS], acc[RS];
+#pragma unroll
+    for (int k = 0; k < RS; ++k) {
+      const int i = t0 + k * 64 + lane;
+      const bool in = i < n;
+      const double4 tv = in ? tgt[lo + i] : make_double4(FAR_TARGET, 0.0, 0.0, 0.0);
+      sx[k] = tv.x;
+      sy[k] = tv.y;
+      sz[k] = tv.z;
+      sq[k] = in ? q[lo + i] : 0.0;
+      acc[k] = 0.0;
+    }
+    const int per = (P + sch - 1) / sch;
+    const int s0 = c * per, s1 = s0 + per < P ? s0 + per : P;
+    const int pl = plan_of ? plan_of[b] : 0;
+    const double4 *nd = nodes + (size_t)pl * P;
+    const double2 *qb = qd + (size_t)b * P;
+    for (int m = s0; m < s1; ++m) {
+      const double4 yv = nd[m];
+      const double2 wv = qb[m];
+#pragma unroll
+      for (int k = 0; k < RS; ++k) {
+        const double dx = sx[k] - yv.x, dy = sy[k] - yv.y, dz = sz[k] - yv.z;
+        const double ri = rinv(dx * dx + dy * dy + dz * dz);
+        if (mono) {
+          acc[k] = fma(wv.x, ri, acc[k]);
+        } else {
+          const double dot = dx * yv.x + dy * yv.y + dz * yv.z;
+          acc[k] = fma(ri, fma(wv.y * dot, ri * ri, wv.x), acc[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RS; ++k) e = fma(sq[k], acc[k], e);
+  } else {
+    const int64_t B = cdiv64(n, TB);
+    int I, J;
+    block_pair(item - S.ie[b], B, I, J);
+    const int t0 = I * TB;
+    double tx[R], ty[R], tz[R], s1[R], s2[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int i = t0 + k * 64 + lane;
+      const double4 t = i < n ? tgt[lo + i] : make_double4(FAR_TARGET, 0.0, 0.0, 0.0);
+      tx[k] = t.x;
+      ty[k] = t.y;
+      tz[k] = t.z;
+      s1[k] = 0.0;
+      s2[k] = 0.0;
+    }
+    const double4 *im = img + lo;
+    const int j0 = J * TB, j1 = j0 + TB < n ? j0 + TB : n;
+    // the sums hold twice the pair terms (rinv2); halved once at the end
+    if (I == J) {
+      // diagonal block: every ordered pair j != i (the own image is the analytic term)
+      for (int j = j0; j < j1; ++j) {
+        const double4 v = im[j];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const double dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
+          double ri = rinv2(dx * dx + dy * dy + dz * dz);
+          ri = (j == t0 + k * 64 + lane) ? 0.0 : ri;
+          s1[k] = fma(v.w, ri, s1[k]);
+        }
+      }
+    } else {
+      const double *cr = qr + lo;
+      for (int j = j0; j < j1; ++j) {
+        const double4 v = im[j];
+        const double cj = cr[j];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const double dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
+          const double ri = rinv2(dx * dx + dy * dy + dz * dz);
+          s1[k] = fma(v.w, ri, s1[k]);
+          s2[k] = fma(cj, ri, s2[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int i = t0 + k * 64 + lane;
+      if (i < n) e = fma(q[lo + i], s1[k], fma(wk[lo + i], s2[k], e));
+    }
+    e *= 0.5;
+  }
+  e = wave_sum(e);
+  if (lane == 0) epair[item] = e;
+}
+
+// Fixed-order sums of the item energies: chunk f of system b holds EC consecutive items of its
+// block pairs, or of its surface items after those; 256 threads sum them lane-strided and by a
+// tree.
+__global__ __launch_bounds__(256) void k_energy_chunks(int nsys, int P, int sym_tb, int sch,
+                                                       const int64_t *__restrict__ base,
+                                                       const double *__restrict__ epair, double *__restrict__ echunk) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ double red[256];
+  const int64_t f = blockIdx.x;
+  if (!sched_ok(S) || f >= S.ec[nsys]) return;  // uniform across the block
+  const int b = system_of(S.ec, nsys, f);
+  const int64_t n = S.off[b + 1] - S.off[b];
+  int64_t pairs, surf, parts;
+  eval_counts(n, P, 0, sym_tb, sch, pairs, surf, parts);
+  const int64_t k = f - S.ec[b], cp = cdiv64(pairs, EC);
+  const int64_t first = k < cp ? S.ie[b] + k * EC : S.is[b] + (k - cp) * EC;
+  const int64_t end = k < cp ? S.ie[b] + pairs : S.is[b] + surf;
+  const int64_t last = first + EC < end ? first + EC : end;
+  double s = 0.0;
+  for (int64_t i = first + threadIdx.x; i < last; i += 256) s += epair[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) echunk[f] = red[0];
+}
+
+// E_b = (own-image block partials, 1/2 included) + 1/2 (sum of system b's chunk sums), each
+// lane-strided and reduced by a shuffle tree.
+__global__ __launch_bounds__(64) void k_energy_items(int nsys, const int64_t *__restrict__ base,
+                                                     const double *__restrict__ epart,
+                                                     const double *__restrict__ echunk, double *__restrict__ E) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;
+  const int b = blockIdx.x;
+  double s = 0.0, t = 0.0;
+  for (int64_t f = S.fb[b] + threadIdx.x; f < S.fb[b + 1]; f += 64) s += epart[f];
+  for (int64_t f = S.ec[b] + threadIdx.x; f < S.ec[b + 1]; f += 64) t += echunk[f];
+  s = wave_sum(s);
+  t = wave_sum(t);
+  if (threadIdx.x == 0) E[b] = s + 0.5 * t;
+}
+
+// Block partials of 1/2 sum_i q_i self_i (the own-image energy), for the energy-only path.
+__global__ __launch_bounds__(FINB) void k_self_energy(int nsys, const int64_t *__restrict__ base,
+                                                      const int *__restrict__ sys_f, const double *__restrict__ self,
+                                                      const double *__restrict__ q, double *__restrict__ epart) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ double red[FINB];
+  const int64_t f = blockIdx.x;
+  if (!sched_ok(S) || f >= S.fb[nsys]) return;  // uniform across the block
+  const int b = sys_f[f];
+  const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
+  const int64_t il = (f - S.fb[b]) * FINB + threadIdx.x;
+  red[threadIdx.x] = il < n ? 0.5 * q[lo + il] * self[lo + il] : 0.0;
+  __syncthreads();
+  for (int o = FINB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) epart[f] = red[0];
+}
+
 // Phi_i = own-image term + fixed-order sum of the chunk partials; block partial of 1/2 sum q Phi.
 __global__ __launch_bounds__(FINB) void k_finish(int nsys, int P, int che, int sym_tb, int sch,
                                                  const int64_t *__restrict__ base,
@@ -1664,6 +1890,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   bd.fin = L.fin;
   bd.parts_c = L.parts_c;
   bd.parts_e = L.parts_e;
+  bd.echunks = L.eonly ? L.echunks : INT64_MAX;  // only energy-only launches store the chunk sums
   bd.nplans = grp->nplans;
   // symmetric kernel: surface items last when the block pairs fill at most SYM_TAIL_ROUNDS
   // rounds of the device's resident waves
@@ -1672,11 +1899,12 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
                                ? INT64_MAX
                                : SYM_TAIL_ROUNDS * g->ncu * WAVES * grp->tune.occ_sym[L.sym_tb == 512];
   k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, Pe, L.chc, L.che, L.sym_tb, L.sch, sym_tail, grid_c,
-                                    grid_e, base, grp->flag);
+                                    grid_e, (L.eonly ? 1 : 0) + 16 * L.prec, base, grp->flag);
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f, plans, plan_of, x, y, z, q, img, tgt,
                                              srcw, self,
                                              (T *)(ws + L.wk), (double *)(ws + L.rk),
+                                             L.eonly ? (double *)(ws + L.qr) : nullptr,
                                              L.field ? (double4 *)(ws + L.sfield) : nullptr,
                                              L.lo ? (float4 *)(ws + L.tlo) : nullptr,
                                              L.lo ? (float4 *)(ws + L.ilo) : nullptr, grp->flag);
@@ -1724,6 +1952,34 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   if (L.upto_fit) {
     HSMA_HIP(hipGetLastError());
     return HSMA_OK;
+  }
+
+  if constexpr (MODE == HSMA_PAIR_FP64) {
+    if (L.eonly) {  // the energy alone: FP64 pair sums without potentials
+      double *epair = (double *)(ws + L.eval_part);
+      pr = prof_begin(grp, ST_EVAL, st);
+      if (L.items_e > 0) {
+        const unsigned gs = (unsigned)cdiv(L.items_e, WAVES);
+        const double *wk = (const double *)(ws + L.wk);
+        const double *qr = (const double *)(ws + L.qr);
+        if (L.sym_tb == 256)
+          k_energy64<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, q, wk,
+                                            qr, grp->nodes64, qd, epair);
+        else
+          k_energy64<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, q, wk,
+                                            qr, grp->nodes64, qd, epair);
+      }
+      prof_end(pr, st);
+      pr = prof_begin(grp, ST_FINISH, st);
+      if (L.fin > 0) k_self_energy<<<(int)L.fin, FINB, 0, st>>>(nsys, base, sys_f, self, q, epart);
+      double *echunk = (double *)(ws + L.echunk);
+      if (L.echunks > 0)
+        k_energy_chunks<<<(unsigned)L.echunks, 256, 0, st>>>(nsys, Pe, L.sym_tb, L.sch, base, epair, echunk);
+      if (E) k_energy_items<<<nsys, 64, 0, st>>>(nsys, base, epart, echunk, E);
+      prof_end(pr, st);
+      HSMA_HIP(hipGetLastError());
+      return HSMA_OK;
+    }
   }
 
   pr = prof_begin(grp, ST_EVAL, st);
@@ -1785,13 +2041,16 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
 // Item sizes are chosen from upper bounds known on the host (system count, total and
 // largest system size): the check chunk aims at about 8192 items, the evaluation chunk at
 // about 8192 items of the largest possible pair count; both multiples of 4 waves x 32.
-Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n, bool field, bool no_sym) {
+Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n, bool field, bool no_sym,
+              bool eonly) {
   Layout L;
   L.field = field;
+  L.eonly = eonly && !field;
+  L.prec = L.eonly ? HSMA_PAIR_FP64 : grp->pair_prec;
   const Geometry *g = grp->geo;
   const int64_t M = g->M, Pf = g->P, K = g->K;
   const int64_t P = grp->P_ev;  // surface sources of the evaluation
-  const bool fp64 = grp->pair_prec == HSMA_PAIR_FP64;
+  const bool fp64 = L.prec == HSMA_PAIR_FP64;
   L.nsys = nsys;
   L.total_n = total_n;
   L.max_n = max_n;
@@ -1817,8 +2076,19 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.sym_tb = 0;
   L.sch = 0;
   const int mode = grp->tune.symmetric;
-  if ((grp->pair_prec == HSMA_PAIR_FP32_COMP || grp->pair_prec == HSMA_PAIR_FP64) && mode != 0 && total_n > 0 &&
-      !field && !no_sym) {
+  if (L.eonly && total_n > 0) {
+    // the energy kernel: blocks of 256 ions, or 512 when asked for; one FP64 value per item
+    const int64_t tb = mode == 3 ? 512 : 256;
+    const int64_t bmax = cdiv(max_n, tb);
+    const int64_t sch = cdiv(P, (2 * tb) / 3);
+    const int64_t sb = total_n / tb + nsys;
+    L.sym_tb = (int)tb;
+    L.sch = (int)sch;
+    L.items_e = sb * (bmax + 1) / 2 + sb * sch * SYM_SH + 1;
+    L.parts_e = total_n * (bmax + sch);  // the schedule's bound check only: no slots are stored
+    L.echunks = L.items_e / EC + 2 * (int64_t)nsys + 1;
+  } else if ((L.prec == HSMA_PAIR_FP32_COMP || L.prec == HSMA_PAIR_FP64) && mode != 0 && total_n > 0 && !field &&
+             !no_sym) {
     for (int r = 4; r <= 8; r *= 2) {
       if ((mode == 2 && r != 4) || (mode == 3 && r != 8)) continue;
       const int64_t tb = 64 * r;
@@ -1847,7 +2117,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
     o = align256(o + bytes);
     return at;
   };
-  L.sched = take(sizeof(int64_t) * (7 * (size_t)(nsys + 1) + 8));
+  L.sched = take(sizeof(int64_t) * (8 * (size_t)(nsys + 1) + 8));
   L.item_sys_c = take(sizeof(int) * (size_t)L.items_c);
   L.item_sys_e = take(sizeof(int) * (size_t)L.items_e);
   L.fin_sys = take(sizeof(int) * (size_t)L.fin);
@@ -1864,7 +2134,10 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.h32 = L.mfma ? take(sizeof(float) * 2 * (size_t)K * nsys) : 0;
   L.gemm2 = L.mfma ? take(sizeof(float) * 2 * (size_t)Pf * nsys) : 0;
   L.qd = take(sizeof(double2) * (size_t)P * nsys);
-  L.eval_part = take((field ? sizeof(double4) : sizeof(double)) * (size_t)L.parts_e);
+  L.eval_part = take(L.eonly ? sizeof(double) * (size_t)L.items_e
+                             : (field ? sizeof(double4) : sizeof(double)) * (size_t)L.parts_e);
+  L.qr = L.eonly ? take(sizeof(double) * (size_t)total_n) : 0;
+  L.echunk = L.eonly ? take(sizeof(double) * (size_t)(L.echunks + 1)) : 0;
   L.sfield = field ? take(sizeof(double4) * (size_t)total_n) : 0;
   L.lo = field && !fp64;
   L.tlo = L.lo ? take(sizeof(float4) * (size_t)total_n) : 0;
@@ -1876,6 +2149,33 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   return L;
 }
 
+size_t call_workspace_bytes(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n, bool field) {
+  const size_t a = layout(grp, nsys, total_n, max_n, field).total;
+  const size_t b = layout(grp, nsys, total_n, max_n, false, false, true).total;
+  return a > b ? a : b;
+}
+
+namespace {
+hsma_status launch_prec(hsma_group_s *grp, const Layout &L, const int64_t *offsets, const int32_t *plan_of,
+                        int64_t total_n, const double *x, const double *y, const double *z, const double *q,
+                        double *phi, double *E, double *ex, double *ey, double *ez, char *w, hipStream_t st) {
+  switch (L.prec) {
+    case HSMA_PAIR_FP32:
+      return launch<HSMA_PAIR_FP32>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
+    case HSMA_PAIR_FP32_COMP:
+      return launch<HSMA_PAIR_FP32_COMP>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
+    case HSMA_PAIR_FP64:
+      return launch<HSMA_PAIR_FP64>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
+    default:
+      return HSMA_EINVAL;
+  }
+}
+}  // namespace
+
+// Energies always come from FP64 pair sums: a call that asks for E runs the energy-only launch,
+// and then, if it also asks for potentials (or fields), the potential launch in the group's pair
+// precision on the same workspace.  An energy is therefore the same bit for bit whether or not
+// the call also asks for potentials.
 hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, const int32_t *plan_of, int64_t total_n,
                         int64_t max_n, const double *x, const double *y, const double *z, const double *q,
                         double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t st, double *ex, double *ey,
@@ -1890,20 +2190,23 @@ hsma_status run_batched(hsma_group_s *grp, int nsys, const int64_t *offsets, con
   int dev = -1;
   HSMA_HIP(hipGetDevice(&dev));
   if (dev != grp->device) return HSMA_ESTATE;
+  const bool one_pass = !E;
+  const bool want_pot = phi || field;
   const Layout L = layout(grp, nsys, total_n, max_n, field);
-  if (ws_bytes < L.total) return HSMA_EINVAL;  // workspace sized for other sizes or launch parameters
+  const Layout Le = layout(grp, nsys, total_n, max_n, false, false, true);
+  // workspace sized for other sizes or launch parameters
+  if (ws_bytes < (one_pass ? L.total : (want_pot ? (L.total > Le.total ? L.total : Le.total) : Le.total)))
+    return HSMA_EINVAL;
   char *w = (char *)ws;
-  if (!phi) phi = (double *)(w + L.phi);
-  switch (grp->pair_prec) {
-    case HSMA_PAIR_FP32:
-      return launch<HSMA_PAIR_FP32>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
-    case HSMA_PAIR_FP32_COMP:
-      return launch<HSMA_PAIR_FP32_COMP>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
-    case HSMA_PAIR_FP64:
-      return launch<HSMA_PAIR_FP64>(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
-    default:
-      return HSMA_EINVAL;
+  if (one_pass) {
+    if (!phi) phi = (double *)(w + L.phi);
+    return launch_prec(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, E, ex, ey, ez, w, st);
   }
+  hsma_status rc =
+      launch_prec(grp, Le, offsets, plan_of, total_n, x, y, z, q, nullptr, E, nullptr, nullptr, nullptr, w, st);
+  if (rc != HSMA_OK || !want_pot) return rc;
+  if (!phi) phi = (double *)(w + L.phi);
+  return launch_prec(grp, L, offsets, plan_of, total_n, x, y, z, q, phi, nullptr, ex, ey, ez, w, st);
 }
 
 hsma_status run_front(hsma_group_s *grp, const Layout &L, int64_t n, const double *x, const double *y,
@@ -2006,7 +2309,7 @@ using namespace hsma;
 // ---------------------------------------------------------------------------------
 extern "C" size_t hsma_workspace_bytes(hsma_plan_t pl, int64_t N) {
   if (!pl || N < 0) return 0;
-  return layout(pl->self, 1, N, N).total;
+  return call_workspace_bytes(pl->self, 1, N, N, false);
 }
 
 extern "C" hsma_status hsma_potential(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
@@ -2024,7 +2327,7 @@ extern "C" hsma_status hsma_energy(hsma_plan_t pl, int64_t N, const double *x, c
 
 extern "C" size_t hsma_field_workspace_bytes(hsma_plan_t pl, int64_t N) {
   if (!pl || N < 0) return 0;
-  return layout(pl->self, 1, N, N, true).total;
+  return call_workspace_bytes(pl->self, 1, N, N, true);
 }
 
 extern "C" hsma_status hsma_field(hsma_plan_t pl, int64_t N, const double *x, const double *y, const double *z,
@@ -2036,7 +2339,7 @@ extern "C" hsma_status hsma_field(hsma_plan_t pl, int64_t N, const double *x, co
 
 extern "C" size_t hsma_field_batched_workspace_bytes(hsma_group_t grp, int nsys, int64_t total_n, int64_t max_n) {
   if (!grp || nsys < 1 || total_n < 0 || max_n < 0) return 0;
-  return layout(grp, nsys, total_n, max_n, true).total;
+  return call_workspace_bytes(grp, nsys, total_n, max_n, true);
 }
 
 extern "C" hsma_status hsma_field_batched(hsma_group_t grp, int nsys, const int64_t *offsets, const int32_t *plan_of,
@@ -2049,7 +2352,7 @@ extern "C" hsma_status hsma_field_batched(hsma_group_t grp, int nsys, const int6
 
 extern "C" size_t hsma_batched_workspace_bytes(hsma_group_t grp, int nsys, int64_t total_n, int64_t max_n) {
   if (!grp || nsys < 1 || total_n < 0 || max_n < 0) return 0;
-  return layout(grp, nsys, total_n, max_n).total;
+  return call_workspace_bytes(grp, nsys, total_n, max_n, false);
 }
 
 extern "C" hsma_status hsma_energy_batched(hsma_group_t grp, int nsys, const int64_t *offsets, const int32_t *plan_of,
@@ -2100,10 +2403,17 @@ extern "C" int hsma_group_fit_route(hsma_group_t grp, int nsys) {
 extern "C" hsma_status hsma_debug_intermediates(hsma_plan_t pl, int64_t N, const void *ws, hipStream_t st, double *u,
                                                 double *v, double *Q, double *D) {
   if (!pl || !ws || N < 0) return HSMA_EINVAL;
-  const Layout L = layout(pl->self, 1, N, N);
   const char *w = (const char *)ws;
   const int M = pl->geo->M, P = pl->geo->P;
   HSMA_HIP(hipStreamSynchronize(st));
+  // the schedule of the last launch on ws records which layout it used (both start with it)
+  int64_t kind = 0;
+  HSMA_HIP(hipMemcpy(&kind, w + layout(pl->self, 1, N, N).sched + sizeof(int64_t) * (8 * 2 + 3), sizeof(int64_t),
+                     hipMemcpyDeviceToHost));
+  const bool eonly = (kind & 15) == 1;
+  const int prec = (int)(kind >> 4);
+  if (prec < HSMA_PAIR_FP32 || prec > HSMA_PAIR_FP64) return HSMA_ESTATE;  // no launch recorded
+  const Layout L = layout(pl->self, 1, N, N, false, false, eonly);
   if (u) HSMA_HIP(hipMemcpy(u, w + L.uv, sizeof(double) * M, hipMemcpyDeviceToHost));
   if (v) HSMA_HIP(hipMemcpy(v, w + L.uv + sizeof(double) * M, sizeof(double) * M, hipMemcpyDeviceToHost));
   if (Q || D) {
@@ -2112,7 +2422,7 @@ extern "C" hsma_status hsma_debug_intermediates(hsma_plan_t pl, int64_t N, const
     const double dyc = pl->host.dyc;
     double2 *h = new double2[Pe];
     hipError_t e;
-    if (pl->self->pair_prec == HSMA_PAIR_FP64) {
+    if (prec == HSMA_PAIR_FP64) {
       e = hipMemcpy(h, w + L.qd, sizeof(double2) * Pe, hipMemcpyDeviceToHost);
     } else {
       float2 *f = new float2[Pe];

@@ -73,6 +73,7 @@ struct hsma_server_s {
   std::vector<EnergySlot> eslots;
   std::thread th;
   std::atomic<bool> stop{false};
+  bool failed = false;  // a device error was seen: every later request completes with HSMA_EDEVICE
   std::chrono::steady_clock::time_point t0;
   hipStream_t admin = nullptr;  // system creation
   // statistics
@@ -109,14 +110,21 @@ bool valid_request(hsma_server_s *S, const hsma_request &r) {
 }
 
 // One pass of the scheduler; returns true when anything happened.  Called with S->mu held.
+// Only hipErrorNotReady means that a slot's work is still running; any other error from the
+// event completes the slot's requests with HSMA_EDEVICE and marks the server failed, after which
+// every waiting and every new request completes at once with HSMA_EDEVICE.
 bool schedule_once(hsma_server_s *S) {
   bool did = false;
   // completions
   for (DeltaSlot &d : S->dslots) {
-    if (!d.busy || hipEventQuery(d.ev) != hipSuccess) continue;
+    if (!d.busy) continue;
+    const hipError_t q = hipEventQuery(d.ev);
+    if (q == hipErrorNotReady) continue;
+    const int status = q == hipSuccess ? HSMA_OK : HSMA_EDEVICE;
+    if (status != HSMA_OK) S->failed = true;
     const double t = S->now();
     for (size_t i = 0; i < d.reqs.size(); ++i) {
-      finish(S, d.reqs[i], HSMA_OK, d.h_dE[i], d.t_start, t);
+      finish(S, d.reqs[i], status, status == HSMA_OK ? d.h_dE[i] : 0.0, d.t_start, t);
       S->busy[d.reqs[i].r.sys] = 0;
     }
     d.reqs.clear();
@@ -124,13 +132,23 @@ bool schedule_once(hsma_server_s *S) {
     did = true;
   }
   for (EnergySlot &e : S->eslots) {
-    if (!e.busy || hipEventQuery(e.ev) != hipSuccess) continue;
-    finish(S, e.req, HSMA_OK, *e.h_E, e.t_start, S->now());
+    if (!e.busy) continue;
+    const hipError_t q = hipEventQuery(e.ev);
+    if (q == hipErrorNotReady) continue;
+    const int status = q == hipSuccess ? HSMA_OK : HSMA_EDEVICE;
+    if (status != HSMA_OK) S->failed = true;
+    finish(S, e.req, status, status == HSMA_OK ? *e.h_E : 0.0, e.t_start, S->now());
     S->busy[e.req.r.sys] = 0;
     e.busy = false;
     did = true;
   }
   if (S->pending.empty()) return did;
+  if (S->failed) {
+    const double t = S->now();
+    for (const Pending &p : S->pending) finish(S, p, HSMA_EDEVICE, 0.0, t, t);
+    S->pending.clear();
+    return true;
+  }
   // a scan in arrival order; a system with an earlier request left waiting is blocked
   std::vector<char> blocked(S->systems.size(), 0);
   DeltaSlot *ds = nullptr;
@@ -420,6 +438,12 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
       slot = (int)i;
       break;
     }
+  if (slot < 0 && (int)S->systems.size() >= S->opts.max_systems) {
+    // another add took the last id while this system was built outside the lock
+    S->used -= sys->footprint;
+    hsma_system_destroy(sys);
+    return HSMA_EBUSY;
+  }
   if (slot < 0) {
     slot = (int)S->systems.size();
     S->systems.push_back(nullptr);
@@ -481,6 +505,10 @@ extern "C" hsma_status hsma_server_submit(hsma_server_t S, const hsma_request *r
       finish(S, p, HSMA_EINVAL, 0.0, t, t);
       continue;
     }
+    if (S->failed) {
+      finish(S, p, HSMA_EDEVICE, 0.0, t, t);
+      continue;
+    }
     S->pending.push_back(p);
   }
   S->wake.notify_one();
@@ -514,11 +542,20 @@ extern "C" hsma_status hsma_server_stats(hsma_server_t S, hsma_server_info *info
 
 // Open-loop load: request i is submitted at arrival[i] seconds after the call starts (a
 // busy-waiting injector thread); returns when every request has a result, in out[i]
-// (matched by position; tags are overwritten with the request index).
+// (matched by position; tags are overwritten with the request index).  A request that has no
+// result RUN_LOAD_GRACE seconds after the last arrival is reported with HSMA_EDEVICE and the call
+// returns HSMA_EDEVICE, as it does when any request completed with HSMA_EDEVICE.
+constexpr double RUN_LOAD_GRACE = 120.0;
 extern "C" hsma_status hsma_server_run_load(hsma_server_t S, const hsma_request *reqs, const double *arrival, int n,
                                             hsma_result *out) {
   if (!S || n < 0 || (n > 0 && (!reqs || !arrival || !out))) return HSMA_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(arrival[i] >= 0.0 && arrival[i] < 1e6)) return HSMA_EINVAL;
   const double t_begin = S->now();
+  double last = 0.0;
+  for (int i = 0; i < n; ++i) last = arrival[i] > last ? arrival[i] : last;
+  const double deadline = t_begin + last + RUN_LOAD_GRACE;
+  std::vector<char> have(n > 0 ? n : 1, 0);
   std::thread inj([&]() {
     for (int i = 0; i < n; ++i) {
       const double due = t_begin + arrival[i];
@@ -532,23 +569,40 @@ extern "C" hsma_status hsma_server_run_load(hsma_server_t S, const hsma_request 
     }
   });
   int got = 0;
+  bool timed_out = false, device_error = false;
   std::vector<hsma_result> buf(1024);
   while (got < n) {
     const int k = hsma_server_poll(S, buf.data(), (int)buf.size());
     for (int i = 0; i < k; ++i) {
       const uint64_t t = buf[i].tag;
-      if (t < (uint64_t)n) {
+      if (t < (uint64_t)n && !have[t]) {
         out[t] = buf[i];
+        have[t] = 1;
+        device_error = device_error || buf[i].status == HSMA_EDEVICE;
         ++got;
       }
     }
-    if (k == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    if (k == 0) {
+      if (S->now() > deadline) {
+        timed_out = true;
+        break;
+      }
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
   }
   inj.join();
   for (int i = 0; i < n; ++i) {  // times relative to the start of the load
+    if (!have[i]) {
+      out[i] = hsma_result();
+      out[i].tag = (uint64_t)i;
+      out[i].type = reqs[i].type;
+      out[i].sys = reqs[i].sys;
+      out[i].status = HSMA_EDEVICE;
+      out[i].t_submit = out[i].t_start = out[i].t_done = S->now();
+    }
     out[i].t_submit -= t_begin;
     out[i].t_start -= t_begin;
     out[i].t_done -= t_begin;
   }
-  return HSMA_OK;
+  return timed_out || device_error ? HSMA_EDEVICE : HSMA_OK;
 }

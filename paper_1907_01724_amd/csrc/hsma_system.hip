@@ -373,7 +373,7 @@ hsma_status launch_delta(const SysDev *systems, const DeReq *reqs, DeReq one, in
 
 hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
   if (ws_bytes < system_workspace_bytes(sys)) return HSMA_EINVAL;
-  const size_t lt = layout(sys->g64, 1, sys->n, sys->n).total;
+  const size_t lt = layout(sys->g64, 1, sys->n, sys->n, false, false, true).total;
   hsma_status rc = run_batched(sys->g64, 1, nullptr, nullptr, sys->n, sys->n, sys->h.x, sys->h.y, sys->h.z, sys->h.q,
                                nullptr, E, ws, lt, st);
   if (rc != HSMA_OK || !sys->h.coulomb) return rc;
@@ -381,7 +381,7 @@ hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t w
 }
 
 size_t system_workspace_bytes(const hsma_system_s *sys) {
-  return layout(sys->g64, 1, sys->n, sys->n).total + (sys->h.coulomb ? coul_bytes(sys->n) : 0);
+  return layout(sys->g64, 1, sys->n, sys->n, false, false, true).total + (sys->h.coulomb ? coul_bytes(sys->n) : 0);
 }
 
 }  // namespace hsma
@@ -437,7 +437,8 @@ extern "C" hsma_status hsma_system_create_ex(hsma_plan_t pl, int64_t N, const do
                    sizeof(SysDev);
   double *phi = nullptr;
   Layout L = layout(sys->g64, 1, N, N);
-  sys->ws_bytes = L.total + (h.coulomb ? coul_bytes(N) : 0);
+  const size_t wsb = call_workspace_bytes(sys->g64, 1, N, N, false);  // energy and potential launches
+  sys->ws_bytes = wsb + (h.coulomb ? coul_bytes(N) : 0);
 #define HSMA_TRY(call)          \
   do {                          \
     if ((call) != hipSuccess) { \
@@ -466,10 +467,10 @@ extern "C" hsma_status hsma_system_create_ex(hsma_plan_t pl, int64_t N, const do
   HSMA_TRY(hipMemcpyAsync(h.q, q, nb, hipMemcpyDeviceToDevice, st));
   HSMA_TRY(hipMemcpyAsync(sys->d, &h, sizeof(SysDev), hipMemcpyHostToDevice, st));
   phi = (double *)((char *)sys->ws + L.phi);
-  rc = run_batched(sys->g64, 1, nullptr, nullptr, N, N, h.x, h.y, h.z, h.q, phi, h.E, sys->ws, L.total, st);
+  rc = run_batched(sys->g64, 1, nullptr, nullptr, N, N, h.x, h.y, h.z, h.q, phi, h.E, sys->ws, wsb, st);
   if (rc != HSMA_OK) goto fail;
   if (h.coulomb) {
-    rc = add_coulomb(h, N, h.E, (char *)sys->ws + L.total, st);
+    rc = add_coulomb(h, N, h.E, (char *)sys->ws + wsb, st);
     if (rc != HSMA_OK) goto fail;
   }
   k_sys_s<<<(P + 255) / 256, 256, 0, st>>>(P, h.pl.dipole, h.pl.dyc, (const double2 *)((char *)sys->ws + L.qd), h.s);

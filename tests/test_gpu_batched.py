@@ -3,8 +3,9 @@
 Each system of a batch is compared with the oracle run on that system alone, and with
 the library's own single-system call (the same result alone and in the mix, within the
 tolerance), including empty and one-ion systems, systems of ragged sizes, several plans
-(different cavities) in one group, the MFMA fit path (eight or more systems) and HIP
-graph replay.
+(different cavities) in one group, a batch of 200 systems (the automatic fit route applies
+the FP32 MFMA GEMMs to the potentials from 192 systems on) and HIP graph replay.  Energies
+are held to 1e-9 of |E*| in every pair precision: they always come from FP64 pair sums.
 """
 import numpy as np
 import pytest
@@ -18,13 +19,7 @@ pytestmark = pytest.mark.gpu
 import paper_1907_01724_amd as hs  # noqa: E402
 
 TOL_PHI = {"fp32c": 1e-6, "fp64": 1e-10}
-TOL_E = {"fp32c": 2.0 ** -24, "fp64": 1e-11}  # FP32: one unit roundoff of the magnitude sum
-
-
-def _e_scale(prec, q, ref, e_ref):
-    """Energy error scale: |E| for FP64 pairs; for FP32 pairs, whose per-pair rounding does
-    not cancel with the charges, the magnitude sum (1/2) sum_i |q_i Phi_i| (>= |E|)."""
-    return abs(e_ref) if prec == "fp64" else 0.5 * float(np.sum(np.abs(q * ref)))
+TOL_E = 1e-9  # relative to |E*|, every pair precision
 
 
 @pytest.fixture(scope="module")
@@ -64,15 +59,15 @@ def _check_systems(group, plans_of_sys, systems, off, phi, E, prec, dev):
         e_ref = oracle.energy(s.q, ref)
         print(f"  sys {b} N={s.n} relL2={_rel(got, ref):.2e} relE={abs(E[b] - e_ref) / abs(e_ref):.2e}")
         assert _rel(got, ref) <= TOL_PHI[prec], (b, s.n, _rel(got, ref))
-        scale = _e_scale(prec, s.q, ref, e_ref)
-        assert abs(E[b] - e_ref) <= TOL_E[prec] * scale, (b, s.n, abs(E[b] - e_ref) / scale)
+        scale = abs(e_ref)
+        assert abs(E[b] - e_ref) <= TOL_E * scale, (b, s.n, abs(E[b] - e_ref) / scale)
         # alone: the single-system entry point on the same ions
         x, y, z, q = (torch.tensor(getattr(s, k), dtype=torch.float64, device=dev) for k in "xyzq")
         alone = torch.empty(s.n, dtype=torch.float64, device=dev)
         ea = pl.energy(x, y, z, q, phi=alone)
         assert pl.stream_check() == 0
         assert _rel(got, alone.cpu().numpy()) <= TOL_PHI[prec]
-        assert abs(E[b] - float(ea.cpu()[0])) <= 2 * TOL_E[prec] * scale
+        assert abs(E[b] - float(ea.cpu()[0])) <= 2 * TOL_E * scale
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
@@ -101,8 +96,8 @@ def _uneven_systems(a, sizes, seed0):
 @pytest.mark.parametrize("prec,persistent,items", [("fp32c", False, 8192), ("fp64", False, 8192),
                                                    ("fp32c", True, 8192), ("fp32c", True, 300)])
 def test_uneven_batch_shared_plan(dev, prec, persistent, items):
-    """24 systems sharing a = 25, P = 1024, M = 1536 (MFMA fit path in FP32), ragged sizes;
-    both launch shapes of the pair kernels, with few and many items per block."""
+    """24 systems sharing a = 25, P = 1024, M = 1536 (the GEMV fit below 192 systems), ragged
+    sizes; both launch shapes of the pair kernels, with few and many items per block."""
     a = 25.0
     plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536, pair_prec=prec)
     group = hs.Group([plan])
@@ -195,4 +190,36 @@ def test_inconsistent_sizes_are_refused(dev):
     for b, s in enumerate(systems):
         ref = oracle.hsma_eval(_oparams(plan), s.x, s.y, s.z, s.q)
         e_ref = oracle.energy(s.q, ref)
-        assert abs(float(E[b].cpu()) - e_ref) <= TOL_E["fp32c"] * _e_scale("fp32c", s.q, ref, e_ref)
+        assert abs(float(E[b].cpu()) - e_ref) <= TOL_E * abs(e_ref)
+
+
+def test_batch_of_200_systems_automatic_route(dev):
+    """200 systems of the batched geometry (a = 25, eps1 = 1, eps2 = 78.5, kappa = 0.3, P = 1024,
+    M = 1536; sizes log-uniform in [100, 2000], even, as the 4096-system workload draws them on
+    [100, 20000]) in one call with the default settings: the potentials take the FP32 MFMA fit
+    (192 systems or more), the energies the FP64 energy launch.  Every system against the oracle."""
+    a = 25.0
+    plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536)
+    group = hs.Group([plan])
+    assert group.fit_route(200) == 2
+    sizes = W.c4_sizes(200, 100, 2000, seed=W.SEED_BASE + 30)
+    systems = []
+    for b, n in enumerate(sizes):
+        rng = np.random.Generator(np.random.PCG64((W.SEED_BASE + 30) * 1000003 + b))
+        pos = W.uniform_ball(rng, int(n), a)
+        systems.append(W.System(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), W.balanced_charges(rng, int(n)),
+                                W.Physics(a, 1.0, 78.5, 0.3)))
+    off, off_d, t = _batch(systems, dev)
+    phi = torch.empty(int(off[-1]), dtype=torch.float64, device=dev)
+    E = group.energy(off_d, *t, total_n=int(off[-1]), max_n=int(max(sizes)), phi=phi)
+    assert group.stream_check() == 0
+    phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
+    worst_phi = worst_e = 0.0
+    for b, s in enumerate(systems):
+        ref = oracle.hsma_eval(_oparams(plan), s.x, s.y, s.z, s.q)
+        e_ref = oracle.energy(s.q, ref)
+        worst_phi = max(worst_phi, _rel(phi_h[off[b]:off[b + 1]], ref))
+        worst_e = max(worst_e, abs(E_h[b] - e_ref) / abs(e_ref))
+    print(f"200 systems: worst rel L2 {worst_phi:.2e}, worst rel E {worst_e:.2e}")
+    assert worst_phi <= TOL_PHI["fp32c"]
+    assert worst_e <= TOL_E

@@ -61,8 +61,7 @@ def test_c1_field(dev, prec):
     assert _rel(f, ref_f) <= TOL[prec]
     assert _rel(phi, ref_phi) <= TOL[prec]
     e_ref = oracle.energy(s.q, ref_phi)
-    scale = abs(e_ref) if prec == "fp64" else 0.5 * float(np.sum(np.abs(s.q * ref_phi)))
-    assert abs(E - e_ref) <= (1e-11 if prec == "fp64" else 2.0 ** -24 * (4 if prec == "fp32" else 1)) * scale
+    assert abs(E - e_ref) <= 1e-9 * abs(e_ref)  # energies come from FP64 pair sums in every precision
     plan.close()
 
 

@@ -63,15 +63,16 @@ def _rel(a, b):
 
 
 def _tols(case, info, route, ref, kelvin):
-    """Potential tolerance (relative L2) and energy tolerance (in units of (1/2) sum |q Phi|):
-    1e-6 and 2^-24, except split-BF16x3 on the primitive shell system (the budget above, for
-    both)."""
+    """Potential tolerance (relative L2) and energy tolerance (relative to |E*|): 1e-6 and 1e-9,
+    except for the potentials of split-BF16x3 on the primitive shell system (the budget above).
+    The energy does not depend on the route: it is always summed from FP64 pairs with the FP64
+    fit."""
     if route != 3 or not case.startswith("primitive"):
-        return 1e-6, 2.0 ** -24
+        return 1e-6, 1e-9
     A = (info["rc"] / info["a"]) ** (info["p"] + 1) * (info["R_tau"] / info["a"]) ** info["p"]
     share = float(np.linalg.norm(ref - kelvin) / np.linalg.norm(ref))
     budget = max(1e-6, 3 * 2.0 ** -16 * A * share)
-    return budget, budget
+    return budget, 1e-9
 
 
 def _single(plan, s, dev, route):
@@ -118,7 +119,7 @@ def test_single_system_routes(dev, case, route):
     tol_phi, tol_e = _tols(case, info, route, ref, dg["kelvin"])
     assert _rel(phi, ref) <= tol_phi
     assert eq <= GROSS_QD and ed <= GROSS_QD
-    assert abs(E - e_ref) <= tol_e * 0.5 * float(np.sum(np.abs(s.q * ref)))
+    assert abs(E - e_ref) <= tol_e * abs(e_ref)
     plan.close()
 
 

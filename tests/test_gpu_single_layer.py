@@ -66,8 +66,7 @@ def test_c1(dev, prec, route):
     assert not np.any(D) and not np.any(dg["D"])
     assert _rel(Q, dg["Q"] / (4 * np.pi)) <= 1e-3
     e_ref = oracle.energy(s.q, ref)
-    scale = abs(e_ref) if prec == "fp64" else 0.5 * float(np.sum(np.abs(s.q * ref)))
-    assert abs(float(E.cpu().numpy()[0]) - e_ref) <= (1e-11 if prec == "fp64" else 2.0 ** -24) * scale
+    assert abs(float(E.cpu().numpy()[0]) - e_ref) <= 1e-9 * abs(e_ref)
     plan.close()
 
 

@@ -169,7 +169,7 @@ def test_paper_claim_tau_insensitive_at_095():
         (r,) = _self_energy_errors(c["p"], tau, c["F1"], c["F2"], [c["r_s"]], g["setup"])
         errs.append(r["hsma"])
         assert r["hsma"] < c["abs_err_below"]
-    # "not very sensitive": within one order of magnitude of each other
+    # little change with tau: within one order of magnitude of each other
     assert max(errs) / min(errs) < 10.0
 
 
