@@ -156,6 +156,20 @@ hsma_status hsma_potential(hsma_plan_t plan, int64_t N, const double *x, const d
 hsma_status hsma_energy(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
                         const double *q, double *phi, double *E, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): hsma_energy without a caller workspace.  The
+ * workspace is a device array of HSMA_NOALLOC_BYTES in the library's code object, one per
+ * device, held until the process ends; the call allocates and frees nothing.  Arguments,
+ * results and errors as hsma_energy; N whose hsma_workspace_bytes(plan, N) exceeds
+ * HSMA_NOALLOC_BYTES is refused with HSMA_EINVAL before anything is enqueued (64 MiB: up to
+ * N = 42797 with P = 1600 surface nodes and M = 2400 check points).  Every call on a device shares that
+ * device's array, so calls that overlap on one device (several streams or threads) race and
+ * must be ordered by the caller.  The array needs no clearing: each call writes what it
+ * reads. */
+#define HSMA_NOALLOC_BYTES (64u << 20)
+hsma_status hsma_energy_noalloc(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,
+                                const double *q, double *phi, double *E, hipStream_t stream);
+
 /* Potential and field at every ion (Algorithm 1, step 5, which evaluates both at the ions):
  * E_i = -grad Phi_RF(x) at x = x_i with every image, the ion's own
  * included, and every surface charge held fixed; the force on ion i is q_i E_i up to the

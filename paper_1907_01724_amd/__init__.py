@@ -93,6 +93,7 @@ def load_library(path: str | None = None):
     L.hsma_workspace_bytes.restype = C.c_size_t
     L.hsma_potential.argtypes = [_VP, C.c_int64] + [_VP] * 5 + [_VP, C.c_size_t, _VP]
     L.hsma_energy.argtypes = [_VP, C.c_int64] + [_VP] * 6 + [_VP, C.c_size_t, _VP]
+    L.hsma_energy_noalloc.argtypes = [_VP, C.c_int64] + [_VP] * 6 + [_VP]
     L.hsma_debug_intermediates.argtypes = [_VP, C.c_int64, _VP, _VP, _DP, _DP, _DP, _DP]
     L.hsma_stream_check.argtypes = [_VP, _VP]
     L.hsma_status_string.argtypes = [C.c_int]
@@ -151,7 +152,7 @@ def load_library(path: str | None = None):
     L.hsma_server_stats.argtypes = [_VP, C.POINTER(ServerInfo)]
     L.hsma_server_run_load.argtypes = [_VP, C.POINTER(Request), C.POINTER(C.c_double), C.c_int, C.POINTER(Result)]
     for name in ("hsma_plan", "hsma_plan_ex", "hsma_plan_destroy", "hsma_plan_get_info", "hsma_potential",
-                 "hsma_energy", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
+                 "hsma_energy", "hsma_energy_noalloc", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
                  "hsma_group_set_fit", "hsma_group_set_sym_order", "hsma_field", "hsma_field_batched",
@@ -283,6 +284,20 @@ class Plan:
                                              _dev_ptr(z, "z", N), _dev_ptr(q, "q", N), _dev_ptr(phi, "phi", N),
                                              w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_potential")
         return phi
+
+    def energy_noalloc(self, x, y, z, q, phi=None, E=None, stream=None):
+        """hsma_energy on the library's own device scratch (no workspace, nothing allocated by
+        the library); E must be given for the call to allocate nothing here either."""
+        torch = _torch()
+        N = x.numel()
+        if E is None:
+            E = torch.empty(1, dtype=torch.float64, device=x.device)
+        _check(load_library().hsma_energy_noalloc(self._h, N, _dev_ptr(x, "x", N), _dev_ptr(y, "y", N),
+                                                  _dev_ptr(z, "z", N), _dev_ptr(q, "q", N),
+                                                  _dev_ptr(phi, "phi", N) if phi is not None else None,
+                                                  _dev_ptr(E, "E", 1), _stream_ptr(stream)),
+               "hsma_energy_noalloc")
+        return E
 
     def energy(self, x, y, z, q, phi=None, E=None, stream=None, ws: Workspace | None = None):
         torch = _torch()

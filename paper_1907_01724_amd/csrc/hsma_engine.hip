@@ -2305,6 +2305,47 @@ void prof_free(hsma_group_s *grp) {
 using namespace hsma;
 
 // ---------------------------------------------------------------------------------
+// Scratch of the allocation-free entry point: a device array of HSMA_NOALLOC_BYTES in the code
+// object, so every device the library runs on holds one until the process ends.  In host code
+// its name is only a stand-in: the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current (at plan creation, else at the entry point's first call there),
+// and only that address is passed to kernels.
+// ---------------------------------------------------------------------------------
+namespace {
+__device__ __align__(256) char scratch[HSMA_NOALLOC_BYTES];
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex noalloc_mu;
+void *noalloc_ptr[NOALLOC_DEVICES];
+}  // namespace
+
+namespace hsma {
+// The scratch address on device dev (the current device), looked up on first use.
+void *noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= NOALLOC_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    noalloc_ptr[dev] = ptr;
+  }
+  return noalloc_ptr[dev];
+}
+}  // namespace hsma
+
+extern "C" hsma_status hsma_energy_noalloc(hsma_plan_t pl, int64_t N, const double *x, const double *y,
+                                           const double *z, const double *q, double *phi, double *E,
+                                           hipStream_t st) {
+  if (!pl || N < 0) return HSMA_EINVAL;
+  int dev = -1;
+  HSMA_HIP(hipGetDevice(&dev));
+  if (dev != pl->device) return HSMA_ESTATE;
+  if (call_workspace_bytes(pl->self, 1, N, N, false) > (size_t)HSMA_NOALLOC_BYTES) return HSMA_EINVAL;
+  void *ws = noalloc_scratch(dev);
+  if (!ws) return HSMA_EDEVICE;
+  return run_batched(pl->self, 1, nullptr, nullptr, N, N, x, y, z, q, phi, E, ws, (size_t)HSMA_NOALLOC_BYTES, st);
+}
+
+// ---------------------------------------------------------------------------------
 // C ABI.
 // ---------------------------------------------------------------------------------
 extern "C" size_t hsma_workspace_bytes(hsma_plan_t pl, int64_t N) {

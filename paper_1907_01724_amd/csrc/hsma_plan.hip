@@ -654,6 +654,7 @@ extern "C" hsma_status hsma_plan_ex(double a, double eps1, double eps2, double k
   self_list[0] = pl;
   rc = group_build(1, self_list, 1, &pl->self);
   if (rc != HSMA_OK) goto fail;
+  (void)noalloc_scratch(pl->device);  // set-up of hsma_energy_noalloc on this device (retried there)
   *out = pl;
   return HSMA_OK;
 fail:
