@@ -1,20 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the HSMA reaction-potential hot path on one MI355X.
 
-Workload (default): one ion configuration, N = 20,000 ions with 30% in the shell
-r in [a - 1/2, a) of a cavity of radius a = 30, charges +-1 balanced, P = 1,600
-surface nodes, M = 2,400 check points, evaluated for four parameter sets
-(eps1, eps2) in {(80, 80), (1, 80)} x kappa in {0.05, 0.5}.  One step = the whole
-hot path for all four parameter sets: Kelvin images, check sums, fit apply,
-evaluation pair sums, potentials and FP64 energy reduction (hsma_energy).
-Inputs are resident in HBM before timing starts.
+Headline workload: N = 1,000,000 ions uniform in a cavity of radius a = 200, charges +-1 and
++-2 (2:1, neutral), eps1 = 1, eps2 = 80, kappa = 0.1, P = 6,400 surface nodes, M = 9,600
+check points (p = 40): the timing workload of Sec. 4.2 at its largest N.  One step = the
+reaction energy E = 1/2 sum q_i Phi_i of the whole system (hsma_energy): Kelvin images, FP64
+check sums, FP64 fit, FP64 energy pair sums (the symmetric energy kernel), fixed-order FP64
+reduction.  Inputs are resident in HBM before timing starts.
 
-Pairs per system and step = N*M (check) + N*(N-1) (Kelvin images, own image
-analytic) + N*P (surface nodes).  value = pairs / time, in GPairs/s.
+Pairs per step = N*M (check) + N*(N-1) (Kelvin images, own image analytic) + N*P (surface
+nodes) = 1.016e12.  value = pairs / time, in GPairs/s; systems/s = steps / time.  The energy
+is compared with the oracle's full evaluation stored in tests/golden/c3_reference.json.
 
-Prints one JSON line.  Accuracy against the FP64 CPU oracle is measured outside the
-timed regions, by the cpu_baseline leg at the end, which also times the oracle on the host
-cores; the other legs hand it their GPU results as plain arrays.
+Prints one JSON line.  Accuracy against the FP64 CPU oracle is measured outside the timed
+regions, by the cpu_baseline leg at the end, which also times the oracle on the host cores;
+the other legs hand it their GPU results as plain arrays.
 """
 from __future__ import annotations
 
@@ -29,25 +29,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Derived ALU ceiling of the evaluation kernel: 256 CUs x 4 SIMDs x 16 lanes issue
-# 256 * 64 FP32 lane-instructions per cycle at 2.4 GHz (78.6 TFLOP/s of FMA; packed FP32
-# is not used).  Only the non-transcendental VALU instructions are counted, one issue cycle
-# each; how the transcendental v_rsq_f32 overlaps with them is left out, so the peak is an
-# upper bound.  One-directional Kelvin pair: 3 sub, 1 mul + 2 fma for |d|^2, 1 fma to
-# accumulate = 7; surface-node pair: 3 sub, 3 for |d|^2, 3 for d.y_s, 4 for the
-# monopole+dipole = 13.
-CU, LANES, CLOCK = 256, 64, 2.4e9
-ISSUE_RATE = CU * LANES * CLOCK              # lane-instructions / s
-SLOTS_KELVIN, SLOTS_SURFACE = 7, 13
-# The symmetric Kelvin kernel computes each ion pair's reciprocal image distance once for both
-# ions: 3 sub, 3 for |d|^2 and one fma per direction, 8 instructions per unordered pair, i.e. 4
-# per Kelvin pair counted in one direction.
-SLOTS_KELVIN_SYM = 4
-# Field kernel (potential and E = -grad Phi together): Kelvin pair with hi/lo coordinates 9 (d) +
-# 3 (|d|^2) + 2 (strength / r, potential) + 2 (1/r^3 factor) + 3 (E); surface node 3 + 3 + 1 (1/r^2)
-# + 3 (d . y) + 2 + 1 + 1 (potential) + 4 (factors) + 6 (E).  rsq not counted, as above.
-SLOTS_FIELD_KELVIN, SLOTS_FIELD_SURFACE = 19, 24
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hsma_eval_c2_n20000_hbm_traffic.txt")
+# Published MI355X vector peaks (dense): FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s.
+PEAK_FP64, PEAK_FP32 = 78.6e12, 157.3e12
+# Algorithmic flops of one pair term (its minimal FP arithmetic; a fused multiply-add counts 2):
+#   Kelvin image: 3 sub, |d|^2 (mul + 2 fma: 5), reciprocal root 1, accumulate (fma: 2) = 11;
+#   surface node: 3 sub, |d|^2 5, root 1, d.y_s 5, 1/r^2 1, monopole + dipole (2 fma: 4), 2 = 21;
+#   check point: the Kelvin pair with a second accumulator = 13.
+FLOP_KELVIN, FLOP_SURFACE, FLOP_CHECK = 11, 21, 13
+# Potential and field of a pair (the field kernel): the potential's flops plus the gradient:
+#   Kelvin image: 11 + r^-3 (2) + strength r^-3 (1) + three fma into E (6) = 20;
+#   surface node: 21 + r^-2, r^-3 and the dipole factor (6) + two vector fma into E (12) = 39.
+FLOP_FIELD_KELVIN, FLOP_FIELD_SURFACE = 20, 39
+# VALU issue model, reported as a utilisation beside the roofline: 256 CUs x 4 SIMDs x 16 lanes at
+# 2.4 GHz issue 3.93e13 lane-instructions/s.  The energy kernel spends per unordered ion pair 11
+# FP64 instructions and one v_rsq_f64, charged 4 issue cycles (quarter rate): 15 cycles, i.e.
+# 7.5 per Kelvin pair counted in one direction; per surface pair 18 + 4.
+ISSUE_RATE = 256 * 64 * 2.4e9
+ISSUE_ENERGY_KELVIN, ISSUE_ENERGY_SURFACE = 7.5, 22.0
+GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "c3_reference.json")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
 ENGINE_SRC = os.path.join(ROOT, "paper_1907_01724_amd", "csrc", "hsma_engine.hip")
 
 
@@ -72,15 +72,16 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"])
-    ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy check and the CPU baseline")
+    ap.add_argument("--prec", default="fp32c", choices=["fp32", "fp32c", "fp64"],
+                    help="pair precision of the potentials in the legs (energies always use FP64 pairs)")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy checks and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="batched,serving,sweep,field,kirkwood,accuracy,single_layer,tree",
-                    help="extra workloads after the headline one: batched, serving, sweep, field, kirkwood, "
+    ap.add_argument("--legs", default="c2,batched,serving,sweep,field,kirkwood,accuracy,single_layer,tree",
+                    help="extra workloads after the headline one: c2, batched, serving, sweep, field, kirkwood, "
                          "accuracy, single_layer, tree (comma list, or none)")
     ap.add_argument("--settle-s", type=float, default=1.0,
                     help="seconds of untimed steps before the warm-up steps, so that the device has left its idle "
-                         "clock state when timing starts (the first steps after idle run about 8%% slower)")
+                         "clock state when timing starts")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--serving-slots", default="1,2",
                     help="request server: concurrent single-ion-move batches and full energies")
@@ -107,37 +108,25 @@ def main() -> int:
         torch.cuda.synchronize()
         log("bench: copy calibration: 2 x (256 MiB read + 256 MiB written)")
         del src, dst
-    wl = W.workload_c2()
-    d = wl.disc
-    systems = wl.systems
-    s0 = systems[0]
-    N = s0.n
-    nsys = len(systems)
-    plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=args.prec)
-             for s in systems]
-    group = hs.Group(plans)
-    # the four parameter sets share the ion configuration: one batch of four systems
-    cat = [np.concatenate([getattr(s, k) for s in systems]) for k in "xyzq"]
-    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
-    off = torch.tensor(np.arange(nsys + 1) * N, dtype=torch.int64, device=dev)
-    plan_of = torch.arange(nsys, dtype=torch.int32, device=dev)
-    phi = torch.empty(nsys * N, dtype=torch.float64, device=dev)
-    E = torch.empty(nsys, dtype=torch.float64, device=dev)
-    ws = hs.workspace(group.workspace_bytes(nsys, nsys * N, N), dev)
-    stream = torch.cuda.current_stream()
-    inf = plans[0].info
+    wl = W.workload_c3()
+    s, d = wl.systems[0], wl.disc
+    N = s.n
+    t0 = time.perf_counter()
+    plan = hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=args.prec)
+    t_plan = time.perf_counter() - t0
+    inf = plan.info
     M, P = inf["M"], inf["P"]
-    pairs_check = N * M
-    pairs_kelvin = N * (N - 1)
-    pairs_surface = N * P
-    pairs_sys = pairs_check + pairs_kelvin + pairs_surface
-    pairs_step = pairs_sys * nsys
+    x, y, z, q = (torch.tensor(v, dtype=torch.float64, device=dev) for v in (s.x, s.y, s.z, s.q))
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = hs.workspace(plan.workspace_bytes(N), dev)
+    stream = torch.cuda.current_stream()
+    pairs_check, pairs_kelvin, pairs_surface = N * M, N * (N - 1), N * P
+    pairs_step = pairs_check + pairs_kelvin + pairs_surface
 
     def step():
-        group.energy(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of, phi=phi, E=E,
-                     stream=stream, ws=ws)
+        plan.energy(x, y, z, q, E=E, stream=stream, ws=ws)
 
-    log(f"bench: workload {wl.name}, N={N}, P={P}, M={M}, p={inf['p']}, prec={args.prec}, {nsys} systems/step")
+    log(f"bench: workload {wl.name}, N={N}, P={P}, M={M}, p={inf['p']}, energy (FP64 pairs), plan {t_plan:.2f} s")
     t_settle, settle_steps = time.perf_counter(), 0
     while time.perf_counter() - t_settle < args.settle_s:
         step()
@@ -146,7 +135,7 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    assert group.stream_check() == 0
+    assert plan.stream_check() == 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -154,39 +143,21 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    log(f"bench: {ms:.4f} ms/step over {args.steps} steps")
+    e_gpu = float(E.cpu().numpy()[0])
+    log(f"bench: {ms:.3f} ms/step over {args.steps} steps, E = {e_gpu!r}")
     stages = {}
+    prof_steps = min(args.steps, 5)
     if not args.no_profile:
-        # per-stage HIP events in a separate pass of the same steps (events cost time of their own)
-        group.profile(True)
-        group.profile_read()
-        for _ in range(args.steps):
+        # per-stage HIP events on the launch stream, in a separate pass (events cost time of their own)
+        plan.profile(True)
+        plan.profile_read()
+        for _ in range(prof_steps):
             step()
         torch.cuda.synchronize()
-        stages = {k: list(v) for k, v in group.profile_read().items()}
-        group.profile(False)
-
-    # the plain per-system path on the same work, for comparison (not the reported value)
-    x, y, z, q = xb[:N], yb[:N], zb[:N], qb[:N]
-    single_ws = [hs.workspace(p.workspace_bytes(N), dev) for p in plans]
-    single_phi = [torch.empty(N, dtype=torch.float64, device=dev) for _ in plans]
-    single_E = [torch.empty(1, dtype=torch.float64, device=dev) for _ in plans]
-
-    def step_single():
-        for p, w, ph, e in zip(plans, single_ws, single_phi, single_E):
-            p.energy(x, y, z, q, phi=ph, E=e, stream=stream, ws=w)
-
-    for _ in range(args.warmup):
-        step_single()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        step_single()
-    torch.cuda.synchronize()
-    ms_single = (time.perf_counter() - t2) * 1e3 / args.steps
-
+        stages = {k: list(v) for k, v in plan.profile_read().items()}
+        plan.profile(False)
     out = {
-        "metric": "GPairs/s (HSMA reaction potential + energy, pairs = check + Kelvin + surface)",
+        "metric": "GPairs/s and systems/s at <=1e-6 rel err vs FP64; p50/p99 dE latency",
         "value": pairs_step / (ms * 1e-3) / 1e9,
         "unit": "GPairs/s",
         "n_gpus": 1,
@@ -196,70 +167,72 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp32c": "f32 pairs, f64 tile accumulation", "fp64": "f64"}[args.prec],
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "single cavity a=30, N=20000 (30% in the shell [a-1/2,a)), +-1 charges, "
-                               "P=1600, M=2400, p=20, 4 (eps1,eps2,kappa) sets",
-                   "N": N, "P": P, "M": M, "p": inf["p"], "systems_per_step": len(plans),
-                   "pair_precision": args.prec},
-        "systems_per_s": nsys / (ms * 1e-3),
+        "config": {"workload": "N=1e6 ions uniform in a=200, charges +-1/+-2 (2:1, neutral), eps1=1, eps2=80, "
+                               "kappa=0.1, P=6400, M=9600, p=40; reaction energy of the whole system per step",
+                   "N": N, "P": P, "M": M, "p": inf["p"], "systems_per_step": 1,
+                   "pairs_per_step": pairs_step, "energy_pairs": "fp64"},
+        "systems_per_s": 1.0 / (ms * 1e-3),
         "settle": {"seconds": args.settle_s, "steps": settle_steps},
-        "per_system_path_ms_per_step": ms_single,
+        "plan_s": t_plan,
     }
+    with open(GOLDEN_C3) as f:
+        golden = json.load(f)
+    if golden["N"] == N and golden["P"] == P and golden["M"] == M:
+        out["rel_err_energy"] = abs(e_gpu - golden["E"]) / abs(golden["E"])
+        out["energy_reference"] = "tests/golden/c3_reference.json (oracle O1, full FP64 evaluation)"
+        log(f"bench: energy vs the stored oracle evaluation: rel {out['rel_err_energy']:.2e}")
     if stages:
         ev_ms, ev_n = stages["eval"]
-        avg = ev_ms / max(ev_n, 1) * 1e-3               # one launch covers the whole batch
-        eval_pairs = (pairs_kelvin + pairs_surface) * nsys
-        sym = group.eval_kernel(nsys, nsys * N, N)
-        sk = SLOTS_KELVIN_SYM if sym > 0 else SLOTS_KELVIN
-        t_min = (pairs_kelvin * sk + pairs_surface * SLOTS_SURFACE) * nsys / ISSUE_RATE
-        peak = eval_pairs / t_min
-        achieved = eval_pairs / avg
-        traffic = _measured_traffic(args.prec, "k_kelvin_sym<%d>" % (sym // 64) if sym > 0 else "k_eval<%d>" % {
-            "fp32": 0, "fp32c": 1, "fp64": 2}[args.prec])
+        avg = ev_ms / max(ev_n, 1) * 1e-3  # one energy-kernel launch per step
+        flop = FLOP_KELVIN * pairs_kelvin + FLOP_SURFACE * pairs_surface
+        t_issue = (ISSUE_ENERGY_KELVIN * pairs_kelvin + ISSUE_ENERGY_SURFACE * pairs_surface) / ISSUE_RATE
         out["roofline"] = {
             "bound": "alu",
-            "kernel": ("k_kelvin_sym (symmetric Kelvin pairs in blocks of %d ions + surface chunks)" % sym if sym > 0
-                       else "k_eval (evaluation pair sums)") + ", all systems of the step in one launch",
-            "achieved": achieved / 1e9,
-            "peak": peak / 1e9,
-            "unit": "Gpair/s",
-            "frac": achieved / peak,
-            "traffic": traffic,
+            "kernel": "k_energy64 (FP64 energy pair sums: symmetric Kelvin block pairs + surface chunks)",
+            "achieved": flop / avg / 1e12,
+            "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": flop / avg / PEAK_FP64,
+            "traffic": _measured_traffic("k_energy64", flop),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy)",
-            "algorithmic_bytes": 40 * N * nsys + 24 * P * nsys,
+            "algorithmic_bytes": 48 * N + 48 * P,
             "avg_launch_ms": avg * 1e3,
-            "pairs_per_launch": eval_pairs,
-            "peak_model": "256 CU x 64 lanes x 2.4 GHz VALU issue, one instruction per cycle; %s non-transcendental "
-                          "VALU instructions per Kelvin pair, 13 per surface pair" % sk,
+            "flop_per_launch": flop,
+            "flop_model": "11 per Kelvin pair N(N-1), 21 per surface pair NP (algorithmic, both directions of a "
+                          "pair counted); peak: published FP64 vector rate",
+            "valu_issue_utilisation": t_issue / avg,
         }
-        out["stage_ms_per_step"] = {k: v[0] / args.steps for k, v in stages.items()}
+        out["stage_ms_per_step"] = {k: v[0] / prof_steps for k, v in stages.items()}
+        log(f"bench: energy kernel {avg * 1e3:.2f} ms/launch, {out['roofline']['achieved']:.1f} TFLOP/s = "
+            f"{out['roofline']['frac']:.3f} of the FP64 peak")
+    del ws
 
     checks = None if args.no_oracle else OracleChecks()
     if checks is not None:
-        phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
-
         def report_headline(r):
-            out["rel_err_phi_l2_max"] = max(r["rel_phi"])
-            out["rel_err_energy_max"] = max(r["rel_e"])
             out["cpu_baseline"] = {
-                "value": pairs_sys * r["calls"] / r["seconds"] / 1e9,
+                "value": r["pairs"] / r["seconds"] / 1e9,
                 "unit": "GPairs/s",
                 "cores": r["cores"],
                 "kind": "oracle",
-                "sample": f"{r['calls']} oracle evaluations (cycling over the four parameter sets) of the full "
-                          f"N={N} configuration: FP64 direct check sums, Householder least squares, Kelvin and "
-                          f"surface sums",
+                "sample": "%d oracle (O1, FP64) evaluations of the headline system, each at 1000 sampled ions: "
+                          "check sums of all 1e6 ions at the 9600 check points, Householder least squares, surface "
+                          "strengths, Kelvin and surface sums at the 1000 ions (%.3g pairs in all)" % (r["calls"],
+                                                                                                  r["pairs"]),
                 "seconds": r["seconds"],
+                "build": r["build"],
             }
-            log(f"bench: oracle: phi rel L2 {out['rel_err_phi_l2_max']:.2e}, energy {out['rel_err_energy_max']:.2e}; "
-                f"cpu_baseline {out['cpu_baseline']['value']:.2f} GPairs/s on {r['cores']} threads")
+            log(f"bench: cpu_baseline {out['cpu_baseline']['value']:.2f} GPairs/s on {r['cores']} threads "
+                f"({r['seconds']:.1f} s, {r['build']})")
 
-        checks.add("baseline", report_headline, infos=[p.info for p in plans],
-                   systems=[(s.x, s.y, s.z, s.q) for s in systems],
-                   phis=[phi_h[b * N:(b + 1) * N] for b in range(nsys)], Es=[float(e) for e in E_h],
-                   min_seconds=10.0)
+        checks.add("baseline_sampled", report_headline, info=inf, system=(s.x, s.y, s.z, s.q), targets=1000,
+                   seed=W.SEED_BASE + 22, min_seconds=10.0)
+    plan.close()
     legs = [l for l in args.legs.split(",") if l and l != "none"]
+    if "c2" in legs:
+        out["c2"] = leg_c2(args, checks)
     if "batched" in legs:
         out["batched"] = leg_batched(args, checks)
     if "serving" in legs:
@@ -282,27 +255,146 @@ def main() -> int:
     return 0
 
 
-def _measured_traffic(prec: str, kernel: str):
-    """HBM bytes per launch of the batched evaluation kernel from the committed PMC summary, or
-    None when the kernel, its source (hash) or the pair precision differ from the counted run."""
+def _measured_traffic(kernel: str, _flop=None):
+    """HBM bytes per launch of a kernel from its committed PMC summary (profiles/<kernel>_*hbm_traffic.txt),
+    or None when no summary exists or the engine source changed since the counted run (its hash)."""
+    import glob
     import hashlib
     try:
-        kv = dict(l.split(None, 1) for l in open(TRAFFIC_FILE) if l.strip() and not l.startswith((" ", "#")))
         with open(ENGINE_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError):
+        for path in sorted(glob.glob(os.path.join(PROFILE_DIR, f"{kernel}_*hbm_traffic.txt"))):
+            kv = dict(l.split(None, 1) for l in open(path) if l.strip() and not l.startswith((" ", "#")))
+            if kv.get("engine_source_sha256", "").strip() == sha and kv.get("kernel", "").strip() == kernel:
+                return float(kv["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
         return None
-    if (kv.get("engine_source_sha256", "").strip() != sha or kv.get("pair_precision", "").strip() != prec
-            or kv.get("kernel", "").strip() != kernel):
-        return None
-    return float(kv["traffic_bytes_per_launch"])
+    return None
 
 
-def _eval_roofline(pairs_kelvin, pairs_surface, avg_s, sym=0):
-    t_min = (pairs_kelvin * (SLOTS_KELVIN_SYM if sym > 0 else SLOTS_KELVIN) + pairs_surface * SLOTS_SURFACE) / ISSUE_RATE
-    pairs = pairs_kelvin + pairs_surface
-    return {"bound": "alu", "achieved": pairs / avg_s / 1e9, "peak": pairs / t_min / 1e9, "unit": "Gpair/s",
-            "frac": t_min / avg_s, "avg_launch_ms": avg_s * 1e3, "symmetric_block": sym}
+def _pot_roofline(pairs_kelvin, pairs_surface, avg_s, prec, kernel):
+    """Roofline of a potential launch (Kelvin + surface pairs) against the published vector peak of
+    its pair precision, with the algorithmic flops of FLOP_KELVIN / FLOP_SURFACE per pair."""
+    peak = PEAK_FP64 if prec == "fp64" else PEAK_FP32
+    flop = FLOP_KELVIN * pairs_kelvin + FLOP_SURFACE * pairs_surface
+    return {"bound": "alu", "kernel": kernel, "achieved": flop / avg_s / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": flop / avg_s / peak, "avg_launch_ms": avg_s * 1e3, "flop_per_launch": flop}
+
+
+def _energy_roofline(pairs_kelvin, pairs_surface, avg_s):
+    flop = FLOP_KELVIN * pairs_kelvin + FLOP_SURFACE * pairs_surface
+    t_issue = (ISSUE_ENERGY_KELVIN * pairs_kelvin + ISSUE_ENERGY_SURFACE * pairs_surface) / ISSUE_RATE
+    return {"bound": "alu", "kernel": "k_energy64", "achieved": flop / avg_s / 1e12, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": flop / avg_s / PEAK_FP64, "avg_launch_ms": avg_s * 1e3,
+            "valu_issue_utilisation": t_issue / avg_s}
+
+
+def leg_c2(args, checks) -> dict:
+    """N = 20,000 ions with 30% in the shell r in [a - 1/2, a) of a cavity of radius a = 30,
+    charges +-1 balanced, P = 1,600, M = 2,400, under the four parameter sets (eps1, eps2) in
+    {(80, 80), (1, 80)} x kappa in {0.05, 0.5}, as one batched call of four systems: potentials
+    alone (the pair precision of --prec), energies alone (FP64 pairs), and both; the potential
+    kernel against its roofline; the plain per-system path on the same work."""
+    import numpy as np
+    import torch
+
+    import paper_1907_01724_amd as hs
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    wl = W.workload_c2()
+    d = wl.disc
+    systems = wl.systems
+    N = systems[0].n
+    nsys = len(systems)
+    plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, d.P, d.M, pair_prec=args.prec)
+             for s in systems]
+    group = hs.Group(plans)
+    cat = [np.concatenate([getattr(s, k) for s in systems]) for k in "xyzq"]
+    xb, yb, zb, qb = (torch.tensor(v, dtype=torch.float64, device=dev) for v in cat)
+    off = torch.tensor(np.arange(nsys + 1) * N, dtype=torch.int64, device=dev)
+    plan_of = torch.arange(nsys, dtype=torch.int32, device=dev)
+    phi = torch.empty(nsys * N, dtype=torch.float64, device=dev)
+    E = torch.empty(nsys, dtype=torch.float64, device=dev)
+    ws = hs.workspace(group.workspace_bytes(nsys, nsys * N, N), dev)
+    inf = plans[0].info
+    M, P = inf["M"], inf["P"]
+    pk, ps, pc = N * (N - 1) * nsys, N * P * nsys, N * M * nsys
+    pairs = pk + ps + pc
+    calls = {
+        "potentials": lambda: group.potential(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of,
+                                              phi=phi, ws=ws),
+        "energies": lambda: group.energy(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of, E=E,
+                                         ws=ws),
+        "potentials_and_energies": lambda: group.energy(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N,
+                                                        plan_of=plan_of, phi=phi, E=E, ws=ws),
+    }
+    res = {"workload": "N=20000, a=30, 30% in the shell [a-1/2,a), +-1 charges, P=1600, M=2400, p=20, "
+                       "4 (eps1,eps2,kappa) sets in one call", "pairs_per_call": pairs, "pair_precision": args.prec}
+    steps = 20
+    for name, call in calls.items():
+        t_settle = time.perf_counter()
+        while time.perf_counter() - t_settle < max(args.settle_s, 0.5):  # leave the idle clock state
+            call()
+            torch.cuda.synchronize()
+        assert group.stream_check() == 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        group.profile(True)
+        group.profile_read()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        st = group.profile_read()
+        group.profile(False)
+        ev = st["eval"][0] / steps * 1e-3
+        r = {"ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9,
+             "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()}}
+        if name == "potentials":
+            sym = group.eval_kernel(nsys, nsys * N, N)
+            r["roofline"] = _pot_roofline(pk, ps, ev, args.prec, "k_kelvin_sym<%d>" % (sym // 64) if sym > 0
+                                          else "k_eval")
+            r["roofline"]["traffic"] = _measured_traffic("k_kelvin_sym4") if sym == 256 else None
+        elif name == "energies":
+            r["roofline"] = _energy_roofline(pk, ps, ev)
+        res[name] = r
+        log(f"bench[c2]: {name}: {ms:.4f} ms/call, evaluation {ev * 1e3:.4f} ms")
+    # the plain per-system path on the same work, for comparison
+    x, y, z, q = xb[:N], yb[:N], zb[:N], qb[:N]
+    single_ws = [hs.workspace(p.workspace_bytes(N), dev) for p in plans]
+    single_phi = [torch.empty(N, dtype=torch.float64, device=dev) for _ in plans]
+    single_E = [torch.empty(1, dtype=torch.float64, device=dev) for _ in plans]
+
+    def step_single():
+        for p, w, ph, e in zip(plans, single_ws, single_phi, single_E):
+            p.energy(x, y, z, q, phi=ph, E=e, ws=w)
+
+    step_single()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        step_single()
+    torch.cuda.synchronize()
+    res["per_system_path_ms_per_call"] = (time.perf_counter() - t2) * 1e3 / steps
+    if checks is not None:
+        calls["potentials_and_energies"]()
+        phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
+
+        def report(r):
+            res["rel_err_phi_l2_max"] = max(r["rel_phi"]["phi"])
+            res["rel_err_energy_max"] = max(r["rel_e"])
+            log(f"bench[c2]: oracle: phi rel L2 {res['rel_err_phi_l2_max']:.2e}, energy "
+                f"{res['rel_err_energy_max']:.2e}")
+
+        checks.add("potentials", report, infos=[p.info for p in plans],
+                   systems=[(s.x, s.y, s.z, s.q) for s in systems],
+                   phis={"phi": [phi_h[b * N:(b + 1) * N] for b in range(nsys)]}, Es=[float(e) for e in E_h])
+    for p in plans:
+        p.close()
+    return res
 
 
 def leg_field(args, checks) -> dict:
@@ -332,6 +424,9 @@ def leg_field(args, checks) -> dict:
     def call():
         return group.field(off, xb, yb, zb, qb, total_n=total, max_n=N, plan_of=plan_of)
 
+    def call_field_only():  # potential and field without the energy launch, for the kernel's roofline
+        return group.field(off, xb, yb, zb, qb, total_n=total, max_n=N, plan_of=plan_of, E=False)
+
     call()
     torch.cuda.synchronize()
     assert group.stream_check() == 0
@@ -347,21 +442,25 @@ def leg_field(args, checks) -> dict:
         call()
     torch.cuda.synchronize()
     st = group.profile_read()
+    for _ in range(steps):
+        call_field_only()
+    torch.cuda.synchronize()
+    st_f = group.profile_read()
     group.profile(False)
     inf = plans[0].info
     P, M = inf["P"], inf["M"]
     pk, ps = N * (N - 1) * nsys, N * P * nsys
     pairs = pk + ps + N * M * nsys
-    ev = st["eval"][0] / steps * 1e-3
-    t_min = (pk * SLOTS_FIELD_KELVIN + ps * SLOTS_FIELD_SURFACE) / ISSUE_RATE
+    # the eval stage holds the energy launch's k_energy64 and the field launch's k_eval_field
+    peak = PEAK_FP64 if args.prec == "fp64" else PEAK_FP32
     res = {"workload": "N=20000, a=30, 30% in the shell [a-1/2,a), P=1600, M=2400, p=20, 4 (eps1,eps2,kappa) sets, "
                        "potential + field + energy", "ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9,
-           "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()},
-           "roofline": {"bound": "alu", "kernel": "k_eval_field (potential and field pair sums)",
-                        "achieved": (pk + ps) / ev / 1e9, "peak": (pk + ps) / t_min / 1e9, "unit": "Gpair/s",
-                        "frac": t_min / ev, "avg_launch_ms": ev * 1e3,
-                        "peak_model": "%d / %d non-transcendental VALU instructions per Kelvin / surface pair" % (
-                            SLOTS_FIELD_KELVIN, SLOTS_FIELD_SURFACE)}}
+           "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()}}
+    evf = st_f["eval"][0] / steps * 1e-3
+    flop = FLOP_FIELD_KELVIN * pk + FLOP_FIELD_SURFACE * ps
+    res["roofline"] = {"bound": "alu", "kernel": "k_eval_field (potential and field pair sums)",
+                       "achieved": flop / evf / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": flop / evf / peak,
+                       "avg_launch_ms": evf * 1e3, "flop_model": "20 per Kelvin pair, 39 per surface pair"}
     if checks is not None:
         phi_h, f_h = phi.cpu().numpy(), f.cpu().numpy()
 
@@ -376,7 +475,8 @@ def leg_field(args, checks) -> dict:
                    fields=[f_h[b * N:(b + 1) * N] for b in range(nsys)])
     for p in plans:
         p.close()
-    log(f"bench[field]: {ms:.3f} ms/call, eval {ev * 1e3:.3f} ms ({res['roofline']['frac']:.2f} of its ALU peak)")
+    log(f"bench[field]: {ms:.3f} ms/call, field kernel {evf * 1e3:.3f} ms ({res['roofline']['frac']:.2f} of the "
+        f"vector peak)")
     return res
 
 
@@ -409,7 +509,7 @@ def leg_single_layer(args, checks) -> dict:
         group = hs.Group(plans)
 
         def step():
-            group.energy(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of, phi=phi, E=E)
+            group.potential(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of, phi=phi)
 
         t_settle = time.perf_counter()
         while time.perf_counter() - t_settle < max(args.settle_s, 0.5):  # leave the idle clock state
@@ -429,6 +529,7 @@ def leg_single_layer(args, checks) -> dict:
         st = group.profile_read()
         group.profile(False)
         res[form] = {"ms_per_step": ms, "eval_ms": st["eval"][0] / steps}
+        group.energy(off, xb, yb, zb, qb, total_n=nsys * N, max_n=N, plan_of=plan_of, E=E)
         log(f"bench[single_layer]: {form}: {ms:.4f} ms/step, evaluation {st['eval'][0] / steps:.4f} ms")
         if checks is not None:
             phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
@@ -494,7 +595,8 @@ def leg_kirkwood(args, checks) -> dict:
     E = torch.empty(1, dtype=torch.float64, device=dev)
     times = {}
     for name, fn in (("kirkwood_order40_fp64", lambda: p2.kirkwood(*t2, order=40, E=E)),
-                     ("hsma_fp32c", lambda: p2.energy(*t2, E=E))):
+                     ("hsma_energy_fp64", lambda: p2.energy(*t2, E=E)),
+                     ("hsma_potentials_fp32c", lambda: p2.potential(*t2))):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -511,8 +613,9 @@ def leg_kirkwood(args, checks) -> dict:
 
 def leg_batched(args, checks) -> dict:
     """4096 configurations (a = 25, eps1 = 1, eps2 = 78.5, kappa = 0.3, P = 1024, M = 1536),
-    N log-uniform in [100, 20000]: one batched call (shared plan, fit as MFMA GEMMs) per step,
-    against the plain per-system path on the same systems."""
+    N log-uniform in [100, 20000]: one batched call (shared plan) per step for the energies (FP64
+    energy launch; systems/s) and one for the potentials (pair precision of --prec, fit as FP32 MFMA
+    GEMMs), against the plain per-system path on the same systems."""
     import numpy as np
     import torch
 
@@ -535,31 +638,39 @@ def leg_batched(args, checks) -> dict:
     phi = torch.empty(total, dtype=torch.float64, device=dev)
     E = torch.empty(nsys, dtype=torch.float64, device=dev)
     ws = hs.workspace(group.workspace_bytes(nsys, total, max_n), dev)
-
-    def call():
-        group.energy(off, xb, yb, zb, qb, total_n=total, max_n=max_n, phi=phi, E=E, ws=ws)
-
-    call()
-    torch.cuda.synchronize()
-    assert group.stream_check() == 0
-    steps = 3
-    t1 = time.perf_counter()
-    for _ in range(steps):
-        call()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t1) * 1e3 / steps
-    group.profile(True)
-    group.profile_read()
-    for _ in range(steps):
-        call()
-    torch.cuda.synchronize()
-    st = group.profile_read()
-    group.profile(False)
     info = plan.info
     pk = float(np.sum(sizes * (sizes - 1)))
     ps = float(np.sum(sizes)) * info["P"]
     pc = float(np.sum(sizes)) * info["M"]
-    # plain per-system path: one single-system call per configuration
+    steps = 3
+
+    def timed(call):
+        call()
+        torch.cuda.synchronize()
+        assert group.stream_check() == 0
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / steps
+        group.profile(True)
+        group.profile_read()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        st = group.profile_read()
+        group.profile(False)
+        return ms, {k: v[0] / steps for k, v in st.items()}
+
+    def energies():
+        group.energy(off, xb, yb, zb, qb, total_n=total, max_n=max_n, E=E, ws=ws)
+
+    def potentials():
+        group.potential(off, xb, yb, zb, qb, total_n=total, max_n=max_n, phi=phi, ws=ws)
+
+    ms_e, st_e = timed(energies)
+    ms_p, st_p = timed(potentials)
+    # plain per-system path: one single-system energy call per configuration
     single_ws = hs.workspace(plan.workspace_bytes(max_n), dev)
     e1 = torch.empty(1, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
@@ -569,38 +680,37 @@ def leg_batched(args, checks) -> dict:
         plan.energy(xb[lo:hi], yb[lo:hi], zb[lo:hi], qb[lo:hi], E=e1, ws=single_ws)
     torch.cuda.synchronize()
     ms_single = (time.perf_counter() - t2) * 1e3
+    sym = group.eval_kernel(nsys, total, max_n)
     res = {
         "workload": "4096 configurations, N log-uniform in [100, 20000], a=25, eps1=1, eps2=78.5, kappa=0.3, "
                     "P=1024, M=1536, shared plan",
-        "systems": nsys, "total_ions": total, "ms_per_call": ms, "systems_per_s": nsys / (ms * 1e-3),
-        "gpairs_per_s": (pc + pk + ps) / (ms * 1e-3) / 1e9,
+        "systems": nsys, "total_ions": total, "pairs_per_call": pc + pk + ps,
+        "energies": {"ms_per_call": ms_e, "systems_per_s": nsys / (ms_e * 1e-3),
+                     "gpairs_per_s": (pc + pk + ps) / (ms_e * 1e-3) / 1e9, "stage_ms_per_call": st_e,
+                     "roofline": _energy_roofline(pk, ps, st_e["eval"] * 1e-3)},
+        "potentials": {"ms_per_call": ms_p, "systems_per_s": nsys / (ms_p * 1e-3),
+                       "gpairs_per_s": (pc + pk + ps) / (ms_p * 1e-3) / 1e9, "stage_ms_per_call": st_p,
+                       "roofline": _pot_roofline(pk, ps, st_p["eval"] * 1e-3, args.prec,
+                                                 "k_kelvin_sym<%d>" % (sym // 64) if sym > 0 else "k_eval")},
         "per_system_path_ms": ms_single, "per_system_path_systems_per_s": nsys / (ms_single * 1e-3),
-        "stage_ms_per_call": {k: v[0] / steps for k, v in st.items()},
-        "roofline": _eval_roofline(pk, ps, st["eval"][0] / steps * 1e-3, group.eval_kernel(nsys, total, max_n)),
     }
-    # sampled systems for the oracle checks: the default route's potentials and energies here,
+    # sampled systems for the oracle checks: the default route's potentials and the energies here,
     # each fit route's potentials below
     rng = np.random.default_rng(0)
     pick = rng.choice(np.nonzero(sizes <= 3000)[0], 6, replace=False)
     phi_h, E_h = phi.cpu().numpy(), E.cpu().numpy()
     sampled = {"default": [phi_h[off_h[b]:off_h[b + 1]] for b in pick]}
     res["sampled_systems"] = [int(b) for b in pick]
-    # The fit apply by each route on the same call: stage time, rate against the MFMA peak of its
-    # type (the split-BF16 routes count their term products), and the sampled errors.
+    # The fit apply by each route on the potential call: stage time, rate against the MFMA peak of
+    # its type (the split-BF16 routes count their term products), and the sampled errors.
     K, P, M = info["K"], info["P"], info["M"]
     fit_flop = 2.0 * K * M * 2 * nsys + 2.0 * P * K * 2 * nsys
     routes = {}
     for mode, name, peak, mult in ((1, "gemv_fp32", None, 1), (2, "mfma_fp32", 157.3, 1),
                                    (3, "mfma_bf16x3", 2500.0, 3), (4, "mfma_bf16x6", 2500.0, 6)):
         group.set_fit(mode)
-        call()
-        group.profile(True)
-        group.profile_read()
-        for _ in range(steps):
-            call()
-        torch.cuda.synchronize()
-        fit_ms = group.profile_read()["fit"][0] / steps
-        group.profile(False)
+        _, st = timed(potentials)
+        fit_ms = st["fit"]
         r = {"fit_ms": fit_ms}
         if peak is not None:
             tf = fit_flop * mult / (fit_ms * 1e-3) / 1e12
@@ -624,8 +734,8 @@ def leg_batched(args, checks) -> dict:
         checks.add("potentials", report, infos=[info] * len(pick),
                    systems=[(wl.systems[b].x, wl.systems[b].y, wl.systems[b].z, wl.systems[b].q) for b in pick],
                    phis=sampled, Es=[float(E_h[b]) for b in pick])
-    log(f"bench[batched]: {ms:.2f} ms/call, {res['systems_per_s']:.0f} systems/s "
-        f"(per-system path {res['per_system_path_systems_per_s']:.0f})")
+    log(f"bench[batched]: energies {ms_e:.2f} ms/call ({res['energies']['systems_per_s']:.0f} systems/s), "
+        f"potentials {ms_p:.2f} ms/call; per-system path {res['per_system_path_systems_per_s']:.0f} systems/s")
     return res
 
 
@@ -635,7 +745,8 @@ def leg_sweep(args, checks) -> dict:
     FP32 and FP64 pair sums (fit applied with FP32 GEMVs for the FP32 modes, FP64 GEMVs for FP64
     pairs), and the compensated FP32 path again with the fit applied as FP32 MFMA GEMMs and as
     split-BF16x3 and split-BF16x6 MFMA GEMMs.  The potentials of 256 sampled ions go to the oracle
-    checks, the energies are compared with the FP64 run's; each run also reports its fit-stage time."""
+    checks; each run also reports its fit-stage time.  Potentials only (hsma_potential): the
+    energies, FP64 in every mode, are the headline's."""
     import numpy as np
     import torch
 
@@ -657,7 +768,7 @@ def leg_sweep(args, checks) -> dict:
     runs = (("fp32", "fp32", 0), ("fp32c", "fp32c", 0), ("fp32c_fit_mfma_fp32", "fp32c", 2),
             ("fp32c_fit_mfma_bf16x3", "fp32c", 3), ("fp32c_fit_mfma_bf16x6", "fp32c", 4), ("fp64", "fp64", 0))
     route_name = {1: "gemv", 2: "mfma_fp32", 3: "mfma_bf16x3", 4: "mfma_bf16x6"}
-    phis, Es = {}, {}
+    phis = {}
     plans = {}
     for label, prec, fit in runs:
         t0 = time.perf_counter()
@@ -668,29 +779,26 @@ def leg_sweep(args, checks) -> dict:
         plan.set_fit(fit)
         ws = hs.workspace(plan.workspace_bytes(N), dev)
         phi = torch.empty(N, dtype=torch.float64, device=dev)
-        E = torch.empty(1, dtype=torch.float64, device=dev)
-        plan.energy(x, y, z, q, phi=phi, E=E, ws=ws)
+        plan.potential(x, y, z, q, phi=phi, ws=ws)
         torch.cuda.synchronize()
         assert plan.stream_check() == 0
         t1 = time.perf_counter()
         for _ in range(2):
-            plan.energy(x, y, z, q, phi=phi, E=E, ws=ws)
+            plan.potential(x, y, z, q, phi=phi, ws=ws)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t1) * 1e3 / 2
         plan.profile(True)
-        plan.energy(x, y, z, q, phi=phi, E=E, ws=ws)
+        plan.potential(x, y, z, q, phi=phi, ws=ws)
         st = plan.profile_read()
         plan.profile(False)
         phis[label] = phi[idx_d].cpu().numpy()
-        Es[label] = float(E.cpu().numpy()[0])
-        res[label] = {"ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9, "plan_s": t_plan, "E": Es[label],
+        res[label] = {"ms_per_call": ms, "gpairs_per_s": pairs / (ms * 1e-3) / 1e9, "plan_s": t_plan,
                       "fit": route_name[plan.fit_route()] if prec != "fp64" else "gemv_fp64",
-                      "fit_stage_ms": st["fit"][0]}
+                      "fit_stage_ms": st["fit"][0],
+                      "roofline": _pot_roofline(N * (N - 1), N * d.P, st["eval"][0] * 1e-3, prec, "evaluation")}
         log(f"bench[sweep]: {label}: {ms:.1f} ms/call ({pairs / (ms * 1e-3) / 1e9:.0f} GPairs/s), "
             f"fit {res[label]['fit']} {st['fit'][0]:.3f} ms, plan {t_plan:.2f} s")
         del ws, phi
-    for label, _, _ in runs[:-1]:
-        res[label]["rel_err_energy_vs_fp64"] = abs(Es[label] - Es["fp64"]) / abs(Es["fp64"])
     if checks is not None:
         def report(r):
             res["oracle_s"] = r["seconds"]
@@ -796,6 +904,18 @@ def leg_cpu_baseline(checks: OracleChecks) -> None:
 
     import oracle
 
+    # The timed oracle is the same C source built for the host it runs on (-O3 -march=native, no
+    # fast-math), in a scratch directory; the accuracy references use the same build.
+    build = "gcc -O2 (oracle/__init__.py build)"
+    try:
+        import tempfile
+        native = os.path.join(tempfile.mkdtemp(prefix="hsma_oracle_"), "libhsma_oracle_native.so")
+        flags = oracle.build_native(native)
+        oracle.use_library(native)
+        build = "gcc " + " ".join(flags)
+    except Exception as e:  # keep the default build
+        log(f"bench: native oracle build failed ({e}); timing the default build")
+
     def params(i):
         return oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"],
                              M=i["M"], tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"], dipole=i["dipole"],
@@ -805,7 +925,23 @@ def leg_cpu_baseline(checks: OracleChecks) -> None:
         return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
 
     for kind, d, report in checks.jobs:
-        if kind == "baseline":
+        if kind == "baseline_sampled":
+            # whole oracle evaluations at 1000 sampled ions each (check sums of all ions, the fit,
+            # Kelvin and surface sums at the sample), repeated with fresh samples for at least 10 s
+            x, y, z, q = d["system"]
+            i = d["info"]
+            n = len(x)
+            rng = np.random.Generator(np.random.PCG64(d["seed"]))
+            secs, pairs, calls = 0.0, 0.0, 0
+            while secs < d["min_seconds"]:
+                idx = np.sort(rng.choice(n, d["targets"], replace=False))
+                t0 = time.perf_counter()
+                oracle.hsma_eval(params(i), x, y, z, q, targets=np.stack([x[idx], y[idx], z[idx]], axis=1))
+                secs += time.perf_counter() - t0
+                pairs += float(n) * i["M"] + float(len(idx)) * (n + i["P"])
+                calls += 1
+            report({"seconds": secs, "pairs": pairs, "calls": calls, "cores": oracle.num_threads(), "build": build})
+        elif kind == "baseline":
             rel_phi, rel_e, secs, calls = [], [], 0.0, 0
             for i, (x, y, z, q), ph, e in zip(d["infos"], d["systems"], d["phis"], d["Es"]):
                 t0 = time.perf_counter()
@@ -893,7 +1029,7 @@ def leg_tree(args, checks) -> dict:
     for label, cfg in runs:
         if cfg is None:
             def call():
-                plan.energy(x, y, z, q, phi=phi, E=E)
+                plan.potential(x, y, z, q, phi=phi)
         else:
             def call(cfg=cfg):
                 plan.energy_tree(x, y, z, q, order=cfg[0], theta=cfg[1], phi=phi, E=E)
@@ -906,6 +1042,8 @@ def leg_tree(args, checks) -> dict:
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / 3
         sampled[label] = phi[idx_d].cpu().numpy()
+        if cfg is None:
+            plan.energy(x, y, z, q, E=E)  # the direct energy, FP64 pairs
         res[label] = {"ms_per_call": ms, "E": float(E.cpu().numpy()[0])}
         log(f"bench[tree]: {label}: {ms:.1f} ms/call")
     for label, _ in runs[1:]:

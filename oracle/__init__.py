@@ -32,6 +32,23 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+NATIVE_FLAGS = ["-O3", "-march=native", "-std=c11", "-fopenmp", "-fPIC", "-shared"]
+
+
+def build_native(path: str) -> list:
+    """Compile the same source for the host it runs on (-O3 -march=native, no fast-math) into
+    ``path`` (for timing the oracle as a CPU baseline); returns the flags used."""
+    subprocess.check_call(["gcc", *NATIVE_FLAGS, "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", path, "-lm"])
+    return list(NATIVE_FLAGS)
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from ``path`` from now on (a build of the same source)."""
+    global _lib, _LIB_PATH
+    _LIB_PATH = path
+    _lib = None
+
+
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("eps1", C.c_double), ("eps2", C.c_double), ("kappa", C.c_double),
                 ("tau", C.c_double), ("rc_over_a", C.c_double), ("p", C.c_int), ("P", C.c_int),

@@ -494,9 +494,31 @@ class Group:
             _dev_ptr(E, "E", nsys), w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_energy_batched")
         return E
 
+    def potential(self, offsets, x, y, z, q, total_n: int, max_n: int, plan_of=None, phi=None, stream=None,
+                  ws=None):
+        """Potentials alone (hsma_energy_batched with E = NULL: the launch in the group's pair
+        precision, no energy launch).  Returns phi."""
+        torch = _torch()
+        nsys = offsets.numel() - 1
+        if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise TypeError("offsets must be a contiguous int64 device tensor")
+        if plan_of is not None and (plan_of.dtype != torch.int32 or not plan_of.is_cuda or plan_of.numel() != nsys):
+            raise TypeError("plan_of must be an int32 device tensor of nsys entries")
+        if phi is None:
+            phi = torch.empty(int(total_n), dtype=torch.float64, device=x.device)
+        w = ws if ws is not None else _ensure(self._ws, (nsys, int(total_n), int(max_n), str(x.device)),
+                                              self.workspace_bytes(nsys, total_n, max_n), x.device)
+        _check(load_library().hsma_energy_batched(
+            self._h, nsys, offsets.data_ptr(), plan_of.data_ptr() if plan_of is not None else None, int(total_n),
+            int(max_n), _dev_ptr(x, "x", total_n), _dev_ptr(y, "y", total_n), _dev_ptr(z, "z", total_n),
+            _dev_ptr(q, "q", total_n), _dev_ptr(phi, "phi", total_n), None, w.ptr, w.nbytes,
+            _stream_ptr(stream)), "hsma_energy_batched")
+        return phi
+
     def field(self, offsets, x, y, z, q, total_n: int, max_n: int, plan_of=None, phi=None, E=None, stream=None,
               ws=None):
-        """Potentials, fields (total_n x 3) and energies of nsys systems."""
+        """Potentials, fields (total_n x 3) and energies of nsys systems (E=False: no energies, so no
+        energy launch)."""
         torch = _torch()
         nsys = offsets.numel() - 1
         if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
@@ -508,6 +530,7 @@ class Group:
         if phi is None:
             phi = torch.empty(int(total_n), dtype=torch.float64, device=x.device)
         f = torch.empty((3, int(total_n)), dtype=torch.float64, device=x.device)
+        e_ptr = None if E is False else _dev_ptr(E, "E", nsys)
         lib = load_library()
         w = ws if ws is not None else _ensure(
             self._ws, ("field", nsys, int(total_n), int(max_n), str(x.device)),
@@ -516,8 +539,8 @@ class Group:
             self._h, nsys, offsets.data_ptr(), plan_of.data_ptr() if plan_of is not None else None, int(total_n),
             int(max_n), _dev_ptr(x, "x", total_n), _dev_ptr(y, "y", total_n), _dev_ptr(z, "z", total_n),
             _dev_ptr(q, "q", total_n), _dev_ptr(phi, "phi", total_n), f[0].data_ptr(), f[1].data_ptr(),
-            f[2].data_ptr(), _dev_ptr(E, "E", nsys), w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_field_batched")
-        return phi, f.t(), E
+            f[2].data_ptr(), e_ptr, w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_field_batched")
+        return phi, f.t(), (None if E is False else E)
 
     def tune(self, persistent: bool = False, target_items: int = 16384):
         _check(load_library().hsma_group_tune(self._h, 1 if persistent else 0, int(target_items)), "hsma_group_tune")
