@@ -142,16 +142,26 @@ struct Bounds {
   int nplans;
 };
 
-// Evaluation items of a system: one-directional (items), or for the symmetric kernel its block
-// pairs I <= J (items) and its surface items (surf: SYM_SH per block and surface chunk).
+// Super-tiles of the energy kernel's block pairs: a system of B >= 64 blocks numbers its pairs by
+// tiles of ST x ST blocks (the triangle of tiles row by row, a tile's pairs row by row, ST^2
+// item numbers per tile, those outside the triangle or beyond B left empty), so that the pairs
+// of one tile, 2 ST blocks of data, are neighbours in the item order; smaller systems number the
+// triangle of blocks row by row (ST = 1).
+constexpr int ST = 16;
+__host__ __device__ __forceinline__ int64_t super_of(int64_t B) { return B >= 64 ? ST : 1; }
+
+// Evaluation items of a system: one-directional (items), or for the symmetric kernels its block
+// pairs I <= J (items; numbered in super-tiles when tiles is set) and its surface items (surf:
+// SYM_SH per block and surface chunk).
 __device__ __forceinline__ void eval_counts(int64_t n, int P, int che, int sym_tb, int sch, int64_t &items,
-                                            int64_t &surf, int64_t &parts) {
+                                            int64_t &surf, int64_t &parts, bool tiles = false) {
   surf = 0;
   if (n <= 0) {
     items = parts = 0;
   } else if (sym_tb > 0) {
     const int64_t B = cdiv64(n, sym_tb);
-    items = B * (B + 1) / 2;
+    const int64_t S = tiles ? super_of(B) : 1, NB = cdiv64(B, S);
+    items = NB * (NB + 1) / 2 * S * S;
     surf = B * sch * SYM_SH;
     parts = n * (B + sch);
   } else {
@@ -188,7 +198,7 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     const int64_t n = hi - lo;
     const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
     int64_t items_e, surf_e, parts_e;
-    eval_counts(n, P, che, sym_tb, sch, items_e, surf_e, parts_e);
+    eval_counts(n, P, che, sym_tb, sch, items_e, surf_e, parts_e, (kind & 15) == 1);
     acc[0] += Gc * chunks_c;
     acc[1] += items_e;
     acc[2] += cdiv64(n, FINB);
@@ -217,7 +227,7 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     const int64_t n = hi - lo;
     const int64_t chunks_c = n > 0 ? cdiv64(n, chc) : 0;
     int64_t items_e, surf_e, parts_e;
-    eval_counts(n, P, che, sym_tb, sch, items_e, surf_e, parts_e);
+    eval_counts(n, P, che, sym_tb, sch, items_e, surf_e, parts_e, (kind & 15) == 1);
     S.off[b] = lo;
     S.ic[b] = run[0];
     S.ie[b] = surf_last ? run[1] : run[1] + run[5];
@@ -1564,6 +1574,20 @@ __device__ __forceinline__ void block_pair(int64_t loc, int64_t B, int &I, int &
   J = __builtin_amdgcn_readfirstlane((int)(r + (loc - (r * B - r * (r - 1) / 2))));
 }
 
+// The device's accelerator dies: gfx950 (MI355X) has 8, each with its own L2, and places
+// workgroup w on die w % NXCD.  xcd_item deals the item numbers out in runs of XQ workgroups (one
+// super-tile's ST^2 items): die x takes runs x, x + NXCD, x + 2 NXCD, ..., so the pairs of a tile
+// run on one die and share its L2, and the dies share the work evenly.  The grid must be a multiple
+// of NXCD XQ workgroups.  Only locality depends on the die count: the map is a bijection of
+// [0, WAVES grid) whatever it is.
+constexpr int NXCD = 8;
+constexpr int XQ = ST * ST / WAVES;
+__device__ __forceinline__ int64_t xcd_item(int w) {
+  const int64_t x = blockIdx.x % NXCD, k = blockIdx.x / NXCD;
+  const int64_t run = (k / XQ) * NXCD + x;
+  return (run * XQ + k % XQ) * WAVES + w;
+}
+
 template <int R>
 __global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int mono, const int64_t *__restrict__ base,
                                                   const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
@@ -1577,7 +1601,7 @@ __global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int 
   Sched S(const_cast<int64_t *>(base), nsys);
   const int lane = threadIdx.x & 63, w = wave_id();
   if (!sched_ok(S)) return;
-  const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);  // one item per wave
+  const int64_t item = uniform64(xcd_item(w));  // one item per wave
   if (item >= S.is[nsys]) return;
   const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
   const bool surface = item >= S.is[b];
@@ -1626,9 +1650,21 @@ __global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int 
 #pragma unroll
     for (int k = 0; k < RS; ++k) e = fma(sq[k], acc[k], e);
   } else {
-    const int64_t B = cdiv64(n, TB);
+    const int64_t B = cdiv64(n, TB), sup = super_of(B), loc = item - S.ie[b];
     int I, J;
-    block_pair(item - S.ie[b], B, I, J);
+    if (sup == 1) {
+      block_pair(loc, B, I, J);
+    } else {
+      int SI, SJ;
+      block_pair(loc / (sup * sup), cdiv64(B, sup), SI, SJ);
+      const int wi = (int)(loc % (sup * sup));
+      I = SI * (int)sup + wi / (int)sup;
+      J = SJ * (int)sup + wi % (int)sup;
+      if (I >= B || J >= B || J < I) {  // a slot of the tile outside the triangle: no pairs
+        if (lane == 0) epair[item] = 0.0;
+        return;
+      }
+    }
     const int t0 = I * TB;
     double tx[R], ty[R], tz[R], s1[R], s2[R];
 #pragma unroll
@@ -1694,7 +1730,7 @@ __global__ __launch_bounds__(256) void k_energy_chunks(int nsys, int P, int sym_
   const int b = system_of(S.ec, nsys, f);
   const int64_t n = S.off[b + 1] - S.off[b];
   int64_t pairs, surf, parts;
-  eval_counts(n, P, 0, sym_tb, sch, pairs, surf, parts);
+  eval_counts(n, P, 0, sym_tb, sch, pairs, surf, parts, true);
   const int64_t k = f - S.ec[b], cp = cdiv64(pairs, EC);
   const int64_t first = k < cp ? S.ie[b] + k * EC : S.is[b] + (k - cp) * EC;
   const int64_t end = k < cp ? S.ie[b] + pairs : S.is[b] + surf;
@@ -1959,7 +1995,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       double *epair = (double *)(ws + L.eval_part);
       pr = prof_begin(grp, ST_EVAL, st);
       if (L.items_e > 0) {
-        const unsigned gs = (unsigned)cdiv(L.items_e, WAVES);
+        const unsigned gs = (unsigned)(cdiv(cdiv(L.items_e, WAVES), NXCD * XQ) * NXCD * XQ);
         const double *wk = (const double *)(ws + L.wk);
         const double *qr = (const double *)(ws + L.qr);
         if (L.sym_tb == 256)
@@ -2084,7 +2120,8 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
     const int64_t sb = total_n / tb + nsys;
     L.sym_tb = (int)tb;
     L.sch = (int)sch;
-    L.items_e = sb * (bmax + 1) / 2 + sb * sch * SYM_SH + 1;
+    // super-tiles: a system of B blocks has at most (B + ST) (B + 2 ST) / 2 pair slots
+    L.items_e = (bmax + 2 * ST) * (sb + ST * (int64_t)nsys) / 2 + sb * sch * SYM_SH + 1;
     L.parts_e = total_n * (bmax + sch);  // the schedule's bound check only: no slots are stored
     L.echunks = L.items_e / EC + 2 * (int64_t)nsys + 1;
   } else if ((L.prec == HSMA_PAIR_FP32_COMP || L.prec == HSMA_PAIR_FP64) && mode != 0 && total_n > 0 && !field &&
