@@ -83,6 +83,9 @@ def main() -> int:
                     help="seconds of untimed steps before the warm-up steps, so that the device has left its idle "
                          "clock state when timing starts")
     ap.add_argument("--serving-requests", type=int, default=6000)
+    ap.add_argument("--serving-energy-workgroups", default="0,-1",
+                    help="request server: full-energy grids to measure, comma-separated (0: half the compute units, "
+                         "-1: no limit); the first is the headline")
     ap.add_argument("--serving-slots", default="1,2",
                     help="request server: concurrent single-ion-move batches and full energies")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1065,8 +1068,11 @@ def leg_serving(args) -> dict:
     """512 resident configurations (N log-uniform in [500, 50000], a ~ U[15, 40], kappa ~
     U[0.05, 1], eps1 = 1, eps2 = 78.5, P = 1024, M = 1536); requests 90% single-ion moves
     (ion and system uniform, displacement U([-1/2, 1/2]^3) kept inside, committed with
-    probability 1/2) and 10% fresh full energies.  Capacity from a burst, then Poisson
-    arrivals at 0.25, 0.5, 0.75, 0.9 and 1.1 of it; latency = done - submitted."""
+    probability 1/2) and 10% fresh full energies.  For each full-energy grid of the request server
+    (--serving-energy-workgroups): capacity from a burst, then Poisson arrivals at 0.25, 0.5, 0.75,
+    0.9 and 1.1 of that capacity, the same requests and the same unit-rate arrival gaps for every
+    grid; latency = done - submitted.  Then the plain per-system path (each request run alone,
+    synchronously, on its resident system) under the first grid's arrival streams."""
     import numpy as np
     import torch
 
@@ -1078,15 +1084,11 @@ def leg_serving(args) -> dict:
     wl = W.workload_c5()
     plans = [hs.Plan(s.phys.a, s.phys.eps1, s.phys.eps2, s.phys.kappa, wl.disc.P, wl.disc.M) for s in wl.systems]
     dsl, esl = (int(v) for v in args.serving_slots.split(","))
-    server = hs.Server(max_batch=512, delta_slots=dsl, energy_slots=esl)
-    for p, s in zip(plans, wl.systems):
-        t = [torch.tensor(getattr(s, k), dtype=torch.float64, device=dev) for k in "xyzq"]
-        server.add_system(p, *t)
-    torch.cuda.synchronize()
-    log(f"bench[serving]: {len(plans)} systems resident, {server.stats()['memory_used'] / 2**30:.2f} GiB, "
-        f"set up in {time.perf_counter() - t0:.1f} s")
+    tens = [[torch.tensor(getattr(s, k), dtype=torch.float64, device=dev) for k in "xyzq"] for s in wl.systems]
     rng = np.random.default_rng(1907017244)
     pos = [np.stack([s.x, s.y, s.z], axis=1).copy() for s in wl.systems]
+    n = args.serving_requests
+    fractions = (0.25, 0.5, 0.75, 0.9, 1.1)
 
     def stream(n):
         reqs = []
@@ -1103,62 +1105,100 @@ def leg_serving(args) -> dict:
             reqs.append((hs.REQ_DELTA, b, commit, k, *new))
         return reqs
 
-    def summarize(res, reqs, wall):
-        lat = np.array([r.t_done - r.t_submit for r in res]) * 1e3
-        dl = np.array([r.t_done - r.t_submit for r, q in zip(res, reqs) if q[0] == hs.REQ_DELTA]) * 1e3
-        el = np.array([r.t_done - r.t_submit for r, q in zip(res, reqs) if q[0] == hs.REQ_ENERGY]) * 1e3
-        assert all(r.status == 0 for r in res)
-        return {"requests": len(res), "requests_per_s": len(res) / wall, "p50_ms": float(np.percentile(lat, 50)),
+    def summarize(lat_s, kinds, wall):
+        lat = np.asarray(lat_s) * 1e3
+        kinds = np.asarray(kinds)
+        dl, el = lat[kinds == hs.REQ_DELTA], lat[kinds == hs.REQ_ENERGY]
+        return {"requests": len(lat), "requests_per_s": len(lat) / wall, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "delta_p50_ms": float(np.percentile(dl, 50)),
                 "delta_p99_ms": float(np.percentile(dl, 99)), "energy_p50_ms": float(np.percentile(el, 50)),
                 "energy_p99_ms": float(np.percentile(el, 99))}
 
-    n = args.serving_requests
-    server.run_load(stream(500), np.zeros(500))  # warm-up
-    reqs = stream(n)
-    st0 = server.stats()
-    res = server.run_load(reqs, np.zeros(n))
-    st1 = server.stats()
-    wall = max(r.t_done for r in res)
-    burst = summarize(res, reqs, wall)
-    cap = burst["requests_per_s"]
+    # one request sequence for every variant: warm-up, burst, then one stream per offered load
+    warm, burst_reqs = stream(500), stream(n)
+    loads = [(f, stream(n), np.cumsum(rng.exponential(1.0, n))) for f in fractions]
     out = {"workload": "512 resident configurations, N log-uniform in [500, 50000], a~U[15,40], kappa~U[0.05,1], "
                        "P=1024, M=1536; 90% single-ion moves (commit p=1/2), 10% fresh FP64 energies",
-           "slots": {"moves": dsl, "energies": esl},
-           "capacity_requests_per_s": cap, "burst": burst,
-           "mean_batch": (st1["batched_requests"] - st0["batched_requests"]) / max(1, st1["batches"] - st0["batches"]),
-           "loads": []}
-    for f in (0.25, 0.5, 0.75, 0.9, 1.1):  # 1.1: overload, the queue grows over the run
-        reqs = stream(n)
-        arrival = np.cumsum(rng.exponential(1.0 / (f * cap), n))
-        res = server.run_load(reqs, arrival)
-        wall = max(r.t_done for r in res)
-        d = summarize(res, reqs, wall)
-        d["offered_fraction"] = f
-        d["offered_requests_per_s"] = f * cap
-        out["loads"].append(d)
-        log(f"bench[serving]: load {f:.2f} x capacity: p50 {d['p50_ms']:.3f} ms, p99 {d['p99_ms']:.3f} ms "
-            f"(moves {d['delta_p50_ms']:.3f} / {d['delta_p99_ms']:.3f} ms)")
-    server.close()
-    # plain per-system path: one synchronous single-ion query at a time on a resident system
-    b = int(np.argmax([len(p) for p in pos]))
-    s = wl.systems[b]
-    t = [torch.tensor(v, dtype=torch.float64, device=dev) for v in (pos[b][:, 0], pos[b][:, 1], pos[b][:, 2], s.q)]
-    one = hs.System(plans[b], *t)
+           "slots": {"moves": dsl, "energies": esl}, "server": []}
+    cap_ref = None
+    for ewg in (int(v) for v in args.serving_energy_workgroups.split(",")):
+        server = hs.Server(max_batch=512, delta_slots=dsl, energy_slots=esl, energy_workgroups=ewg)
+        for p, t in zip(plans, tens):
+            server.add_system(p, *t)
+        torch.cuda.synchronize()
+        label = f"energy_workgroups={ewg}"
+        log(f"bench[serving]: {label}: {len(plans)} systems resident, {server.stats()['memory_used'] / 2**30:.2f} GiB, "
+            f"set up in {time.perf_counter() - t0:.1f} s")
+        server.run_load(warm, np.zeros(len(warm)))
+        st0 = server.stats()
+        res = server.run_load(burst_reqs, np.zeros(n))
+        st1 = server.stats()
+        assert all(r.status == 0 for r in res)
+        burst = summarize([r.t_done - r.t_submit for r in res], [q[0] for q in burst_reqs], max(r.t_done for r in res))
+        cap = burst["requests_per_s"]
+        cap_ref = cap if cap_ref is None else cap_ref
+        d_out = {"energy_workgroups": ewg, "capacity_requests_per_s": cap, "burst": burst,
+                 "mean_batch": (st1["batched_requests"] - st0["batched_requests"]) / max(1, st1["batches"] - st0["batches"]),
+                 "loads": []}
+        log(f"bench[serving]: {label}: capacity {cap:.0f} req/s (burst)")
+        for f, reqs_f, gaps in loads:
+            res = server.run_load(reqs_f, gaps / (f * cap))
+            assert all(r.status == 0 for r in res)
+            d = summarize([r.t_done - r.t_submit for r in res], [q[0] for q in reqs_f], max(r.t_done for r in res))
+            d["offered_fraction"] = f
+            d["offered_requests_per_s"] = f * cap
+            d_out["loads"].append(d)
+            log(f"bench[serving]: {label}: load {f:.2f} x {cap:.0f} req/s: p50 {d['p50_ms']:.3f} ms, p99 "
+                f"{d['p99_ms']:.3f} ms (moves {d['delta_p50_ms']:.3f} / {d['delta_p99_ms']:.3f} ms, energies "
+                f"{d['energy_p50_ms']:.3f} / {d['energy_p99_ms']:.3f} ms)")
+        server.close()
+        out["server"].append(d_out)
+    streams = [(f, r, g / (f * cap_ref)) for f, r, g in loads]
+    # the plain per-system path under the same arrival streams: each request alone, synchronously,
+    # on its resident system, in arrival order (a request that arrives while another runs waits)
+    systems = [hs.System(p, *t) for p, t in zip(plans, tens)]
+    ws = hs.workspace(max(s.workspace_bytes() for s in systems), dev)
     dE = torch.empty(1, dtype=torch.float64, device=dev)
+    E1 = torch.empty(1, dtype=torch.float64, device=dev)
+    plain = {"loads": []}
+    for f, reqs_f, arrival in streams:
+        m = min(n, 2000)  # bounded: the plain path cannot keep up at these rates and its queue grows
+        lat, kinds = [], []
+        tb = time.perf_counter()
+        for (kind, b, commit, k, x, y, z), ta in zip(reqs_f[:m], arrival[:m]):
+            while time.perf_counter() - tb < ta:
+                pass
+            if kind == hs.REQ_DELTA:
+                systems[b].delta_energy(k, (x, y, z), out=dE)
+                if commit:
+                    systems[b].commit(k, (x, y, z))
+                torch.cuda.synchronize()
+            else:
+                systems[b].full_energy(out=E1, ws=ws)
+            lat.append(time.perf_counter() - tb - ta)
+            kinds.append(kind)
+        d = summarize(lat, kinds, time.perf_counter() - tb)
+        d["offered_fraction"] = f
+        d["offered_requests_per_s"] = f * cap_ref
+        plain["loads"].append(d)
+        log(f"bench[serving]: per-system path: load {f:.2f}: p50 {d['p50_ms']:.3f} ms, p99 {d['p99_ms']:.3f} ms "
+            f"(moves {d['delta_p50_ms']:.3f} / {d['delta_p99_ms']:.3f} ms), first {m} requests")
+    # and its unloaded service rate: one synchronous move query at a time on the largest system
+    b = int(np.argmax([len(p) for p in pos]))
     lat = []
     for i in range(300):
         k = int(rng.integers(len(pos[b])))
-        new = W.random_move(rng, pos[b][k], s.phys.a)
+        new = W.random_move(rng, pos[b][k], wl.systems[b].phys.a)
         ta = time.perf_counter()
-        one.delta_energy(k, new, out=dE)
+        systems[b].delta_energy(k, new, out=dE)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ta)
-    one.close()
     lat = np.array(lat[20:]) * 1e3
-    out["per_system_path"] = {"system_ions": int(len(pos[b])), "delta_requests_per_s": float(1e3 / lat.mean()),
-                              "delta_p50_ms": float(np.percentile(lat, 50)), "delta_p99_ms": float(np.percentile(lat, 99))}
-    log(f"bench[serving]: capacity {cap:.0f} req/s (burst), per-system path {1e3 / lat.mean():.0f} req/s")
+    plain.update({"system_ions": int(len(pos[b])), "delta_requests_per_s_alone": float(1e3 / lat.mean()),
+                  "delta_p50_ms_alone": float(np.percentile(lat, 50)), "delta_p99_ms_alone": float(np.percentile(lat, 99))})
+    for sysm in systems:
+        sysm.close()
+    out["per_system_path"] = plain
     return out
 
 

@@ -429,6 +429,12 @@ typedef struct {
 typedef struct {
   size_t memory_budget; /* bytes; 0 = half of the free device memory */
   int max_systems, max_batch, delta_slots, energy_slots;
+  int energy_workgroups; /* full energies run their pair kernels persistent on this many workgroups,
+                            leaving the rest of the device's wave slots to the move batches, so that a
+                            move does not wait for a long energy to drain; 0 (default): the compute
+                            units' count (one workgroup per compute unit and energy slot); < 0: no
+                            limit (one item per wave on the whole device: more full energies per
+                            second, longer move tails).  Results do not depend on it. */
 } hsma_server_opts;
 typedef struct {
   size_t memory_used, memory_budget;

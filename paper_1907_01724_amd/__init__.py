@@ -57,7 +57,7 @@ class Result(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("memory_budget", C.c_size_t), ("max_systems", C.c_int), ("max_batch", C.c_int),
-                ("delta_slots", C.c_int), ("energy_slots", C.c_int)]
+                ("delta_slots", C.c_int), ("energy_slots", C.c_int), ("energy_workgroups", C.c_int)]
 
 
 class ServerInfo(C.Structure):
@@ -618,13 +618,17 @@ class System:
                "hsma_system_energy")
         return out
 
-    def full_energy(self, out=None, stream=None):
-        """A fresh FP64 full evaluation of the current energy (state unchanged)."""
+    def workspace_bytes(self) -> int:
+        return int(load_library().hsma_system_workspace_bytes(self._h))
+
+    def full_energy(self, out=None, stream=None, ws: Workspace | None = None):
+        """A fresh FP64 full evaluation of the current energy (state unchanged); synchronises."""
         torch = _torch()
         L = load_library()
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=self.device)
-        ws = Workspace(int(L.hsma_system_workspace_bytes(self._h)), self.device)
+        if ws is None:
+            ws = Workspace(int(L.hsma_system_workspace_bytes(self._h)), self.device)
         _check(L.hsma_system_full_energy(self._h, _dev_ptr(out, "E"), ws.ptr, ws.nbytes, _stream_ptr(stream)),
                "hsma_system_full_energy")
         torch.cuda.synchronize()
@@ -663,9 +667,10 @@ class Server:
     """Continuous-batching request server over resident systems (see hsma_server_* in hsma.h)."""
 
     def __init__(self, memory_budget: int = 0, max_systems: int = 1024, max_batch: int = 256, delta_slots: int = 1,
-                 energy_slots: int = 2):
+                 energy_slots: int = 2, energy_workgroups: int = 0):
         L = load_library()
-        o = ServerOpts(int(memory_budget), int(max_systems), int(max_batch), int(delta_slots), int(energy_slots))
+        o = ServerOpts(int(memory_budget), int(max_systems), int(max_batch), int(delta_slots), int(energy_slots),
+                       int(energy_workgroups))
         h = _VP()
         _check(L.hsma_server_create(C.byref(o), C.byref(h)), "hsma_server_create")
         self._h = h

@@ -115,9 +115,10 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 //       at [2][b] otherwise, and its surface items start at [6][b].
 //   [7] prefix of the energy-sum chunks (energy-only launches: EC consecutive item energies of
 //       one system, its block pairs first, then its surface items).
-// followed by 8 words: [0] check item counter, [1] eval item counter, [2] schedule valid,
+// followed by 16 words: [0] check item counter, [1] eval item counter, [2] schedule valid,
 // [3] launch kind: 1 for the energy-only launch, else 0, plus 16 x the pair precision (read back by
-// hsma_debug_intermediates).
+// hsma_debug_intermediates), [8..15] the energy kernel's item counters, one per die (persistent
+// form).
 // ---------------------------------------------------------------------------------
 constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
 struct Sched {
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     S.pe[nsys] = sc[4][t];
     S.is[nsys] = sc[1][t] + sc[5][t];
     S.ec[nsys] = sc[6][t];
-    for (int k = 0; k < 8; ++k) S.ctr[k] = 0;
+    for (int k = 0; k < 16; ++k) S.ctr[k] = 0;
     S.ctr[0] = grid_c;  // items below the grid size are taken by block index
     S.ctr[1] = grid_e;
     S.ctr[3] = kind;
@@ -1588,21 +1589,70 @@ __device__ __forceinline__ int64_t xcd_item(int w) {
   return (run * XQ + k % XQ) * WAVES + w;
 }
 
+// Persistent form: die x's items are its runs' items in order, t = 0, 1, ... (run t / (XQ WAVES),
+// offset t % (XQ WAVES)); its waves take them EG at a time from the die's own counter, so that the
+// dies do not contend for one counter and a run still stays on one die.  Every die index 0..NXCD-1
+// has workgroups (the grid is a multiple of NXCD), so every item is taken, wherever the workgroups
+// actually run.
+constexpr int EG = 4;  // items per claim
+__device__ __forceinline__ int64_t die_item(int64_t x, int64_t t) {
+  constexpr int64_t RUN = (int64_t)XQ * WAVES;
+  return ((t / RUN) * NXCD + x) * RUN + t % RUN;
+}
+
 template <int R>
+__device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int sch, int mono, const Sched &S, int lane,
+                                            const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
+                                            const double4 *__restrict__ tgt, const double4 *__restrict__ img,
+                                            const double *__restrict__ q, const double *__restrict__ wk,
+                                            const double *__restrict__ qr, const double4 *__restrict__ nodes,
+                                            const double2 *__restrict__ qd, double *__restrict__ epair);
+
+template <int R, bool PERSIST>
 __global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int mono, const int64_t *__restrict__ base,
                                                   const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
                                                   const double4 *__restrict__ tgt, const double4 *__restrict__ img,
                                                   const double *__restrict__ q, const double *__restrict__ wk,
                                                   const double *__restrict__ qr, const double4 *__restrict__ nodes,
                                                   const double2 *__restrict__ qd, double *__restrict__ epair) {
-  constexpr int TB = 64 * R;
-  constexpr int RS = R / SYM_SH;
-  constexpr double FAR_TARGET = 3.0e18;  // stand-in position of an empty target lane (zero charge)
   Sched S(const_cast<int64_t *>(base), nsys);
   const int lane = threadIdx.x & 63, w = wave_id();
   if (!sched_ok(S)) return;
-  const int64_t item = uniform64(xcd_item(w));  // one item per wave
-  if (item >= S.is[nsys]) return;
+  const int64_t total = S.is[nsys];
+  if constexpr (!PERSIST) {  // one item per wave
+    const int64_t item = uniform64(xcd_item(w));
+    if (item < total)
+      energy_item<R>(item, nsys, P, sch, mono, S, lane, sys_e, plan_of, tgt, img, q, wk, qr, nodes, qd, epair);
+    return;
+  } else {
+  // persistent: claims of EG items from this die's counter until the die's items run out
+  const int64_t x = blockIdx.x % NXCD;
+  for (;;) {
+    int64_t t = 0;
+    if (lane == 0) t = (int64_t)atomicAdd((unsigned long long *)&S.ctr[8 + x], (unsigned long long)EG);
+    t = uniform64(__shfl(t, 0, 64));
+    if (die_item(x, t) >= total) return;  // every later claim of this die lies beyond too
+    for (int g = 0; g < EG; ++g) {
+      const int64_t item = die_item(x, t + g);
+      if (item < total)
+        energy_item<R>(item, nsys, P, sch, mono, S, lane, sys_e, plan_of, tgt, img, q, wk, qr, nodes, qd, epair);
+    }
+  }
+  }
+}
+
+// One item of the energy kernels (block pair or surface item); writes epair[item].
+template <int R>
+__device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int sch, int mono, const Sched &S,
+                                            int lane, const int *__restrict__ sys_e,
+                                            const int32_t *__restrict__ plan_of, const double4 *__restrict__ tgt,
+                                            const double4 *__restrict__ img, const double *__restrict__ q,
+                                            const double *__restrict__ wk, const double *__restrict__ qr,
+                                            const double4 *__restrict__ nodes, const double2 *__restrict__ qd,
+                                            double *__restrict__ epair) {
+  constexpr int TB = 64 * R;
+  constexpr int RS = R / SYM_SH;
+  constexpr double FAR_TARGET = 3.0e18;  // stand-in position of an empty target lane (zero charge)
   const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
   const bool surface = item >= S.is[b];
   const int64_t lo = S.off[b];
@@ -1913,7 +1963,11 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   const PlanDev *plans = grp->dev;
   const int persistent = grp->tune.persistent;
   const int64_t pgrid_c = (int64_t)g->ncu * grp->tune.occ_check, pgrid_e = (int64_t)g->ncu * grp->tune.occ_eval;
-  const int64_t grid_c = persistent ? (L.items_c < pgrid_c ? L.items_c : pgrid_c) : L.items_c;
+  // an energy launch on a limited grid (tune.ewaves) runs its check sums persistent on that grid too
+  const bool throttle = L.eonly && grp->tune.ewaves > 0;
+  const int persistent_c = persistent || throttle;
+  const int64_t cap_c = throttle ? (int64_t)grp->tune.ewaves : pgrid_c;
+  const int64_t grid_c = persistent_c ? (L.items_c < cap_c ? L.items_c : cap_c) : L.items_c;
   const int64_t grid_e = persistent ? (L.items_e < pgrid_e ? L.items_e : pgrid_e) : L.items_e;
 
   hipEvent_t pr = prof_begin(grp, ST_PACK, st);
@@ -1948,7 +2002,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
 
   pr = prof_begin(grp, ST_CHECK, st);
   if (L.items_c > 0)
-    k_check<MODE><<<(unsigned)grid_c, TPB, 0, st>>>(persistent, nsys, M, L.chc, base, sys_c, plans, plan_of, tgt, srcw,
+    k_check<MODE><<<(unsigned)grid_c, TPB, 0, st>>>(persistent_c, nsys, M, L.chc, base, sys_c, plans, plan_of, tgt, srcw,
                                                     L.parts_c, chk_part);
   k_check_finish<<<(int)cdiv((int64_t)nsys * M, 256), 256, 0, st>>>(nsys, M, L.chc, base, L.parts_c, chk_part, uv,
                                                                      uv32);
@@ -1995,15 +2049,21 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       double *epair = (double *)(ws + L.eval_part);
       pr = prof_begin(grp, ST_EVAL, st);
       if (L.items_e > 0) {
-        const unsigned gs = (unsigned)(cdiv(cdiv(L.items_e, WAVES), NXCD * XQ) * NXCD * XQ);
+        // one item per wave, the grid dealt out per die in runs; or a persistent grid of ewaves
+        // workgroups (a multiple of the die count) taking items from per-die counters
+        const int persist = grp->tune.ewaves > 0;
+        const unsigned gs = persist ? (unsigned)(cdiv(grp->tune.ewaves, NXCD) * NXCD)
+                                    : (unsigned)(cdiv(cdiv(L.items_e, WAVES), NXCD * XQ) * NXCD * XQ);
         const double *wk = (const double *)(ws + L.wk);
         const double *qr = (const double *)(ws + L.qr);
+        auto run = [&](auto kern) {
+          kern<<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, q, wk, qr,
+                                   grp->nodes64, qd, epair);
+        };
         if (L.sym_tb == 256)
-          k_energy64<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, q, wk,
-                                            qr, grp->nodes64, qd, epair);
+          persist ? run(k_energy64<4, true>) : run(k_energy64<4, false>);
         else
-          k_energy64<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, q, wk,
-                                            qr, grp->nodes64, qd, epair);
+          persist ? run(k_energy64<8, true>) : run(k_energy64<8, false>);
       }
       prof_end(pr, st);
       pr = prof_begin(grp, ST_FINISH, st);
@@ -2154,7 +2214,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
     o = align256(o + bytes);
     return at;
   };
-  L.sched = take(sizeof(int64_t) * (8 * (size_t)(nsys + 1) + 8));
+  L.sched = take(sizeof(int64_t) * (8 * (size_t)(nsys + 1) + 16));
   L.item_sys_c = take(sizeof(int) * (size_t)L.items_c);
   L.item_sys_e = take(sizeof(int) * (size_t)L.items_e);
   L.fin_sys = take(sizeof(int) * (size_t)L.fin);

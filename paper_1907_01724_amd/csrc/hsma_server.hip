@@ -343,6 +343,7 @@ extern "C" hsma_server_opts hsma_server_opts_default(void) {
   o.max_batch = 256;
   o.delta_slots = 1;
   o.energy_slots = 2;
+  o.energy_workgroups = 0;
   return o;
 }
 
@@ -360,6 +361,11 @@ extern "C" hsma_status hsma_server_create(const hsma_server_opts *opts, hsma_ser
   size_t fre = 0, tot = 0;
   if (rc == HSMA_OK && hipMemGetInfo(&fre, &tot) != hipSuccess) rc = HSMA_EDEVICE;
   S->budget = o.memory_budget ? o.memory_budget : fre / 2;
+  if (rc == HSMA_OK && o.energy_workgroups == 0) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess) rc = HSMA_EDEVICE;
+    S->opts.energy_workgroups = ncu > 0 ? ncu : 1;
+  }
   if (rc == HSMA_OK && (hipMalloc(&S->d_sys, sizeof(SysDev) * o.max_systems) != hipSuccess ||
                         hipStreamCreateWithFlags(&S->admin, hipStreamNonBlocking) != hipSuccess))
     rc = HSMA_EDEVICE;
@@ -456,6 +462,7 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
   }
   S->systems[slot] = sys;
   S->busy[slot] = 0;
+  sys->g64->tune.ewaves = S->opts.energy_workgroups > 0 ? S->opts.energy_workgroups : 0;
   // Full-energy workspaces grow here, at admission, rather than in the scheduler, where freeing
   // device memory would stall every request in flight (a slot busy now grows when next used).
   for (EnergySlot &e : S->eslots) {

@@ -2,7 +2,8 @@
 
 Each result is compared with the same request run alone (the system API, requests of a
 system replayed in their order): single-ion moves and full energies come out bitwise
-equal, because a request's work and reduction order do not depend on its batch.  Also:
+equal, because a request's work and reduction order do not depend on its batch, nor on
+the grid its full energy runs on.  Also:
 admission by memory budget, invalid requests, an open-loop Poisson run, and the served
 full energies against the oracle.
 """
@@ -71,9 +72,12 @@ def _collect(server, n, timeout=120.0):
     return [got[i] for i in range(n)]
 
 
-def test_mix_equals_alone(dev):
+@pytest.mark.parametrize("ewg", [0, -1, 8])
+def test_mix_equals_alone(dev, ewg):
+    """Full energies on a limited persistent grid (0: half the compute units; 8: one workgroup per
+    die) or on the whole device (-1) take the same items in the same reduction order."""
     items = _make(6, 11, dev)
-    server = hs.Server(max_batch=64)
+    server = hs.Server(max_batch=64, energy_workgroups=ewg)
     ids = [server.add_system(p, *t) for p, _, t in items]
     assert ids == list(range(6))
     reqs, final_pos = _stream(items, 240, 5)
