@@ -76,8 +76,8 @@ def main() -> int:
                     help="pair precision of the potentials in the legs (energies always use FP64 pairs)")
     ap.add_argument("--no-oracle", action="store_true", help="skip the accuracy checks and the CPU baseline")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--legs", default="c2,batched,serving,sweep,field,kirkwood,accuracy,single_layer,tree",
-                    help="extra workloads after the headline one: c2, batched, serving, sweep, field, kirkwood, "
+    ap.add_argument("--legs", default="plan,c2,batched,serving,sweep,field,kirkwood,accuracy,single_layer,tree",
+                    help="extra workloads after the headline one: plan, c2, batched, serving, sweep, field, kirkwood, "
                          "accuracy, single_layer, tree (comma list, or none)")
     ap.add_argument("--settle-s", type=float, default=1.0,
                     help="seconds of untimed steps before the warm-up steps, so that the device has left its idle "
@@ -234,6 +234,8 @@ def main() -> int:
                    seed=W.SEED_BASE + 22, min_seconds=10.0)
     plan.close()
     legs = [l for l in args.legs.split(",") if l and l != "none"]
+    if "plan" in legs:
+        out["plan_build"] = leg_plan(args)
     if "c2" in legs:
         out["c2"] = leg_c2(args, checks)
     if "batched" in legs:
@@ -815,6 +817,28 @@ def leg_sweep(args, checks) -> dict:
     for plan in plans.values():
         plan.close()
     return res
+
+
+def leg_plan(args) -> dict:
+    """Plan set-up time (geometry on the GPU: nodes, bases, normal equations, Cholesky factor and
+    the blocked triangular solves for the pseudo-inverse) for the C2 geometry (a = 30, P = 1600,
+    M = 2400, p = 20), the C3 geometry (a = 200, P = 6400, M = 9600, p = 40) and the C3 geometry
+    at p = 60 (K = 3721).  Each is built fresh: no other plan holds its geometry."""
+    import torch
+
+    import paper_1907_01724_amd as hs
+
+    torch.cuda.synchronize()
+    out = {}
+    for label, a, P, M, p in (("c2_p20_K441", 30.0, 1600, 2400, None), ("c3_p40_K1681", 200.0, 6400, 9600, None),
+                              ("c3_p60_K3721", 200.0, 6400, 9600, 60)):
+        t0 = time.perf_counter()
+        pl = hs.Plan(a, 1.0, 80.0, 0.1, P, M, p=p)
+        torch.cuda.synchronize()
+        out[label + "_ms"] = (time.perf_counter() - t0) * 1e3
+        pl.close()
+        log(f"bench[plan]: {label}: {out[label + '_ms']:.1f} ms")
+    return out
 
 
 def leg_accuracy(args, checks) -> dict:

@@ -322,25 +322,90 @@ __global__ void k_syrk_update(int K, int j0, int jb, double *G) {
   G[(size_t)i * K + k] -= s;
 }
 
-// X = G^{-1} B for the K x M right-hand side B stored in X (row-major), one column per
-// thread: forward substitution with L, then backward with L^T.
-__global__ void k_chol_solve(int K, int M, const double *L, double *X, double *X32src, float *X32) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= M) return;
-  for (int i = 0; i < K; ++i) {
-    double s = X[(size_t)i * M + c];
-    const double *Li = L + (size_t)i * K;
-    for (int t = 0; t < i; ++t) s -= Li[t] * X[(size_t)t * M + c];
-    X[(size_t)i * M + c] = s / Li[i];
+// ---------------------------------------------------------------------------------
+// X = G^{-1} B = L^{-T} (L^{-1} B) for the K x M right-hand side B held in X (row-major, one
+// column per check point), in blocks of SB rows.  The diagonal blocks of L are inverted once;
+// then block row I of the forward substitution is  X_I <- Linv_I (X_I - L_{I,<I} X_{<I})  and of
+// the backward one  X_I <- Linv_I^T (X_I - (L_{>I,I})^T X_{>I}):  one launch per block row and
+// direction, one workgroup per tile of CT columns (the columns are independent right-hand sides).
+// ---------------------------------------------------------------------------------
+constexpr int SB = 64, CT = 32, KC = 32, SOLVE_T = 256;
+
+// Linv_I: the inverse of L's diagonal block I (order jb = min(SB, K - I SB)), zero-padded to
+// SB x SB; thread t forms its column t by forward substitution of the unit vector e_t.
+__global__ __launch_bounds__(SB) void k_trtri_diag(int K, const double *L, double *Linv) {
+  __shared__ double A[SB][SB + 1], Y[SB][SB + 1];
+  const int I = blockIdx.x, j0 = I * SB, jb = min(SB, K - j0), t = threadIdx.x;
+  for (int r = 0; r < SB; ++r) A[r][t] = (r < jb && t <= r) ? L[(size_t)(j0 + r) * K + j0 + t] : 0.0;
+  __syncthreads();
+  for (int r = 0; r < SB; ++r) {  // only column t of Y is touched by thread t
+    double s = 0.0;
+    if (r < jb && t < jb && r >= t) {
+      s = r == t ? 1.0 : 0.0;
+      for (int u = t; u < r; ++u) s -= A[r][u] * Y[u][t];
+      s /= A[r][r];
+    }
+    Y[r][t] = s;
   }
-  for (int i = K - 1; i >= 0; --i) {
-    double s = X[(size_t)i * M + c];
-    for (int t = i + 1; t < K; ++t) s -= L[(size_t)t * K + i] * X[(size_t)t * M + c];
-    const double v = s / L[(size_t)i * K + i];
-    X[(size_t)i * M + c] = v;
-    X32[(size_t)i * M + c] = (float)v;
+  double *out = Linv + (size_t)I * SB * SB;
+  for (int r = 0; r < SB; ++r) out[(size_t)r * SB + t] = Y[r][t];
+}
+
+// One block row I of the forward (BACK = false) or backward (BACK = true) substitution for the
+// columns [blockIdx.x CT, + CT).  Thread (tr, tc) holds rows tr + 8u (u < SB / 8) of column tc.
+// The backward pass also writes the FP32 copy X32.
+template <bool BACK>
+__global__ __launch_bounds__(SOLVE_T) void k_solve_block(int K, int M, int I, const double *L, const double *Linv,
+                                                         double *X, float *X32) {
+  constexpr int RU = SB / (SOLVE_T / CT);  // rows per thread
+  __shared__ double As[SB][KC + 1], Bs[KC][CT + 1], Ys[SB][CT + 1];
+  const int j0 = I * SB, jb = min(SB, K - j0), c0 = blockIdx.x * CT;
+  const int tc = threadIdx.x % CT, tr = threadIdx.x / CT;
+  const int kbeg = BACK ? j0 + jb : 0, kend = BACK ? K : j0;
+  double acc[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) acc[u] = 0.0;
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    for (int e = threadIdx.x; e < SB * KC; e += SOLVE_T) {
+      if (!BACK) {  // As[r][k] = L[j0 + r][k0 + k]
+        const int r = e / KC, k = e % KC;
+        As[r][k] = (r < jb && k0 + k < kend) ? L[(size_t)(j0 + r) * K + k0 + k] : 0.0;
+      } else {  // As[r][k] = L[k0 + k][j0 + r], read along the row of L
+        const int k = e / SB, r = e % SB;
+        As[r][k] = (r < jb && k0 + k < kend) ? L[(size_t)(k0 + k) * K + j0 + r] : 0.0;
+      }
+    }
+    for (int e = threadIdx.x; e < KC * CT; e += SOLVE_T) {
+      const int k = e / CT, c = e % CT;
+      Bs[k][c] = (k0 + k < kend && c0 + c < M) ? X[(size_t)(k0 + k) * M + c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < KC; ++k) {
+      const double bv = Bs[k][tc];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) acc[u] = fma(As[tr + 8 * u][k], bv, acc[u]);
+    }
+    __syncthreads();
   }
-  (void)X32src;
+  const bool col = c0 + tc < M;
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const int r = tr + 8 * u;
+    Ys[r][tc] = (r < jb && col) ? X[(size_t)(j0 + r) * M + c0 + tc] - acc[u] : 0.0;
+  }
+  __syncthreads();
+  const double *Li = Linv + (size_t)I * SB * SB;
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const int r = tr + 8 * u;
+    double v = 0.0;
+    for (int w = 0; w < SB; ++w) v = fma(BACK ? Li[(size_t)w * SB + r] : Li[(size_t)r * SB + w], Ys[w][tc], v);
+    if (r < jb && col) {
+      X[(size_t)(j0 + r) * M + c0 + tc] = v;
+      if (BACK) X32[(size_t)(j0 + r) * M + c0 + tc] = (float)v;
+    }
+  }
 }
 
 // Per-plan node coordinates: check points at radius rc, surface nodes at R_tau.
@@ -390,7 +455,7 @@ hsma_status geometry_build(Geometry *g) {
   const int p = g->p, K = g->K, P = g->P, M = g->M;
   hipStream_t st;
   HSMA_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-  double *YT = nullptr, *G = nullptr;
+  double *YT = nullptr, *G = nullptr, *Linv = nullptr;
   int *bad = nullptr;
   hsma_status rc = HSMA_OK;
 #define HSMA_TRY(call)                   \
@@ -441,7 +506,15 @@ hsma_status geometry_build(Geometry *g) {
       k_syrk_update<<<gr, tb, 0, st>>>(K, j0, jb, G);
     }
   }
-  k_chol_solve<<<blocks(M, 64), 64, 0, st>>>(K, M, G, g->pinv64, nullptr, g->pinv32);
+  {
+    const int nsb = blocks(K, SB), ncol = blocks(M, CT);
+    HSMA_TRY(hipMalloc(&Linv, sizeof(double) * (size_t)nsb * SB * SB));
+    k_trtri_diag<<<nsb, SB, 0, st>>>(K, G, Linv);
+    for (int I = 0; I < nsb; ++I)
+      k_solve_block<false><<<ncol, SOLVE_T, 0, st>>>(K, M, I, G, Linv, g->pinv64, g->pinv32);
+    for (int I = nsb - 1; I >= 0; --I)
+      k_solve_block<true><<<ncol, SOLVE_T, 0, st>>>(K, M, I, G, Linv, g->pinv64, g->pinv32);
+  }
   k_split_bf16<<<blocks((int64_t)K * g->Mp, 256), 256, 0, st>>>(K, M, g->Mp, g->pinv64, g->pinv_bf);
   k_split_bf16<<<blocks((int64_t)P * g->Kp, 256), 256, 0, st>>>(P, K, g->Kp, g->lhat64, g->lhat_bf);
   HSMA_TRY(hipGetLastError());
@@ -454,6 +527,7 @@ hsma_status geometry_build(Geometry *g) {
 out:
 #undef HSMA_TRY
   (void)hipFree(G);
+  (void)hipFree(Linv);
   (void)hipFree(bad);
   (void)hipStreamDestroy(st);
   return rc;
