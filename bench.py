@@ -1052,7 +1052,9 @@ def leg_tree(args, checks) -> dict:
     sampled = {}
     runs = [("direct", None), ("tree_order4_theta0.5", (4, 0.5)), ("tree_order6_theta0.5", (6, 0.5)),
             ("tree_order6_theta0.4", (6, 0.4)), ("tree_order8_theta0.5", (8, 0.5)), ("tree_order6_theta0.3", (6, 0.3)),
-            ("tree_order8_theta0.4", (8, 0.4))]
+            ("tree_order8_theta0.4", (8, 0.4)), ("tree_order8_theta0.35", (8, 0.35)), ("tree_order8_theta0.3", (8, 0.3)),
+            ("tree_order10_theta0.5", (10, 0.5)), ("tree_order10_theta0.45", (10, 0.45)),
+            ("tree_order10_theta0.4", (10, 0.4))]
     for label, cfg in runs:
         if cfg is None:
             def call():

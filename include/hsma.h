@@ -323,19 +323,20 @@ hsma_status hsma_profile_read(hsma_group_t group, double *ms /* [host] 5 */, int
  * ions' Kelvin images and over the surface nodes are approximated.  The images are sorted into
  * an octree over the cube of half-width 8a (depth levels below the root; images farther out, of
  * ions within a/8 of the centre, are summed directly at theta = 0 and as one local expansion about
- * the centre otherwise), the surface nodes into patches of up to 64.  The targets are grouped by their own positions, in groups of up to 64.  A cell or patch
- * of radius r_c at distance d from a group of radius r_g is evaluated from its Cartesian
- * multipole moments of the given order when r_c + r_g < theta d, else opened; leaves and
- * patches that are not accepted are summed directly.
+ * the centre otherwise), the surface nodes into patches of up to 64.  The targets are grouped
+ * by their own positions, in groups of up to 64.  A cell or patch of radius r_c at distance d
+ * from a group of radius r_g is evaluated from its Cartesian multipole moments of the given
+ * order when r_c + r_g < theta d, else opened; leaves and patches that are not accepted are
+ * summed directly.
  *   theta: in [0, 1); 0 accepts no cell (every image and node is then summed directly, the
- *          check of the traversal); order: 2, 4, 6 or 8; depth: 2..9, or 0 for a depth from N (7 at
- *          N = 10^6).
+ *          check of the traversal); order: 2, 4, 6, 8 or 10; depth: 2..9, or 0 for a depth
+ *          from N (7 at N = 10^6).
  * The error is the treecode's. On 10^6 ions uniform in a cavity with balanced charges, the
- * relative L2 errors of sampled potentials are 9.5e-4 (order 4, theta 0.5), 9.4e-5 (order 6,
- * theta 0.5), 1.4e-5 (order 6, theta 0.4) and 1.3e-6 (order 8, theta 0.4).  Against the direct
- * symmetric sums of hsma_energy these run 14, 9.7, 6.7 and 4.4 times faster; at 2 10^5 ions
- * 2.1 times at order 4, theta 0.5, and even at order 6, theta 0.4; below about 10^5 ions the
- * direct path is faster at any setting.
+ * relative L2 errors of 2048 sampled potentials against an FP64 evaluation are 9.1e-4 (order 4,
+ * theta 0.5), 1.2e-6 (order 8, theta 0.4), 6.3e-7 (order 8, theta 0.35) and 7.5e-7 (order 10,
+ * theta 0.45); the direct sum in compensated FP32 pairs is at 3.0e-7.  Against that direct sum
+ * these run 14, 4.5, 3.4 and 3.8 times faster; at 2 10^5 ions 2.1 times at order 4, theta 0.5;
+ * below about 10^5 ions the direct path is faster at any setting.
  *   phi: [device] N doubles (required); E: [device] one double or NULL (1/2 sum q_i phi_i of the
  *   treecode's potentials, so of the treecode's accuracy);
  *   ws: [device] ws_bytes >= hsma_tree_workspace_bytes(plan, N, opts) (0 for invalid arguments).

@@ -355,7 +355,7 @@ class Plan:
     def energy_tree(self, x, y, z, q, theta: float = 0.5, order: int = 4, depth: int = 0, phi=None, E=None,
                     stream=None, ws: Workspace | None = None):
         """Potentials (and the energy when E is given) with the Kelvin-image sum by the treecode
-        (opening angle theta, multipole order 2, 4, 6 or 8; depth 0 = from N).  Returns phi."""
+        (opening angle theta, multipole order 2, 4, 6, 8 or 10; depth 0 = from N).  Returns phi."""
         torch = _torch()
         N = x.numel()
         if phi is None:

@@ -884,14 +884,15 @@ __global__ __launch_bounds__(256) void k_tree_esum(int nb, const double *__restr
 
 inline int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Calls f with the multipole order as a compile-time constant (decltype(o)::value): 2, 4, 6 or 8.
+// Calls f with the multipole order as a compile-time constant (decltype(o)::value): 2, 4, 6, 8 or 10.
 template <typename F>
 void with_order(int P, F &&f) {
   switch (P) {
     case 2: f(std::integral_constant<int, 2>{}); break;
     case 4: f(std::integral_constant<int, 4>{}); break;
     case 6: f(std::integral_constant<int, 6>{}); break;
-    default: f(std::integral_constant<int, 8>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: f(std::integral_constant<int, 10>{}); break;
   }
 }
 
@@ -1047,7 +1048,9 @@ static hsma_status tree_args(hsma_plan_t pl, int64_t N, const hsma_tree_opts *op
   if (!pl || N < 0 || !opts) return HSMA_EINVAL;
   if (pl->opts.pair_prec != HSMA_PAIR_FP32 && pl->opts.pair_prec != HSMA_PAIR_FP32_COMP) return HSMA_EINVAL;
   if (!(opts->theta >= 0.0 && opts->theta < 1.0)) return HSMA_EINVAL;
-  if (opts->order != 2 && opts->order != 4 && opts->order != 6 && opts->order != 8) return HSMA_EINVAL;
+  if (opts->order != 2 && opts->order != 4 && opts->order != 6 && opts->order != 8 &&
+      opts->order != 10)
+    return HSMA_EINVAL;
   if (opts->depth != 0 && (opts->depth < 2 || opts->depth > TR_MAX_DEPTH - 1)) return HSMA_EINVAL;
   if (N > ((int64_t)1 << 27) - 1) return HSMA_EINVAL;  // global cell numbers, at most (D + 1) N, in an int
   D = opts->depth ? opts->depth : auto_depth(N);
