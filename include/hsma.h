@@ -300,13 +300,66 @@ hsma_status hsma_group_set_sym_order(hsma_group_t group, int mode);
  * term products: about 2^-24, as FP32).  The fit amplifies the rounding of the check fields
  * and of the operators strongly (balanced charges cancel in u, v), so mode 3 can miss the 1e-6
  * potential target where the surface term is a large share of the potential; modes 1, 2 and
- * 4 hold it.  The FP64 pair mode always applies the fit with FP64 GEMVs.
+ * 4 hold it.  In FP64 pairs (the FP64 mode and every energy launch) the fit is applied with
+ * FP64 GEMVs below 192 systems and FP64 MFMA GEMMs (v_mfma_f64_16x16x4f64) from 192 on; mode 1
+ * forces the GEMVs there, modes 2-4 the FP64 GEMMs.
  * Errors: HSMA_EINVAL (mode outside 0..4). */
 hsma_status hsma_group_set_fit(hsma_group_t group, int mode);
 
-/* Which fit route hsma_energy_batched would take for nsys systems: 1 GEMV, 2 FP32 MFMA,
- * 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA; -1 for invalid arguments. */
+/* Which fit route hsma_energy_batched would take for nsys systems in the group's pair precision:
+ * 1 GEMV, 2 MFMA GEMMs (FP32, or FP64 in the FP64 mode), 3 split-BF16x3 MFMA, 4 split-BF16x6
+ * MFMA; -1 for invalid arguments. */
 int hsma_group_fit_route(hsma_group_t group, int nsys);
+
+/* Energy launch shape (the FP64 energy-only launch of hsma_energy / hsma_energy_batched):
+ * block = 256 or 512 ions per block of the symmetric pair kernel, 0 (default) for 512 when
+ * hsma_group_set_symmetric chose mode 3, else 256; workgroups = 0 (default): one item per
+ * wave over the whole device; > 0: a persistent grid of that many workgroups (rounded up to a
+ * multiple of the die count) taking items from per-die counters, the check sums persistent on
+ * the same grid.  Energies depend on block only through the summation order (rounding) and
+ * not at all on workgroups.  Errors: HSMA_EINVAL. */
+hsma_status hsma_group_set_energy_launch(hsma_group_t group, int block, int workgroups);
+
+/* The group's launch settings, as set by hsma_group_tune, hsma_group_set_symmetric,
+ * hsma_group_set_sym_order, hsma_group_set_fit and hsma_group_set_energy_launch. */
+typedef struct {
+  int persistent, target_items, symmetric, sym_order, fit; /* check and potential launches */
+  int energy_block, energy_workgroups;                      /* energy launches */
+} hsma_launch_settings;
+hsma_status hsma_group_get_settings(hsma_group_t group, hsma_launch_settings *out /* [host] */);
+/* Sets all of them at once, each validated as by its own setter.  Errors: HSMA_EINVAL. */
+hsma_status hsma_group_apply_settings(hsma_group_t group, const hsma_launch_settings *s /* [host] */);
+
+/* Timing-based choice of the group's launch settings for one call shape: the call
+ * hsma_energy_batched(group, nsys, offsets, plan_of, total_n, max_n, x, y, z, q, phi, E, ws,
+ * ws_bytes, stream) is run with candidate settings and timed with HIP events on the stream, one
+ * setting at a time from the group's current ones (coordinate descent over: for potentials the
+ * Kelvin kernel (symmetric mode), its item order and the fit route of the FP32 modes (never
+ * split-BF16x3, which can miss the potential target); for energies the energy block and grid;
+ * for both the persistent form and the chunk length (target_items)), a change kept when it
+ * is at least 2% faster.  Candidates whose workspace exceeds ws_bytes are skipped.  The best
+ * settings are left on the group and kept in a process-wide cache under (device architecture,
+ * compute units, pair precision, surface form, M, P, K, which outputs, and the bit lengths of
+ * nsys, total_n and max_n); a later call with the same key applies the cached settings without
+ * running anything, unless flags has HSMA_TUNE_FORCE.  Tuned settings change results only in
+ * rounding (summation order), as each setter states.  The call overwrites phi, E and ws,
+ * synchronises the stream, creates HIP events and must not be captured into a graph.
+ * Errors: those of hsma_energy_batched for the group's current settings; HSMA_EDEVICE. */
+#define HSMA_TUNE_FORCE 1
+typedef struct {
+  hsma_launch_settings chosen;
+  double ms_start, ms_tuned; /* the call with the settings found on entry, and with the chosen
+                                ones (0 when taken from the cache) */
+  int timed;                 /* candidate settings timed */
+  int cached;                /* 1: applied from the cache without timing */
+} hsma_tune_result;
+hsma_status hsma_group_autotune(hsma_group_t group, int nsys, const int64_t *offsets, const int32_t *plan_of,
+                                int64_t total_n, int64_t max_n, const double *x, const double *y, const double *z,
+                                const double *q, double *phi, double *E, void *ws, size_t ws_bytes,
+                                hipStream_t stream, int flags, hsma_tune_result *out /* [host] */);
+/* A workspace size that admits every candidate setting of hsma_group_autotune for these sizes
+ * (the largest over all combinations, 256-byte multiple); 0 for invalid arguments. */
+size_t hsma_group_autotune_workspace_bytes(hsma_group_t group, int nsys, int64_t total_n, int64_t max_n);
 
 /* Stage timing: when enabled, every compute call on the group records HIP events on its
  * stream around its kernel groups (0 schedule/Kelvin images/packing, 1 check sums, 2 fit

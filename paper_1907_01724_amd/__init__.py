@@ -60,6 +60,19 @@ class ServerOpts(C.Structure):
                 ("delta_slots", C.c_int), ("energy_slots", C.c_int), ("energy_workgroups", C.c_int)]
 
 
+class LaunchSettings(C.Structure):
+    _fields_ = [("persistent", C.c_int), ("target_items", C.c_int), ("symmetric", C.c_int), ("sym_order", C.c_int),
+                ("fit", C.c_int), ("energy_block", C.c_int), ("energy_workgroups", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("chosen", LaunchSettings), ("ms_start", C.c_double), ("ms_tuned", C.c_double), ("timed", C.c_int),
+                ("cached", C.c_int)]
+
+
 class ServerInfo(C.Structure):
     _fields_ = [("memory_used", C.c_size_t), ("memory_budget", C.c_size_t), ("pending", C.c_int64),
                 ("completed", C.c_uint64), ("batches", C.c_uint64), ("batched_requests", C.c_uint64),
@@ -116,6 +129,13 @@ def load_library(path: str | None = None):
     L.hsma_group_eval_kernel.restype = C.c_int
     L.hsma_group_set_fit.argtypes = [_VP, C.c_int]
     L.hsma_group_set_sym_order.argtypes = [_VP, C.c_int]
+    L.hsma_group_set_energy_launch.argtypes = [_VP, C.c_int, C.c_int]
+    L.hsma_group_autotune_workspace_bytes.argtypes = [_VP, C.c_int, C.c_int64, C.c_int64]
+    L.hsma_group_autotune_workspace_bytes.restype = C.c_size_t
+    L.hsma_group_get_settings.argtypes = [_VP, C.POINTER(LaunchSettings)]
+    L.hsma_group_apply_settings.argtypes = [_VP, C.POINTER(LaunchSettings)]
+    L.hsma_group_autotune.argtypes = [_VP, C.c_int, _VP, _VP, C.c_int64, C.c_int64] + [_VP] * 6 + [
+        _VP, C.c_size_t, _VP, C.c_int, C.POINTER(TuneResult)]
     L.hsma_system_create_ex.argtypes = [_VP, C.c_int64] + [_VP] * 4 + [C.c_int, _VP, C.POINTER(_VP)]
     L.hsma_kirkwood_workspace_bytes.argtypes = [C.c_int, C.c_int64]
     L.hsma_kirkwood_workspace_bytes.restype = C.c_size_t
@@ -155,7 +175,9 @@ def load_library(path: str | None = None):
                  "hsma_energy", "hsma_energy_noalloc", "hsma_debug_intermediates", "hsma_stream_check", "hsma_profile_enable",
                  "hsma_profile_read", "hsma_group_create", "hsma_group_destroy", "hsma_energy_batched",
                  "hsma_group_stream_check", "hsma_group_tune", "hsma_group_set_symmetric", "hsma_group_eval_kernel",
-                 "hsma_group_set_fit", "hsma_group_set_sym_order", "hsma_field", "hsma_field_batched",
+                 "hsma_group_set_fit", "hsma_group_set_sym_order", "hsma_group_set_energy_launch",
+                 "hsma_group_get_settings", "hsma_group_apply_settings", "hsma_group_autotune", "hsma_field",
+                 "hsma_field_batched",
                  "hsma_kirkwood", "hsma_energy_tree", "hsma_system_create_ex", "hsma_system_create", "hsma_delta_energy",
                  "hsma_system_commit", "hsma_system_energy", "hsma_system_positions", "hsma_system_destroy",
                  "hsma_system_full_energy", "hsma_server_create", "hsma_server_destroy", "hsma_server_add_system",
@@ -567,6 +589,46 @@ class Group:
     def fit_route(self, nsys: int) -> int:
         """1 GEMV, 2 FP32 MFMA, 3 split-BF16x3 MFMA, 4 split-BF16x6 MFMA."""
         return int(load_library().hsma_group_fit_route(self._h, int(nsys)))
+
+    def autotune_workspace_bytes(self, nsys: int, total_n: int, max_n: int) -> int:
+        return int(load_library().hsma_group_autotune_workspace_bytes(self._h, int(nsys), int(total_n), int(max_n)))
+
+    def set_energy_launch(self, block: int = 0, workgroups: int = 0):
+        """Energy launch: ions per block (0 automatic, 256, 512) and grid (0: one item per wave;
+        > 0: persistent grid of that many workgroups)."""
+        _check(load_library().hsma_group_set_energy_launch(self._h, int(block), int(workgroups)),
+               "hsma_group_set_energy_launch")
+
+    def settings(self) -> dict:
+        s = LaunchSettings()
+        _check(load_library().hsma_group_get_settings(self._h, C.byref(s)), "hsma_group_get_settings")
+        return s.as_dict()
+
+    def apply_settings(self, settings: dict):
+        s = LaunchSettings(**{k: int(settings[k]) for k, _ in LaunchSettings._fields_})
+        _check(load_library().hsma_group_apply_settings(self._h, C.byref(s)), "hsma_group_apply_settings")
+
+    def autotune(self, offsets, x, y, z, q, total_n: int, max_n: int, plan_of=None, phi=None, E=None, stream=None,
+                 ws=None, force: bool = False) -> dict:
+        """Times the call energy(..., phi=phi, E=E) (E None: potentials alone) under candidate launch
+        settings and leaves the fastest on the group (hsma_group_autotune); overwrites phi, E, ws."""
+        torch = _torch()
+        nsys = offsets.numel() - 1
+        if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise TypeError("offsets must be a contiguous int64 device tensor")
+        if plan_of is not None and (plan_of.dtype != torch.int32 or not plan_of.is_cuda or plan_of.numel() != nsys):
+            raise TypeError("plan_of must be an int32 device tensor of nsys entries")
+        w = ws if ws is not None else _ensure(self._ws, ("tune", nsys, int(total_n), int(max_n), str(x.device)),
+                                              self.autotune_workspace_bytes(nsys, total_n, max_n), x.device)
+        r = TuneResult()
+        _check(load_library().hsma_group_autotune(
+            self._h, nsys, offsets.data_ptr(), plan_of.data_ptr() if plan_of is not None else None, int(total_n),
+            int(max_n), _dev_ptr(x, "x", total_n), _dev_ptr(y, "y", total_n), _dev_ptr(z, "z", total_n),
+            _dev_ptr(q, "q", total_n), _dev_ptr(phi, "phi", total_n) if phi is not None else None,
+            _dev_ptr(E, "E", nsys) if E is not None else None, w.ptr, w.nbytes, _stream_ptr(stream),
+            1 if force else 0, C.byref(r)), "hsma_group_autotune")
+        return {"chosen": r.chosen.as_dict(), "ms_start": r.ms_start, "ms_tuned": r.ms_tuned, "timed": r.timed,
+                "cached": bool(r.cached)}
 
     def profile(self, on: bool = True):
         _profile(self._h, on)

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsma.so")
-SOURCES = ["hsma_plan.hip", "hsma_engine.hip", "hsma_system.hip", "hsma_server.hip", "hsma_kirkwood.hip", "hsma_tree.hip"]
+SOURCES = ["hsma_plan.hip", "hsma_engine.hip", "hsma_system.hip", "hsma_server.hip", "hsma_kirkwood.hip", "hsma_tree.hip",
+           "hsma_tune.hip"]
 ARCH = os.environ.get("HSMA_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for every device compilation: the

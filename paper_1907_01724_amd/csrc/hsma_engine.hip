@@ -115,12 +115,13 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 //       at [2][b] otherwise, and its surface items start at [6][b].
 //   [7] prefix of the energy-sum chunks (energy-only launches: EC consecutive item energies of
 //       one system, its block pairs first, then its surface items).
-// followed by 16 words: [0] check item counter, [1] eval item counter, [2] schedule valid,
-// [3] launch kind: 1 for the energy-only launch, else 0, plus 16 x the pair precision (read back by
-// hsma_debug_intermediates), [8..15] the energy kernel's item counters, one per die (persistent
-// form).
+// followed by 32 words: [2] schedule valid, [3] launch kind: 1 for the energy-only launch, else 0,
+// plus 16 x the pair precision (read back by hsma_debug_intermediates); the persistent kernels'
+// item counters, one per die: [8..15] the energy kernel, [16..23] the check sums, [24..31] the
+// evaluation kernels.
 // ---------------------------------------------------------------------------------
 constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
+constexpr int CTR_WORDS = 32, CTR_ENERGY = 8, CTR_CHECK = 16, CTR_EVAL = 24;
 struct Sched {
   int64_t *off, *ic, *ie, *fb, *pc, *pe, *is, *ec, *ctr;
   __host__ __device__ Sched(int64_t *base, int nsys) {
@@ -174,7 +175,7 @@ __device__ __forceinline__ void eval_counts(int64_t n, int P, int che, int sym_t
 __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *__restrict__ offsets,
                                                       const int32_t *__restrict__ plan_of, Bounds bd, int M, int P,
                                                       int chc, int che, int sym_tb, int sch, int64_t sym_tail,
-                                                      int64_t grid_c, int64_t grid_e, int kind,
+                                                      int kind,
                                                       int64_t *__restrict__ base, int *__restrict__ flag) {
   Sched S(base, nsys);
   __shared__ int64_t sc[7][SCHED_T];
@@ -254,9 +255,7 @@ __global__ __launch_bounds__(SCHED_T) void k_schedule(int nsys, const int64_t *_
     S.pe[nsys] = sc[4][t];
     S.is[nsys] = sc[1][t] + sc[5][t];
     S.ec[nsys] = sc[6][t];
-    for (int k = 0; k < 16; ++k) S.ctr[k] = 0;
-    S.ctr[0] = grid_c;  // items below the grid size are taken by block index
-    S.ctr[1] = grid_e;
+    for (int k = 0; k < CTR_WORDS; ++k) S.ctr[k] = 0;
     S.ctr[3] = kind;
     const bool fits = sc[0][t] <= bd.items_c && sc[1][t] + sc[5][t] <= bd.items_e && sc[2][t] <= bd.fin &&
                       sc[3][t] <= bd.parts_c && sc[4][t] <= bd.parts_e && sc[6][t] <= bd.echunks;
@@ -391,13 +390,39 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   if (qr) qr[i] = qi / reff;  // the charge over the radius (energy sums)
 }
 
+// The device's accelerator dies: gfx950 (MI355X) has 8, each with its own L2, and places
+// workgroup w on die w % NXCD.  xcd_item deals the item numbers out in runs of XQ workgroups (one
+// super-tile's ST^2 items): die x takes runs x, x + NXCD, x + 2 NXCD, ..., so the pairs of a tile
+// run on one die and share its L2, and the dies share the work evenly.  The grid must be a multiple
+// of NXCD XQ workgroups.  Only locality depends on the die count: the map is a bijection of
+// [0, WAVES grid) whatever it is.
+constexpr int NXCD = 8;
+constexpr int XQ = ST * ST / WAVES;
+__device__ __forceinline__ int64_t xcd_item(int w) {
+  const int64_t x = blockIdx.x % NXCD, k = blockIdx.x / NXCD;
+  const int64_t run = (k / XQ) * NXCD + x;
+  return (run * XQ + k % XQ) * WAVES + w;
+}
+
+// Persistent form: die x's items are its runs' items in order, t = 0, 1, ... (run t / (XQ WAVES),
+// offset t % (XQ WAVES)); its waves take them EG at a time from the die's own counter, so that the
+// dies do not contend for one counter and a run still stays on one die.  Every die index 0..NXCD-1
+// has workgroups (the grid is a multiple of NXCD), so every item is taken, wherever the workgroups
+// actually run.
+constexpr int EG = 4;  // items per claim
+__device__ __forceinline__ int64_t die_item(int64_t x, int64_t t) {
+  constexpr int64_t RUN = (int64_t)XQ * WAVES;
+  return ((t / RUN) * NXCD + x) * RUN + t % RUN;
+}
+
 // ---------------------------------------------------------------------------------
-// Item loop.  The first item of a block is its block index; in the persistent form the
-// following items come from a device counter that the schedule kernel starts at the grid
-// size.  A relaxed read of the counter lets a block that finds the queue drained leave
-// without an atomic, so same-address atomics only serve items that exist.  The item index
-// is made wave-uniform (readfirstlane) so that everything derived from it stays in scalar
-// registers and the source loads remain scalar loads.
+// Item loop of the check and evaluation kernels.  One item per block: the block index.  The
+// persistent form runs a grid of resident blocks (a multiple of NXCD): die x = blockIdx % NXCD
+// takes the items of its runs, IRUN consecutive items dealt out per die as in die_item, IC at a
+// time from its own counter, so that the dies do not contend for one address and a claim serves
+// several items.  A relaxed read of the counter lets a block that finds its die's items drained
+// leave without an atomic.  The item index is made wave-uniform (readfirstlane) so that
+// everything derived from it stays in scalar registers and the source loads remain scalar loads.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
@@ -405,23 +430,45 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ bool next_item(bool persistent, bool first, int64_t total, int64_t *ctr, int64_t *slot,
-                                          int64_t &item) {
-  if (first) {
-    item = (int64_t)blockIdx.x;
+constexpr int IC = 2;         // items per claim of a persistent block
+constexpr int64_t IRUN = 16;  // consecutive items per run of a die
+__device__ __forceinline__ int64_t die_run_item(int64_t x, int64_t t) {
+  return ((t / IRUN) * NXCD + x) * IRUN + t % IRUN;
+}
+
+struct ItemLoop {
+  int64_t t = 0;
+  int left = 0;
+  bool first = true;
+  // dctr: the NXCD per-die counters (zero at the start of the launch); slot: one shared word
+  __device__ __forceinline__ bool next(bool persistent, int64_t total, int64_t *dctr, int64_t *slot,
+                                       int64_t &item) {
+    if (!persistent) {
+      if (!first) return false;
+      first = false;
+      item = (int64_t)blockIdx.x;
+      return item < total;
+    }
+    const int64_t x = blockIdx.x % NXCD;
+    if (!first) __syncthreads();  // every wave is done with the previous item's shared data
+    first = false;
+    if (left == 0) {
+      if (threadIdx.x == 0) {
+        const int64_t cur = (int64_t)__hip_atomic_load((unsigned long long *)&dctr[x], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        *slot = die_run_item(x, cur) >= total ? cur
+                                              : (int64_t)atomicAdd((unsigned long long *)&dctr[x], (unsigned long long)IC);
+      }
+      __syncthreads();
+      t = uniform64(*slot);
+      left = IC;
+    }
+    item = die_run_item(x, t);  // increasing in t: once past the end, every later claim is too
+    ++t;
+    --left;
     return item < total;
   }
-  if (!persistent) return false;
-  __syncthreads();  // every wave is done with the previous item's shared data
-  if (threadIdx.x == 0) {
-    const int64_t cur = (int64_t)__hip_atomic_load((unsigned long long *)ctr, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-    *slot = cur >= total ? cur : (int64_t)atomicAdd((unsigned long long *)ctr, 1ULL);
-  }
-  __syncthreads();
-  item = uniform64(*slot);
-  return item < total;
-}
+};
 
 // The slice of an item's source range [b0, b1) that wave w takes: the range split evenly over
 // the waves in whole 32-source tiles (the last slices may be short or empty).
@@ -503,7 +550,8 @@ __global__ __launch_bounds__(TPB) void k_check(int persistent, int nsys, int M, 
   const int64_t total = S.ic[nsys];
   const int64_t Gc = cdiv64(M, GRP);
   int64_t item;
-  for (bool first = true; next_item(persistent, first, total, &S.ctr[0], &s_item, item); first = false) {
+  ItemLoop loop;
+  while (loop.next(persistent, total, &S.ctr[CTR_CHECK], &s_item, item)) {
     const int b = sys_c[item];
     const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
     const int64_t loc = item - S.ic[b];
@@ -712,6 +760,51 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int nrows, int ncols, int kdim,
     }
 }
 
+// The same product in FP64: C[col][row] = sum_k A[row][k] B[col][k] on v_mfma_f64_16x16x4f64,
+// whose lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and
+// receives D[l / 16 + 4 v][l % 16], v = 0..3.  Block tile 64 x 64, four waves of 32 x 32, k
+// staged through LDS 16 at a time; the accumulators are FP64 throughout.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_gemm64_nt(int nrows, int ncols, int kdim, const double *__restrict__ A,
+                                                   const double *__restrict__ B, double *__restrict__ C) {
+  __shared__ double As[64][17];
+  __shared__ double Bs[64][17];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+  doublex4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kdim; k0 += 16) {
+    for (int e = t; e < 64 * 16; e += 256) {
+      const int r = e >> 4, kk = e & 15;
+      const int gr = row0 + r, gc = col0 + r, gk = k0 + kk;
+      As[r][kk] = (gr < nrows && gk < kdim) ? A[(size_t)gr * kdim + gk] : 0.0;
+      Bs[r][kk] = (gc < ncols && gk < kdim) ? B[(size_t)gc * kdim + gk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kl = kk + (lane >> 4);
+      double a[2], bb[2];
+      for (int i = 0; i < 2; ++i) a[i] = As[wr * 32 + i * 16 + (lane & 15)][kl];
+      for (int j = 0; j < 2; ++j) bb[j] = Bs[wc * 32 + j * 16 + (lane & 15)][kl];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int col = col0 + wc * 32 + j * 16 + (lane & 15);
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * v;
+        if (row < nrows && col < ncols) C[(size_t)col * nrows + row] = acc[i][j][v];
+      }
+    }
+}
+
 // Fit apply on BF16 MFMA with split products.  Every factor x is taken as a sum of BF16
 // terms b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1), and the product of two
 // factors as the sum of the term products whose orders add to at most NS - 1:
@@ -820,11 +913,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf(int nrows, int ncols, int kdim,
 }
 
 // h = f . alpha' + g . beta' from the first GEMM's output ab32 [2 nsys][K]; writes the
-// second GEMM's operand h32 [2 nsys][K]: row 2b = n . h, row 2b+1 = h.
+// second GEMM's operand h32 [2 nsys][K]: row 2b = n . h, row 2b+1 = h (TF: FP32 or FP64).
+template <typename TF>
 __global__ __launch_bounds__(256) void k_fit_h(int nsys, const int64_t *__restrict__ base, int K,
-                                               const float *__restrict__ ab32, const PlanDev *__restrict__ plans,
+                                               const TF *__restrict__ ab32, const PlanDev *__restrict__ plans,
                                                const int32_t *__restrict__ plan_of, const int *__restrict__ nidx,
-                                               float *__restrict__ h32) {
+                                               TF *__restrict__ h32) {
   Sched S(const_cast<int64_t *>(base), nsys);
   if (!sched_ok(S)) return;  // plan_of was checked by the schedule
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -833,14 +927,14 @@ __global__ __launch_bounds__(256) void k_fit_h(int nsys, const int64_t *__restri
   const PlanDev &c = plans[plan_of ? plan_of[b] : 0];
   const double h = c.fg[k] * (double)ab32[(size_t)(2 * b) * K + k] +
                    c.fg[K + k] * (double)ab32[(size_t)(2 * b + 1) * K + k];
-  h32[(size_t)(2 * b) * K + k] = (float)(h * (double)degree_weight(nidx[k], c.dipole));
-  h32[(size_t)(2 * b + 1) * K + k] = (float)h;
+  h32[(size_t)(2 * b) * K + k] = (TF)(h * (double)degree_weight(nidx[k], c.dipole));
+  h32[(size_t)(2 * b + 1) * K + k] = (TF)h;
 }
 
 // qd[b][s] = (C[2b][s], -C[2b+1][s]) from the second GEMM's output [2 nsys][P].
-template <typename T2>
+template <typename T2, typename TF>
 __global__ __launch_bounds__(256) void k_fit_qd(int nsys, int P, int Pe, const PlanDev *__restrict__ plans,
-                                                const int32_t *__restrict__ plan_of, const float *__restrict__ Cq,
+                                                const int32_t *__restrict__ plan_of, const TF *__restrict__ Cq,
                                                 T2 *__restrict__ qd) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)nsys * P) return;
@@ -945,7 +1039,8 @@ __global__ __launch_bounds__(TPB) void k_eval(int persistent, int nsys, int P, i
   if (!sched_ok(S)) return;
   const int64_t total = S.ie[nsys];
   int64_t item;
-  for (bool first = true; next_item(persistent, first, total, &S.ctr[1], &s_item, item); first = false) {
+  ItemLoop loop;
+  while (loop.next(persistent, total, &S.ctr[CTR_EVAL], &s_item, item)) {
     const int b = sys_e[item];
     const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
     const int64_t loc = item - S.ie[b];
@@ -1120,7 +1215,8 @@ __global__ __launch_bounds__(TPB) void k_eval_field(int persistent, int nsys, in
   if (!sched_ok(S)) return;
   const int64_t total = S.ie[nsys];
   int64_t item;
-  for (bool first = true; next_item(persistent, first, total, &S.ctr[1], &s_item, item); first = false) {
+  ItemLoop loop;
+  while (loop.next(persistent, total, &S.ctr[CTR_EVAL], &s_item, item)) {
     const int b = sys_e[item];
     const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
     const int64_t loc = item - S.ie[b];
@@ -1228,22 +1324,17 @@ __device__ __forceinline__ void sym_surface(const float (&sx)[RS], const float (
   }
 }
 
+// One item of the symmetric kernel (a block pair or a surface item), by one wave.
 template <int R>
-__global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, int mono,
-                                                    const int64_t *__restrict__ base,
-                                                    const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
-                                                    const float4 *__restrict__ tgt, const float4 *__restrict__ img,
-                                                    const float *__restrict__ wk, const double *__restrict__ rk,
-                                                    const float4 *__restrict__ nodes,
-                                                    const float2 *__restrict__ qd, double *__restrict__ part) {
+__device__ __forceinline__ void sym_item(int64_t item, const Sched &S, int lane, int P, int sch, int mono,
+                                         const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
+                                         const float4 *__restrict__ tgt, const float4 *__restrict__ img,
+                                         const float *__restrict__ wk, const double *__restrict__ rk,
+                                         const float4 *__restrict__ nodes, const float2 *__restrict__ qd,
+                                         double *__restrict__ part) {
   constexpr int TB = 64 * R;
   constexpr int RS = R / SYM_SH;         // target sets per lane of a surface item
   constexpr float FAR_TARGET = 3.0e18f;  // stand-in position of an empty target lane
-  Sched S(const_cast<int64_t *>(base), nsys);
-  const int lane = threadIdx.x & 63, w = wave_id();
-  if (!sched_ok(S)) return;
-  const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);  // one item per wave
-  if (item >= S.is[nsys]) return;
   const int b = __builtin_amdgcn_readfirstlane(sys_e[item]);
   const bool surface = item >= S.is[b];
   const int64_t lo = S.off[b];
@@ -1392,6 +1483,39 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, in
   for (int k = 0; k < R; ++k) {
     const int i = t0 + k * 64 + lane;
     if (i < n) pb[(size_t)slot * n + i] = acc[k];
+  }
+}
+
+// The symmetric kernel: one item per wave (a block's waves take consecutive items), or the
+// persistent form, whose waves take items EG at a time from their die's counter in the order of
+// die_item until the die's items run out.  Every item writes the same slots either way.
+template <int R, bool PERSIST>
+__global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, int mono,
+                                                    const int64_t *__restrict__ base,
+                                                    const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
+                                                    const float4 *__restrict__ tgt, const float4 *__restrict__ img,
+                                                    const float *__restrict__ wk, const double *__restrict__ rk,
+                                                    const float4 *__restrict__ nodes,
+                                                    const float2 *__restrict__ qd, double *__restrict__ part) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  if (!sched_ok(S)) return;
+  const int64_t total = S.is[nsys];
+  if constexpr (!PERSIST) {
+    const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);
+    if (item < total) sym_item<R>(item, S, lane, P, sch, mono, sys_e, plan_of, tgt, img, wk, rk, nodes, qd, part);
+  } else {
+    const int64_t x = blockIdx.x % NXCD;
+    for (;;) {
+      int64_t t = 0;
+      if (lane == 0) t = (int64_t)atomicAdd((unsigned long long *)&S.ctr[CTR_EVAL + x], (unsigned long long)EG);
+      t = uniform64(__shfl(t, 0, 64));
+      if (die_item(x, t) >= total) return;  // every later claim of this die lies beyond too
+      for (int g = 0; g < EG; ++g) {
+        const int64_t item = die_item(x, t + g);
+        if (item < total) sym_item<R>(item, S, lane, P, sch, mono, sys_e, plan_of, tgt, img, wk, rk, nodes, qd, part);
+      }
+    }
   }
 }
 
@@ -1575,31 +1699,6 @@ __device__ __forceinline__ void block_pair(int64_t loc, int64_t B, int &I, int &
   J = __builtin_amdgcn_readfirstlane((int)(r + (loc - (r * B - r * (r - 1) / 2))));
 }
 
-// The device's accelerator dies: gfx950 (MI355X) has 8, each with its own L2, and places
-// workgroup w on die w % NXCD.  xcd_item deals the item numbers out in runs of XQ workgroups (one
-// super-tile's ST^2 items): die x takes runs x, x + NXCD, x + 2 NXCD, ..., so the pairs of a tile
-// run on one die and share its L2, and the dies share the work evenly.  The grid must be a multiple
-// of NXCD XQ workgroups.  Only locality depends on the die count: the map is a bijection of
-// [0, WAVES grid) whatever it is.
-constexpr int NXCD = 8;
-constexpr int XQ = ST * ST / WAVES;
-__device__ __forceinline__ int64_t xcd_item(int w) {
-  const int64_t x = blockIdx.x % NXCD, k = blockIdx.x / NXCD;
-  const int64_t run = (k / XQ) * NXCD + x;
-  return (run * XQ + k % XQ) * WAVES + w;
-}
-
-// Persistent form: die x's items are its runs' items in order, t = 0, 1, ... (run t / (XQ WAVES),
-// offset t % (XQ WAVES)); its waves take them EG at a time from the die's own counter, so that the
-// dies do not contend for one counter and a run still stays on one die.  Every die index 0..NXCD-1
-// has workgroups (the grid is a multiple of NXCD), so every item is taken, wherever the workgroups
-// actually run.
-constexpr int EG = 4;  // items per claim
-__device__ __forceinline__ int64_t die_item(int64_t x, int64_t t) {
-  constexpr int64_t RUN = (int64_t)XQ * WAVES;
-  return ((t / RUN) * NXCD + x) * RUN + t % RUN;
-}
-
 template <int R>
 __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int sch, int mono, const Sched &S, int lane,
                                             const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
@@ -1629,7 +1728,7 @@ __global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int 
   const int64_t x = blockIdx.x % NXCD;
   for (;;) {
     int64_t t = 0;
-    if (lane == 0) t = (int64_t)atomicAdd((unsigned long long *)&S.ctr[8 + x], (unsigned long long)EG);
+    if (lane == 0) t = (int64_t)atomicAdd((unsigned long long *)&S.ctr[CTR_ENERGY + x], (unsigned long long)EG);
     t = uniform64(__shfl(t, 0, 64));
     if (die_item(x, t) >= total) return;  // every later claim of this die lies beyond too
     for (int g = 0; g < EG; ++g) {
@@ -1967,8 +2066,9 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   const bool throttle = L.eonly && grp->tune.ewaves > 0;
   const int persistent_c = persistent || throttle;
   const int64_t cap_c = throttle ? (int64_t)grp->tune.ewaves : pgrid_c;
-  const int64_t grid_c = persistent_c ? (L.items_c < cap_c ? L.items_c : cap_c) : L.items_c;
-  const int64_t grid_e = persistent ? (L.items_e < pgrid_e ? L.items_e : pgrid_e) : L.items_e;
+  // persistent grids: resident blocks, at most one per item, a multiple of the die count
+  const int64_t grid_c = persistent_c ? round_up(L.items_c < cap_c ? L.items_c : cap_c, NXCD) : L.items_c;
+  const int64_t grid_e = persistent ? round_up(L.items_e < pgrid_e ? L.items_e : pgrid_e, NXCD) : L.items_e;
 
   hipEvent_t pr = prof_begin(grp, ST_PACK, st);
   const int sched_t = nsys >= SCHED_T ? SCHED_T : (int)((nsys + 63) / 64 * 64);
@@ -1988,8 +2088,8 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
                            : grp->tune.sym_order == 2
                                ? INT64_MAX
                                : SYM_TAIL_ROUNDS * g->ncu * WAVES * grp->tune.occ_sym[L.sym_tb == 512];
-  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, Pe, L.chc, L.che, L.sym_tb, L.sch, sym_tail, grid_c,
-                                    grid_e, (L.eonly ? 1 : 0) + 16 * L.prec, base, grp->flag);
+  k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, Pe, L.chc, L.che, L.sym_tb, L.sch, sym_tail,
+                                    (L.eonly ? 1 : 0) + 16 * L.prec, base, grp->flag);
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f, plans, plan_of, x, y, z, q, img, tgt,
                                              srcw, self,
@@ -2020,7 +2120,8 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       k_gemm_bf<3><<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->Mp, g->pinv_bf, uv32, ab32);
     else
       k_gemm_nt<<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->pinv32, uv32, ab32);
-    k_fit_h<<<(int)cdiv((int64_t)nsys * K, 256), 256, 0, st>>>(nsys, base, K, ab32, plans, plan_of, g->nidx, h32);
+    k_fit_h<float><<<(int)cdiv((int64_t)nsys * K, 256), 256, 0, st>>>(nsys, base, K, ab32, plans, plan_of, g->nidx,
+                                                                      h32);
     dim3 g2((unsigned)cdiv(P, 64), (unsigned)cdiv(2 * (int64_t)nsys, 64));
     if (L.bf_terms == 2)
       k_gemm_bf<2><<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->Kp, g->lhat_bf, h32, c2);
@@ -2028,7 +2129,17 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       k_gemm_bf<3><<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->Kp, g->lhat_bf, h32, c2);
     else
       k_gemm_nt<<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->lhat32, h32, c2);
-    k_fit_qd<T2><<<(int)cdiv((int64_t)nsys * P, 256), 256, 0, st>>>(nsys, P, Pe, plans, plan_of, c2, qd);
+    k_fit_qd<T2, float><<<(int)cdiv((int64_t)nsys * P, 256), 256, 0, st>>>(nsys, P, Pe, plans, plan_of, c2, qd);
+  } else if (MODE == HSMA_PAIR_FP64 && L.gemm64) {
+    double *h64 = (double *)(ws + L.h32);
+    double *c2 = (double *)(ws + L.gemm2);
+    dim3 g1((unsigned)cdiv(K, 64), (unsigned)cdiv(2 * (int64_t)nsys, 64));
+    k_gemm64_nt<<<g1, 256, 0, st>>>(K, 2 * nsys, M, g->pinv64, uv, ab);
+    k_fit_h<double><<<(int)cdiv((int64_t)nsys * K, 256), 256, 0, st>>>(nsys, base, K, ab, plans, plan_of, g->nidx,
+                                                                       h64);
+    dim3 g2((unsigned)cdiv(P, 64), (unsigned)cdiv(2 * (int64_t)nsys, 64));
+    k_gemm64_nt<<<g2, 256, 0, st>>>(P, 2 * nsys, K, g->lhat64, h64, c2);
+    k_fit_qd<T2, double><<<(int)cdiv((int64_t)nsys * P, 256), 256, 0, st>>>(nsys, P, Pe, plans, plan_of, c2, qd);
   } else if constexpr (MODE == HSMA_PAIR_FP64) {
     k_fit_moments<double><<<dim3((unsigned)cdiv(K, 4), nsys), 256, 0, st>>>(K, M, g->pinv64, uv, ab);
     k_fit_surface<double, T2><<<dim3((unsigned)cdiv(P, 4), nsys), 256, 0, st>>>(nsys, base, P, Pe, K, g->lhat64, plans,
@@ -2082,15 +2193,19 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   bool done = false;
   if constexpr (MODE == HSMA_PAIR_FP32_COMP) {
     if (L.sym_tb > 0 && L.items_e > 0) {
-      const unsigned gs = (unsigned)cdiv(L.items_e, WAVES);
+      // one item per wave, or persistent: the kernel's resident blocks, a multiple of the die count
+      const unsigned gs = persistent ? (unsigned)round_up((int64_t)g->ncu * grp->tune.occ_sym[L.sym_tb == 512], NXCD)
+                                     : (unsigned)cdiv(L.items_e, WAVES);
       const float *wk = (const float *)(ws + L.wk);
       const double *rk = (const double *)(ws + L.rk);
+      auto run = [&](auto kern) {
+        kern<<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, wk, rk,
+                                 grp->nodes32, qd, eval_part);
+      };
       if (L.sym_tb == 256)
-        k_kelvin_sym<4><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img,
-                                            wk, rk, grp->nodes32, qd, eval_part);
+        persistent ? run(k_kelvin_sym<4, true>) : run(k_kelvin_sym<4, false>);
       else
-        k_kelvin_sym<8><<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img,
-                                            wk, rk, grp->nodes32, qd, eval_part);
+        persistent ? run(k_kelvin_sym<8, true>) : run(k_kelvin_sym<8, false>);
       done = true;
     }
   } else if constexpr (MODE == HSMA_PAIR_FP64) {
@@ -2174,7 +2289,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   const int mode = grp->tune.symmetric;
   if (L.eonly && total_n > 0) {
     // the energy kernel: blocks of 256 ions, or 512 when asked for; one FP64 value per item
-    const int64_t tb = mode == 3 ? 512 : 256;
+    const int64_t tb = grp->tune.eblock ? grp->tune.eblock : (mode == 3 ? 512 : 256);
     const int64_t bmax = cdiv(max_n, tb);
     const int64_t sch = cdiv(P, (2 * tb) / 3);
     const int64_t sb = total_n / tb + nsys;
@@ -2204,7 +2319,9 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   }
   L.fin = total_n > 0 ? total_n / FINB + nsys : 0;
   const int fit = grp->tune.fit;
-  L.mfma = !fp64 && (fit >= 2 || (fit == 0 && nsys >= FIT_MFMA_MIN_SYS));
+  const bool gemm = fit >= 2 || (fit == 0 && nsys >= FIT_MFMA_MIN_SYS);
+  L.mfma = !fp64 && gemm;
+  L.gemm64 = fp64 && gemm;
   L.bf_terms = fp64 ? 0 : fit == 3 ? 2 : fit == 4 ? 3 : 0;
   const size_t t4 = fp64 ? sizeof(double4) : sizeof(float4);
   const size_t t1 = fp64 ? sizeof(double) : sizeof(float);
@@ -2214,7 +2331,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
     o = align256(o + bytes);
     return at;
   };
-  L.sched = take(sizeof(int64_t) * (8 * (size_t)(nsys + 1) + 16));
+  L.sched = take(sizeof(int64_t) * (8 * (size_t)(nsys + 1) + CTR_WORDS));
   L.item_sys_c = take(sizeof(int) * (size_t)L.items_c);
   L.item_sys_e = take(sizeof(int) * (size_t)L.items_e);
   L.fin_sys = take(sizeof(int) * (size_t)L.fin);
@@ -2228,8 +2345,10 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.uv = take(sizeof(double) * 2 * (size_t)M * nsys);
   L.uv32 = L.mfma ? take(sizeof(float) * 2 * (size_t)M * nsys) : 0;
   L.ab = take(sizeof(double) * 2 * (size_t)K * nsys);
-  L.h32 = L.mfma ? take(sizeof(float) * 2 * (size_t)K * nsys) : 0;
-  L.gemm2 = L.mfma ? take(sizeof(float) * 2 * (size_t)Pf * nsys) : 0;
+  L.h32 = L.mfma ? take(sizeof(float) * 2 * (size_t)K * nsys) : L.gemm64 ? take(sizeof(double) * 2 * (size_t)K * nsys) : 0;
+  L.gemm2 = L.mfma    ? take(sizeof(float) * 2 * (size_t)Pf * nsys)
+            : L.gemm64 ? take(sizeof(double) * 2 * (size_t)Pf * nsys)
+                       : 0;
   L.qd = take(sizeof(double2) * (size_t)P * nsys);
   L.eval_part = take(L.eonly ? sizeof(double) * (size_t)L.items_e
                              : (field ? sizeof(double4) : sizeof(double)) * (size_t)L.parts_e);
@@ -2334,8 +2453,8 @@ hsma_status occupancy_of(int *oc, int *oe) {
 
 hsma_status sym_occupancy(int *o256, int *o512) {
   int a = 0, b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_kelvin_sym<4>, TPB, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_kelvin_sym<8>, TPB, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_kelvin_sym<4, true>, TPB, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_kelvin_sym<8, true>, TPB, 0) != hipSuccess)
     return HSMA_EDEVICE;
   *o256 = a > 0 ? a : 1;
   *o512 = b > 0 ? b : 1;
@@ -2535,7 +2654,7 @@ extern "C" hsma_status hsma_group_set_fit(hsma_group_t grp, int mode) {
 extern "C" int hsma_group_fit_route(hsma_group_t grp, int nsys) {
   if (!grp || nsys < 1) return -1;
   const Layout L = layout(grp, nsys, 0, 0);
-  return L.bf_terms == 3 ? 4 : L.bf_terms == 2 ? 3 : L.mfma ? 2 : 1;
+  return L.bf_terms == 3 ? 4 : L.bf_terms == 2 ? 3 : (L.mfma || L.gemm64) ? 2 : 1;
 }
 
 extern "C" hsma_status hsma_debug_intermediates(hsma_plan_t pl, int64_t N, const void *ws, hipStream_t st, double *u,

@@ -810,6 +810,7 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
   grp->tune.symmetric = 1;
   grp->tune.fit = 0;
   grp->tune.sym_order = 0;
+  grp->tune.eblock = 0;
   grp->tune.ewaves = 0;
   if (pair_occupancy(prec, &grp->tune.occ_check, &grp->tune.occ_eval) != HSMA_OK ||
       sym_occupancy(&grp->tune.occ_sym[0], &grp->tune.occ_sym[1]) != HSMA_OK) {

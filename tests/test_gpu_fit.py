@@ -123,13 +123,29 @@ def test_single_system_routes(dev, case, route):
     plan.close()
 
 
-def test_fp64_pairs_keep_the_fp64_fit(dev):
-    s = W.workload_c1().systems[0]
+@pytest.mark.parametrize("case", ["c1", "ragged_K_M"])
+def test_fp64_pairs_fit_routes(dev, case):
+    """FP64 pairs apply the fit in FP64: GEMVs (mode 1) or FP64 MFMA GEMMs (modes 2-4).  Both
+    within 1e-10 of the oracle, and within 1e-12 of each other (summation order only)."""
+    name, make, (P, M) = next(c for c in CASES if c[0] == case)
+    s = make()
     ph = s.phys
-    plan = hs.Plan(ph.a, ph.eps1, ph.eps2, ph.kappa, 400, 600, pair_prec="fp64")
-    for mode in (2, 3, 4):
+    plan = hs.Plan(ph.a, ph.eps1, ph.eps2, ph.kappa, P, M, pair_prec="fp64")
+    ref = oracle.hsma_eval(_params(plan), s.x, s.y, s.z, s.q)
+    e_ref = oracle.energy(s.q, ref)
+    for mode in (3, 4):
         plan.set_fit(mode)
-        assert plan.fit_route() == 1
+        assert plan.fit_route() == 2
+    out = {}
+    for mode in (1, 2):
+        phi, E, _, _ = _single(plan, s, dev, mode)
+        out[mode] = (phi, E)
+        print(f"[{case} fp64 fit route {mode}] phi relL2 {_rel(phi, ref):.3e} E rel {abs(E - e_ref) / abs(e_ref):.2e}",
+              flush=True)
+        assert _rel(phi, ref) <= 1e-10
+        assert abs(E - e_ref) <= 1e-9 * abs(e_ref)
+    assert _rel(out[2][0], out[1][0]) <= 1e-12
+    assert abs(out[2][1] - out[1][1]) <= 1e-12 * abs(out[1][1])
     plan.close()
 
 
