@@ -685,6 +685,19 @@ def leg_batched(args, checks) -> dict:
     t_tune = time.perf_counter() - t_tune
     tuned_settings = group.settings()
 
+    def trial_lines(r):
+        out = []
+        for tr in r["trials"]:
+            diff = {k: v for k, v in tr["settings"].items() if v != default_settings[k]}
+            out.append({"changed": diff, "ms": tr["ms"]})
+        return out
+
+    tune_e["trials"] = trial_lines(tune_e)
+    tune_p["trials"] = trial_lines(tune_p)
+    for name, r in (("energies", tune_e), ("potentials", tune_p)):
+        log(f"bench[batched]: tuner, {name}: " + ", ".join(
+            f"{' '.join(f'{k}={v}' for k, v in t['changed'].items()) or 'default'} {t['ms']:.2f}" for t in r["trials"]))
+
     def energies_t(stream=None):
         group.energy(off, xb, yb, zb, qb, total_n=total, max_n=max_n, E=E, ws=tws, stream=stream)
 

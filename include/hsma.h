@@ -346,12 +346,18 @@ hsma_status hsma_group_apply_settings(hsma_group_t group, const hsma_launch_sett
  * synchronises the stream, creates HIP events and must not be captured into a graph.
  * Errors: those of hsma_energy_batched for the group's current settings; HSMA_EDEVICE. */
 #define HSMA_TUNE_FORCE 1
+#define HSMA_TUNE_MAX_TRIALS 32
+typedef struct {
+  hsma_launch_settings s;
+  double ms; /* mean time of one call; < 0: refused (its workspace exceeds ws_bytes) */
+} hsma_tune_trial;
 typedef struct {
   hsma_launch_settings chosen;
   double ms_start, ms_tuned; /* the call with the settings found on entry, and with the chosen
                                 ones (0 when taken from the cache) */
-  int timed;                 /* candidate settings timed */
+  int timed;                 /* settings timed, the entry settings included (0 from the cache) */
   int cached;                /* 1: applied from the cache without timing */
+  hsma_tune_trial trials[HSMA_TUNE_MAX_TRIALS]; /* the first min(timed, 32) trials, in order */
 } hsma_tune_result;
 hsma_status hsma_group_autotune(hsma_group_t group, int nsys, const int64_t *offsets, const int32_t *plan_of,
                                 int64_t total_n, int64_t max_n, const double *x, const double *y, const double *z,

@@ -68,9 +68,13 @@ class LaunchSettings(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class TuneTrial(C.Structure):
+    _fields_ = [("s", LaunchSettings), ("ms", C.c_double)]
+
+
 class TuneResult(C.Structure):
     _fields_ = [("chosen", LaunchSettings), ("ms_start", C.c_double), ("ms_tuned", C.c_double), ("timed", C.c_int),
-                ("cached", C.c_int)]
+                ("cached", C.c_int), ("trials", TuneTrial * 32)]
 
 
 class ServerInfo(C.Structure):
@@ -628,7 +632,8 @@ class Group:
             _dev_ptr(E, "E", nsys) if E is not None else None, w.ptr, w.nbytes, _stream_ptr(stream),
             1 if force else 0, C.byref(r)), "hsma_group_autotune")
         return {"chosen": r.chosen.as_dict(), "ms_start": r.ms_start, "ms_tuned": r.ms_tuned, "timed": r.timed,
-                "cached": bool(r.cached)}
+                "cached": bool(r.cached),
+                "trials": [{"settings": r.trials[i].s.as_dict(), "ms": r.trials[i].ms} for i in range(min(r.timed, 32))]}
 
     def profile(self, on: bool = True):
         _profile(self._h, on)

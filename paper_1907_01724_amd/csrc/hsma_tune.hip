@@ -204,6 +204,7 @@ extern "C" hsma_status hsma_group_autotune(hsma_group_t grp, int nsys, const int
     rc = time_call(c, a, b, reps, best_ms);
   }
   out->ms_start = best_ms;
+  if (rc == HSMA_OK) out->trials[0] = hsma_tune_trial{start, best_ms};
   const Dims dims = tune_dims(grp, phi != nullptr || E == nullptr, E != nullptr);
   int timed = 1;
   for (size_t d = 0; d < dims.size() && rc == HSMA_OK; ++d) {
@@ -216,6 +217,7 @@ extern "C" hsma_status hsma_group_autotune(hsma_group_t grp, int nsys, const int
       double ms = 0.0;
       rc = time_call(c, a, b, reps, ms);
       if (rc != HSMA_OK) break;
+      if (timed < HSMA_TUNE_MAX_TRIALS) out->trials[timed] = hsma_tune_trial{cand, ms};
       ++timed;
       if (ms > 0.0 && ms < 0.98 * best_ms) {
         best = cand;
