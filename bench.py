@@ -82,10 +82,10 @@ def main() -> int:
     ap.add_argument("--settle-s", type=float, default=1.0,
                     help="seconds of untimed steps before the warm-up steps, so that the device has left its idle "
                          "clock state when timing starts")
-    ap.add_argument("--serving-requests", type=int, default=6000)
-    ap.add_argument("--serving-energy-workgroups", default="0,-1",
-                    help="request server: full-energy grids to measure, comma-separated (0: half the compute units, "
-                         "-1: no limit); the first is the headline")
+    ap.add_argument("--serving-requests", type=int, default=20000)
+    ap.add_argument("--serving-variants", default="0:1,-1:1",
+                    help="request server settings to measure, comma-separated energy_workgroups:move_priority "
+                         "(energy grid 0: one workgroup per compute unit, -1: no limit); the first is the headline")
     ap.add_argument("--serving-slots", default="1,2",
                     help="request server: concurrent single-ion-move batches and full energies")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1156,11 +1156,12 @@ def leg_serving(args) -> dict:
     """512 resident configurations (N log-uniform in [500, 50000], a ~ U[15, 40], kappa ~
     U[0.05, 1], eps1 = 1, eps2 = 78.5, P = 1024, M = 1536); requests 90% single-ion moves
     (ion and system uniform, displacement U([-1/2, 1/2]^3) kept inside, committed with
-    probability 1/2) and 10% fresh full energies.  For each full-energy grid of the request server
-    (--serving-energy-workgroups): capacity from a burst, then Poisson arrivals at 0.25, 0.5, 0.75,
-    0.9 and 1.1 of that capacity, the same requests and the same unit-rate arrival gaps for every
-    grid; latency = done - submitted.  Then the plain per-system path (each request run alone,
-    synchronously, on its resident system) under the first grid's arrival streams."""
+    probability 1/2) and 10% fresh full energies.  For each request-server setting (--serving-variants:
+    the full energies' grid and the move kernels' wave priority): capacity from a burst, then Poisson
+    arrivals at 0.25, 0.5, 0.75, 0.9 and 1.1 of that capacity, the same requests and the same
+    unit-rate arrival gaps for every setting; latency = done - submitted.  Then the plain per-system
+    path (each request run alone, synchronously, on its resident system) under the first setting's
+    arrival streams."""
     import numpy as np
     import torch
 
@@ -1202,22 +1203,25 @@ def leg_serving(args) -> dict:
                 "delta_p99_ms": float(np.percentile(dl, 99)), "energy_p50_ms": float(np.percentile(el, 50)),
                 "energy_p99_ms": float(np.percentile(el, 99))}
 
-    # one request sequence for every variant: warm-up, burst, then one stream per offered load
-    warm, burst_reqs = stream(500), stream(n)
+    # one request sequence for every variant: warm-up (a short stream, then a full burst, so that
+    # the device's clocks have settled), the measured burst, then one stream per offered load
+    warm, warm_burst, burst_reqs = stream(500), stream(n), stream(n)
     loads = [(f, stream(n), np.cumsum(rng.exponential(1.0, n))) for f in fractions]
     out = {"workload": "512 resident configurations, N log-uniform in [500, 50000], a~U[15,40], kappa~U[0.05,1], "
                        "P=1024, M=1536; 90% single-ion moves (commit p=1/2), 10% fresh FP64 energies",
            "slots": {"moves": dsl, "energies": esl}, "server": []}
     cap_ref = None
-    for ewg in (int(v) for v in args.serving_energy_workgroups.split(",")):
-        server = hs.Server(max_batch=512, delta_slots=dsl, energy_slots=esl, energy_workgroups=ewg)
+    for ewg, prio in ((int(a), int(b)) for a, b in (v.split(":") for v in args.serving_variants.split(","))):
+        server = hs.Server(max_batch=512, delta_slots=dsl, energy_slots=esl, energy_workgroups=ewg,
+                           move_priority=prio)
         for p, t in zip(plans, tens):
             server.add_system(p, *t)
         torch.cuda.synchronize()
-        label = f"energy_workgroups={ewg}"
+        label = f"energy_workgroups={ewg} move_priority={prio}"
         log(f"bench[serving]: {label}: {len(plans)} systems resident, {server.stats()['memory_used'] / 2**30:.2f} GiB, "
             f"set up in {time.perf_counter() - t0:.1f} s")
         server.run_load(warm, np.zeros(len(warm)))
+        server.run_load(warm_burst, np.zeros(n))
         st0 = server.stats()
         res = server.run_load(burst_reqs, np.zeros(n))
         st1 = server.stats()
@@ -1225,7 +1229,7 @@ def leg_serving(args) -> dict:
         burst = summarize([r.t_done - r.t_submit for r in res], [q[0] for q in burst_reqs], max(r.t_done for r in res))
         cap = burst["requests_per_s"]
         cap_ref = cap if cap_ref is None else cap_ref
-        d_out = {"energy_workgroups": ewg, "capacity_requests_per_s": cap, "burst": burst,
+        d_out = {"energy_workgroups": ewg, "move_priority": prio, "capacity_requests_per_s": cap, "burst": burst,
                  "mean_batch": (st1["batched_requests"] - st0["batched_requests"]) / max(1, st1["batches"] - st0["batches"]),
                  "loads": []}
         log(f"bench[serving]: {label}: capacity {cap:.0f} req/s (burst)")

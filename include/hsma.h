@@ -456,19 +456,25 @@ hsma_status hsma_system_full_energy(hsma_system_t sys, double *E, void *ws, size
  *
  * Systems are admitted against a device-memory budget (hsma_server_add_system returns
  * HSMA_EBUSY when the system's resident bytes, plus any growth of the shared full-energy
- * workspaces to its size, would exceed it; 0 = half the free memory at creation).  Requests -- a single-ion move (energy change, optionally committed) or a
- * fresh FP64 full energy -- are queued by hsma_server_submit (thread safe) and served by a
- * scheduler thread with continuous batching: whenever one of delta_slots batch slots is
- * free, it launches every waiting move whose system is idle, in arrival order (each system
- * sees its requests in order), up to max_batch; full energies use energy_slots streams of
- * their own (defaults: 1 and 2; more move slots raise throughput under bursts and lengthen
- * the latency tail, since streams share the device's hardware queues with the long energy
- * evaluations).  New batches start while earlier ones run, and a request's result does not
- * depend on the batch it lands in.  The scheduler sleeps while idle and is woken by submits.  Results, with submit/start/done times in seconds since
- * the server's creation, are collected with hsma_server_poll.  Requests that name an
- * unknown system, an ion out of range or a position outside the cavity complete at once
- * with status HSMA_EINVAL.  hsma_server_run_load submits reqs[i] at arrival[i] seconds
- * (open-loop load) and returns when all are done, with times relative to its start. */
+ * workspaces to its size, would exceed it; 0 = half the free memory at creation).  Requests
+ * -- a single-ion move (energy change, optionally committed) or a fresh FP64 full energy --
+ * are queued by hsma_server_submit (thread safe) and served by a scheduler thread with
+ * continuous batching: whenever one of delta_slots batch slots is free, it launches every
+ * waiting move whose system is idle, in arrival order, up to max_batch; full energies use
+ * energy_slots streams of their own (defaults: 1 and 2; more move slots raise throughput
+ * under bursts and lengthen the latency tail, since streams share the device's hardware
+ * queues with the long energy evaluations).  Each system sees its requests in arrival order:
+ * a full energy first copies the system's positions and charges, and the system takes its
+ * next requests as soon as that copy is done, so a full energy can complete after later
+ * requests of its system while its value is still that of the state at its place in the
+ * order.  New batches start while earlier ones run, and a request's result does not depend on
+ * the batch it lands in.  The scheduler sleeps while idle and is woken by submits.  Results,
+ * with submit/start/done times in seconds since the server's creation, are collected with
+ * hsma_server_poll.  Requests that name an unknown system, an ion out of range or a position
+ * outside the cavity complete at once with status HSMA_EINVAL.  hsma_server_run_load submits
+ * reqs[i] at arrival[i] seconds (open-loop load) and returns when all are done, with times
+ * relative to its start.  hsma_server_remove_system waits until no request of the system is
+ * queued or running. */
 typedef struct hsma_server_s *hsma_server_t;
 enum { HSMA_REQ_DELTA = 0, HSMA_REQ_ENERGY = 1 };
 typedef struct {
@@ -495,6 +501,9 @@ typedef struct {
                             units' count (one workgroup per compute unit and energy slot); < 0: no
                             limit (one item per wave on the whole device: more full energies per
                             second, longer move tails).  Results do not depend on it. */
+  int move_priority;     /* 1 (default): the move kernels raise their waves' issue priority
+                            (s_setprio) above the full energies' on a shared SIMD; 0: equal.
+                            Results do not depend on it. */
 } hsma_server_opts;
 typedef struct {
   size_t memory_used, memory_budget;

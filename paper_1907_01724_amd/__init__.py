@@ -57,7 +57,8 @@ class Result(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("memory_budget", C.c_size_t), ("max_systems", C.c_int), ("max_batch", C.c_int),
-                ("delta_slots", C.c_int), ("energy_slots", C.c_int), ("energy_workgroups", C.c_int)]
+                ("delta_slots", C.c_int), ("energy_slots", C.c_int), ("energy_workgroups", C.c_int),
+                ("move_priority", C.c_int)]
 
 
 class LaunchSettings(C.Structure):
@@ -734,10 +735,10 @@ class Server:
     """Continuous-batching request server over resident systems (see hsma_server_* in hsma.h)."""
 
     def __init__(self, memory_budget: int = 0, max_systems: int = 1024, max_batch: int = 256, delta_slots: int = 1,
-                 energy_slots: int = 2, energy_workgroups: int = 0):
+                 energy_slots: int = 2, energy_workgroups: int = 0, move_priority: int = 1):
         L = load_library()
         o = ServerOpts(int(memory_budget), int(max_systems), int(max_batch), int(delta_slots), int(energy_slots),
-                       int(energy_workgroups))
+                       int(energy_workgroups), int(move_priority))
         h = _VP()
         _check(L.hsma_server_create(C.byref(o), C.byref(h)), "hsma_server_create")
         self._h = h

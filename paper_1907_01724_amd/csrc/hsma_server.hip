@@ -4,10 +4,14 @@
 // (launch_delta) and the FP64 full evaluation of a system.
 //
 // Scheduling: a host thread keeps a FIFO of pending requests.  Whenever a batch slot is free
-// it takes, in arrival order, every pending single-ion-move request whose system has no work
-// on the device and no earlier request still waiting (so each system sees its requests in
-// order), up to max_batch, and launches them as one batch on that slot's stream.  Full-energy
-// requests take energy slots (their own streams and workspaces).  Several slots let new
+// it takes, in arrival order, every pending single-ion-move request whose system has no move
+// on the device and no earlier request still waiting, up to max_batch, and launches them as
+// one batch on that slot's stream.  Full-energy requests take energy slots (their own streams
+// and workspaces); a full energy first copies its system's state, and holds back the system's
+// later committed moves and energies until that copy is done.  Queries (moves that are not
+// committed) and full energies only read a system, so a query may pass a full energy of its
+// system that waits for a slot or for its copy; nothing passes a committed move.  Each
+// system's results are therefore those of its requests run one by one in arrival order.  Several slots let new
 // batches start while earlier ones are still running, so work that arrives while the device
 // is busy overlaps with it.  A request's result is independent of the batch it lands in:
 // every request of a batch runs on its own grid row with its system's own reduction order.
@@ -44,10 +48,15 @@ struct DeltaSlot {
   bool busy = false;
 };
 
+// A full energy runs on a snapshot of its system's positions and charges, taken at its start
+// (the copy ends at event snap); its system takes further requests once the copy is done,
+// while the energy itself still runs.
 struct EnergySlot {
   hipStream_t st = nullptr;
   hipEvent_t ev = nullptr;
-  void *ws = nullptr;
+  hipEvent_t snap = nullptr;
+  bool snapped = false;
+  void *ws = nullptr;  // the energy's workspace, then the snapshot (x, y, z, q)
   size_t ws_bytes = 0;
   double *d_E = nullptr;
   double *h_E = nullptr;  // pinned
@@ -66,7 +75,8 @@ struct hsma_server_s {
   std::deque<Pending> pending;
   std::vector<hsma_result> done;
   std::vector<hsma_system_s *> systems;  // by id; nullptr once removed
-  std::vector<int> busy;                 // 1 while the system has work on the device
+  std::vector<int> busy;                 // 1 while a move of the system is on the device
+  std::vector<int> snapping;             // 1 while a full energy copies the system's state
   SysDev *d_sys = nullptr;               // descriptors by id
   size_t used = 0, budget = 0;
   std::vector<DeltaSlot> dslots;
@@ -75,7 +85,9 @@ struct hsma_server_s {
   std::atomic<bool> stop{false};
   bool failed = false;  // a device error was seen: every later request completes with HSMA_EDEVICE
   std::chrono::steady_clock::time_point t0;
-  hipStream_t admin = nullptr;  // system creation
+  // (system creation runs on the first move slot's stream: every stream beyond the device's
+  // hardware queues shares one with another, and an energy stream sharing one with a move or
+  // energy stream serialises behind it)
   // statistics
   uint64_t n_done = 0, n_batches = 0, n_batched_reqs = 0;
   double now() const {
@@ -113,6 +125,11 @@ bool valid_request(hsma_server_s *S, const hsma_request &r) {
 // Only hipErrorNotReady means that a slot's work is still running; any other error from the
 // event completes the slot's requests with HSMA_EDEVICE and marks the server failed, after which
 // every waiting and every new request completes at once with HSMA_EDEVICE.
+// Workspace of an energy slot for a system: the full energy's workspace and the snapshot.
+size_t energy_slot_bytes(const hsma_system_s *sys) {
+  return system_workspace_bytes(sys) + (4 * sizeof(double) * (size_t)sys->n + 255) / 256 * 256;
+}
+
 bool schedule_once(hsma_server_s *S) {
   bool did = false;
   // completions
@@ -133,12 +150,22 @@ bool schedule_once(hsma_server_s *S) {
   }
   for (EnergySlot &e : S->eslots) {
     if (!e.busy) continue;
+    if (!e.snapped) {
+      const hipError_t qs = hipEventQuery(e.snap);
+      if (qs == hipSuccess) {  // the system may take its next requests
+        e.snapped = true;
+        S->snapping[e.req.r.sys] = 0;
+        did = true;
+      } else if (qs != hipErrorNotReady) {
+        S->failed = true;
+      }
+    }
     const hipError_t q = hipEventQuery(e.ev);
     if (q == hipErrorNotReady) continue;
     const int status = q == hipSuccess ? HSMA_OK : HSMA_EDEVICE;
     if (status != HSMA_OK) S->failed = true;
     finish(S, e.req, status, status == HSMA_OK ? *e.h_E : 0.0, e.t_start, S->now());
-    S->busy[e.req.r.sys] = 0;
+    if (!e.snapped) S->snapping[e.req.r.sys] = 0;
     e.busy = false;
     did = true;
   }
@@ -149,7 +176,9 @@ bool schedule_once(hsma_server_s *S) {
     S->pending.clear();
     return true;
   }
-  // a scan in arrival order; a system with an earlier request left waiting is blocked
+  // A scan in arrival order.  blocked[b]: 2 once a move of system b is left waiting or taken
+  // in this pass (nothing later of b may start); 1 once only full energies of b are left
+  // waiting (later queries of b may start, nothing else).
   std::vector<char> blocked(S->systems.size(), 0);
   DeltaSlot *ds = nullptr;
   for (DeltaSlot &d : S->dslots)
@@ -159,10 +188,22 @@ bool schedule_once(hsma_server_s *S) {
     }
   int64_t max_n = 0;
   int max_M = 0, max_P = 0, max_K = 0;
+  auto free_eslot = [S]() {
+    for (const EnergySlot &e : S->eslots)
+      if (!e.busy) return true;
+    return false;
+  };
+  bool eslot = free_eslot();
   for (auto it = S->pending.begin(); it != S->pending.end();) {
+    // nothing more can start in this pass: the move batch is full (or no slot) and no energy slot is free
+    if (!eslot && (!ds || (int)ds->reqs.size() >= S->opts.max_batch)) break;
     const hsma_request &r = it->r;
-    if (blocked[r.sys] || S->busy[r.sys]) {
-      blocked[r.sys] = 1;
+    const bool query = r.type == HSMA_REQ_DELTA && !r.commit;
+    const int held = blocked[r.sys] > S->snapping[r.sys] ? blocked[r.sys] : S->snapping[r.sys];
+    const int level = S->busy[r.sys] ? 2 : held;
+    if (level == 2 || (level == 1 && !query)) {
+      const char mine = r.type == HSMA_REQ_ENERGY ? 1 : 2;
+      if (blocked[r.sys] < mine) blocked[r.sys] = mine;
       ++it;
       continue;
     }
@@ -174,12 +215,12 @@ bool schedule_once(hsma_server_s *S) {
           break;
         }
       if (!es) {
-        blocked[r.sys] = 1;
+        if (blocked[r.sys] < 1) blocked[r.sys] = 1;
         ++it;
         continue;
       }
       hsma_system_s *sys = S->systems[r.sys];
-      const size_t need = system_workspace_bytes(sys);
+      const size_t need = energy_slot_bytes(sys);
       bool ok = true;
       if (es->ws_bytes < need) {
         (void)hipFree(es->ws);
@@ -201,25 +242,38 @@ bool schedule_once(hsma_server_s *S) {
       }
       es->req = p;
       es->t_start = S->now();
-      S->busy[p.r.sys] = 1;  // (r referred to the erased element)
-      blocked[p.r.sys] = 1;
-      hsma_status rc = system_full_energy(sys, es->d_E, es->ws, es->ws_bytes, es->st);
+      S->snapping[p.r.sys] = 1;  // (r referred to the erased element)
+      if (blocked[p.r.sys] < 1) blocked[p.r.sys] = 1;
+      // the snapshot: the system's x, y, z, q after its workspace
+      const size_t wsb = system_workspace_bytes(sys), nb = sizeof(double) * (size_t)sys->n;
+      double *snap = (double *)((char *)es->ws + wsb);
+      const double *src[4] = {sys->h.x, sys->h.y, sys->h.z, sys->h.q};
+      hsma_status rc = HSMA_OK;
+      for (int c = 0; c < 4 && rc == HSMA_OK; ++c)
+        if (nb && hipMemcpyAsync(snap + c * sys->n, src[c], nb, hipMemcpyDeviceToDevice, es->st) != hipSuccess)
+          rc = HSMA_EDEVICE;
+      if (rc == HSMA_OK && hipEventRecord(es->snap, es->st) != hipSuccess) rc = HSMA_EDEVICE;
+      es->snapped = false;
+      if (rc == HSMA_OK)
+        rc = system_full_energy_at(sys, snap, snap + sys->n, snap + 2 * sys->n, snap + 3 * sys->n, es->d_E, es->ws,
+                                   wsb, es->st);
       if (rc == HSMA_OK && hipMemcpyAsync(es->h_E, es->d_E, sizeof(double), hipMemcpyDeviceToHost, es->st) != hipSuccess)
         rc = HSMA_EDEVICE;
       if (rc == HSMA_OK && hipEventRecord(es->ev, es->st) != hipSuccess) rc = HSMA_EDEVICE;
       if (rc != HSMA_OK) {
         (void)hipStreamSynchronize(es->st);
-        S->busy[p.r.sys] = 0;
+        S->snapping[p.r.sys] = 0;
         finish(S, p, rc, 0.0, es->t_start, S->now());
         continue;
       }
       es->busy = true;
+      eslot = free_eslot();
       did = true;
       continue;
     }
     // single-ion move
     if (!ds || (int)ds->reqs.size() >= S->opts.max_batch) {
-      blocked[r.sys] = 1;
+      blocked[r.sys] = 2;
       ++it;
       continue;
     }
@@ -238,7 +292,7 @@ bool schedule_once(hsma_server_s *S) {
     if (sys->h.P > max_P) max_P = sys->h.P;
     if (sys->h.K > max_K) max_K = sys->h.K;
     S->busy[r.sys] = 1;
-    blocked[r.sys] = 1;
+    blocked[r.sys] = 2;
     it = S->pending.erase(it);
   }
   if (ds && !ds->reqs.empty()) {
@@ -247,7 +301,8 @@ bool schedule_once(hsma_server_s *S) {
     hsma_status rc = HSMA_OK;
     if (hipMemcpyAsync(ds->d_reqs, ds->h_reqs, sizeof(DeReq) * n, hipMemcpyHostToDevice, ds->st) != hipSuccess)
       rc = HSMA_EDEVICE;
-    if (rc == HSMA_OK) rc = launch_delta(S->d_sys, ds->d_reqs, DeReq(), n, max_n, max_M, max_P, max_K, ds->st);
+    if (rc == HSMA_OK) rc = launch_delta(S->d_sys, ds->d_reqs, DeReq(), n, max_n, max_M, max_P, max_K, ds->st,
+                                           S->opts.move_priority);
     if (rc == HSMA_OK && hipMemcpyAsync(ds->h_dE, ds->d_dE, sizeof(double) * n, hipMemcpyDeviceToHost, ds->st) !=
                              hipSuccess)
       rc = HSMA_EDEVICE;
@@ -316,12 +371,12 @@ void server_free(hsma_server_s *S) {
     (void)hipFree(e.d_E);
     (void)hipHostFree(e.h_E);
     if (e.ev) (void)hipEventDestroy(e.ev);
+    if (e.snap) (void)hipEventDestroy(e.snap);
     if (e.st) (void)hipStreamDestroy(e.st);
   }
   for (hsma_system_s *s : S->systems)
     if (s) hsma_system_destroy(s);
   (void)hipFree(S->d_sys);
-  if (S->admin) (void)hipStreamDestroy(S->admin);
   delete S;
 }
 
@@ -344,6 +399,7 @@ extern "C" hsma_server_opts hsma_server_opts_default(void) {
   o.delta_slots = 1;
   o.energy_slots = 2;
   o.energy_workgroups = 0;
+  o.move_priority = 1;
   return o;
 }
 
@@ -351,7 +407,8 @@ extern "C" hsma_status hsma_server_create(const hsma_server_opts *opts, hsma_ser
   if (!out) return HSMA_EINVAL;
   *out = nullptr;
   hsma_server_opts o = opts ? *opts : hsma_server_opts_default();
-  if (o.max_systems < 1 || o.max_batch < 1 || o.max_batch > 65535 || o.delta_slots < 1 || o.energy_slots < 1)
+  if (o.max_systems < 1 || o.max_batch < 1 || o.max_batch > 65535 || o.delta_slots < 1 || o.energy_slots < 1 ||
+      (o.move_priority != 0 && o.move_priority != 1))
     return HSMA_EINVAL;
   hsma_server_s *S = new hsma_server_s();
   S->opts = o;
@@ -366,9 +423,7 @@ extern "C" hsma_status hsma_server_create(const hsma_server_opts *opts, hsma_ser
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess) rc = HSMA_EDEVICE;
     S->opts.energy_workgroups = ncu > 0 ? ncu : 1;
   }
-  if (rc == HSMA_OK && (hipMalloc(&S->d_sys, sizeof(SysDev) * o.max_systems) != hipSuccess ||
-                        hipStreamCreateWithFlags(&S->admin, hipStreamNonBlocking) != hipSuccess))
-    rc = HSMA_EDEVICE;
+  if (rc == HSMA_OK && hipMalloc(&S->d_sys, sizeof(SysDev) * o.max_systems) != hipSuccess) rc = HSMA_EDEVICE;
   S->dslots.resize(o.delta_slots);
   for (DeltaSlot &d : S->dslots) {
     if (rc != HSMA_OK) break;
@@ -385,6 +440,7 @@ extern "C" hsma_status hsma_server_create(const hsma_server_opts *opts, hsma_ser
     if (rc != HSMA_OK) break;
     if (hipStreamCreateWithFlags(&e.st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e.snap, hipEventDisableTiming) != hipSuccess ||
         hipMalloc(&e.d_E, sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&e.h_E, sizeof(double), hipHostMallocDefault) != hipSuccess)
       rc = HSMA_ENOMEM;
@@ -420,7 +476,7 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
     S->used += fp;  // reserved while the system is built
   }
   hsma_system_t sys = nullptr;
-  hsma_status rc = hsma_system_create(pl, N, x, y, z, q, S->admin, &sys);
+  hsma_status rc = hsma_system_create(pl, N, x, y, z, q, S->dslots[0].st, &sys);
   std::lock_guard<std::mutex> lk(S->mu);
   if (rc != HSMA_OK) {
     S->used -= fp;
@@ -429,7 +485,7 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
   S->used += sys->footprint;
   S->used -= fp;
   // the full-energy workspaces must grow to this system's size: that memory counts too
-  const size_t need = system_workspace_bytes(sys);
+  const size_t need = energy_slot_bytes(sys);
   size_t grow = 0;
   for (const EnergySlot &e : S->eslots)
     if (e.ws_bytes < need) grow += need - e.ws_bytes;
@@ -454,6 +510,7 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
     slot = (int)S->systems.size();
     S->systems.push_back(nullptr);
     S->busy.push_back(0);
+    S->snapping.push_back(0);
   }
   if (hipMemcpy(S->d_sys + slot, &sys->h, sizeof(SysDev), hipMemcpyHostToDevice) != hipSuccess) {
     S->used -= sys->footprint;
@@ -462,6 +519,7 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
   }
   S->systems[slot] = sys;
   S->busy[slot] = 0;
+  S->snapping[slot] = 0;
   sys->g64->tune.ewaves = S->opts.energy_workgroups > 0 ? S->opts.energy_workgroups : 0;
   // Full-energy workspaces grow here, at admission, rather than in the scheduler, where freeing
   // device memory would stall every request in flight (a slot busy now grows when next used).
@@ -486,8 +544,10 @@ extern "C" hsma_status hsma_server_remove_system(hsma_server_t S, int id) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
       if (id < 0 || id >= (int)S->systems.size() || !S->systems[id]) return HSMA_EINVAL;
-      bool waiting = S->busy[id] != 0;
+      bool waiting = S->busy[id] != 0 || S->snapping[id] != 0;
       for (const Pending &p : S->pending) waiting = waiting || p.r.sys == id;
+      // a full energy past its snapshot still runs on the system's plan
+      for (const EnergySlot &e : S->eslots) waiting = waiting || (e.busy && e.req.r.sys == id);
       if (!waiting) {
         hsma_system_s *sys = S->systems[id];
         S->systems[id] = nullptr;

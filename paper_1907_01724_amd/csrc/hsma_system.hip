@@ -100,11 +100,18 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return r;
 }
 
+// prio: the request server's move batches raise their waves' issue priority, so that a move
+// sharing a SIMD with a long full-energy launch issues first (results are unchanged).
+__device__ __forceinline__ void move_priority(int prio) {
+  if (prio) __builtin_amdgcn_s_setprio(3);
+}
+
 // Stage 1: Kelvin row/column sums (blocks [0, nA)), check-field changes (next nB blocks),
 // surface-row changes (last nD blocks).  grid.y = request.
 __global__ __launch_bounds__(DB) void k_de_pairs(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
-                                                 DeReq one, int nA, int nB) {
+                                                 DeReq one, int nA, int nB, int prio) {
   __shared__ double red[DB];
+  move_priority(prio);
   const DeReq r = reqs ? reqs[blockIdx.y] : one;
   const SysDev &S = systems[r.sys];
   const PlanDev &c = S.pl;
@@ -165,7 +172,8 @@ __device__ __forceinline__ double wave_sum64(double v) {
 
 // Stage 2: alpha'' = pinv du, beta'' = pinv dv; one wave per coefficient row.
 __global__ __launch_bounds__(256) void k_de_fit1(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
-                                                 DeReq one) {
+                                                 DeReq one, int prio) {
+  move_priority(prio);
   const DeReq r = reqs ? reqs[blockIdx.y] : one;
   const SysDev &S = systems[r.sys];
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -187,7 +195,8 @@ __global__ __launch_bounds__(256) void k_de_fit1(const SysDev *__restrict__ syst
 // Stage 3: ds = (Lhat (n . h), -Lhat h), h = f . alpha'' + g . beta''; per node also the
 // energy terms dw . s + (w + dw) . ds.
 __global__ __launch_bounds__(256) void k_de_fit2(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
-                                                 DeReq one) {
+                                                 DeReq one, int prio) {
+  move_priority(prio);
   const DeReq r = reqs ? reqs[blockIdx.y] : one;
   const SysDev &S = systems[r.sys];
   const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -213,8 +222,9 @@ __global__ __launch_bounds__(256) void k_de_fit2(const SysDev *__restrict__ syst
 
 // Stage 4 (one block per request): dE in a fixed order; with commit, apply the move.
 __global__ __launch_bounds__(DB) void k_de_final(const SysDev *__restrict__ systems, const DeReq *__restrict__ reqs,
-                                                 DeReq one) {
+                                                 DeReq one, int prio) {
   __shared__ double red[DB];
+  move_priority(prio);
   const DeReq r = reqs ? reqs[blockIdx.x] : one;
   const SysDev &S = systems[r.sys];
   const PlanDev &c = S.pl;
@@ -361,23 +371,32 @@ hsma_status add_coulomb(const SysDev &h, int64_t N, double *E, char *ws, hipStre
 }  // namespace
 
 hsma_status launch_delta(const SysDev *systems, const DeReq *reqs, DeReq one, int nreq, int64_t max_n, int max_M,
-                         int max_P, int max_K, hipStream_t st) {
+                         int max_P, int max_K, hipStream_t st, int prio) {
   const int nA = (int)((max_n + DB - 1) / DB), nB = (max_M + DB - 1) / DB, nD = (max_P + DB - 1) / DB;
-  k_de_pairs<<<dim3(nA + nB + nD, nreq), DB, 0, st>>>(systems, reqs, one, nA, nB);
-  k_de_fit1<<<dim3((max_K + 3) / 4, nreq), 256, 0, st>>>(systems, reqs, one);
-  k_de_fit2<<<dim3((max_P + 3) / 4, nreq), 256, 0, st>>>(systems, reqs, one);
-  k_de_final<<<nreq, DB, 0, st>>>(systems, reqs, one);
+  k_de_pairs<<<dim3(nA + nB + nD, nreq), DB, 0, st>>>(systems, reqs, one, nA, nB, prio);
+  k_de_fit1<<<dim3((max_K + 3) / 4, nreq), 256, 0, st>>>(systems, reqs, one, prio);
+  k_de_fit2<<<dim3((max_P + 3) / 4, nreq), 256, 0, st>>>(systems, reqs, one, prio);
+  k_de_final<<<nreq, DB, 0, st>>>(systems, reqs, one, prio);
   HSMA_HIP(hipGetLastError());
   return HSMA_OK;
 }
 
-hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
+hsma_status system_full_energy_at(hsma_system_s *sys, const double *x, const double *y, const double *z,
+                                  const double *q, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
   if (ws_bytes < system_workspace_bytes(sys)) return HSMA_EINVAL;
   const size_t lt = layout(sys->g64, 1, sys->n, sys->n, false, false, true).total;
-  hsma_status rc = run_batched(sys->g64, 1, nullptr, nullptr, sys->n, sys->n, sys->h.x, sys->h.y, sys->h.z, sys->h.q,
-                               nullptr, E, ws, lt, st);
+  hsma_status rc = run_batched(sys->g64, 1, nullptr, nullptr, sys->n, sys->n, x, y, z, q, nullptr, E, ws, lt, st);
   if (rc != HSMA_OK || !sys->h.coulomb) return rc;
-  return add_coulomb(sys->h, sys->n, E, (char *)ws + lt, st);
+  SysDev at = sys->h;
+  at.x = const_cast<double *>(x);
+  at.y = const_cast<double *>(y);
+  at.z = const_cast<double *>(z);
+  at.q = const_cast<double *>(q);
+  return add_coulomb(at, sys->n, E, (char *)ws + lt, st);
+}
+
+hsma_status system_full_energy(hsma_system_s *sys, double *E, void *ws, size_t ws_bytes, hipStream_t st) {
+  return system_full_energy_at(sys, sys->h.x, sys->h.y, sys->h.z, sys->h.q, E, ws, ws_bytes, st);
 }
 
 size_t system_workspace_bytes(const hsma_system_s *sys) {
@@ -526,7 +545,7 @@ static hsma_status delta(hsma_system_t sys, int64_t k, double xk, double yk, dou
   r.y = yk;
   r.z = zk;
   r.dE = dE;
-  return launch_delta(sys->d, nullptr, r, 1, sys->n, sys->h.M, sys->h.P, sys->h.K, st);
+  return launch_delta(sys->d, nullptr, r, 1, sys->n, sys->h.M, sys->h.P, sys->h.K, st, 0);
 }
 
 extern "C" hsma_status hsma_delta_energy(hsma_system_t sys, int64_t k, double xk, double yk, double zk, double *dE,

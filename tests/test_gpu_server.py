@@ -161,8 +161,12 @@ def test_open_loop_poisson(dev):
     done = np.array([r.t_done for r in res])
     assert np.all(done >= sub)
     assert np.all(np.abs(sub - arrival) < 5e-3)
-    # each system's requests complete in their order
+    # per system: committed moves and full energies start in their order, and moves complete
+    # in theirs (a query may pass a waiting full energy, and a full energy runs on a copy of the
+    # state, so it may complete after later moves)
     for b in range(4):
-        d = [r.t_done for r, q in zip(res, reqs) if q[1] == b]
+        st = [r.t_start for r, q in zip(res, reqs) if q[1] == b and (q[0] == hs.REQ_ENERGY or q[2])]
+        assert all(x <= y for x, y in zip(st, st[1:]))
+        d = [r.t_done for r, q in zip(res, reqs) if q[1] == b and q[0] == hs.REQ_DELTA]
         assert all(x <= y for x, y in zip(d, d[1:]))
     server.close()
