@@ -312,8 +312,9 @@ hsma_status hsma_group_set_fit(hsma_group_t group, int mode);
 int hsma_group_fit_route(hsma_group_t group, int nsys);
 
 /* Energy launch shape (the FP64 energy-only launch of hsma_energy / hsma_energy_batched):
- * block = 256 or 512 ions per block of the symmetric pair kernel, 0 (default) for 512 when
- * hsma_group_set_symmetric chose mode 3, else 256; workgroups = 0 (default): one item per
+ * block = 128, 256 or 512 ions per block of the symmetric pair kernel; 0 (default): 512 when
+ * hsma_group_set_symmetric chose mode 3, else 128 for launches whose block pairs of 256 would
+ * fill fewer than four rounds of the device's wave slots, else 256; workgroups = 0 (default): one item per
  * wave over the whole device; > 0: a persistent grid of that many workgroups (rounded up to a
  * multiple of the die count) taking items from per-die counters, the check sums persistent on
  * the same grid.  Energies depend on block only through the summation order (rounding) and

@@ -121,6 +121,7 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 // evaluation kernels.
 // ---------------------------------------------------------------------------------
 constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
+constexpr int64_t ETAIL_ROUNDS = 4;  // energy launches: blocks of 128 below this many rounds of wave slots
 constexpr int CTR_WORDS = 32, CTR_ENERGY = 8, CTR_CHECK = 16, CTR_EVAL = 24;
 struct Sched {
   int64_t *off, *ic, *ie, *fb, *pc, *pe, *is, *ec, *ctr;
@@ -2171,7 +2172,9 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
           kern<<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, q, wk, qr,
                                    grp->nodes64, qd, epair);
         };
-        if (L.sym_tb == 256)
+        if (L.sym_tb == 128)
+          persist ? run(k_energy64<2, true>) : run(k_energy64<2, false>);
+        else if (L.sym_tb == 256)
           persist ? run(k_energy64<4, true>) : run(k_energy64<4, false>);
         else
           persist ? run(k_energy64<8, true>) : run(k_energy64<8, false>);
@@ -2288,8 +2291,14 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.sch = 0;
   const int mode = grp->tune.symmetric;
   if (L.eonly && total_n > 0) {
-    // the energy kernel: blocks of 256 ions, or 512 when asked for; one FP64 value per item
-    const int64_t tb = grp->tune.eblock ? grp->tune.eblock : (mode == 3 ? 512 : 256);
+    // the energy kernel: blocks of 256 ions; of 128 when the launch's block pairs of 256 would
+    // fill fewer than ETAIL_ROUNDS rounds of the device's wave slots (more, smaller items fill
+    // the end of a small launch); 512 with symmetric mode 3; or as set.  One FP64 value per item.
+    const int64_t pairs256 = (total_n / 256 + nsys) * (cdiv(max_n, 256) + 1) / 2;
+    const int64_t tb = grp->tune.eblock                                    ? grp->tune.eblock
+                       : mode == 3                                         ? 512
+                       : pairs256 < ETAIL_ROUNDS * (int64_t)g->ncu * WAVES * 8 ? 128
+                                                                           : 256;
     const int64_t bmax = cdiv(max_n, tb);
     const int64_t sch = cdiv(P, (2 * tb) / 3);
     const int64_t sb = total_n / tb + nsys;

@@ -521,6 +521,9 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
   S->busy[slot] = 0;
   S->snapping[slot] = 0;
   sys->g64->tune.ewaves = S->opts.energy_workgroups > 0 ? S->opts.energy_workgroups : 0;
+  // Full energies in blocks of 256 ions whatever the system's size: blocks of 128 finish a lone
+  // energy sooner, but beside the move batches they raised the moves' p99 several times (measured)
+  sys->g64->tune.eblock = 256;
   // Full-energy workspaces grow here, at admission, rather than in the scheduler, where freeing
   // device memory would stall every request in flight (a slot busy now grows when next used).
   for (EnergySlot &e : S->eslots) {

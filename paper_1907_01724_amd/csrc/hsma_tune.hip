@@ -31,7 +31,8 @@ hsma_launch_settings settings_of(const hsma_group_s *g) {
 bool settings_valid(const hsma_launch_settings &s) {
   return (s.persistent == 0 || s.persistent == 1) && s.target_items >= 64 && s.target_items <= (1 << 22) &&
          s.symmetric >= 0 && s.symmetric <= 3 && s.sym_order >= 0 && s.sym_order <= 2 && s.fit >= 0 && s.fit <= 4 &&
-         (s.energy_block == 0 || s.energy_block == 256 || s.energy_block == 512) && s.energy_workgroups >= 0 &&
+         (s.energy_block == 0 || s.energy_block == 128 || s.energy_block == 256 || s.energy_block == 512) &&
+         s.energy_workgroups >= 0 &&
          s.energy_workgroups <= (1 << 20);
 }
 
@@ -104,7 +105,7 @@ Dims tune_dims(const hsma_group_s *g, bool pot, bool energy) {
   }
   if (energy) {
     const int ncu = g->geo->ncu;
-    d.push_back({&hsma_launch_settings::energy_block, {256, 512}});
+    d.push_back({&hsma_launch_settings::energy_block, {0, 128, 256, 512}});
     d.push_back({&hsma_launch_settings::energy_workgroups, {0, ncu, 2 * ncu, 4 * ncu}});
   }
   d.push_back({&hsma_launch_settings::persistent, {0, 1}});
@@ -143,7 +144,8 @@ extern "C" size_t hsma_group_autotune_workspace_bytes(hsma_group_t grp, int nsys
 }
 
 extern "C" hsma_status hsma_group_set_energy_launch(hsma_group_t grp, int block, int workgroups) {
-  if (!grp || (block != 0 && block != 256 && block != 512) || workgroups < 0 || workgroups > (1 << 20))
+  if (!grp || (block != 0 && block != 128 && block != 256 && block != 512) || workgroups < 0 ||
+      workgroups > (1 << 20))
     return HSMA_EINVAL;
   grp->tune.eblock = block;
   grp->tune.ewaves = workgroups;

@@ -81,7 +81,8 @@ def batch(dev):
 
 CASES = [("persistent", 1), ("symmetric", 0), ("symmetric", 2), ("symmetric", 3), ("sym_order", 1),
          ("sym_order", 2), ("target_items", 4096), ("target_items", 65536), ("fit", 1), ("fit", 2), ("fit", 4),
-         ("energy_block", 256), ("energy_block", 512), ("energy_workgroups", 8), ("energy_workgroups", 256)]
+         ("energy_block", 128), ("energy_block", 256), ("energy_block", 512), ("energy_workgroups", 8),
+         ("energy_workgroups", 256)]
 
 
 @pytest.mark.parametrize("field,value", CASES)
@@ -182,7 +183,7 @@ def test_graph_replay_of_tuned_persistent_call(batch):
 def test_invalid_settings(batch):
     g = batch["group"]
     for field, bad in (("persistent", 2), ("target_items", 10), ("symmetric", 4), ("sym_order", 3), ("fit", 5),
-                       ("energy_block", 128), ("energy_workgroups", -1)):
+                       ("energy_block", 64), ("energy_workgroups", -1)):
         with pytest.raises(hs.HsmaError) as ei:
             g.apply_settings(dict(batch["default"], **{field: bad}))
         assert ei.value.code == 1
