@@ -462,9 +462,12 @@ hsma_status hsma_system_full_energy(hsma_system_t sys, double *E, void *ws, size
  * are queued by hsma_server_submit (thread safe) and served by a scheduler thread with
  * continuous batching: whenever one of delta_slots batch slots is free, it launches every
  * waiting move whose system is idle, in arrival order, up to max_batch; full energies use
- * energy_slots streams of their own (defaults: 1 and 2; more move slots raise throughput
- * under bursts and lengthen the latency tail, since streams share the device's hardware
- * queues with the long energy evaluations).  Each system sees its requests in arrival order:
+ * energy_slots streams of their own (defaults: 1 and 2).  Every slot's stream is created with
+ * a hardware queue of its own (a CU mask enabling every CU), so that a move batch never waits
+ * in a queue behind a full energy or behind other work of the process; such streams
+ * synchronise with the legacy default stream (stream 0): device work enqueued there while the
+ * server runs waits for the server's work in flight, and the reverse, so the caller's own
+ * device work belongs on other streams.  Each system sees its requests in arrival order:
  * a full energy first copies the system's positions and charges, and the system takes its
  * next requests as soon as that copy is done, so a full energy can complete after later
  * requests of its system while its value is still that of the state at its place in the

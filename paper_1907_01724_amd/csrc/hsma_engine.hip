@@ -121,6 +121,9 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 // evaluation kernels.
 // ---------------------------------------------------------------------------------
 constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
+// Energy pairs whose source lies within r <= NEAR_R a take the expanded form of the squared image
+// distance (see energy_item); sources nearer the interface take the exact form.
+constexpr double NEAR_R = 0.98;
 constexpr int64_t ETAIL_ROUNDS = 4;  // energy launches: blocks of 128 below this many rounds of wave slots
 constexpr int CTR_WORDS = 32, CTR_ENERGY = 8, CTR_CHECK = 16, CTR_EVAL = 24;
 struct Sched {
@@ -294,6 +297,95 @@ __device__ __forceinline__ void fill_maps(const Sched &S, int nsys, int *__restr
 }
 
 // ---------------------------------------------------------------------------------
+// Energy launches place each system's ions with r > NEAR_R a after its other ions, keeping
+// the order within each part, so that the energy kernel's source blocks below the boundary
+// hold no ion near the interface (see energy_item).  Per finish block: the count of such ions
+// (k_near_count), then per system the start of each block's part of either kind (k_near_scan),
+// then each ion's packed position (partition_rank, in k_pack).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ bool near_interface(double x, double y, double z, double a) {
+  return x * x + y * y + z * z > (NEAR_R * a) * (NEAR_R * a);  // false for non-finite input
+}
+
+__global__ __launch_bounds__(FINB) void k_near_count(int nsys, const int64_t *__restrict__ base,
+                                                     const PlanDev *__restrict__ plans,
+                                                     const int32_t *__restrict__ plan_of, const double *__restrict__ x,
+                                                     const double *__restrict__ y, const double *__restrict__ z,
+                                                     int *__restrict__ cnt) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  if (!sched_ok(S)) return;
+  const int64_t f = blockIdx.x;
+  if (f >= S.fb[nsys]) return;  // uniform across the block
+  const int b = system_of(S.fb, nsys, f);
+  const int64_t lo = S.off[b], n = S.off[b + 1] - lo, il = (f - S.fb[b]) * FINB + threadIdx.x;
+  const double a = plans[plan_of ? plan_of[b] : 0].a;
+  const bool nr = il < n && near_interface(x[lo + il], y[lo + il], z[lo + il], a);
+  const int c = __syncthreads_count(nr);
+  if (threadIdx.x == 0) cnt[f] = c;
+}
+
+// One block per system: its ions far from the interface first, then the others, each part in
+// the order of the finish blocks; block-wide scans over the system's finish blocks, 256 at a time.
+__global__ __launch_bounds__(256) void k_near_scan(int nsys, const int64_t *__restrict__ base,
+                                                   const int *__restrict__ cnt, int64_t *__restrict__ farst,
+                                                   int64_t *__restrict__ nearst, int64_t *__restrict__ nfar) {
+  Sched S(const_cast<int64_t *>(base), nsys);
+  __shared__ int64_t sn[256], sf[256];
+  if (!sched_ok(S)) return;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t n = S.off[b + 1] - S.off[b], f0 = S.fb[b], f1 = S.fb[b + 1];
+  int64_t tot = 0;
+  for (int64_t f = f0 + t; f < f1; f += 256) tot += cnt[f];
+  sn[t] = tot;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) sn[t] += sn[t + o];
+    __syncthreads();
+  }
+  const int64_t nf = n - sn[0];
+  if (t == 0) nfar[b] = nf;
+  __syncthreads();
+  int64_t cf = 0, cn = nf;  // starts of the next chunk's far and near parts
+  for (int64_t c0 = f0; c0 < f1; c0 += 256) {
+    const int64_t f = c0 + t;
+    const int64_t m = f < f1 ? ((n - (f - f0) * FINB) < FINB ? n - (f - f0) * FINB : FINB) : 0;  // ions of block f
+    const int64_t vn = f < f1 ? cnt[f] : 0, vf = m - vn;
+    sn[t] = vn;
+    sf[t] = vf;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {  // inclusive scans
+      const int64_t an = t >= o ? sn[t - o] : 0, af = t >= o ? sf[t - o] : 0;
+      __syncthreads();
+      sn[t] += an;
+      sf[t] += af;
+      __syncthreads();
+    }
+    if (f < f1) {
+      farst[f] = cf + sf[t] - vf;
+      nearst[f] = cn + sn[t] - vn;
+    }
+    cf += sf[255];
+    cn += sn[255];
+    __syncthreads();
+  }
+}
+
+// The packed position within its system of an ion of finish block f (all threads of the block
+// take part; the valid ions are the block's first threads): its part's start plus the ions of
+// the same kind before it in the block.
+__device__ __forceinline__ int64_t partition_rank(bool nr, int64_t far0, int64_t near0) {
+  __shared__ int wn[FINB / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(nr);
+  if (lane == 0) wn[wv] = __popcll(bal);
+  __syncthreads();
+  int below = 0;
+  for (int k = 0; k < wv; ++k) below += wn[k];
+  below += __popcll(bal & ((1ull << lane) - 1ull));
+  return nr ? near0 + below : far0 + ((int)threadIdx.x - below);
+}
+
+// ---------------------------------------------------------------------------------
 // Kelvin images and packing: one finish block (256 ions of one system) per block.
 // ---------------------------------------------------------------------------------
 // Also fills the item -> system maps the later kernels of the call read.
@@ -307,8 +399,10 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
                                               typename PT<MODE>::T4 *__restrict__ tgt,
                                               typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
                                               typename PT<MODE>::T *__restrict__ wk, double *__restrict__ rk,
-                                              double *__restrict__ qr, double4 *__restrict__ sfield,
-                                              float4 *__restrict__ tlo,
+                                              double *__restrict__ qr, double4 *__restrict__ emx,
+                                              double2 *__restrict__ ew, const int64_t *__restrict__ farst,
+                                              const int64_t *__restrict__ nearst, double *__restrict__ qpk,
+                                              double4 *__restrict__ sfield, float4 *__restrict__ tlo,
                                               float4 *__restrict__ ilo, int *__restrict__ flag) {
   using T4 = typename PT<MODE>::T4;
   using T = typename PT<MODE>::T;
@@ -316,32 +410,40 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   if (!sched_ok(S)) return;
   fill_maps(S, nsys, sys_c, sys_e, sys_f);
   const int64_t f = blockIdx.x;
-  if (f >= S.fb[nsys]) return;
+  if (f >= S.fb[nsys]) return;  // uniform across the block
   const int b = system_of(S.fb, nsys, f);
   const int64_t il = (f - S.fb[b]) * FINB + threadIdx.x;
   const int64_t lo = S.off[b], n = S.off[b + 1] - lo;
-  if (il >= n) return;
-  const int64_t i = lo + il;
+  const bool in = il < n;
+  const int64_t i = lo + (in ? il : 0);
   const PlanDev c = plans[plan_of ? plan_of[b] : 0];
   const double xi = x[i], yi = y[i], zi = z[i], qi = q[i];
+  // packed position: the ion's own, or after its system's far ions when it lies near the interface
+  const int64_t d = farst ? lo + partition_rank(in && near_interface(xi, yi, zi, c.a), farst[f], nearst[f]) : i;
+  if (!in) return;
+  if (qpk) qpk[d] = qi;
   const double r2 = xi * xi + yi * yi + zi * zi;
   const double r = sqrt(r2);
   const bool ok = isfinite(xi) && isfinite(yi) && isfinite(zi) && isfinite(qi) && r < c.a;
   if (!ok) {
     atomicOr(flag, 1);
-    img[i] = make4<T4>(0.0, 0.0, 2.0 * c.far, 0.0);
-    tgt[i] = make4<T4>(0.0, 0.0, 0.0, 0.0);
-    srcw[i] = (T)0;
-    self[i] = 0.0;
+    img[d] = make4<T4>(0.0, 0.0, 2.0 * c.far, 0.0);
+    tgt[d] = make4<T4>(0.0, 0.0, 0.0, 0.0);
+    srcw[d] = (T)0;
+    self[d] = 0.0;
     if (wk) {
-      wk[i] = (T)0;
-      rk[i] = 0.0;
+      wk[d] = (T)0;
+      rk[d] = 0.0;
     }
-    if (qr) qr[i] = 0.0;
-    if (sfield) sfield[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (qr) qr[d] = 0.0;
+    if (emx) {
+      emx[d] = make_double4(0.0, 0.0, 0.0, 0.0);
+      ew[d] = make_double2(0.0, 0.0);
+    }
+    if (sfield) sfield[d] = make_double4(0.0, 0.0, 0.0, 0.0);
     if (tlo) {
-      tlo[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      ilo[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      tlo[d] = make_float4(0.f, 0.f, 0.f, 0.f);
+      ilo[d] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     return;
   }
@@ -368,27 +470,37 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
   // own image: q_K / (4 pi eps1 |x - r_K|) with |x - r_K| = (a^2 - r^2) / r, written so that it
   // stays regular at r = 0 and keeps FP64 accuracy as r -> a
   const double sp = qp / c.a * (c.gamma * c.a2 + 0.5 * c.dbar * (c.Rtau * r - c.a2)) / ((c.a - r) * (c.a + r));
-  self[i] = sp;
+  self[d] = sp;
   if (sfield) {
     // its field: q'_K (x - r_K) / |x - r_K|^3 with x - r_K = -x (a^2 - r^2) / r^2, i.e.
     // -x times the own-image potential over (a^2 - r^2); zero at the centre
     const double e = -sp / ((c.a - r) * (c.a + r));
-    sfield[i] = make_double4(e * xi, e * yi, e * zi, 0.0);
+    sfield[d] = make_double4(e * xi, e * yi, e * zi, 0.0);
   }
-  img[i] = make4<T4>(kx, ky, kz, qk);
-  tgt[i] = make4<T4>(xi, yi, zi, qp);
+  img[d] = make4<T4>(kx, ky, kz, qk);
+  tgt[d] = make4<T4>(xi, yi, zi, qp);
   if (tlo) {  // what FP32 rounding left of each coordinate, so that pair differences keep ~2^-48 a
-    tlo[i] = make_float4((float)(xi - (double)(float)xi), (float)(yi - (double)(float)yi),
+    tlo[d] = make_float4((float)(xi - (double)(float)xi), (float)(yi - (double)(float)yi),
                          (float)(zi - (double)(float)zi), 0.f);
-    ilo[i] = make_float4((float)(kx - (double)(float)kx), (float)(ky - (double)(float)ky),
+    ilo[d] = make_float4((float)(kx - (double)(float)kx), (float)(ky - (double)(float)ky),
                          (float)(kz - (double)(float)kz), 0.f);
   }
-  srcw[i] = (T)(qp * r / c.a);
+  srcw[d] = (T)(qp * r / c.a);
   if (wk) {
-    wk[i] = (T)(qk * reff);  // c0 q_K r: the ion's image strength times its radius
-    rk[i] = 1.0 / reff;
+    wk[d] = (T)(qk * reff);  // c0 q_K r: the ion's image strength times its radius
+    rk[d] = 1.0 / reff;
   }
-  if (qr) qr[i] = qi / reff;  // the charge over the radius (energy sums)
+  if (qr) qr[d] = qi / reff;  // the charge over the radius (energy sums)
+  if (emx) {
+    // The expanded pair form of the energy kernel (see energy_item): the position whose Kelvin
+    // point is the image (x itself, or the stand-in's) scaled by -2/a, and (r/a)^2; the weights
+    // c0 q_K r / a^2 and q / a^2 of the two pair sums.
+    const double ex = r >= c.rmin ? xi : kx * reff * reff / c.a2, ey = r >= c.rmin ? yi : ky * reff * reff / c.a2,
+                 ez = r >= c.rmin ? zi : kz * reff * reff / c.a2;
+    const double u = (reff / c.a) * (reff / c.a);
+    emx[d] = make_double4(-2.0 * ex / c.a, -2.0 * ey / c.a, -2.0 * ez / c.a, u);
+    ew[d] = make_double2(qk * reff / c.a2, qi / c.a2);
+  }
 }
 
 // The device's accelerator dies: gfx950 (MI355X) has 8, each with its own L2, and places
@@ -1700,21 +1812,34 @@ __device__ __forceinline__ void block_pair(int64_t loc, int64_t B, int &I, int &
   J = __builtin_amdgcn_readfirstlane((int)(r + (loc - (r * B - r * (r - 1) / 2))));
 }
 
+// The energy kernel's expanded pair form: per source (-2x/a, -2y/a, -2z/a, (r/a)^2) and the two
+// weights, the plans (for 1/a of the targets), and per system the count of its ions far from the
+// interface (packed first).
+struct EnergyExt {
+  const double4 *emx;
+  const double2 *ew;
+  const PlanDev *plans;
+  const int64_t *nfar;
+};
+
 template <int R>
 __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int sch, int mono, const Sched &S, int lane,
                                             const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
                                             const double4 *__restrict__ tgt, const double4 *__restrict__ img,
                                             const double *__restrict__ q, const double *__restrict__ wk,
                                             const double *__restrict__ qr, const double4 *__restrict__ nodes,
-                                            const double2 *__restrict__ qd, double *__restrict__ epair);
+                                            const double2 *__restrict__ qd, double *__restrict__ epair,
+                                            const EnergyExt ex);
 
+// The launch bound caps the registers at five waves per SIMD (two for blocks of 512 ions): both
+// the unbounded kernel and caps of six or seven waves measured slower.
 template <int R, bool PERSIST>
-__global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int mono, const int64_t *__restrict__ base,
-                                                  const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
-                                                  const double4 *__restrict__ tgt, const double4 *__restrict__ img,
-                                                  const double *__restrict__ q, const double *__restrict__ wk,
-                                                  const double *__restrict__ qr, const double4 *__restrict__ nodes,
-                                                  const double2 *__restrict__ qd, double *__restrict__ epair) {
+__global__ __launch_bounds__(TPB, (R == 8 ? 2 : 5)) void k_energy64(
+    int nsys, int P, int sch, int mono, const int64_t *__restrict__ base, const int *__restrict__ sys_e,
+    const int32_t *__restrict__ plan_of, const double4 *__restrict__ tgt, const double4 *__restrict__ img,
+    const double *__restrict__ q, const double *__restrict__ wk, const double *__restrict__ qr,
+    const double4 *__restrict__ nodes, const double2 *__restrict__ qd, double *__restrict__ epair,
+    const EnergyExt ex) {
   Sched S(const_cast<int64_t *>(base), nsys);
   const int lane = threadIdx.x & 63, w = wave_id();
   if (!sched_ok(S)) return;
@@ -1722,7 +1847,7 @@ __global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int 
   if constexpr (!PERSIST) {  // one item per wave
     const int64_t item = uniform64(xcd_item(w));
     if (item < total)
-      energy_item<R>(item, nsys, P, sch, mono, S, lane, sys_e, plan_of, tgt, img, q, wk, qr, nodes, qd, epair);
+      energy_item<R>(item, nsys, P, sch, mono, S, lane, sys_e, plan_of, tgt, img, q, wk, qr, nodes, qd, epair, ex);
     return;
   } else {
   // persistent: claims of EG items from this die's counter until the die's items run out
@@ -1735,7 +1860,8 @@ __global__ __launch_bounds__(TPB) void k_energy64(int nsys, int P, int sch, int 
     for (int g = 0; g < EG; ++g) {
       const int64_t item = die_item(x, t + g);
       if (item < total)
-        energy_item<R>(item, nsys, P, sch, mono, S, lane, sys_e, plan_of, tgt, img, q, wk, qr, nodes, qd, epair);
+        energy_item<R>(item, nsys, P, sch, mono, S, lane, sys_e, plan_of, tgt, img, q, wk, qr, nodes, qd, epair,
+                       ex);
     }
   }
   }
@@ -1749,7 +1875,7 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
                                             const double4 *__restrict__ img, const double *__restrict__ q,
                                             const double *__restrict__ wk, const double *__restrict__ qr,
                                             const double4 *__restrict__ nodes, const double2 *__restrict__ qd,
-                                            double *__restrict__ epair) {
+                                            double *__restrict__ epair, const EnergyExt ex) {
   constexpr int TB = 64 * R;
   constexpr int RS = R / SYM_SH;
   constexpr double FAR_TARGET = 3.0e18;  // stand-in position of an empty target lane (zero charge)
@@ -1843,16 +1969,49 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
         }
       }
     } else {
-      const double *cr = qr + lo;
-      for (int j = j0; j < j1; ++j) {
-        const double4 v = im[j];
-        const double cj = cr[j];
+      // Off-diagonal block, in units of a.  When every source of block J lies at r_j <= NEAR_R a
+      // (the energy launch packs the ions nearer the interface last), the squared image distance
+      // times (r_j/a)^2 is expanded, D = (r_i/a)^2 (r_j/a)^2 + 1 - 2 (x_i/a).(x_j/a) (the identity
+      // behind the symmetric form), and 1/|x_i - r_K,j| = (r_j/a^2) D^-1/2 with r_j/a^2 folded
+      // into the weights: four operations instead of six.  D >= (1 - r_j/a)^2 >= 4e-4 there, so
+      // its rounding stays below about 1e-12 relative.  Other blocks take the differences
+      // x_i/a - r_K,j/a, with 1/a joining their weights.
+      const double ia = 1.0 / ex.plans[plan_of ? plan_of[b] : 0].a;
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          const double dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
-          const double ri = rinv2(dx * dx + dy * dy + dz * dz);
-          s1[k] = fma(v.w, ri, s1[k]);
-          s2[k] = fma(cj, ri, s2[k]);
+      for (int k = 0; k < R; ++k) {
+        tx[k] *= ia;
+        ty[k] *= ia;
+        tz[k] *= ia;
+      }
+      if ((int64_t)j1 <= ex.nfar[b]) {
+        const double4 *em = ex.emx + lo;
+        const double2 *ewt = ex.ew + lo;
+        double uu[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) uu[k] = fma(tx[k], tx[k], fma(ty[k], ty[k], tz[k] * tz[k]));
+        for (int j = j0; j < j1; ++j) {
+          const double4 m = em[j];
+          const double2 wj = ewt[j];
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double d = fma(tx[k], m.x, fma(ty[k], m.y, fma(tz[k], m.z, fma(uu[k], m.w, 1.0))));
+            const double ri = rinv2(d);
+            s1[k] = fma(wj.x, ri, s1[k]);
+            s2[k] = fma(wj.y, ri, s2[k]);
+          }
+        }
+      } else {
+        const double *cr = qr + lo;
+        for (int j = j0; j < j1; ++j) {
+          const double4 v = im[j];
+          const double vx = v.x * ia, vy = v.y * ia, vz = v.z * ia, w1 = v.w * ia, w2 = cr[j] * ia;
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double dx = tx[k] - vx, dy = ty[k] - vy, dz = tz[k] - vz;
+            const double ri = rinv2(dx * dx + dy * dy + dz * dz);
+            s1[k] = fma(w1, ri, s1[k]);
+            s2[k] = fma(w2, ri, s2[k]);
+          }
         }
       }
     }
@@ -2091,11 +2250,21 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
                                : SYM_TAIL_ROUNDS * g->ncu * WAVES * grp->tune.occ_sym[L.sym_tb == 512];
   k_schedule<<<1, sched_t, 0, st>>>(nsys, offsets, plan_of, bd, M, Pe, L.chc, L.che, L.sym_tb, L.sch, sym_tail,
                                     (L.eonly ? 1 : 0) + 16 * L.prec, base, grp->flag);
+  if (L.eonly && L.fin > 0) {  // the energy launch packs the ions near the interface last
+    k_near_count<<<(int)L.fin, FINB, 0, st>>>(nsys, base, plans, plan_of, x, y, z, (int *)(ws + L.ncnt));
+    k_near_scan<<<nsys, 256, 0, st>>>(nsys, base, (const int *)(ws + L.ncnt), (int64_t *)(ws + L.farst),
+                                      (int64_t *)(ws + L.nearst), (int64_t *)(ws + L.nfar));
+  }
   if (L.fin > 0)
     k_pack<MODE><<<(int)L.fin, 256, 0, st>>>(nsys, base, sys_c, sys_e, sys_f, plans, plan_of, x, y, z, q, img, tgt,
                                              srcw, self,
                                              (T *)(ws + L.wk), (double *)(ws + L.rk),
                                              L.eonly ? (double *)(ws + L.qr) : nullptr,
+                                             L.eonly ? (double4 *)(ws + L.emx) : nullptr,
+                                             L.eonly ? (double2 *)(ws + L.ew) : nullptr,
+                                             L.eonly ? (const int64_t *)(ws + L.farst) : nullptr,
+                                             L.eonly ? (const int64_t *)(ws + L.nearst) : nullptr,
+                                             L.eonly ? (double *)(ws + L.qpk) : nullptr,
                                              L.field ? (double4 *)(ws + L.sfield) : nullptr,
                                              L.lo ? (float4 *)(ws + L.tlo) : nullptr,
                                              L.lo ? (float4 *)(ws + L.ilo) : nullptr, grp->flag);
@@ -2168,9 +2337,12 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
                                     : (unsigned)(cdiv(cdiv(L.items_e, WAVES), NXCD * XQ) * NXCD * XQ);
         const double *wk = (const double *)(ws + L.wk);
         const double *qr = (const double *)(ws + L.qr);
+        const double *qpk = (const double *)(ws + L.qpk);
         auto run = [&](auto kern) {
-          kern<<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, q, wk, qr,
-                                   grp->nodes64, qd, epair);
+          kern<<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, qpk, wk, qr,
+                                   grp->nodes64, qd, epair,
+                                   EnergyExt{(const double4 *)(ws + L.emx), (const double2 *)(ws + L.ew), plans,
+                                             (const int64_t *)(ws + L.nfar)});
         };
         if (L.sym_tb == 128)
           persist ? run(k_energy64<2, true>) : run(k_energy64<2, false>);
@@ -2181,7 +2353,8 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       }
       prof_end(pr, st);
       pr = prof_begin(grp, ST_FINISH, st);
-      if (L.fin > 0) k_self_energy<<<(int)L.fin, FINB, 0, st>>>(nsys, base, sys_f, self, q, epart);
+      if (L.fin > 0)
+        k_self_energy<<<(int)L.fin, FINB, 0, st>>>(nsys, base, sys_f, self, (const double *)(ws + L.qpk), epart);
       double *echunk = (double *)(ws + L.echunk);
       if (L.echunks > 0)
         k_energy_chunks<<<(unsigned)L.echunks, 256, 0, st>>>(nsys, Pe, L.sym_tb, L.sch, base, epair, echunk);
@@ -2362,6 +2535,13 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
   L.eval_part = take(L.eonly ? sizeof(double) * (size_t)L.items_e
                              : (field ? sizeof(double4) : sizeof(double)) * (size_t)L.parts_e);
   L.qr = L.eonly ? take(sizeof(double) * (size_t)total_n) : 0;
+  L.emx = L.eonly ? take(sizeof(double4) * (size_t)total_n) : 0;
+  L.ew = L.eonly ? take(sizeof(double2) * (size_t)total_n) : 0;
+  L.ncnt = L.eonly ? take(sizeof(int) * (size_t)L.fin) : 0;
+  L.farst = L.eonly ? take(sizeof(int64_t) * (size_t)L.fin) : 0;
+  L.nearst = L.eonly ? take(sizeof(int64_t) * (size_t)L.fin) : 0;
+  L.nfar = L.eonly ? take(sizeof(int64_t) * (size_t)nsys) : 0;
+  L.qpk = L.eonly ? take(sizeof(double) * (size_t)total_n) : 0;
   L.echunk = L.eonly ? take(sizeof(double) * (size_t)(L.echunks + 1)) : 0;
   L.sfield = field ? take(sizeof(double4) * (size_t)total_n) : 0;
   L.lo = field && !fp64;

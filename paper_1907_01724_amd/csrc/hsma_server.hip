@@ -31,6 +31,23 @@ using namespace hsma;
 
 namespace {
 
+// A stream with a hardware queue of its own.  The runtime gives a process a few hardware queues
+// (four by default) and maps further streams onto them, so a server stream could share a queue
+// with a stream used before it (the caller's, a graph capture's, another server's), and a move
+// batch would then wait behind whatever that queue holds; both were measured (move latencies ten
+// times longer, or the two energy streams on one queue).  A stream created with a CU mask always
+// gets a new queue; the mask here enables every CU.  Such streams synchronise with the legacy
+// default stream.
+hipError_t own_queue_stream(int device, hipStream_t *st) {
+  int ncu = 0;
+  hipError_t e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  if (ncu < 1 || ncu > 32 * 64) return hipErrorInvalidValue;
+  uint32_t mask[64] = {};
+  for (int i = 0; i < ncu; ++i) mask[i / 32] |= 1u << (i % 32);
+  return hipExtStreamCreateWithCUMask(st, (uint32_t)((ncu + 31) / 32), mask);
+}
+
 struct Pending {
   hsma_request r;
   double t_submit;
@@ -427,7 +444,7 @@ extern "C" hsma_status hsma_server_create(const hsma_server_opts *opts, hsma_ser
   S->dslots.resize(o.delta_slots);
   for (DeltaSlot &d : S->dslots) {
     if (rc != HSMA_OK) break;
-    if (hipStreamCreateWithFlags(&d.st, hipStreamNonBlocking) != hipSuccess ||
+    if (own_queue_stream(S->device, &d.st) != hipSuccess ||
         hipEventCreateWithFlags(&d.ev, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void **)&d.h_reqs, sizeof(DeReq) * o.max_batch, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&d.h_dE, sizeof(double) * o.max_batch, hipHostMallocDefault) != hipSuccess ||
@@ -438,7 +455,7 @@ extern "C" hsma_status hsma_server_create(const hsma_server_opts *opts, hsma_ser
   S->eslots.resize(o.energy_slots);
   for (EnergySlot &e : S->eslots) {
     if (rc != HSMA_OK) break;
-    if (hipStreamCreateWithFlags(&e.st, hipStreamNonBlocking) != hipSuccess ||
+    if (own_queue_stream(S->device, &e.st) != hipSuccess ||
         hipEventCreateWithFlags(&e.ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&e.snap, hipEventDisableTiming) != hipSuccess ||
         hipMalloc(&e.d_E, sizeof(double)) != hipSuccess ||
@@ -521,9 +538,6 @@ extern "C" hsma_status hsma_server_add_system(hsma_server_t S, hsma_plan_t pl, i
   S->busy[slot] = 0;
   S->snapping[slot] = 0;
   sys->g64->tune.ewaves = S->opts.energy_workgroups > 0 ? S->opts.energy_workgroups : 0;
-  // Full energies in blocks of 256 ions whatever the system's size: blocks of 128 finish a lone
-  // energy sooner, but beside the move batches they raised the moves' p99 several times (measured)
-  sys->g64->tune.eblock = 256;
   // Full-energy workspaces grow here, at admission, rather than in the scheduler, where freeing
   // device memory would stall every request in flight (a slot busy now grows when next used).
   for (EnergySlot &e : S->eslots) {

@@ -450,6 +450,10 @@ extern "C" hsma_status hsma_system_create_ex(hsma_plan_t pl, int64_t N, const do
     return rc;
   }
   sys->g64->pair_prec = HSMA_PAIR_FP64;  // full evaluations of the state in FP64
+  // Full energies of a resident system in blocks of 256 ions whatever its size: the request
+  // server needs that size beside its move batches (blocks of 128 raised the moves' p99 several
+  // times), and the same size here keeps a served energy the same bit for bit as this API's.
+  sys->g64->tune.eblock = 256;
   const size_t nb = sizeof(double) * (size_t)N;
   const int nA = (int)((N + DB - 1) / DB);
   sys->footprint = 4 * nb + sizeof(double) * (6 * (size_t)P + 2 * (size_t)M + 2 * (size_t)K + 1 + (size_t)nA + P) +
