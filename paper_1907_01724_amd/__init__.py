@@ -599,7 +599,7 @@ class Group:
         return int(load_library().hsma_group_autotune_workspace_bytes(self._h, int(nsys), int(total_n), int(max_n)))
 
     def set_energy_launch(self, block: int = 0, workgroups: int = 0):
-        """Energy launch: ions per block (0 automatic, 256, 512) and grid (0: one item per wave;
+        """Energy launch: ions per block (0 automatic, 128, 256, 512) and grid (0: one item per wave;
         > 0: persistent grid of that many workgroups)."""
         _check(load_library().hsma_group_set_energy_launch(self._h, int(block), int(workgroups)),
                "hsma_group_set_energy_launch")
