@@ -247,6 +247,34 @@ def test_kirkwood_truncated_converges():
     assert errs[-1] < 1e-14
 
 
+def test_kirkwood_truncation_order_is_exact():
+    """The truncated series (order n) holds exactly the terms 0..n of eq. "phirf" summed over m: the
+    difference of orders n and n - 1 is the single term q/(4 pi eps1 a) M_n t^n P_n(c), with M_n from
+    the factor function (pinned to scipy's Bessel functions elsewhere) and P_n from scipy's Legendre
+    polynomials, not the oracle's recurrence; an off-by-one in the truncation gives the neighbouring
+    term instead."""
+    from scipy.special import eval_legendre
+    a, eps1, eps2, kappa = 1.5, 2.0, 80.0, 0.7
+    src = np.array([[0.3, -0.5, 0.6]])
+    tgt = np.array([[-0.2, 0.7, 0.4], [0.9, 0.1, -0.3]])
+    q = 1.7
+    rs, rt = np.linalg.norm(src[0]), np.linalg.norm(tgt, axis=1)
+    t = rt * rs / a ** 2
+    c = tgt @ src[0] / (rt * rs)
+    _, M = oracle.kirkwood_factor(12, eps1 / eps2, kappa * a)
+    pref = q / (4 * math.pi * eps1 * a)
+
+    def o2(order):
+        return oracle.kirkwood_eval(a, eps1, eps2, kappa, src[:, 0], src[:, 1], src[:, 2], [q], targets=tgt,
+                                    order=order)
+
+    one = pref * (M[0] + M[1] * t * c)
+    assert np.allclose(o2(1), one, rtol=1e-14, atol=0)
+    for n in range(2, 12):
+        term = pref * M[n] * t ** n * eval_legendre(n, c)
+        assert np.allclose(o2(n) - o2(n - 1), term, rtol=1e-9, atol=1e-15 * abs(one).max()), n
+
+
 def test_coulomb_energy_closed_forms():
     """Two charges: q1 q2 / (4 pi eps1 r); a unit square of alternating charges: four nearest
     pairs at distance 1 and two diagonal pairs at sqrt 2."""
