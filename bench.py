@@ -40,12 +40,10 @@ FLOP_KELVIN, FLOP_SURFACE, FLOP_CHECK = 11, 21, 13
 #   Kelvin image: 11 + r^-3 (2) + strength r^-3 (1) + three fma into E (6) = 20;
 #   surface node: 21 + r^-2, r^-3 and the dipole factor (6) + two vector fma into E (12) = 39.
 FLOP_FIELD_KELVIN, FLOP_FIELD_SURFACE = 20, 39
-# VALU issue model, reported as a utilisation beside the roofline: 256 CUs x 4 SIMDs x 16 lanes at
-# 2.4 GHz issue 3.93e13 lane-instructions/s.  The energy kernel spends per unordered ion pair 11
-# FP64 instructions and one v_rsq_f64, charged 4 issue cycles (quarter rate): 15 cycles, i.e.
-# 7.5 per Kelvin pair counted in one direction; per surface pair 18 + 4.
-ISSUE_RATE = 256 * 64 * 2.4e9
-ISSUE_ENERGY_KELVIN, ISSUE_ENERGY_SURFACE = 7.5, 22.0
+# VALU issue beside the roofline: the energy kernel's VALU instructions per launch (SQ_INSTS_VALU
+# from the committed counter summary of the same engine source) over one FP64 wave instruction per
+# 4 cycles on each of the 256 x 4 SIMDs at 2.4 GHz.
+FP64_WAVE_ISSUE_RATE = 256 * 4 * 2.4e9 / 4
 GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "c3_reference.json")
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 ENGINE_SRC = os.path.join(ROOT, "paper_1907_01724_amd", "csrc", "hsma_engine.hip")
@@ -190,7 +188,7 @@ def main() -> int:
         ev_ms, ev_n = stages["eval"]
         avg = ev_ms / max(ev_n, 1) * 1e-3  # one energy-kernel launch per step
         flop = FLOP_KELVIN * pairs_kelvin + FLOP_SURFACE * pairs_surface
-        t_issue = (ISSUE_ENERGY_KELVIN * pairs_kelvin + ISSUE_ENERGY_SURFACE * pairs_surface) / ISSUE_RATE
+        valu = _measured_value("k_energy64", "sq_counters", "valu_instructions_per_launch")
         out["roofline"] = {
             "bound": "alu",
             "kernel": "k_energy64 (FP64 energy pair sums: symmetric Kelvin block pairs + surface chunks)",
@@ -205,7 +203,8 @@ def main() -> int:
             "flop_per_launch": flop,
             "flop_model": "11 per Kelvin pair N(N-1), 21 per surface pair NP (algorithmic, both directions of a "
                           "pair counted); peak: published FP64 vector rate",
-            "valu_issue_utilisation": t_issue / avg,
+            "valu_instructions_per_launch": valu,
+            "valu_issue_fraction": valu / avg / FP64_WAVE_ISSUE_RATE if valu else None,
         }
         out["stage_ms_per_step"] = {k: v[0] / prof_steps for k, v in stages.items()}
         log(f"bench: energy kernel {avg * 1e3:.2f} ms/launch, {out['roofline']['achieved']:.1f} TFLOP/s = "
@@ -260,21 +259,27 @@ def main() -> int:
     return 0
 
 
-def _measured_traffic(kernel: str, _flop=None):
-    """HBM bytes per launch of a kernel from its committed PMC summary (profiles/<kernel>_*hbm_traffic.txt),
-    or None when no summary exists or the engine source changed since the counted run (its hash)."""
+def _measured_value(kernel: str, kind: str, key: str):
+    """A per-launch figure of a kernel from its committed PMC summary (profiles/<kernel>_*<kind>.txt:
+    its 'key value' lines), or None when no summary exists or the engine source changed since the
+    counted run (its hash)."""
     import glob
     import hashlib
     try:
         with open(ENGINE_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-        for path in sorted(glob.glob(os.path.join(PROFILE_DIR, f"{kernel}_*hbm_traffic.txt"))):
+        for path in sorted(glob.glob(os.path.join(PROFILE_DIR, f"{kernel}_*{kind}.txt"))):
             kv = dict(l.split(None, 1) for l in open(path) if l.strip() and not l.startswith((" ", "#")))
             if kv.get("engine_source_sha256", "").strip() == sha and kv.get("kernel", "").strip() == kernel:
-                return float(kv["traffic_bytes_per_launch"])
+                return float(kv[key])
     except (OSError, ValueError, KeyError):
         return None
     return None
+
+
+def _measured_traffic(kernel: str, _flop=None):
+    """HBM bytes per launch of a kernel from its committed PMC summary (profiles/<kernel>_*hbm_traffic.txt)."""
+    return _measured_value(kernel, "hbm_traffic", "traffic_bytes_per_launch")
 
 
 def _pot_roofline(pairs_kelvin, pairs_surface, avg_s, prec, kernel):
@@ -288,10 +293,8 @@ def _pot_roofline(pairs_kelvin, pairs_surface, avg_s, prec, kernel):
 
 def _energy_roofline(pairs_kelvin, pairs_surface, avg_s):
     flop = FLOP_KELVIN * pairs_kelvin + FLOP_SURFACE * pairs_surface
-    t_issue = (ISSUE_ENERGY_KELVIN * pairs_kelvin + ISSUE_ENERGY_SURFACE * pairs_surface) / ISSUE_RATE
     return {"bound": "alu", "kernel": "k_energy64", "achieved": flop / avg_s / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": flop / avg_s / PEAK_FP64, "avg_launch_ms": avg_s * 1e3,
-            "valu_issue_utilisation": t_issue / avg_s}
+            "unit": "TFLOP/s", "frac": flop / avg_s / PEAK_FP64, "avg_launch_ms": avg_s * 1e3}
 
 
 def leg_c2(args, checks) -> dict:
