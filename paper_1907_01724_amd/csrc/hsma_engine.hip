@@ -124,6 +124,9 @@ constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
 // Energy pairs whose source lies within r <= NEAR_R a take the expanded form of the squared image
 // distance (see energy_item); sources nearer the interface take the exact form.
 constexpr double NEAR_R = 0.98;
+// Surface pairs of the energy launch take the expanded squared distance when every node lies on
+// the sphere R_tau >= SURF_EXPANDED a (see energy_item).
+constexpr double SURF_EXPANDED = 1.05;
 constexpr int64_t ETAIL_ROUNDS = 4;  // energy launches: blocks of 128 below this many rounds of wave slots
 constexpr int CTR_WORDS = 32, CTR_ENERGY = 8, CTR_CHECK = 16, CTR_EVAL = 24;
 struct Sched {
@@ -1942,40 +1945,72 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
     const int rem = (int)(t % (sch * SYM_SH));
     const int c = __builtin_amdgcn_readfirstlane(rem / SYM_SH), h = __builtin_amdgcn_readfirstlane(rem % SYM_SH);
     const int t0 = I * TB + h * RS * 64;
-    double sx[RS], sy[RS], sz[RS], sq[RS], acc[RS];
-#pragma unroll
-    for (int k = 0; k < RS; ++k) {
-      const int i = t0 + k * 64 + lane;
-      const bool in = i < n;
-      const double4 tv = in ? tgt[lo + i] : make_double4(FAR_TARGET, 0.0, 0.0, 0.0);
-      sx[k] = tv.x;
-      sy[k] = tv.y;
-      sz[k] = tv.z;
-      sq[k] = in ? q[lo + i] : 0.0;
-      acc[k] = 0.0;
-    }
     const int per = (P + sch - 1) / sch;
     const int s0 = c * per, s1 = s0 + per < P ? s0 + per : P;
     const int pl = plan_of ? plan_of[b] : 0;
     const double4 *nd = nodes + (size_t)pl * P;
     const double2 *qb = qd + (size_t)b * P;
-    for (int m = s0; m < s1; ++m) {
-      const double4 yv = nd[m];
-      const double2 wv = qb[m];
+    const double Rt = ex.plans[pl].Rtau, R2 = Rt * Rt;
+    // Every node on the sphere R_tau (not the point-pair form) with R_tau >= 1.05 a: |x - y|^2 =
+    // |x|^2 + R_tau^2 - 2 x.y, three FMAs from the target's -2x and |x|^2 + R_tau^2, and the
+    // dipole's (x - y).y = (|x|^2 - R_tau^2 - D)/2 from D itself.  D >= (R_tau - a)^2 >= 0.0025 a^2
+    // there, so both round to about 1e-12 relative.  Otherwise the exact differences.
+    const bool sexp = ex.plans[pl].dipole != 1 && Rt >= SURF_EXPANDED * ex.plans[pl].a;
+    double f0[RS], f1[RS], f2[RS], f3[RS], f4[RS], sq[RS], acc[RS];
 #pragma unroll
-      for (int k = 0; k < RS; ++k) {
-        const double dx = sx[k] - yv.x, dy = sy[k] - yv.y, dz = sz[k] - yv.z;
-        const double ri = rinv(dx * dx + dy * dy + dz * dz);
-        if (mono) {
-          acc[k] = fma(wv.x, ri, acc[k]);
-        } else {
-          const double dot = dx * yv.x + dy * yv.y + dz * yv.z;
-          acc[k] = fma(ri, fma(wv.y * dot, ri * ri, wv.x), acc[k]);
+    for (int k = 0; k < RS; ++k) {
+      const int i = t0 + k * 64 + lane;
+      const bool in = i < n;
+      // an empty lane: zero charge, at the origin (expanded) or far away
+      const double4 tv = in ? tgt[lo + i] : make_double4(sexp ? 0.0 : FAR_TARGET, 0.0, 0.0, 0.0);
+      const double xx = fma(tv.x, tv.x, fma(tv.y, tv.y, tv.z * tv.z));
+      f0[k] = sexp ? -2.0 * tv.x : tv.x;
+      f1[k] = sexp ? -2.0 * tv.y : tv.y;
+      f2[k] = sexp ? -2.0 * tv.z : tv.z;
+      f3[k] = xx + R2;
+      f4[k] = 0.125 * (xx - R2);
+      sq[k] = in ? q[lo + i] : 0.0;
+      acc[k] = 0.0;
+    }
+    if (sexp) {
+      // the sums hold twice the terms (rinv2), and (x - y).y / 4 against the cube
+      for (int m = s0; m < s1; ++m) {
+        const double4 yv = nd[m];
+        const double2 wv = qb[m];
+#pragma unroll
+        for (int k = 0; k < RS; ++k) {
+          const double d = fma(f0[k], yv.x, fma(f1[k], yv.y, fma(f2[k], yv.z, f3[k])));
+          const double ri = rinv2(d);
+          if (mono) {
+            acc[k] = fma(wv.x, ri, acc[k]);
+          } else {
+            const double dq = fma(-0.125, d, f4[k]);
+            acc[k] = fma(ri, fma(wv.y * dq, ri * ri, wv.x), acc[k]);
+          }
         }
       }
-    }
 #pragma unroll
-    for (int k = 0; k < RS; ++k) e = fma(sq[k], acc[k], e);
+      for (int k = 0; k < RS; ++k) e = fma(sq[k], acc[k], e);
+      e *= 0.5;
+    } else {
+      for (int m = s0; m < s1; ++m) {
+        const double4 yv = nd[m];
+        const double2 wv = qb[m];
+#pragma unroll
+        for (int k = 0; k < RS; ++k) {
+          const double dx = f0[k] - yv.x, dy = f1[k] - yv.y, dz = f2[k] - yv.z;
+          const double ri = rinv(dx * dx + dy * dy + dz * dz);
+          if (mono) {
+            acc[k] = fma(wv.x, ri, acc[k]);
+          } else {
+            const double dot = dx * yv.x + dy * yv.y + dz * yv.z;
+            acc[k] = fma(ri, fma(wv.y * dot, ri * ri, wv.x), acc[k]);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < RS; ++k) e = fma(sq[k], acc[k], e);
+    }
   } else {
     const int64_t B = cdiv64(n, TB), sup = super_of(B), loc = item - S.ie[b];
     int I, J;
