@@ -2042,8 +2042,8 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
     const double4 *im = img + lo;
     const int j0 = J * TB, j1 = j0 + TB < n ? j0 + TB : n;
     // the sums hold twice the pair terms (rinv2); halved once at the end
-    if (I == J) {
-      // diagonal block: every ordered pair j != i (the own image is the analytic term)
+    if (R == 8 && I == J) {
+      // diagonal block of 512 ions: every ordered pair j != i, one direction (registers)
       for (int j = j0; j < j1; ++j) {
         const double4 v = im[j];
 #pragma unroll
@@ -2052,6 +2052,57 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
           double ri = rinv2(dx * dx + dy * dy + dz * dz);
           ri = (j == t0 + k * 64 + lane) ? 0.0 : ri;
           s1[k] = fma(v.w, ri, s1[k]);
+        }
+      }
+    } else if (I == J) {
+      // Diagonal block: each unordered pair j > i once, both directions through the symmetric
+      // identity as in the off-diagonal blocks (the own image is the analytic term).  Sources in
+      // runs of 64: run jb meets the target rows k <= jb, all of whose pairs count for k < jb and
+      // those with j > i for k = jb.  A block wholly below n_far takes the expanded form.
+      if ((int64_t)j1 <= ex.nfar[b]) {
+        const double ia = 1.0 / ex.plans[plan_of ? plan_of[b] : 0].a;
+        double uu[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          tx[k] *= ia;
+          ty[k] *= ia;
+          tz[k] *= ia;
+          uu[k] = fma(tx[k], tx[k], fma(ty[k], ty[k], tz[k] * tz[k]));
+        }
+        const double4 *em = ex.emx + lo;
+        const double2 *ewt = ex.ew + lo;
+#pragma unroll
+        for (int jb = 0; jb < R; ++jb) {
+          const int js = j0 + 64 * jb, je = js + 64 < j1 ? js + 64 : j1;
+          for (int j = js; j < je; ++j) {
+            const double4 m = em[j];
+            const double2 wj = ewt[j];
+#pragma unroll
+            for (int k = 0; k <= jb; ++k) {
+              double ri = rinv2(fma(tx[k], m.x, fma(ty[k], m.y, fma(tz[k], m.z, fma(uu[k], m.w, 1.0)))));
+              if (k == jb) ri = j > t0 + k * 64 + lane ? ri : 0.0;
+              s1[k] = fma(wj.x, ri, s1[k]);
+              s2[k] = fma(wj.y, ri, s2[k]);
+            }
+          }
+        }
+      } else {
+        const double *cr = qr + lo;
+#pragma unroll
+        for (int jb = 0; jb < R; ++jb) {
+          const int js = j0 + 64 * jb, je = js + 64 < j1 ? js + 64 : j1;
+          for (int j = js; j < je; ++j) {
+            const double4 v = im[j];
+            const double cj = cr[j];
+#pragma unroll
+            for (int k = 0; k <= jb; ++k) {
+              const double dx = tx[k] - v.x, dy = ty[k] - v.y, dz = tz[k] - v.z;
+              double ri = rinv2(dx * dx + dy * dy + dz * dz);
+              if (k == jb) ri = j > t0 + k * 64 + lane ? ri : 0.0;
+              s1[k] = fma(v.w, ri, s1[k]);
+              s2[k] = fma(cj, ri, s2[k]);
+            }
+          }
         }
       }
     } else {
