@@ -1,26 +1,30 @@
 // Hot path of the HSMA reaction potential (Algorithm 1, steps 2-5) for gfx950, for one
 // or many ion configurations ("systems") in one set of launches.
 //
-//   k_schedule     per-system item counts and prefix sums from the ion offsets
-//   k_fill         item -> system maps
-//   k_pack         Kelvin images (Sec. 2.4: r_K = (a/r)^2 x, q_K), exact FP64 own-image term,
-//                  packed sources/targets in the pair precision, domain check
-//   k_check        check fields u_k = sum_i q_i G0(c_k, x_i), v_k = sum_i q_i (r_i/a) G0(c_k, x_i)
-//                  (Algorithm 1, step 2): persistent, items = (system, 64 check points, source chunk)
-//   k_check_finish fixed-order sum of the chunk partials
-//   fit            alpha' = pinv u, beta' = pinv v; h = f . alpha' + g . beta';
-//                  Q' = Lhat (n . h), D' = -Lhat h (steps 3-4: the fixed least-squares fit and
-//                  Green's second identity on the Fibonacci nodes); GEMVs for a few systems,
-//                  FP32 MFMA GEMMs across many
-//   k_eval         Phi_i = sum_{j != i} q_K,j / |x_i - r_K,j| + sum_s [Q'_s + D'_s (d.y_s)/|d|^2]/|d|
-//                  (eq. "phirffinall", step 5): persistent, items = (system, 64 ions, source chunk)
-//   k_finish       Phi_i = own-image term + fixed-order sum of chunk partials; block energy partials
-//   k_energy       E_b = 1/2 sum_i q_i Phi_i per system, fixed order
+//   k_schedule      per-system item counts and prefix sums from the ion offsets
+//   k_near_count,   (energy launches) each system's ions with r > 0.98 a placed after its others,
+//   k_near_scan     so that the energy sums can take expanded distances on the rest
+//   k_pack          item -> system maps; Kelvin images (Sec. 2.4: r_K = (a/r)^2 x, q_K), exact FP64
+//                   own-image term, packed sources/targets in the pair precision, domain check
+//   k_check         check fields u_k = sum_i q_i G0(c_k, x_i), v_k = sum_i q_i (r_i/a) G0(c_k, x_i)
+//                   (Algorithm 1, step 2): items = (system, 64 check points, source chunk)
+//   k_check_finish  fixed-order sum of the chunk partials
+//   fit             alpha' = pinv u, beta' = pinv v; h = f . alpha' + g . beta';
+//                   Q' = Lhat (n . h), D' = -Lhat h (steps 3-4: the fixed least-squares fit and
+//                   Green's second identity on the nodes): k_fit_* GEMVs for a few systems,
+//                   MFMA GEMMs (k_gemm_nt FP32, k_gemm64_nt FP64, k_gemm_bf split BF16) across many
+//   k_kelvin_sym    Phi_i = sum_{j != i} q_K,j / |x_i - r_K,j| + sum_s [Q'_s + D'_s (d.y_s)/|d|^2]/|d|
+//                   (eq. "phirffinall", step 5) over block pairs (I, J >= I), one reciprocal root
+//                   for both directions of a pair (symmetric image distance), and surface items;
+//                   k_kelvin_sym64 in FP64; k_eval the one-directional form for small launches
+//   k_eval_field    the potential and the field at the ions
+//   k_finish        Phi_i = own-image term + fixed-order sum of the partial slots (k_finish_field)
+//   k_energy64      (energy launches) FP64 pair energies of the block pairs and surface items,
+//                   one value per item; k_self_energy, k_energy_chunks, k_energy_items: E_b in a
+//                   fixed order; k_energy: E_b = 1/2 sum_i q_i Phi_i from the potentials
 //
-// Pair kernels: a target per lane; the four waves of a block take four slices of the item's
-// source chunk (read at wave-uniform addresses, i.e. scalar loads, no LDS traffic) and are
-// combined through LDS in a fixed order.  One v_rsq per pair; FP32 sums over 32-source tiles
-// are folded into FP64 (compensated mode).
+// Pair kernels hold targets in registers and read sources at wave-uniform addresses (scalar
+// loads); every sum is reduced in a fixed order, so a call is bitwise reproducible.
 #include <math.h>
 #include <stdlib.h>
 
