@@ -871,18 +871,47 @@ __global__ __launch_bounds__(256) void k_fit_surface(int nsys, const int64_t *__
 }
 
 // ---------------------------------------------------------------------------------
-// Fit apply, many systems: C[col][row] = sum_k A[row][k] B[col][k] with FP32 MFMA
-// (v_mfma_f32_16x16x4f32).  Block tile 64 rows x 64 cols, four waves of 32 x 32,
-// k staged through LDS 16 at a time.
+// Fit apply, many systems: C[col][row] = sum_k A[row][k] B[col][k] on MFMA.  Block tile 64 rows
+// x 64 cols, four waves of 32 x 32 (2 x 2 tiles of 16 x 16); k staged through LDS 32 at a time,
+// and the next 32 values of k read from global memory into registers while the current ones are
+// multiplied, so that the loads' latency overlaps the MFMAs (the products are latency-bound
+// otherwise: one k step's work is a few hundred cycles).
 // ---------------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int GK = 32;  // k values per LDS stage
 
-// The MFMA accumulators are FP32; they are folded into FP64 registers after every 64
-// values of k, so the sum over k = 1536-9600 terms loses no more than a 64-term FP32 sum.
+// One thread's share of a stage: 64 rows (cols) x GK values of k of each operand, 8 values each,
+// rows read 32 consecutive k by consecutive threads; zero beyond the matrices.
+template <typename T>
+struct GemmStage {
+  T ra[8], rb[8];
+  __device__ __forceinline__ void load(const T *__restrict__ A, const T *__restrict__ B, int nrows, int ncols,
+                                       int kdim, int row0, int col0, int k0, int t) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i, r = e >> 5, gk = k0 + (e & 31);
+      ra[i] = (row0 + r < nrows && gk < kdim) ? A[(size_t)(row0 + r) * kdim + gk] : (T)0;
+      rb[i] = (col0 + r < ncols && gk < kdim) ? B[(size_t)(col0 + r) * kdim + gk] : (T)0;
+    }
+  }
+  __device__ __forceinline__ void store(T (*As)[GK + 1], T (*Bs)[GK + 1], int t) const {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i;
+      As[e >> 5][e & 31] = ra[i];
+      Bs[e >> 5][e & 31] = rb[i];
+    }
+  }
+};
+
+// FP32 (v_mfma_f32_16x16x4f32).  The MFMA accumulators are FP32; they are folded into FP64
+// registers after every 64 values of k, so the sum over k = 1536-9600 terms loses no more than a
+// 64-term FP32 sum.
 __global__ __launch_bounds__(256) void k_gemm_nt(int nrows, int ncols, int kdim, const float *__restrict__ A,
                                                  const float *__restrict__ B, float *__restrict__ C) {
-  __shared__ float As[64][17];
-  __shared__ float Bs[64][17];
+  __shared__ float As[64][GK + 1];
+  __shared__ float Bs[64][GK + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
@@ -893,17 +922,15 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int nrows, int ncols, int kdim,
       acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
       for (int r = 0; r < 4; ++r) dacc[i][j][r] = 0.0;
     }
-  int step = 0;
-  for (int k0 = 0; k0 < kdim; k0 += 16) {
-    for (int e = t; e < 64 * 16; e += 256) {
-      const int r = e >> 4, kk = e & 15;
-      const int gr = row0 + r, gc = col0 + r, gk = k0 + kk;
-      As[r][kk] = (gr < nrows && gk < kdim) ? A[(size_t)gr * kdim + gk] : 0.0f;
-      Bs[r][kk] = (gc < ncols && gk < kdim) ? B[(size_t)gc * kdim + gk] : 0.0f;
-    }
+  GemmStage<float> g;
+  g.load(A, B, nrows, ncols, kdim, row0, col0, 0, t);
+  for (int k0 = 0; k0 < kdim; k0 += GK) {
+    __syncthreads();  // every wave is done with the previous stage
+    g.store(As, Bs, t);
     __syncthreads();
+    if (k0 + GK < kdim) g.load(A, B, nrows, ncols, kdim, row0, col0, k0 + GK, t);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    for (int kk = 0; kk < GK; kk += 4) {
       const int kl = kk + (lane >> 4);
       float a[2], bb[2];
       for (int i = 0; i < 2; ++i) a[i] = As[wr * 32 + i * 16 + (lane & 15)][kl];
@@ -911,9 +938,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int nrows, int ncols, int kdim,
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
-    if (++step == 4 || k0 + 16 >= kdim) {
-      step = 0;
+    if ((k0 + GK) % 64 == 0 || k0 + GK >= kdim) {
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) {
           for (int r = 0; r < 4; ++r) dacc[i][j][r] += (double)acc[i][j][r];
@@ -931,32 +956,28 @@ __global__ __launch_bounds__(256) void k_gemm_nt(int nrows, int ncols, int kdim,
     }
 }
 
-// The same product in FP64: C[col][row] = sum_k A[row][k] B[col][k] on v_mfma_f64_16x16x4f64,
-// whose lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and
-// receives D[l / 16 + 4 v][l % 16], v = 0..3.  Block tile 64 x 64, four waves of 32 x 32, k
-// staged through LDS 16 at a time; the accumulators are FP64 throughout.
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
+// The same product in FP64 (v_mfma_f64_16x16x4f64), whose lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step and receives D[l / 16 + 4 v][l % 16], v = 0..3;
+// the accumulators are FP64 throughout.
 __global__ __launch_bounds__(256) void k_gemm64_nt(int nrows, int ncols, int kdim, const double *__restrict__ A,
                                                    const double *__restrict__ B, double *__restrict__ C) {
-  __shared__ double As[64][17];
-  __shared__ double Bs[64][17];
+  __shared__ double As[64][GK + 1];
+  __shared__ double Bs[64][GK + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
   doublex4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < kdim; k0 += 16) {
-    for (int e = t; e < 64 * 16; e += 256) {
-      const int r = e >> 4, kk = e & 15;
-      const int gr = row0 + r, gc = col0 + r, gk = k0 + kk;
-      As[r][kk] = (gr < nrows && gk < kdim) ? A[(size_t)gr * kdim + gk] : 0.0;
-      Bs[r][kk] = (gc < ncols && gk < kdim) ? B[(size_t)gc * kdim + gk] : 0.0;
-    }
+  GemmStage<double> g;
+  g.load(A, B, nrows, ncols, kdim, row0, col0, 0, t);
+  for (int k0 = 0; k0 < kdim; k0 += GK) {
+    __syncthreads();  // every wave is done with the previous stage
+    g.store(As, Bs, t);
     __syncthreads();
+    if (k0 + GK < kdim) g.load(A, B, nrows, ncols, kdim, row0, col0, k0 + GK, t);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    for (int kk = 0; kk < GK; kk += 4) {
       const int kl = kk + (lane >> 4);
       double a[2], bb[2];
       for (int i = 0; i < 2; ++i) a[i] = As[wr * 32 + i * 16 + (lane & 15)][kl];
@@ -964,7 +985,6 @@ __global__ __launch_bounds__(256) void k_gemm64_nt(int nrows, int ncols, int kdi
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
