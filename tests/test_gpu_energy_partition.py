@@ -134,3 +134,38 @@ def test_potential_call_energies_unchanged(batch, dev):
     assert g.stream_check() == 0
     alone = _energies(batch, 0)
     assert np.array_equal(E.cpu().numpy(), alone)
+
+
+# (tau, surface form, r_c / a): the surface pairs take the expanded form when every node lies on
+# R_tau >= 1.05 a (exact dipoles or a single layer), the exact differences otherwise (tau = 0.04,
+# and the point-pair form); check points on the interface itself (r_c = a, the paper's placement)
+# leave the expanded check sums only the ions within 0.98 a.
+SURFACE_CASES = [(0.04, 0, None), (0.05, 0, None), (0.2, 0, None), (0.1, 2, None), (0.04, 2, None),
+                 (0.1, 1, None), (0.1, 0, 1.0)]
+
+
+@pytest.mark.parametrize("tau,dipole,rc", SURFACE_CASES)
+def test_surface_and_check_forms_against_oracle(dev, tau, dipole, rc):
+    a = 15.0
+    rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 620))
+    pos = _mixed(rng, a, 1100, 400)
+    q = W.balanced_charges(rng, len(pos))
+    kw = {"tau": tau, "dipole": dipole}
+    if rc is not None:
+        kw["rc_over_a"] = rc
+    if dipole == 1:
+        kw["dy_over_Rtau"] = 1e-5
+    plan = hs.Plan(a, 1.0, 78.5, 0.3, 1024, 1536, **kw)
+    i = plan.info
+    prm = oracle.Params(a=i["a"], eps1=i["eps1"], eps2=i["eps2"], kappa=i["kappa"], p=i["p"], P=i["P"], M=i["M"],
+                        tau=i["tau"], rc_over_a=i["rc"] / i["a"], F1=i["F1"], dipole=i["dipole"],
+                        dy_over_Rtau=i["dy_over_Rtau"])
+    e_ref = oracle.energy(q, oracle.hsma_eval(prm, pos[:, 0], pos[:, 1], pos[:, 2], q))
+    t = [torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev) for v in (pos[:, 0], pos[:, 1],
+                                                                                          pos[:, 2], q)]
+    E = float(plan.energy(*t).cpu()[0])
+    assert plan.stream_check() == 0
+    rel = abs(E - e_ref) / abs(e_ref)
+    print(f"tau {tau} dipole {dipole} rc/a {i['rc'] / i['a']:.2f}: E rel {rel:.2e}", flush=True)
+    assert rel <= TOL_E
+    plan.close()
