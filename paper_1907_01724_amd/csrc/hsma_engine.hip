@@ -132,6 +132,12 @@ constexpr double NEAR_R = 0.98;
 // the sphere R_tau >= SURF_EXPANDED a (see energy_item).
 constexpr double SURF_EXPANDED = 1.05;
 constexpr int64_t ETAIL_ROUNDS = 4;  // energy launches: blocks of 128 below this many rounds of wave slots
+// One source of the energy launch's check sums in the normalised form (see check_range_expanded):
+// w = (r/a)^2 + (rc/a)^2, the position scaled by -2/(a w), and the weights of u and v over sqrt(w).
+// One record, so that a run of sources is one stretch of scalar loads.
+struct CheckSrc {
+  double x, y, z, wu, wv;
+};
 constexpr int CTR_WORDS = 32, CTR_ENERGY = 8, CTR_CHECK = 16, CTR_EVAL = 24;
 struct Sched {
   int64_t *off, *ic, *ie, *fb, *pc, *pe, *is, *ec, *ctr;
@@ -407,8 +413,8 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
                                               typename PT<MODE>::T *__restrict__ srcw, double *__restrict__ self,
                                               typename PT<MODE>::T *__restrict__ wk, double *__restrict__ rk,
                                               double *__restrict__ qr, double4 *__restrict__ emx,
-                                              double2 *__restrict__ ew, double4 *__restrict__ cmx,
-                                              double2 *__restrict__ cw, const int64_t *__restrict__ farst,
+                                              double2 *__restrict__ ew, CheckSrc *__restrict__ csrc,
+                                              const int64_t *__restrict__ farst,
                                               const int64_t *__restrict__ nearst, double *__restrict__ qpk,
                                               double4 *__restrict__ sfield, float4 *__restrict__ tlo,
                                               float4 *__restrict__ ilo, int *__restrict__ flag) {
@@ -447,8 +453,7 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
     if (emx) {
       emx[d] = make_double4(0.0, 0.0, 0.0, 0.0);
       ew[d] = make_double2(0.0, 0.0);
-      cmx[d] = make_double4(0.0, 0.0, 0.0, 1.0);  // a finite distance for its zero weights
-      cw[d] = make_double2(0.0, 0.0);
+      csrc[d] = CheckSrc{0.0, 0.0, 0.0, 0.0, 0.0};  // a unit distance, zero weights
     }
     if (sfield) sfield[d] = make_double4(0.0, 0.0, 0.0, 0.0);
     if (tlo) {
@@ -510,9 +515,10 @@ __global__ __launch_bounds__(256) void k_pack(int nsys, const int64_t *__restric
     const double u = (reff / c.a) * (reff / c.a);
     emx[d] = make_double4(-2.0 * ex / c.a, -2.0 * ey / c.a, -2.0 * ez / c.a, u);
     ew[d] = make_double2(qk * reff / c.a2, qi / c.a2);
-    // the expanded form of the check sums (see check_range_expanded): the ion itself
-    cmx[d] = make_double4(-2.0 * xi / c.a, -2.0 * yi / c.a, -2.0 * zi / c.a, r2 / c.a2 + (c.rc / c.a) * (c.rc / c.a));
-    cw[d] = make_double2(qp, qp * r / c.a);  // the weights of u and v, as in tgt and srcw
+    // the normalised form of the check sums (see check_range_expanded), from the ion itself; the
+    // weights of u and v as in tgt and srcw
+    const double w = r2 / c.a2 + (c.rc / c.a) * (c.rc / c.a), sc = -2.0 / (c.a * w), sw = 1.0 / sqrt(w);
+    csrc[d] = CheckSrc{xi * sc, yi * sc, zi * sc, qp * sw, qp * r / c.a * sw};
   }
 }
 
@@ -613,33 +619,32 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // ---------------------------------------------------------------------------------
 // Check sums.
 // ---------------------------------------------------------------------------------
-// FP64 check sums of the energy launch over sources [j0, j1) that all lie at r <= NEAR_R a: the
-// squared distance in units of a expanded, (rc/a)^2 + (r/a)^2 - 2 (c/a).(x/a), from the
-// per-source (-2x/a, -2y/a, -2z/a, (r/a)^2 + (rc/a)^2) and weights (q', q' r/a): three
-// operations instead of six.  It is at least ((rc - NEAR_R a)/a)^2 >= 4e-4 there, so its
-// rounding stays below about 1e-12 relative.  Sources in runs of 8 (their scalar loads batched).
-__device__ __forceinline__ void check_range_expanded(const double4 &ck, double ia, const double4 *__restrict__ cmx,
-                                                     const double2 *__restrict__ cw, int j0, int j1, double &au,
-                                                     double &av) {
+// FP64 check sums of the energy launch over sources [j0, j1) that all lie at r <= NEAR_R a.  With
+// w = (r/a)^2 + (rc/a)^2 of the source, |c - x|^2 / (a^2 w) = 1 + (c/a).(-2x/(a w)) (rc the check
+// sphere's radius): three FMAs from the per-source (-2x/(a w), -2y/(a w), -2z/(a w)), with 1/sqrt(w)
+// in the weights (q', q' r/a) / sqrt(w), where the exact differences take six operations.  Every
+// term of the sum is at most 1 in magnitude (2 |c||x| <= |c|^2 + |x|^2) and the sum is at least
+// ((rc - NEAR_R a)/a)^2 / ((rc/a)^2 + NEAR_R^2) >= 2e-4 (rc >= a), so its rounding stays within a
+// few 1e-12 relative.  Sources in runs of 8 (their scalar loads batched).
+__device__ __forceinline__ void check_range_expanded(const double4 &ck, double ia, const CheckSrc *__restrict__ cs,
+                                                     int j0, int j1, double &au, double &av) {
   const double cx = ck.x * ia, cy = ck.y * ia, cz = ck.z * ia;
   double su = 0.0, sv = 0.0;
   int j = j0;
   for (; j + 8 <= j1; j += 8) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const double4 m = cmx[j + t];
-      const double2 wt = cw[j + t];
-      const double ri = rinv2(fma(cx, m.x, fma(cy, m.y, fma(cz, m.z, m.w))));
-      su = fma(wt.x, ri, su);
-      sv = fma(wt.y, ri, sv);
+      const CheckSrc m = cs[j + t];
+      const double ri = rinv2(fma(cx, m.x, fma(cy, m.y, fma(cz, m.z, 1.0))));
+      su = fma(m.wu, ri, su);
+      sv = fma(m.wv, ri, sv);
     }
   }
   for (; j < j1; ++j) {
-    const double4 m = cmx[j];
-    const double2 wt = cw[j];
-    const double ri = rinv2(fma(cx, m.x, fma(cy, m.y, fma(cz, m.z, m.w))));
-    su = fma(wt.x, ri, su);
-    sv = fma(wt.y, ri, sv);
+    const CheckSrc m = cs[j];
+    const double ri = rinv2(fma(cx, m.x, fma(cy, m.y, fma(cz, m.z, 1.0))));
+    su = fma(m.wu, ri, su);
+    sv = fma(m.wv, ri, sv);
   }
   au += 0.5 * ia * su;  // rinv2 holds twice the reciprocal, of the distance over a
   av += 0.5 * ia * sv;
@@ -698,8 +703,8 @@ __global__ __launch_bounds__(TPB) void k_check(int persistent, int nsys, int M, 
                                                const int32_t *__restrict__ plan_of,
                                                const typename PT<MODE>::T4 *__restrict__ src,
                                                const typename PT<MODE>::T *__restrict__ srcw, int64_t parts_bound,
-                                               double *__restrict__ part, const double4 *__restrict__ cmx,
-                                               const double2 *__restrict__ cw, const int64_t *__restrict__ nfar) {
+                                               double *__restrict__ part, const CheckSrc *__restrict__ csrc,
+                                               const int64_t *__restrict__ nfar) {
   using T4 = typename PT<MODE>::T4;
   Sched S(const_cast<int64_t *>(base), nsys);
   __shared__ int64_t s_item;
@@ -724,9 +729,9 @@ __global__ __launch_bounds__(TPB) void k_check(int persistent, int nsys, int M, 
     wave_slice(c * chc, (c + 1) * chc < n ? (c + 1) * chc : n, w, j0, j1);
     double au = 0.0, av = 0.0;
     if constexpr (MODE == HSMA_PAIR_FP64) {
-      if (cmx && j0 < j1) {  // energy launch: its far ions (packed first) in the expanded form
+      if (csrc && j0 < j1) {  // energy launch: its far ions (packed first) in the expanded form
         const int64_t je = nfar[b] < j0 ? j0 : (nfar[b] < j1 ? nfar[b] : j1);
-        if (j0 < je) check_range_expanded(ck, 1.0 / pd.a, cmx + lo, cw + lo, (int)j0, (int)je, au, av);
+        if (j0 < je) check_range_expanded(ck, 1.0 / pd.a, csrc + lo, (int)j0, (int)je, au, av);
         j0 = je;
       }
     }
@@ -2423,8 +2428,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
                                              L.eonly ? (double *)(ws + L.qr) : nullptr,
                                              L.eonly ? (double4 *)(ws + L.emx) : nullptr,
                                              L.eonly ? (double2 *)(ws + L.ew) : nullptr,
-                                             L.eonly ? (double4 *)(ws + L.cmx) : nullptr,
-                                             L.eonly ? (double2 *)(ws + L.cw) : nullptr,
+                                             L.eonly ? (CheckSrc *)(ws + L.csrc) : nullptr,
                                              L.eonly ? (const int64_t *)(ws + L.farst) : nullptr,
                                              L.eonly ? (const int64_t *)(ws + L.nearst) : nullptr,
                                              L.eonly ? (double *)(ws + L.qpk) : nullptr,
@@ -2437,8 +2441,7 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
   if (L.items_c > 0)
     k_check<MODE><<<(unsigned)grid_c, TPB, 0, st>>>(persistent_c, nsys, M, L.chc, base, sys_c, plans, plan_of, tgt, srcw,
                                                     L.parts_c, chk_part,
-                                                    L.eonly ? (const double4 *)(ws + L.cmx) : nullptr,
-                                                    L.eonly ? (const double2 *)(ws + L.cw) : nullptr,
+                                                    L.eonly ? (const CheckSrc *)(ws + L.csrc) : nullptr,
                                                     L.eonly ? (const int64_t *)(ws + L.nfar) : nullptr);
   k_check_finish<<<(int)cdiv((int64_t)nsys * M, 256), 256, 0, st>>>(nsys, M, L.chc, base, L.parts_c, chk_part, uv,
                                                                      uv32);
@@ -2702,8 +2705,7 @@ Layout layout(const hsma_group_s *grp, int nsys, int64_t total_n, int64_t max_n,
                              : (field ? sizeof(double4) : sizeof(double)) * (size_t)L.parts_e);
   L.qr = L.eonly ? take(sizeof(double) * (size_t)total_n) : 0;
   L.emx = L.eonly ? take(sizeof(double4) * (size_t)total_n) : 0;
-  L.cmx = L.eonly ? take(sizeof(double4) * (size_t)total_n) : 0;
-  L.cw = L.eonly ? take(sizeof(double2) * (size_t)total_n) : 0;
+  L.csrc = L.eonly ? take(sizeof(CheckSrc) * (size_t)total_n) : 0;
   L.ew = L.eonly ? take(sizeof(double2) * (size_t)total_n) : 0;
   L.ncnt = L.eonly ? take(sizeof(int) * (size_t)L.fin) : 0;
   L.farst = L.eonly ? take(sizeof(int64_t) * (size_t)L.fin) : 0;
