@@ -2,7 +2,7 @@
 // or many ion configurations ("systems") in one set of launches.
 //
 //   k_schedule      per-system item counts and prefix sums from the ion offsets
-//   k_near_count,   (energy launches) each system's ions with r > 0.98 a placed after its others,
+//   k_near_count,   (energy launches) each system's ions with r > 0.995 a placed after its others,
 //   k_near_scan     so that the energy sums can take expanded distances on the rest
 //   k_pack          item -> system maps; Kelvin images (Sec. 2.4: r_K = (a/r)^2 x, q_K), exact FP64
 //                   own-image term, packed sources/targets in the pair precision, domain check
@@ -127,7 +127,7 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
 // Energy pairs whose source lies within r <= NEAR_R a take the expanded form of the squared image
 // distance (see energy_item); sources nearer the interface take the exact form.
-constexpr double NEAR_R = 0.98;
+constexpr double NEAR_R = 0.995;
 // Surface pairs of the energy launch take the expanded squared distance when every node lies on
 // the sphere R_tau >= SURF_EXPANDED a (see energy_item).
 constexpr double SURF_EXPANDED = 1.05;
@@ -624,8 +624,8 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // sphere's radius): three FMAs from the per-source (-2x/(a w), -2y/(a w), -2z/(a w)), with 1/sqrt(w)
 // in the weights (q', q' r/a) / sqrt(w), where the exact differences take six operations.  Every
 // term of the sum is at most 1 in magnitude (2 |c||x| <= |c|^2 + |x|^2) and the sum is at least
-// ((rc - NEAR_R a)/a)^2 / ((rc/a)^2 + NEAR_R^2) >= 2e-4 (rc >= a), so its rounding stays within a
-// few 1e-12 relative.  Sources in runs of 8 (their scalar loads batched).
+// ((rc - NEAR_R a)/a)^2 / ((rc/a)^2 + NEAR_R^2) >= 1.2e-5 (rc >= a), so its rounding stays within
+// about 5e-11 relative (1e-13 at rc = 1.1 a).  Sources in runs of 8 (their scalar loads batched).
 __device__ __forceinline__ void check_range_expanded(const double4 &ck, double ia, const CheckSrc *__restrict__ cs,
                                                      int j0, int j1, double &au, double &av) {
   const double cx = ck.x * ia, cy = ck.y * ia, cz = ck.z * ia;
@@ -2139,8 +2139,8 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
       // (the energy launch packs the ions nearer the interface last), the squared image distance
       // times (r_j/a)^2 is expanded, D = (r_i/a)^2 (r_j/a)^2 + 1 - 2 (x_i/a).(x_j/a) (the identity
       // behind the symmetric form), and 1/|x_i - r_K,j| = (r_j/a^2) D^-1/2 with r_j/a^2 folded
-      // into the weights: four operations instead of six.  D >= (1 - r_j/a)^2 >= 4e-4 there, so
-      // its rounding stays below about 1e-12 relative.  Other blocks take the differences
+      // into the weights: four operations instead of six.  D >= (1 - r_j/a)^2 >= 2.5e-5 there, so
+      // its rounding stays below about 1e-11 relative.  Other blocks take the differences
       // x_i/a - r_K,j/a, with 1/a joining their weights.
       const double ia = 1.0 / ex.plans[plan_of ? plan_of[b] : 0].a;
 #pragma unroll
