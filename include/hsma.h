@@ -150,11 +150,11 @@ hsma_status hsma_potential(hsma_plan_t plan, int64_t N, const double *x, const d
  * a bilinear form in the charges, so it is summed without forming the potentials: per ion pair
  * one reciprocal root serves both ordered image terms (the symmetric image distance of Sec. 2.4),
  * and every ion block pair and surface-node chunk adds one FP64 value; check sums and fit are
- * FP64 as well.  Pairs whose source lies within 0.995 a of the centre, and surface pairs when the
- * nodes lie on one sphere R_tau >= 1.05 a, take their squared distance in expanded form
- * (|x|^2 + |y|^2 - 2 x.y scaled, for the check sums divided by |x|^2 + |y|^2; a pair's form
- * rounds to at most about 5e-11 relative, for the pairs nearest the interface); the rest take
- * exact differences.  E: [device] one double.  phi: [device] N doubles, or NULL for the energy alone;
+ * FP64 as well.  Ion pairs of which one ion lies within 0.995 a of the centre, check sums over
+ * such ions, and surface pairs when the nodes lie on one sphere R_tau >= 1.05 a, take their
+ * squared distance in expanded form (|x|^2 + |y|^2 - 2 x.y scaled, for the check sums divided
+ * by |x|^2 + |y|^2; a pair's form rounds to at most about 5e-11 relative, for the pairs nearest
+ * the interface); the rest take exact differences.  E: [device] one double.  phi: [device] N doubles, or NULL for the energy alone;
  * when given, a second launch on the same workspace writes the potentials in the plan's pair
  * precision (E is the same bit for bit either way). */
 hsma_status hsma_energy(hsma_plan_t plan, int64_t N, const double *x, const double *y, const double *z,

@@ -125,8 +125,9 @@ __device__ __forceinline__ int64_t cdiv64(int64_t a, int64_t b) { return (a + b 
 // evaluation kernels.
 // ---------------------------------------------------------------------------------
 constexpr int64_t EC = 4096;  // item energies per chunk of the energy reduction
-// Energy pairs whose source lies within r <= NEAR_R a take the expanded form of the squared image
-// distance (see energy_item); sources nearer the interface take the exact form.
+// Energy pairs with an ion within r <= NEAR_R a take the expanded form of the squared image
+// distance (see energy_item), and so do check sums over such sources (check_range_expanded);
+// pairs of two ions nearer the interface, and check sums over them, take the exact form.
 constexpr double NEAR_R = 0.995;
 // Surface pairs of the energy launch take the expanded squared distance when every node lies on
 // the sphere R_tau >= SURF_EXPANDED a (see energy_item).
@@ -311,7 +312,7 @@ __device__ __forceinline__ void fill_maps(const Sched &S, int nsys, int *__restr
 
 // ---------------------------------------------------------------------------------
 // Energy launches place each system's ions with r > NEAR_R a after its other ions, keeping
-// the order within each part, so that the energy kernel's source blocks below the boundary
+// the order within each part, so that the energy kernel's ion blocks below the boundary
 // hold no ion near the interface (see energy_item).  Per finish block: the count of such ions
 // (k_near_count), then per system the start of each block's part of either kind (k_near_scan),
 // then each ion's packed position (partition_rank, in k_pack).
@@ -2135,13 +2136,14 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
         }
       }
     } else {
-      // Off-diagonal block, in units of a.  When every source of block J lies at r_j <= NEAR_R a
-      // (the energy launch packs the ions nearer the interface last), the squared image distance
-      // times (r_j/a)^2 is expanded, D = (r_i/a)^2 (r_j/a)^2 + 1 - 2 (x_i/a).(x_j/a) (the identity
-      // behind the symmetric form), and 1/|x_i - r_K,j| = (r_j/a^2) D^-1/2 with r_j/a^2 folded
-      // into the weights: four operations instead of six.  D >= (1 - r_j/a)^2 >= 2.5e-5 there, so
-      // its rounding stays below about 1e-11 relative.  Other blocks take the differences
-      // x_i/a - r_K,j/a, with 1/a joining their weights.
+      // Off-diagonal block, in units of a.  When every target of block I lies at r_i <= NEAR_R a
+      // (the energy launch packs the ions nearer the interface last, so then do all ions before
+      // them), the squared image distance times (r_j/a)^2 is expanded,
+      // D = (r_i/a)^2 (r_j/a)^2 + 1 - 2 (x_i/a).(x_j/a) (the identity behind the symmetric form),
+      // and 1/|x_i - r_K,j| = (r_j/a^2) D^-1/2 with r_j/a^2 folded into the weights: four
+      // operations instead of six.  D >= (1 - r_i r_j/a^2)^2 >= (1 - r_i/a)^2 >= 2.5e-5 there
+      // (r_j <= a), so its rounding stays within a few 1e-11 relative.  Only pairs of two ions
+      // near the interface take the differences x_i/a - r_K,j/a, with 1/a joining their weights.
       const double ia = 1.0 / ex.plans[plan_of ? plan_of[b] : 0].a;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
@@ -2149,7 +2151,7 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
         ty[k] *= ia;
         tz[k] *= ia;
       }
-      if ((int64_t)j1 <= ex.nfar[b]) {
+      if ((int64_t)(t0 + TB) <= ex.nfar[b]) {
         const double4 *em = ex.emx + lo;
         const double2 *ewt = ex.ew + lo;
         double uu[R];

@@ -2,9 +2,10 @@
 through the C ABI, against the oracle.
 
 The energy launch places each system's ions with r > 0.995 a after its other ions, keeping their
-order within each part; the Kelvin pairs whose source block holds only the first kind, and the
-check sums over those sources, take an expanded squared distance; every other pair takes the
-exact differences.  Which pairs take which form moves with the block size (128, 256 or 512 ions)
+order within each part; the Kelvin pairs whose target block holds only the first kind (all but
+the pairs of two ions near the interface, and those of blocks across the split), and the check
+sums over such ions, take an expanded squared distance; every other pair takes the exact
+differences.  Which pairs take which form moves with the block size (128, 256 or 512 ions)
 and with the split point of each system, so the batch below holds systems whose ions near the
 interface are none, all, about half, exactly two blocks' worth of ions far from it, ions on the
 0.995 a boundary itself, ions within 2e-6 a of the interface, and ragged small systems, in shuffled

@@ -2,9 +2,9 @@
 
 The energy launch replaces exact coordinate differences by expanded forms where they cannot
 cancel badly (the kernels' comments state the bounds):
-- Kelvin pairs whose source lies at r_j <= 0.995 a: D = (r_i/a)^2 (r_j/a)^2 + 1 - 2 (x_i/a).(x_j/a),
-  which is |x_i - r_K,j|^2 (r_j/a)^2 / a^2 for the Kelvin point r_K,j = (a/r_j)^2 x_j (Sec. 2.4)
-  and is symmetric in i and j;
+- Kelvin pairs of which one ion lies at r <= 0.995 a: D = (r_i/a)^2 (r_j/a)^2 + 1 - 2 (x_i/a).(x_j/a),
+  which is |x_i - r_K,j|^2 (r_j/a)^2 / a^2 for the Kelvin point r_K,j = (a/r_j)^2 x_j (Sec. 2.4),
+  is symmetric in i and j, and is at least (1 - r_i r_j / a^2)^2;
 - check sums over sources at r <= 0.995 a: with w = (r/a)^2 + (rc/a)^2 and |c| = rc,
   |c - x|^2 / (a^2 w) = 1 + (c/a).(-2x/(a w));
 - surface pairs with every node on one sphere R_tau >= 1.05 a: |x - y|^2 = |x|^2 + R_tau^2 - 2 x.y,
@@ -60,9 +60,12 @@ def test_kelvin_expanded_form_rounding():
     a = 23.7
     ia = 1.0 / a
     worst = 0.0
-    for t in range(600):
-        ri = a * (0.9 + 0.1 * rng.random()) if t % 2 else a * rng.random() ** (1 / 3)
-        rj = a * NEAR * (1 - 1e-3 * rng.random()) if t % 3 else a * NEAR * rng.random() ** (1 / 3)
+    for t in range(900):
+        # one ion within NEAR a (often just inside it), the other anywhere up to the interface
+        r_far = a * NEAR * (1 - 1e-3 * rng.random()) if t % 3 else a * NEAR * rng.random() ** (1 / 3)
+        r_any = a * (1 - 1e-9 * rng.random()) if t % 4 == 0 else a * (0.9 + 0.1 * rng.random()) if t % 2 \
+            else a * rng.random() ** (1 / 3)
+        ri, rj = (r_far, r_any) if t % 5 < 3 else (r_any, r_far)
         ui = _unit(rng)
         uj = _near(rng, ui, 0.02) if t % 5 else _unit(rng)
         xi = [float(v) for v in ri * ui]
@@ -76,9 +79,9 @@ def test_kelvin_expanded_form_rounding():
         d = fma(tx, m[0], fma(ty, m[1], fma(tz, m[2], fma(uu, m[3], 1.0))))
         A = Fr(a)
         D = _dot(xi, xi) * _dot(xj, xj) / A**4 + 1 - 2 * _dot(xi, xj) / A**2
-        assert D >= (1 - Fr(NEAR)) ** 2 * Fr(99, 100)  # (1 - r_j/a)^2 with r_j <= NEAR a
+        assert D >= (1 - Fr(NEAR)) ** 2 * Fr(99, 100)  # (1 - r_i r_j/a^2)^2, one of them <= NEAR a
         worst = max(worst, float(abs(Fr(d) - D) / D))
-    assert worst <= 1.5e-11, worst
+    assert worst <= 4e-11, worst
 
 
 def test_check_normalised_form():
