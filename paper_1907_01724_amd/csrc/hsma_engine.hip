@@ -1982,11 +1982,14 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
     const double2 *qb = qd + (size_t)b * P;
     const double Rt = ex.plans[pl].Rtau, R2 = Rt * Rt;
     // Every node on the sphere R_tau (not the point-pair form) with R_tau >= 1.05 a: |x - y|^2 =
-    // |x|^2 + R_tau^2 - 2 x.y, three FMAs from the target's -2x and |x|^2 + R_tau^2, and the
-    // dipole's (x - y).y = (|x|^2 - R_tau^2 - D)/2 from D itself.  D >= (R_tau - a)^2 >= 0.0025 a^2
-    // there, so both round to about 1e-12 relative.  Otherwise the exact differences.
+    // |x|^2 + R_tau^2 - 2 x.y, three FMAs from the target's -2x and |x|^2 + R_tau^2.  D >=
+    // (R_tau - a)^2 >= 0.0025 a^2 there, so it rounds to about 1e-12 relative.  The dipole's
+    // (x - y).y = (|x|^2 - R_tau^2 - D)/2, so with r = 2/sqrt(D) (rinv2, D r^2 = 4 up to the Newton
+    // step's 1e-14) twice its term is w_d ((|x|^2 - R_tau^2)/8 r^3 - r/2): two sums over the
+    // nodes per target, both terms of one sign (|x| < R_tau), the first scaled once at the end.
+    // Otherwise the exact differences.  Monopole-only and dipole loops are separate.
     const bool sexp = ex.plans[pl].dipole != 1 && Rt >= SURF_EXPANDED * ex.plans[pl].a;
-    double f0[RS], f1[RS], f2[RS], f3[RS], f4[RS], sq[RS], acc[RS];
+    double f0[RS], f1[RS], f2[RS], f3[RS], f4[RS], sq[RS], acc[RS], acc3[RS], acc1[RS];
 #pragma unroll
     for (int k = 0; k < RS; ++k) {
       const int i = t0 + k * 64 + lane;
@@ -2001,38 +2004,58 @@ __device__ __forceinline__ void energy_item(int64_t item, int nsys, int P, int s
       f4[k] = 0.125 * (xx - R2);
       sq[k] = in ? q[lo + i] : 0.0;
       acc[k] = 0.0;
+      acc3[k] = 0.0;
+      acc1[k] = 0.0;
     }
     if (sexp) {
-      // the sums hold twice the terms (rinv2), and (x - y).y / 4 against the cube
-      for (int m = s0; m < s1; ++m) {
-        const double4 yv = nd[m];
-        const double2 wv = qb[m];
+      // the sums hold twice the terms (rinv2)
+      if (mono) {
+#pragma unroll 2
+        for (int m = s0; m < s1; ++m) {
+          const double4 yv = nd[m];
+          const double wx = qb[m].x;
 #pragma unroll
-        for (int k = 0; k < RS; ++k) {
-          const double d = fma(f0[k], yv.x, fma(f1[k], yv.y, fma(f2[k], yv.z, f3[k])));
-          const double ri = rinv2(d);
-          if (mono) {
+          for (int k = 0; k < RS; ++k)
+            acc[k] = fma(wx, rinv2(fma(f0[k], yv.x, fma(f1[k], yv.y, fma(f2[k], yv.z, f3[k])))), acc[k]);
+        }
+      } else {
+#pragma unroll 2
+        for (int m = s0; m < s1; ++m) {
+          const double4 yv = nd[m];
+          const double2 wv = qb[m];
+#pragma unroll
+          for (int k = 0; k < RS; ++k) {
+            const double ri = rinv2(fma(f0[k], yv.x, fma(f1[k], yv.y, fma(f2[k], yv.z, f3[k]))));
             acc[k] = fma(wv.x, ri, acc[k]);
-          } else {
-            const double dq = fma(-0.125, d, f4[k]);
-            acc[k] = fma(ri, fma(wv.y * dq, ri * ri, wv.x), acc[k]);
+            acc3[k] = fma(wv.y, ri * ri * ri, acc3[k]);
+            acc1[k] = fma(wv.y, ri, acc1[k]);
           }
         }
+#pragma unroll
+        for (int k = 0; k < RS; ++k) acc[k] = fma(f4[k], acc3[k], fma(-0.5, acc1[k], acc[k]));
       }
 #pragma unroll
       for (int k = 0; k < RS; ++k) e = fma(sq[k], acc[k], e);
       e *= 0.5;
     } else {
-      for (int m = s0; m < s1; ++m) {
-        const double4 yv = nd[m];
-        const double2 wv = qb[m];
+      if (mono) {
+        for (int m = s0; m < s1; ++m) {
+          const double4 yv = nd[m];
+          const double wx = qb[m].x;
 #pragma unroll
-        for (int k = 0; k < RS; ++k) {
-          const double dx = f0[k] - yv.x, dy = f1[k] - yv.y, dz = f2[k] - yv.z;
-          const double ri = rinv(dx * dx + dy * dy + dz * dz);
-          if (mono) {
-            acc[k] = fma(wv.x, ri, acc[k]);
-          } else {
+          for (int k = 0; k < RS; ++k) {
+            const double dx = f0[k] - yv.x, dy = f1[k] - yv.y, dz = f2[k] - yv.z;
+            acc[k] = fma(wx, rinv(dx * dx + dy * dy + dz * dz), acc[k]);
+          }
+        }
+      } else {
+        for (int m = s0; m < s1; ++m) {
+          const double4 yv = nd[m];
+          const double2 wv = qb[m];
+#pragma unroll
+          for (int k = 0; k < RS; ++k) {
+            const double dx = f0[k] - yv.x, dy = f1[k] - yv.y, dz = f2[k] - yv.z;
+            const double ri = rinv(dx * dx + dy * dy + dz * dz);
             const double dot = dx * yv.x + dy * yv.y + dz * yv.z;
             acc[k] = fma(ri, fma(wv.y * dot, ri * ri, wv.x), acc[k]);
           }
