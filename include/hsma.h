@@ -264,7 +264,7 @@ hsma_status hsma_field_batched(hsma_group_t group, int nsys, const int64_t *offs
  * one grid of resident blocks (the occupancy limit on every compute unit) whose blocks
  * take (system, 64 targets, source chunk) items from a device counter; 0 (default): one
  * item per block, the hardware workgroup dispatcher balancing the load.  target_items
- * (default 16384, 64..2^22): the number of items each pair kernel aims for, which sets the
+ * (default 65536, 64..2^22): the number of items each pair kernel aims for, which sets the
  * source-chunk length.  Results depend on the launch shape only through the summation
  * order (rounding).  Errors: HSMA_EINVAL. */
 hsma_status hsma_group_tune(hsma_group_t group, int persistent, int target_items);

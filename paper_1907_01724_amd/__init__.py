@@ -419,7 +419,7 @@ class Plan:
         """Handle of the one-plan group this plan owns (for profiling)."""
         return load_library().hsma_plan_group(self._h)
 
-    def tune(self, persistent: bool = False, target_items: int = 16384):
+    def tune(self, persistent: bool = False, target_items: int = 65536):
         _check(load_library().hsma_group_tune(self.group, 1 if persistent else 0, int(target_items)),
                "hsma_group_tune")
 
@@ -569,7 +569,7 @@ class Group:
             f[2].data_ptr(), e_ptr, w.ptr, w.nbytes, _stream_ptr(stream)), "hsma_field_batched")
         return phi, f.t(), (None if E is False else E)
 
-    def tune(self, persistent: bool = False, target_items: int = 16384):
+    def tune(self, persistent: bool = False, target_items: int = 65536):
         _check(load_library().hsma_group_tune(self._h, 1 if persistent else 0, int(target_items)), "hsma_group_tune")
 
     def set_symmetric(self, mode: int = 1):

@@ -806,7 +806,7 @@ hsma_status group_build(int nplans, const hsma_plan_t *plans, int owned_by_plan,
   grp->P_ev = g->P * (dipole == 1 ? 3 : 1);
   grp->dipole = dipole;
   grp->tune.persistent = 0;
-  grp->tune.target_items = 16384;
+  grp->tune.target_items = 65536;
   grp->tune.symmetric = 1;
   grp->tune.fit = 0;
   grp->tune.sym_order = 0;

@@ -109,7 +109,7 @@ Dims tune_dims(const hsma_group_s *g, bool pot, bool energy) {
     d.push_back({&hsma_launch_settings::energy_workgroups, {0, ncu, 2 * ncu, 4 * ncu}});
   }
   d.push_back({&hsma_launch_settings::persistent, {0, 1}});
-  d.push_back({&hsma_launch_settings::target_items, {16384, 4096, 65536}});
+  d.push_back({&hsma_launch_settings::target_items, {65536, 16384, 4096}});
   return d;
 }
 

@@ -80,7 +80,7 @@ def batch(dev):
 
 
 CASES = [("persistent", 1), ("symmetric", 0), ("symmetric", 2), ("symmetric", 3), ("sym_order", 1),
-         ("sym_order", 2), ("target_items", 4096), ("target_items", 65536), ("fit", 1), ("fit", 2), ("fit", 4),
+         ("sym_order", 2), ("target_items", 4096), ("target_items", 16384), ("fit", 1), ("fit", 2), ("fit", 4),
          ("energy_block", 128), ("energy_block", 256), ("energy_block", 512), ("energy_workgroups", 8),
          ("energy_workgroups", 256)]
 
