@@ -1515,15 +1515,29 @@ __device__ __forceinline__ float sym_source(const float4 &v, const float (&tx)[R
 
 // Surface nodes s0..s1-1 onto RS target sets per lane, FP32 tiles of TILE nodes folded into
 // FP64.  MONO: the single-layer form, monopoles only (the dipole strengths are zero).
-template <int RS, bool MONO>
+// SPLIT: exact dipoles with every node on the sphere R_tau (r2t = R_tau^2): (x - y).y =
+// (|x|^2 - R_tau^2 - d^2)/2 and d^2 r^2 = 1 (r = 1/d from the hardware root, to about 2e-7), so a
+// dipole term is w_d ((|x|^2 - R_tau^2)/2 r^3 - r/2): three sums per target, the first scaled at
+// each tile's end, both parts of one sign (|x| < R_tau).  The rest: (x - y).y from the differences.
+template <int RS, bool MONO, bool SPLIT = false>
 __device__ __forceinline__ void sym_surface(const float (&sx)[RS], const float (&sy)[RS], const float (&sz)[RS],
                                             const float4 *__restrict__ nd, const float2 *__restrict__ qb, int s0,
-                                            int s1, double (&acc)[RS]) {
+                                            int s1, double (&acc)[RS], float r2t = 0.0f) {
+  double hf[RS];
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int k = 0; k < RS; ++k)
+      hf[k] = 0.5 * ((double)sx[k] * sx[k] + (double)sy[k] * sy[k] + (double)sz[k] * sz[k] - (double)r2t);
+  }
   for (int sb = s0; sb < s1; sb += TILE) {
     const int se = sb + TILE < s1 ? sb + TILE : s1;
-    float sum[RS];
+    float sum[RS], s3[RS], s1w[RS];
 #pragma unroll
-    for (int k = 0; k < RS; ++k) sum[k] = 0.0f;
+    for (int k = 0; k < RS; ++k) {
+      sum[k] = 0.0f;
+      s3[k] = 0.0f;
+      s1w[k] = 0.0f;
+    }
     for (int m = sb; m < se; ++m) {
       const float4 yv = nd[m];
       const float2 wv = qb[m];
@@ -1533,6 +1547,10 @@ __device__ __forceinline__ void sym_surface(const float (&sx)[RS], const float (
         const float ri = rinv(dx * dx + dy * dy + dz * dz);
         if constexpr (MONO) {
           sum[k] = fmaf(wv.x, ri, sum[k]);
+        } else if constexpr (SPLIT) {
+          sum[k] = fmaf(wv.x, ri, sum[k]);
+          s3[k] = fmaf(wv.y, ri * ri * ri, s3[k]);
+          s1w[k] = fmaf(wv.y, ri, s1w[k]);
         } else {
           const float dot = dx * yv.x + dy * yv.y + dz * yv.z;
           sum[k] = fmaf(ri, fmaf(wv.y * dot, ri * ri, wv.x), sum[k]);
@@ -1540,18 +1558,23 @@ __device__ __forceinline__ void sym_surface(const float (&sx)[RS], const float (
       }
     }
 #pragma unroll
-    for (int k = 0; k < RS; ++k) acc[k] += (double)sum[k];
+    for (int k = 0; k < RS; ++k) {
+      if constexpr (SPLIT)
+        acc[k] += fma(hf[k], (double)s3[k], fma(-0.5, (double)s1w[k], (double)sum[k]));
+      else
+        acc[k] += (double)sum[k];
+    }
   }
 }
 
 // One item of the symmetric kernel (a block pair or a surface item), by one wave.
 template <int R>
-__device__ __forceinline__ void sym_item(int64_t item, const Sched &S, int lane, int P, int sch, int mono,
+__device__ __forceinline__ void sym_item(int64_t item, const Sched &S, int lane, int P, int sch, int dipole,
                                          const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
                                          const float4 *__restrict__ tgt, const float4 *__restrict__ img,
                                          const float *__restrict__ wk, const double *__restrict__ rk,
                                          const float4 *__restrict__ nodes, const float2 *__restrict__ qd,
-                                         double *__restrict__ part) {
+                                         const PlanDev *__restrict__ plans, double *__restrict__ part) {
   constexpr int TB = 64 * R;
   constexpr int RS = R / SYM_SH;         // target sets per lane of a surface item
   constexpr float FAR_TARGET = 3.0e18f;  // stand-in position of an empty target lane
@@ -1592,8 +1615,10 @@ __device__ __forceinline__ void sym_item(int64_t item, const Sched &S, int lane,
     const int pl = plan_of ? plan_of[b] : 0;
     const float4 *nd = nodes + (size_t)pl * P;
     const float2 *qb = qd + (size_t)b * P;
-    if (mono)
+    if (dipole == 2)
       sym_surface<RS, true>(sx, sy, sz, nd, qb, s0, s1, acc);
+    else if (dipole == 0)
+      sym_surface<RS, false, true>(sx, sy, sz, nd, qb, s0, s1, acc, (float)(plans[pl].Rtau * plans[pl].Rtau));
     else
       sym_surface<RS, false>(sx, sy, sz, nd, qb, s0, s1, acc);
     const int64_t slot = B + c;
@@ -1709,20 +1734,20 @@ __device__ __forceinline__ void sym_item(int64_t item, const Sched &S, int lane,
 // persistent form, whose waves take items EG at a time from their die's counter in the order of
 // die_item until the die's items run out.  Every item writes the same slots either way.
 template <int R, bool PERSIST>
-__global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, int mono,
+__global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, int dipole,
                                                     const int64_t *__restrict__ base,
                                                     const int *__restrict__ sys_e, const int32_t *__restrict__ plan_of,
                                                     const float4 *__restrict__ tgt, const float4 *__restrict__ img,
                                                     const float *__restrict__ wk, const double *__restrict__ rk,
-                                                    const float4 *__restrict__ nodes,
-                                                    const float2 *__restrict__ qd, double *__restrict__ part) {
+                                                    const float4 *__restrict__ nodes, const float2 *__restrict__ qd,
+                                                    const PlanDev *__restrict__ plans, double *__restrict__ part) {
   Sched S(const_cast<int64_t *>(base), nsys);
   const int lane = threadIdx.x & 63, w = wave_id();
   if (!sched_ok(S)) return;
   const int64_t total = S.is[nsys];
   if constexpr (!PERSIST) {
     const int64_t item = uniform64((int64_t)blockIdx.x * WAVES + w);
-    if (item < total) sym_item<R>(item, S, lane, P, sch, mono, sys_e, plan_of, tgt, img, wk, rk, nodes, qd, part);
+    if (item < total) sym_item<R>(item, S, lane, P, sch, dipole, sys_e, plan_of, tgt, img, wk, rk, nodes, qd, plans, part);
   } else {
     const int64_t x = blockIdx.x % NXCD;
     for (;;) {
@@ -1732,7 +1757,7 @@ __global__ __launch_bounds__(TPB) void k_kelvin_sym(int nsys, int P, int sch, in
       if (die_item(x, t) >= total) return;  // every later claim of this die lies beyond too
       for (int g = 0; g < EG; ++g) {
         const int64_t item = die_item(x, t + g);
-        if (item < total) sym_item<R>(item, S, lane, P, sch, mono, sys_e, plan_of, tgt, img, wk, rk, nodes, qd, part);
+        if (item < total) sym_item<R>(item, S, lane, P, sch, dipole, sys_e, plan_of, tgt, img, wk, rk, nodes, qd, plans, part);
       }
     }
   }
@@ -2591,8 +2616,8 @@ hsma_status launch(hsma_group_s *grp, const Layout &L, const int64_t *offsets, c
       const float *wk = (const float *)(ws + L.wk);
       const double *rk = (const double *)(ws + L.rk);
       auto run = [&](auto kern) {
-        kern<<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole == 2, base, sys_e, plan_of, tgt, img, wk, rk,
-                                 grp->nodes32, qd, eval_part);
+        kern<<<gs, TPB, 0, st>>>(nsys, Pe, L.sch, grp->dipole, base, sys_e, plan_of, tgt, img, wk, rk,
+                                 grp->nodes32, qd, plans, eval_part);
       };
       if (L.sym_tb == 256)
         persistent ? run(k_kelvin_sym<4, true>) : run(k_kelvin_sym<4, false>);
