@@ -113,11 +113,15 @@ def test_uneven_batch_shared_plan(dev, prec, persistent, items):
     _check_systems(group, [plan] * len(systems), systems, off, phi.cpu().numpy(), E.cpu().numpy(), prec, dev)
 
 
-def test_plans_with_different_cavities(dev):
-    """One group, three cavities of different radius and screening; systems mapped by plan_of."""
+@pytest.mark.parametrize("symmetric", [1, 2])
+def test_plans_with_different_cavities(dev, symmetric):
+    """One group, three cavities of different radius and screening; systems mapped by plan_of.
+    Symmetric mode 1 leaves this small batch to the one-directional kernel; mode 2 forces the
+    symmetric kernel, whose surface items take each system's own sphere radius R_tau."""
     cav = [(15.0, 0.05), (27.0, 0.4), (40.0, 1.0)]
     plans = [hs.Plan(a, 1.0, 78.5, k, 1024, 1536) for a, k in cav]
     group = hs.Group(plans)
+    group.set_symmetric(symmetric)
     which = [0, 2, 1, 1, 0, 2, 2, 0, 1, 0]
     systems = [W.small_uniform(300 + 97 * b, cav[w][0], seed=500 + b) for b, w in enumerate(which)]
     off, off_d, t = _batch(systems, dev)
